@@ -1,0 +1,164 @@
+"""Benchmark of the NCO stream-collide hot path on one MI355X.
+
+Workload: Taylor-Green vortex on a periodic 128^3 D3Q27 lattice, float32
+populations, Re = 1600, Ma = 0.1 (u0 = 0.1/sqrt(3)), NCO collision with a
+27-32-32-4 tanh network (seeded N(0, 0.1) weights), forward only.  One
+"step" is one lattice time step: one fused pull-stream + moments + network +
+relax + back-transform launch over all 128^3 nodes.  BGK and fixed-rate
+moment relaxation are timed on the same grid and reported beside it.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
+FP32_PEAK_TFLOPS = 157.3         # MI355X float32 (vector and dense matrix)
+METRIC = "NCO stream-collide GLUPS & % HBM peak, FP32 vs low-precision; p99 solve latency"
+
+
+def nco_flops_per_node(width):
+    """Multiply-adds of the group-averaged network, counted as 2 flops each:
+    48 x (27 W + W^2) for the two hidden layers of every group element plus
+    4 W for the output layer applied once to the group mean."""
+    return 2 * (48 * (27 * width + width * width) + 4 * width)
+
+
+def bytes_per_node(storage):
+    return 2 * 27 * {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}[storage]
+
+
+def time_op(lat, steps, warmup, torch):
+    """Average wall time of one step (one kernel launch) from HIP events on the
+    lattice's stream, which is torch's current stream."""
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    lat.step(steps)
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def cpu_baseline(n_sample=64, nsteps=2):
+    """The float64 oracle timed on the host, on a bounded sample: the same
+    workload at n_sample^3 for nsteps steps."""
+    from oracle import collision, step
+    from paper_2412_08229_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    u0 = 0.1 / math.sqrt(3.0)
+    _, tau = inputs.viscosity(n_sample, u0, 1600.0)
+    rho, u = inputs.tgv3d(n_sample, u0)
+    layers = collision.unpack_params(inputs.mlp_params(32, 0), 32)
+    op = step.Operator("nco", tau, layers=layers, act="tanh")
+    f = collision.equilibrium(rho, u)
+    t0 = time.perf_counter()
+    step.run(f, op, nsteps)
+    dt = time.perf_counter() - t0
+    glups = n_sample ** 3 * nsteps / dt / 1e9
+    return {"value": glups, "unit": "GLUPS", "cores": int(threads), "kind": "oracle",
+            "sample": "NCO 27-32-32-4 tanh, TGV %d^3, %d steps, float64 numpy, %.1f s"
+                      % (n_sample, nsteps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ops", default="nco,bgk,mrt")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the lattice path runs on a single MI355X; "
+              "multi-GPU domain decomposition is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2412_08229_amd import Lattice, inputs
+
+    n = args.n
+    u0 = 0.1 / math.sqrt(3.0)
+    _, tau = inputs.viscosity(n, u0, 1600.0)
+    rho, u = inputs.tgv3d(n, u0)
+    stream = torch.cuda.current_stream().cuda_stream
+    width = 32
+    params = inputs.mlp_params(width, seed=0)
+    nodes = n ** 3
+    results = {}
+    for op in args.ops.split(","):
+        lat = Lattice((n, n, n), "f32", op, tau, stream=stream)
+        if op == "nco":
+            lat.set_net_weights(params, width, "tanh")
+        if op == "mrt":
+            lat.set_rates([4.0 / 3.0] * 4)
+        lat.init_equilibrium(rho, u)
+        steps = args.steps
+        ms = time_op(lat, steps, args.warmup, torch)
+        s = lat.global_sums()
+        if not np.all(np.isfinite(s)):
+            raise RuntimeError("non-finite state after the %s run" % op)
+        lat.close()
+        glups = nodes / (ms * 1e-3) / 1e9
+        gbs = bytes_per_node("f32") * nodes / (ms * 1e-3) / 1e9
+        results[op] = {"ms_per_step": ms, "glups": glups, "hbm_gbs": gbs,
+                       "hbm_frac": gbs / HBM_PEAK_GBS}
+        print("# %s: %.4f ms/step, %.3f GLUPS, %.0f GB/s" % (op, ms, glups, gbs), file=sys.stderr,
+              flush=True)
+
+    main_op = "nco" if "nco" in results else list(results)[0]
+    r = results[main_op]
+    if main_op == "nco":
+        flops = nco_flops_per_node(width) * nodes
+        achieved = flops / (r["ms_per_step"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "kernel": "k_stream_collide<f32, NCO, W=32, tanh>",
+                "algorithmic_per_node": "%d flop (network) + %d B" % (nco_flops_per_node(width),
+                                                                     bytes_per_node("f32"))}
+    else:
+        roof = {"bound": "hbm", "achieved": r["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": r["hbm_frac"], "traffic": None}
+    out = {
+        "metric": METRIC,
+        "value": r["glups"],
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Taylor-Green vortex %d^3 D3Q27, Re 1600, Ma 0.1, %s collision, "
+                               "27-32-32-4 tanh network, float32 storage, forward only" % (n, main_op.upper()),
+                   "lattice": [n, n, n], "operator": main_op, "storage": "f32", "width": width},
+        "roofline": roof,
+        "operators": results,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,149 @@
+/*
+ * nco.h - C ABI of the MI355X (gfx950) neural-collision-operator lattice
+ * Boltzmann engine.
+ *
+ * The engine advances a periodic D3Q27 lattice by the lattice Boltzmann
+ * equation f_i(x + c_i, t + 1) = f_i(x, t) + Omega_i(f) + S_i(f)
+ * (paper Sec. II.A) with one of three collision operators:
+ *   NCO_OP_BGK  Omega_i = -(f_i - f_i^eq) / tau                (Sec. II.A)
+ *   NCO_OP_MRT  Omega = -M^{-1} S (M f - m^eq), fixed rates    (Eq. omegatheta
+ *               with constant higher-order rates)
+ *   NCO_OP_NCO  the same with the four higher-order rates from the
+ *               group-averaged invariant network               (Eq. omegatheta,
+ *               Eq. gconv_m and the sigmoid rate squashing of Sec. II.B)
+ *   NCO_OP_STREAM no collision: streaming alone (a pure permutation of the
+ *               stored values, exact in every storage format)
+ * where M is the Hermite moment matrix of Sec. II.B, S has rate 1 for the
+ * conserved moments, 1/tau for all second-order moments and one rate per
+ * order 3, 4, 5, 6.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns an nco_status; on failure nco_last_error() holds a
+ *    message for the calling thread.  Nothing aborts the process.
+ *  - Host arrays are float64 (network parameters float32), borrowed for the
+ *    duration of the call only; copies are synchronous with respect to the
+ *    lattice's stream.
+ *  - Node order is [z][y][x] with x fastest.  Populations are [27][z][y][x]
+ *    with velocity index i = 9 (c_z + 1) + 3 (c_y + 1) + (c_x + 1); a
+ *    velocity field is [3][z][y][x].
+ *  - The stored state is the post-collision population.  One step pulls
+ *    f_i(x - c_i) into x (periodic wrap) and collides there.
+ *  - The library owns all device memory it allocates.  A lattice lives on
+ *    the device that was current when it was created and runs its work on
+ *    one HIP stream; calls on different lattices may come from different
+ *    threads, calls on one lattice must not overlap.
+ */
+#ifndef NCO_H
+#define NCO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nco_lattice nco_lattice;
+
+typedef enum {
+    NCO_OK = 0,
+    NCO_E_INVALID = -1,     /* bad argument (size, tau <= 1/2, weight count, ...) */
+    NCO_E_OOM = -2,         /* device allocation failed */
+    NCO_E_HIP = -3,         /* a HIP runtime call failed */
+    NCO_E_UNSTABLE = -4,    /* non-finite populations detected */
+    NCO_E_STATE = -5,       /* call not valid in the lattice's current state */
+    NCO_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} nco_status;
+
+/* Storage of the populations in HBM.  *_DEV stores the deviation from the
+ * rest state, (f_i - w_i) * 2^e_i, with a power-of-two scale per velocity
+ * class (e = 2, 4, 6, 8 for |c|^2 = 0, 1, 2, 3) that keeps the values in the
+ * normal range of the 16-bit formats; arithmetic is float32 in every case
+ * except NCO_F64, which computes in float64. */
+typedef enum { NCO_F32 = 0, NCO_F16_DEV = 1, NCO_BF16_DEV = 2, NCO_F64 = 3 } nco_storage;
+
+typedef enum { NCO_OP_BGK = 0, NCO_OP_MRT = 1, NCO_OP_NCO = 2, NCO_OP_STREAM = 3 } nco_op;
+
+/* Arithmetic of the network: float32 (VALU), float32 matrix cores, or bf16
+ * matrix-core products with float32 accumulation. */
+typedef enum { NCO_MLP_F32 = 0, NCO_MLP_F32_MFMA = 1, NCO_MLP_BF16 = 2 } nco_mlp_prec;
+
+typedef enum { NCO_ACT_TANH = 0, NCO_ACT_RELU = 1 } nco_act;
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int nco_version(void);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* nco_last_error(void);
+
+/* Device bytes a lattice of this size and storage needs (both population
+ * buffers plus per-lattice work space); used for admission decisions. */
+int nco_lattice_bytes(int nx, int ny, int nz, int storage, size_t* bytes);
+
+/* Create a lattice of nx*ny*nz nodes (each >= 1) on the current device.
+ * tau > 1/2 is the shear relaxation time, nu = (tau - 1/2)/3 (Sec. II.B).
+ * stream: a hipStream_t to run on, or NULL for a stream the library creates
+ * (default priority) and owns.  Populations start at the rest state w_i. */
+int nco_lattice_create(int nx, int ny, int nz, int storage, int op, double tau,
+                       void* stream, nco_lattice** out);
+
+int nco_lattice_destroy(nco_lattice* lat);
+
+/* Switch the collision operator and/or tau of an existing lattice. */
+int nco_set_op(nco_lattice* lat, int op, double tau);
+
+/* Fixed rates omega_3..omega_6 of the four higher-order groups (NCO_OP_MRT). */
+int nco_set_rates(nco_lattice* lat, const double omega_high[4]);
+
+/* Network Phi: 27 -> width -> width -> 4 (two hidden layers, Sec. II.B).
+ * params: width*(27 + width + 4) + 2*width + 4 float32 values in the order
+ * W1[27][width], b1[width], W2[width][width], b2[width], W3[width][4], b3[4]
+ * (each W stored [in][out] row-major).  The input is the full moment vector
+ * m^(g) = M Pi_g f in the row order of M; the output is tilde tau_n for the
+ * orders 3..6.  width must be 8, 16, 20 or 32. */
+int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec,
+                        const float* params, size_t n_params);
+
+/* f = f^eq(rho, u) (Eq. EquilibriumDistribution).  rho: N values or NULL
+ * for rho = 1; u: 3N values. */
+int nco_init_equilibrium(nco_lattice* lat, const double* rho, const double* u);
+
+/* Set the populations directly: f holds 27N values. */
+int nco_init_populations(nco_lattice* lat, const double* f);
+
+/* Advance nsteps >= 0 time steps; asynchronous on the lattice's stream. */
+int nco_step(nco_lattice* lat, int nsteps);
+
+/* Block until the lattice's stream has finished its work. */
+int nco_sync(nco_lattice* lat);
+
+/* Copy the populations (27N values) to the host. */
+int nco_read_populations(nco_lattice* lat, double* f);
+
+/* rho = sum_i f_i (N values) and u = sum_i c_i f_i / rho (3N values), either
+ * may be NULL (Sec. II.A). */
+int nco_read_macroscopic(nco_lattice* lat, double* rho, double* u);
+
+/* Relaxation rates omega_3..omega_6 the network assigns to the current
+ * state of every node (4N values, [4][z][y][x]); NCO_OP_NCO only. */
+int nco_read_rates(nco_lattice* lat, double* omega);
+
+/* float64 sums over all nodes: out[0] = mass, out[1..3] = momentum,
+ * out[4] = 1/2 sum |u|^2 with u = j / rho.  Deterministic. */
+int nco_global_sums(nco_lattice* lat, double out[5]);
+
+/* Energy spectrum of u = j / rho on a cubic lattice (nx = ny = nz = n):
+ * u_hat = DFT(u) / n^3, E(k) = 1/2 sum of |u_hat|^2 over the wavevectors in
+ * [-n/2, n/2)^3 with round(|k|) = k, for k = 0 .. nbins-1, computed in
+ * float64 (the loss of Sec. "Learning Task").  nbins must equal
+ * floor(sqrt(3) * (n/2) + 1/2) + 1. */
+int nco_energy_spectrum(nco_lattice* lat, double* E, int nbins);
+
+/* Borrowed device pointer to the current population buffer and its size in
+ * bytes; valid until the next step or destroy. */
+int nco_device_populations(nco_lattice* lat, void** dev_ptr, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NCO_H */

@@ -1,0 +1,424 @@
+// Host side of the C ABI declared in include/nco.h: lattice objects, argument
+// checking, device buffers, the A/B population swap and kernel dispatch.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nco.h"
+#include "kernels.h"
+
+using namespace nco;
+
+namespace nco {
+int spectrum_bins(int n);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? NCO_E_OOM : NCO_E_HIP, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);               \
+    } while (0)
+
+size_t store_bytes(int storage) {
+    switch (storage) {
+        case NCO_F32: return 4;
+        case NCO_F16_DEV: return 2;
+        case NCO_BF16_DEV: return 2;
+        case NCO_F64: return 8;
+        default: return 0;
+    }
+}
+
+bool width_ok(int w) { return w == 8 || w == 16 || w == 20 || w == 32; }
+
+size_t n_params_for(int width) { return (size_t)width * (27 + width + 4) + 2 * (size_t)width + 4; }
+
+// Paper row of a Hermite multi-index (inverse of row_tensor).
+int row_of_tensor(int t) {
+    for (int k = 0; k < 27; ++k)
+        if (row_tensor(k) == t) return k;
+    return -1;
+}
+
+// The 48 elements of O_h as (axis permutation, axis signs): (R c)_r =
+// s_r c_{perm_r}.  For each element and each row k of M, the group action on
+// the moments is m^(g)_k = sign * m_{src}: with h_n(-x) = (-1)^n h_n(x), the
+// row with multi-index n_k evaluated at R c is the row with multi-index n'
+// (n'_{perm_r} = n_{k,r}) times prod_r s_r^{n_{k,r}}.
+struct GroupAction {
+    int src[48][27];
+    float sign[48][27];
+};
+
+GroupAction build_group_action() {
+    GroupAction G;
+    int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int g = 0;
+    for (auto& p : perms)
+        for (int sm = 0; sm < 8; ++sm) {
+            const int s[3] = {(sm & 1) ? -1 : 1, (sm & 2) ? -1 : 1, (sm & 4) ? -1 : 1};
+            for (int k = 0; k < 27; ++k) {
+                const int t = row_tensor(k);
+                const int n[3] = {t % 3, (t / 3) % 3, t / 9};
+                int np[3];
+                int sign = 1;
+                for (int r = 0; r < 3; ++r) {
+                    np[p[r]] = n[r];
+                    if (n[r] % 2 == 1) sign *= s[r];
+                }
+                G.src[g][k] = row_of_tensor(9 * np[2] + 3 * np[1] + np[0]);
+                G.sign[g][k] = (float)sign;
+            }
+            ++g;
+        }
+    return G;
+}
+
+}  // namespace
+
+struct nco_lattice {
+    int nx = 0, ny = 0, nz = 0, n = 0;
+    int storage = 0, op = 0;
+    double tau = 0.0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    size_t pop_bytes = 0;
+    double omega_high[4] = {1.0, 1.0, 1.0, 1.0};
+    float* net = nullptr;
+    int width = 0, act = 0, mlp_prec = 0;
+    double* staging = nullptr;    // 27N doubles, allocated on first use
+    double* partial = nullptr;    // global-sum partials
+    double* small = nullptr;      // 64 doubles of results
+    int* flag = nullptr;
+    void* spec_work = nullptr;
+};
+
+namespace {
+
+int check_lat(nco_lattice* lat) {
+    if (!lat) return fail(NCO_E_INVALID, "null lattice");
+    return NCO_OK;
+}
+
+int set_device(nco_lattice* lat) {
+    HIP_TRY(hipSetDevice(lat->device));
+    return NCO_OK;
+}
+
+int ensure_staging(nco_lattice* lat) {
+    if (!lat->staging) HIP_TRY(hipMalloc(&lat->staging, sizeof(double) * 27 * (size_t)lat->n));
+    return NCO_OK;
+}
+
+StepArgs step_args(const nco_lattice* lat) {
+    StepArgs a;
+    a.nx = lat->nx;
+    a.ny = lat->ny;
+    a.nz = lat->nz;
+    a.n = lat->n;
+    a.op = lat->op;
+    a.width = lat->width;
+    a.act = lat->act;
+    a.omega_nu = 1.0 / lat->tau;
+    a.omega_nu_f = (float)a.omega_nu;
+    for (int k = 0; k < 4; ++k) {
+        a.omega_high[k] = lat->omega_high[k];
+        a.omega_high_f[k] = (float)lat->omega_high[k];
+    }
+    a.net = lat->net;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nco_version(void) { return 100; }
+
+const char* nco_last_error(void) { return g_err.c_str(); }
+
+int nco_lattice_bytes(int nx, int ny, int nz, int storage, size_t* bytes) {
+    if (nx < 1 || ny < 1 || nz < 1 || !bytes) return fail(NCO_E_INVALID, "bad size or null output");
+    const size_t sb = store_bytes(storage);
+    if (!sb) return fail(NCO_E_INVALID, "unknown storage %d", storage);
+    const size_t n = (size_t)nx * ny * nz;
+    // Two population buffers, the global-sum partials and the small result area.
+    *bytes = 2 * 27 * n * sb + 5 * sizeof(double) * ((n + 255) / 256) + 4096;
+    return NCO_OK;
+}
+
+int nco_lattice_create(int nx, int ny, int nz, int storage, int op, double tau, void* stream,
+                       nco_lattice** out) {
+    if (!out) return fail(NCO_E_INVALID, "null output pointer");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(NCO_E_INVALID, "lattice extent must be >= 1");
+    const size_t n = (size_t)nx * ny * nz;
+    if (n * 27 > (size_t)0x7fffffff * 8 || n > (size_t)0x7fffffff)
+        return fail(NCO_E_INVALID, "lattice too large");
+    if (!store_bytes(storage)) return fail(NCO_E_INVALID, "unknown storage %d", storage);
+    if (op < NCO_OP_BGK || op > NCO_OP_STREAM) return fail(NCO_E_INVALID, "unknown operator %d", op);
+    if (!(tau > 0.5) || !std::isfinite(tau)) return fail(NCO_E_INVALID, "tau must be > 1/2 (got %g)", tau);
+    nco_lattice* lat = new nco_lattice;
+    lat->nx = nx;
+    lat->ny = ny;
+    lat->nz = nz;
+    lat->n = (int)n;
+    lat->storage = storage;
+    lat->op = op;
+    lat->tau = tau;
+    int rc = NCO_OK;
+    auto bail = [&](int code) {
+        nco_lattice_destroy(lat);
+        return code;
+    };
+    if (hipGetDevice(&lat->device) != hipSuccess) return bail(fail(NCO_E_HIP, "hipGetDevice failed"));
+    if (stream) {
+        lat->stream = static_cast<hipStream_t>(stream);
+    } else {
+        if (hipStreamCreateWithFlags(&lat->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(NCO_E_HIP, "hipStreamCreate failed"));
+        lat->own_stream = true;
+    }
+    lat->pop_bytes = 27 * n * store_bytes(storage);
+    for (int b = 0; b < 2; ++b)
+        if (hipMalloc(&lat->f[b], lat->pop_bytes) != hipSuccess)
+            return bail(fail(NCO_E_OOM, "cannot allocate %zu bytes of populations", lat->pop_bytes));
+    if (hipMalloc(&lat->partial, 5 * sizeof(double) * (size_t)sums_partial_count(lat->n)) != hipSuccess ||
+        hipMalloc(&lat->small, 64 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&lat->flag, sizeof(int)) != hipSuccess)
+        return bail(fail(NCO_E_OOM, "cannot allocate lattice work space"));
+    // Rest state f = w.
+    std::vector<double> zero(3 * n, 0.0);
+    rc = nco_init_equilibrium(lat, nullptr, zero.data());
+    if (rc != NCO_OK) return bail(rc);
+    *out = lat;
+    return NCO_OK;
+}
+
+int nco_lattice_destroy(nco_lattice* lat) {
+    if (!lat) return NCO_OK;
+    hipSetDevice(lat->device);
+    if (lat->stream) hipStreamSynchronize(lat->stream);
+    for (int b = 0; b < 2; ++b)
+        if (lat->f[b]) hipFree(lat->f[b]);
+    if (lat->net) hipFree(lat->net);
+    if (lat->staging) hipFree(lat->staging);
+    if (lat->partial) hipFree(lat->partial);
+    if (lat->small) hipFree(lat->small);
+    if (lat->flag) hipFree(lat->flag);
+    if (lat->spec_work) hipFree(lat->spec_work);
+    if (lat->own_stream && lat->stream) hipStreamDestroy(lat->stream);
+    delete lat;
+    return NCO_OK;
+}
+
+int nco_set_op(nco_lattice* lat, int op, double tau) {
+    if (int rc = check_lat(lat)) return rc;
+    if (op < NCO_OP_BGK || op > NCO_OP_STREAM) return fail(NCO_E_INVALID, "unknown operator %d", op);
+    if (!(tau > 0.5) || !std::isfinite(tau)) return fail(NCO_E_INVALID, "tau must be > 1/2 (got %g)", tau);
+    lat->op = op;
+    lat->tau = tau;
+    return NCO_OK;
+}
+
+int nco_set_rates(nco_lattice* lat, const double omega_high[4]) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!omega_high) return fail(NCO_E_INVALID, "null rates");
+    for (int k = 0; k < 4; ++k) {
+        if (!(omega_high[k] > 0.0 && omega_high[k] < 2.0))
+            return fail(NCO_E_INVALID, "rate omega_%d = %g outside (0, 2)", k + 3, omega_high[k]);
+        lat->omega_high[k] = omega_high[k];
+    }
+    return NCO_OK;
+}
+
+int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, const float* params,
+                        size_t n_params) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!width_ok(width)) return fail(NCO_E_INVALID, "width %d not supported (8, 16, 20, 32)", width);
+    if (act != NCO_ACT_TANH && act != NCO_ACT_RELU) return fail(NCO_E_INVALID, "unknown activation %d", act);
+    if (mlp_prec != NCO_MLP_F32) return fail(NCO_E_UNSUPPORTED, "network precision %d not built", mlp_prec);
+    if (!params) return fail(NCO_E_INVALID, "null parameters");
+    if (n_params != n_params_for(width))
+        return fail(NCO_E_INVALID, "expected %zu parameters for width %d, got %zu", n_params_for(width),
+                    width, n_params);
+    const int W = width;
+    static const GroupAction G = build_group_action();
+    std::vector<float> buf(net_floats(W), 0.0f);
+    const float* W1 = params;
+    const float* b1 = W1 + 27 * W;
+    const float* W2 = b1 + W;
+    const float* b2 = W2 + W * W;
+    const float* W3 = b2 + W;
+    const float* b3 = W3 + 4 * W;
+    for (int g = 0; g < NGROUP; ++g)
+        for (int k = 0; k < 27; ++k)
+            for (int h = 0; h < W; ++h)
+                buf[g * 27 * W + G.src[g][k] * W + h] = G.sign[g][k] * W1[k * W + h];
+    std::memcpy(&buf[net_off_b1(W)], b1, sizeof(float) * W);
+    std::memcpy(&buf[net_off_w2(W)], W2, sizeof(float) * W * W);
+    std::memcpy(&buf[net_off_b2(W)], b2, sizeof(float) * W);
+    std::memcpy(&buf[net_off_w3(W)], W3, sizeof(float) * W * 4);
+    std::memcpy(&buf[net_off_b3(W)], b3, sizeof(float) * 4);
+    if (int rc = set_device(lat)) return rc;
+    if (lat->net && lat->width != W) {
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        HIP_TRY(hipFree(lat->net));
+        lat->net = nullptr;
+    }
+    if (!lat->net) HIP_TRY(hipMalloc(&lat->net, sizeof(float) * net_floats(W)));
+    HIP_TRY(hipMemcpyAsync(lat->net, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice,
+                           lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->width = W;
+    lat->act = act;
+    lat->mlp_prec = mlp_prec;
+    return NCO_OK;
+}
+
+int nco_init_equilibrium(nco_lattice* lat, const double* rho, const double* u) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!u) return fail(NCO_E_INVALID, "null velocity");
+    if (int rc = set_device(lat)) return rc;
+    if (int rc = ensure_staging(lat)) return rc;
+    const size_t n = lat->n;
+    double* d_u = lat->staging;
+    double* d_rho = rho ? lat->staging + 3 * n : nullptr;
+    HIP_TRY(hipMemcpyAsync(d_u, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, lat->stream));
+    if (rho) HIP_TRY(hipMemcpyAsync(d_rho, rho, sizeof(double) * n, hipMemcpyHostToDevice, lat->stream));
+    HIP_TRY(launch_init_equilibrium(lat->storage, lat->f[lat->cur], d_rho, d_u, lat->n, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return NCO_OK;
+}
+
+int nco_init_populations(nco_lattice* lat, const double* f) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!f) return fail(NCO_E_INVALID, "null populations");
+    if (int rc = set_device(lat)) return rc;
+    if (int rc = ensure_staging(lat)) return rc;
+    HIP_TRY(hipMemcpyAsync(lat->staging, f, sizeof(double) * 27 * (size_t)lat->n, hipMemcpyHostToDevice,
+                           lat->stream));
+    HIP_TRY(launch_from_double(lat->storage, lat->f[lat->cur], lat->staging, lat->n, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return NCO_OK;
+}
+
+int nco_step(nco_lattice* lat, int nsteps) {
+    if (int rc = check_lat(lat)) return rc;
+    if (nsteps < 0) return fail(NCO_E_INVALID, "nsteps must be >= 0");
+    if (lat->op == NCO_OP_NCO && !lat->net) return fail(NCO_E_STATE, "NCO operator needs network weights");
+    if (int rc = set_device(lat)) return rc;
+    const StepArgs a = step_args(lat);
+    for (int s = 0; s < nsteps; ++s) {
+        HIP_TRY(launch_step(lat->storage, lat->f[lat->cur], lat->f[1 - lat->cur], a, lat->stream));
+        lat->cur = 1 - lat->cur;
+    }
+    return NCO_OK;
+}
+
+int nco_sync(nco_lattice* lat) {
+    if (int rc = check_lat(lat)) return rc;
+    if (int rc = set_device(lat)) return rc;
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return NCO_OK;
+}
+
+int nco_read_populations(nco_lattice* lat, double* f) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!f) return fail(NCO_E_INVALID, "null output");
+    if (int rc = set_device(lat)) return rc;
+    if (int rc = ensure_staging(lat)) return rc;
+    HIP_TRY(launch_to_double(lat->storage, lat->f[lat->cur], lat->staging, lat->n, lat->stream));
+    HIP_TRY(hipMemcpyAsync(f, lat->staging, sizeof(double) * 27 * (size_t)lat->n, hipMemcpyDeviceToHost,
+                           lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return NCO_OK;
+}
+
+int nco_read_macroscopic(nco_lattice* lat, double* rho, double* u) {
+    if (int rc = check_lat(lat)) return rc;
+    if (int rc = set_device(lat)) return rc;
+    if (int rc = ensure_staging(lat)) return rc;
+    const size_t n = lat->n;
+    HIP_TRY(launch_macroscopic(lat->storage, lat->f[lat->cur], lat->staging, lat->staging + n, lat->n,
+                               lat->stream));
+    if (rho) HIP_TRY(hipMemcpyAsync(rho, lat->staging, sizeof(double) * n, hipMemcpyDeviceToHost, lat->stream));
+    if (u) HIP_TRY(hipMemcpyAsync(u, lat->staging + n, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return NCO_OK;
+}
+
+int nco_read_rates(nco_lattice* lat, double* omega) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!omega) return fail(NCO_E_INVALID, "null output");
+    if (!lat->net) return fail(NCO_E_STATE, "no network weights set");
+    if (int rc = set_device(lat)) return rc;
+    if (int rc = ensure_staging(lat)) return rc;
+    const StepArgs a = step_args(lat);
+    HIP_TRY(launch_rates(lat->storage, lat->f[lat->cur], lat->staging, a, lat->stream));
+    HIP_TRY(hipMemcpyAsync(omega, lat->staging, sizeof(double) * 4 * (size_t)lat->n, hipMemcpyDeviceToHost,
+                           lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return NCO_OK;
+}
+
+int nco_global_sums(nco_lattice* lat, double out[5]) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!out) return fail(NCO_E_INVALID, "null output");
+    if (int rc = set_device(lat)) return rc;
+    HIP_TRY(launch_global_sums(lat->storage, lat->f[lat->cur], lat->partial, lat->small, lat->n, lat->stream));
+    HIP_TRY(hipMemcpyAsync(out, lat->small, 5 * sizeof(double), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(out[k])) return fail(NCO_E_UNSTABLE, "non-finite global sum %d", k);
+    return NCO_OK;
+}
+
+int nco_energy_spectrum(nco_lattice* lat, double* E, int nbins) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!E) return fail(NCO_E_INVALID, "null output");
+    if (lat->nx != lat->ny || lat->nx != lat->nz) return fail(NCO_E_INVALID, "spectrum needs a cubic lattice");
+    const int n = lat->nx;
+    if (nbins != spectrum_bins(n)) return fail(NCO_E_INVALID, "nbins must be %d for n = %d", spectrum_bins(n), n);
+    if (int rc = set_device(lat)) return rc;
+    if (!lat->spec_work) HIP_TRY(hipMalloc(&lat->spec_work, spectrum_workspace_bytes(n) + 256 * sizeof(double) * 8));
+    double* E_dev = reinterpret_cast<double*>(static_cast<char*>(lat->spec_work) + spectrum_workspace_bytes(n));
+    if (nbins > 256 * 8) return fail(NCO_E_UNSUPPORTED, "too many shells");
+    HIP_TRY(launch_energy_spectrum(lat->storage, lat->f[lat->cur], n, lat->spec_work, E_dev, nbins, lat->stream));
+    HIP_TRY(hipMemcpyAsync(E, E_dev, sizeof(double) * nbins, hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return NCO_OK;
+}
+
+int nco_device_populations(nco_lattice* lat, void** dev_ptr, size_t* bytes) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!dev_ptr || !bytes) return fail(NCO_E_INVALID, "null output");
+    *dev_ptr = lat->f[lat->cur];
+    *bytes = lat->pop_bytes;
+    return NCO_OK;
+}
+
+}  // extern "C"

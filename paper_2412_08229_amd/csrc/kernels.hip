@@ -1,0 +1,409 @@
+// Lattice kernels: fused pull-stream + collide, initialisation, readout and
+// float64 reductions.  One thread per node; populations in structure-of-
+// arrays layout [27][z][y][x] so that each of the 27 loads and stores of a
+// wavefront is a contiguous row segment of one velocity plane.
+#include "kernels.h"
+
+namespace nco {
+
+namespace {
+
+struct NodeIdx {
+    int x, y, z;
+};
+
+__device__ __forceinline__ NodeIdx node_of(int idx, int nx, int ny) {
+    const int nxy = nx * ny;
+    NodeIdx r;
+    r.z = idx / nxy;
+    const int rem = idx - r.z * nxy;
+    r.y = rem / nx;
+    r.x = rem - r.y * nx;
+    return r;
+}
+
+// Pull the 27 populations of node (x, y, z): f_i(x) <- f_i(x - c_i), periodic.
+template <int S>
+__device__ __forceinline__ void pull(const typename Codec<S>::store_t* __restrict__ fin,
+                                     const StepArgs& a, NodeIdx p,
+                                     typename Codec<S>::real (&f)[Q]) {
+    // Source coordinate for c = -1, 0, +1 is x + 1, x, x - 1.
+    const int xs[3] = {p.x == a.nx - 1 ? 0 : p.x + 1, p.x, p.x == 0 ? a.nx - 1 : p.x - 1};
+    const int ys[3] = {(p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx, p.y * a.nx,
+                       (p.y == 0 ? a.ny - 1 : p.y - 1) * a.nx};
+    const int nxy = a.nx * a.ny;
+    const int zs[3] = {(p.z == a.nz - 1 ? 0 : p.z + 1) * nxy, p.z * nxy,
+                       (p.z == 0 ? a.nz - 1 : p.z - 1) * nxy};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int src = zs[cz_of(i) + 1] + ys[cy_of(i) + 1] + xs[cx_of(i) + 1];
+        f[i] = Codec<S>::load(fin + (size_t)i * a.n + src, i);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void load_local(const typename Codec<S>::store_t* __restrict__ fin,
+                                           int n, int idx, typename Codec<S>::real (&f)[Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = Codec<S>::load(fin + (size_t)i * n + idx, i);
+}
+
+template <int S>
+__device__ __forceinline__ void store_local(typename Codec<S>::store_t* __restrict__ fout, int n,
+                                            int idx, const typename Codec<S>::real (&f)[Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Codec<S>::store(fout + (size_t)i * n + idx, i, f[i]);
+}
+
+template <typename R> __device__ __forceinline__ R pick(float f, double d);
+template <> __device__ __forceinline__ float pick<float>(float f, double) { return f; }
+template <> __device__ __forceinline__ double pick<double>(float, double d) { return d; }
+
+// Collision of one node in place; OP and W/ACT select the operator.
+template <typename R, int OP, int W, int ACT>
+__device__ __forceinline__ void collide_node(R (&f)[Q], const StepArgs& a) {
+    const R omega_nu = pick<R>(a.omega_nu_f, a.omega_nu);
+    if constexpr (OP == OP_BGK) {
+        bgk<R, false>(f, omega_nu, R(0), R(0), R(0));
+    } else {
+        R m[Q];
+        to_moments(f, m);
+        R omega[4];
+        if constexpr (OP == OP_NCO) {
+            net_rates<R, W, ACT>(m, a.net, omega);
+        } else {
+#pragma unroll
+            for (int n = 0; n < 4; ++n) omega[n] = pick<R>(a.omega_high_f[n], a.omega_high[n]);
+        }
+        relax_moments<R, false>(m, omega_nu, omega, R(0), R(0), R(0));
+        from_moments(m, f);
+    }
+}
+
+template <int S, int OP, int W, int ACT>
+__global__ __launch_bounds__(256) void k_stream_collide(const typename Codec<S>::store_t* __restrict__ fin,
+                                                        typename Codec<S>::store_t* __restrict__ fout,
+                                                        StepArgs a) {
+    using R = typename Codec<S>::real;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n) return;
+    R f[Q];
+    pull<S>(fin, a, node_of(idx, a.nx, a.ny), f);
+    collide_node<R, OP, W, ACT>(f, a);
+    store_local<S>(fout, a.n, idx, f);
+}
+
+// Streaming alone: the raw stored values are moved, so the result is an exact
+// permutation in every storage format.
+template <int S>
+__global__ __launch_bounds__(256) void k_stream_only(const typename Codec<S>::store_t* __restrict__ fin,
+                                                     typename Codec<S>::store_t* __restrict__ fout,
+                                                     StepArgs a) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n) return;
+    const NodeIdx p = node_of(idx, a.nx, a.ny);
+    const int xs[3] = {p.x == a.nx - 1 ? 0 : p.x + 1, p.x, p.x == 0 ? a.nx - 1 : p.x - 1};
+    const int ys[3] = {(p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx, p.y * a.nx,
+                       (p.y == 0 ? a.ny - 1 : p.y - 1) * a.nx};
+    const int nxy = a.nx * a.ny;
+    const int zs[3] = {(p.z == a.nz - 1 ? 0 : p.z + 1) * nxy, p.z * nxy,
+                       (p.z == 0 ? a.nz - 1 : p.z - 1) * nxy};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int src = zs[cz_of(i) + 1] + ys[cy_of(i) + 1] + xs[cx_of(i) + 1];
+        fout[(size_t)i * a.n + idx] = fin[(size_t)i * a.n + src];
+    }
+}
+
+template <int S, int W, int ACT>
+__global__ __launch_bounds__(256) void k_rates(const typename Codec<S>::store_t* __restrict__ fin,
+                                               double* __restrict__ omega_out, StepArgs a) {
+    using R = typename Codec<S>::real;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n) return;
+    R f[Q], m[Q], omega[4];
+    load_local<S>(fin, a.n, idx, f);
+    to_moments(f, m);
+    net_rates<R, W, ACT>(m, a.net, omega);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) omega_out[(size_t)k * a.n + idx] = (double)omega[k];
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_init_equilibrium(typename Codec<S>::store_t* __restrict__ f,
+                                                          const double* __restrict__ rho,
+                                                          const double* __restrict__ u, int n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const double r = rho ? rho[idx] : 1.0;
+    const double ux = u[idx], uy = u[(size_t)n + idx], uz = u[2 * (size_t)n + idx];
+    const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cu = cx_of(i) * ux + cy_of(i) * uy + cz_of(i) * uz;
+        // f^eq - w computed as w (rho (1 + ...) - 1) keeps the deviation exact
+        // for the 16-bit storage forms.
+        const double dev = weight_of(i) * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        typename Codec<S>::store_t v;
+        if constexpr (S == ST_F16) {
+            v = __float2half_rn((float)(dev * dev_scale(i)));
+        } else if constexpr (S == ST_BF16) {
+            v = __float2bfloat16((float)(dev * dev_scale(i)));
+        } else {
+            v = Codec<S>::from_double(weight_of(i) + dev, i);
+        }
+        f[(size_t)i * n + idx] = v;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_from_double(typename Codec<S>::store_t* __restrict__ f,
+                                                     const double* __restrict__ src, int n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[(size_t)i * n + idx] = Codec<S>::from_double(src[(size_t)i * n + idx], i);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_to_double(const typename Codec<S>::store_t* __restrict__ f,
+                                                   double* __restrict__ dst, int n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[(size_t)i * n + idx] = Codec<S>::to_double(f[(size_t)i * n + idx], i);
+}
+
+// rho and u = j / rho in float64 from the stored populations.
+template <int S>
+__device__ __forceinline__ void macro_double(const typename Codec<S>::store_t* __restrict__ f, int n,
+                                             int idx, double& rho, double& ux, double& uy, double& uz) {
+    double r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = Codec<S>::to_double(f[(size_t)i * n + idx], i);
+        r += v;
+        jx += cx_of(i) * v;
+        jy += cy_of(i) * v;
+        jz += cz_of(i) * v;
+    }
+    rho = r;
+    ux = jx / r;
+    uy = jy / r;
+    uz = jz / r;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_macroscopic(const typename Codec<S>::store_t* __restrict__ f,
+                                                     double* __restrict__ rho_out,
+                                                     double* __restrict__ u_out, int n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double r, ux, uy, uz;
+    macro_double<S>(f, n, idx, r, ux, uy, uz);
+    rho_out[idx] = r;
+    u_out[idx] = ux;
+    u_out[(size_t)n + idx] = uy;
+    u_out[2 * (size_t)n + idx] = uz;
+}
+
+// Block sum of NSUM doubles: wavefront shuffles, then one value per wave in LDS.
+template <int NSUM>
+__device__ __forceinline__ void block_sum(double (&v)[NSUM], double* __restrict__ out) {
+    __shared__ double part[NSUM][256 / 64];
+#pragma unroll
+    for (int s = 0; s < NSUM; ++s)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[s] += __shfl_down(v[s], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int s = 0; s < NSUM; ++s) part[s][wave] = v[s];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < NSUM; ++s) {
+            double t = 0;
+            for (int w = 0; w < (int)(blockDim.x / 64); ++w) t += part[s][w];
+            out[(size_t)s * gridDim.x + blockIdx.x] = t;
+        }
+    }
+}
+
+// Stage 1 of the global sums: one partial per block for mass, j, 1/2|u|^2.
+template <int S>
+__global__ __launch_bounds__(256) void k_sums_partial(const typename Codec<S>::store_t* __restrict__ f,
+                                                      double* __restrict__ partial, int n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[5] = {0, 0, 0, 0, 0};
+    if (idx < n) {
+        double r, ux, uy, uz;
+        macro_double<S>(f, n, idx, r, ux, uy, uz);
+        v[0] = r;
+        v[1] = r * ux;
+        v[2] = r * uy;
+        v[3] = r * uz;
+        v[4] = 0.5 * (ux * ux + uy * uy + uz * uz);
+    }
+    block_sum<5>(v, partial);
+}
+
+// Stage 2: a single block adds the partials in a fixed order.
+__global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ partial, int nblocks,
+                                                    double* __restrict__ out) {
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int s = 0; s < 5; ++s) v[s] += partial[(size_t)s * nblocks + b];
+    __shared__ double part[5][4];
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[s] += __shfl_down(v[s], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int s = 0; s < 5; ++s) part[s][wave] = v[s];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int s = 0; s < 5; ++s) out[s] = part[s][0] + part[s][1] + part[s][2] + part[s][3];
+}
+
+// Non-finite detector: any NaN/Inf population sets *flag (plain store of 1,
+// idempotent, no atomics).
+template <int S>
+__global__ __launch_bounds__(256) void k_check_finite(const typename Codec<S>::store_t* __restrict__ f,
+                                                      int n, int* __restrict__ flag) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = Codec<S>::to_double(f[(size_t)i * n + idx], i);
+        bad |= !(v == v) || v > 1e300 || v < -1e300;
+    }
+    if (bad) *flag = 1;
+}
+
+inline int nblocks(int n) { return (n + 255) / 256; }
+
+template <int S, int OP>
+hipError_t launch_step_op(const void* fin, void* fout, const StepArgs& a, hipStream_t st) {
+    using T = typename Codec<S>::store_t;
+    const T* in = static_cast<const T*>(fin);
+    T* out = static_cast<T*>(fout);
+    if constexpr (OP == OP_NONE) {
+        hipLaunchKernelGGL((k_stream_only<S>), dim3(nblocks(a.n)), dim3(256), 0, st, in, out, a);
+    } else if constexpr (OP != OP_NCO) {
+        hipLaunchKernelGGL((k_stream_collide<S, OP, 8, ACT_TANH>), dim3(nblocks(a.n)), dim3(256), 0, st, in, out, a);
+    } else {
+#define NCO_CASE(WW, AA)                                                                               \
+    if (a.width == WW && a.act == AA) {                                                                \
+        hipLaunchKernelGGL((k_stream_collide<S, OP, WW, AA>), dim3(nblocks(a.n)), dim3(256), 0, st, in, \
+                           out, a);                                                                    \
+        return hipGetLastError();                                                                      \
+    }
+        NCO_CASE(8, ACT_TANH) NCO_CASE(16, ACT_TANH) NCO_CASE(20, ACT_TANH) NCO_CASE(32, ACT_TANH)
+        NCO_CASE(8, ACT_RELU) NCO_CASE(16, ACT_RELU) NCO_CASE(20, ACT_RELU) NCO_CASE(32, ACT_RELU)
+#undef NCO_CASE
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_rates_s(const void* fin, double* out, const StepArgs& a, hipStream_t st) {
+    using T = typename Codec<S>::store_t;
+    const T* in = static_cast<const T*>(fin);
+#define RATE_CASE(WW, AA)                                                                            \
+    if (a.width == WW && a.act == AA) {                                                              \
+        hipLaunchKernelGGL((k_rates<S, WW, AA>), dim3(nblocks(a.n)), dim3(256), 0, st, in, out, a); \
+        return hipGetLastError();                                                                    \
+    }
+    RATE_CASE(8, ACT_TANH) RATE_CASE(16, ACT_TANH) RATE_CASE(20, ACT_TANH) RATE_CASE(32, ACT_TANH)
+    RATE_CASE(8, ACT_RELU) RATE_CASE(16, ACT_RELU) RATE_CASE(20, ACT_RELU) RATE_CASE(32, ACT_RELU)
+#undef RATE_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+#define DISPATCH_STORAGE(S, CALL)                \
+    switch (S) {                                 \
+        case ST_F32: { constexpr int SS = ST_F32; CALL; } \
+        case ST_F16: { constexpr int SS = ST_F16; CALL; } \
+        case ST_BF16: { constexpr int SS = ST_BF16; CALL; } \
+        case ST_F64: { constexpr int SS = ST_F64; CALL; } \
+        default: return hipErrorInvalidValue;    \
+    }
+
+hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs& a, hipStream_t st) {
+    switch (a.op) {
+        case OP_BGK: DISPATCH_STORAGE(storage, return (launch_step_op<SS, OP_BGK>(fin, fout, a, st)))
+        case OP_MRT: DISPATCH_STORAGE(storage, return (launch_step_op<SS, OP_MRT>(fin, fout, a, st)))
+        case OP_NCO: DISPATCH_STORAGE(storage, return (launch_step_op<SS, OP_NCO>(fin, fout, a, st)))
+        case OP_NONE: DISPATCH_STORAGE(storage, return (launch_step_op<SS, OP_NONE>(fin, fout, a, st)))
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_rates(int storage, const void* fin, double* omega, const StepArgs& a, hipStream_t st) {
+    DISPATCH_STORAGE(storage, return launch_rates_s<SS>(fin, omega, a, st))
+}
+
+hipError_t launch_init_equilibrium(int storage, void* f, const double* rho, const double* u, int n,
+                                   hipStream_t st) {
+    DISPATCH_STORAGE(storage, {
+        hipLaunchKernelGGL(k_init_equilibrium<SS>, dim3(nblocks(n)), dim3(256), 0, st,
+                           static_cast<typename Codec<SS>::store_t*>(f), rho, u, n);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_from_double(int storage, void* f, const double* src, int n, hipStream_t st) {
+    DISPATCH_STORAGE(storage, {
+        hipLaunchKernelGGL(k_from_double<SS>, dim3(nblocks(n)), dim3(256), 0, st,
+                           static_cast<typename Codec<SS>::store_t*>(f), src, n);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_to_double(int storage, const void* f, double* dst, int n, hipStream_t st) {
+    DISPATCH_STORAGE(storage, {
+        hipLaunchKernelGGL(k_to_double<SS>, dim3(nblocks(n)), dim3(256), 0, st,
+                           static_cast<const typename Codec<SS>::store_t*>(f), dst, n);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_macroscopic(int storage, const void* f, double* rho, double* u, int n, hipStream_t st) {
+    DISPATCH_STORAGE(storage, {
+        hipLaunchKernelGGL(k_macroscopic<SS>, dim3(nblocks(n)), dim3(256), 0, st,
+                           static_cast<const typename Codec<SS>::store_t*>(f), rho, u, n);
+        return hipGetLastError();
+    })
+}
+
+int sums_partial_count(int n) { return nblocks(n); }
+
+hipError_t launch_global_sums(int storage, const void* f, double* partial, double* out, int n,
+                              hipStream_t st) {
+    const int nb = nblocks(n);
+    DISPATCH_STORAGE(storage, {
+        hipLaunchKernelGGL(k_sums_partial<SS>, dim3(nb), dim3(256), 0, st,
+                           static_cast<const typename Codec<SS>::store_t*>(f), partial, n);
+        hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, st, partial, nb, out);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_check_finite(int storage, const void* f, int n, int* flag, hipStream_t st) {
+    DISPATCH_STORAGE(storage, {
+        hipLaunchKernelGGL(k_check_finite<SS>, dim3(nblocks(n)), dim3(256), 0, st,
+                           static_cast<const typename Codec<SS>::store_t*>(f), n, flag);
+        return hipGetLastError();
+    })
+}
+
+}  // namespace nco

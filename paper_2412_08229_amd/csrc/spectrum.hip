@@ -1,0 +1,192 @@
+// Energy spectrum E(k) of the velocity field, in float64.
+//
+// The loss of Sec. "Learning Task" compares shell-summed kinetic energy
+// spectra.  Here u_hat = DFT(u) / n^3 over a cubic periodic lattice and
+// E(k) = 1/2 sum |u_hat|^2 over the integer wavevectors in [-n/2, n/2)^3 with
+// round(|k|) = k.  Lattice sizes such as 96 and 192 are not powers of two,
+// so the transform is a sum-factorised direct DFT: one O(n) dot product per
+// output element and axis (x, then y, then z), with a float64 twiddle table.
+// The shell sums are deterministic: for each (k_z, k_y) row the k_x values
+// are visited in order of |k_x|, so the shell index never decreases and each
+// (shell, row) partial is written exactly once; a second kernel adds the
+// rows of each shell in a fixed order.
+#include "kernels.h"
+
+namespace nco {
+
+namespace {
+
+template <int S>
+__global__ __launch_bounds__(256) void k_velocity(const typename Codec<S>::store_t* __restrict__ f,
+                                                  double* __restrict__ u, int n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = Codec<S>::to_double(f[(size_t)i * n + idx], i);
+        r += v;
+        jx += cx_of(i) * v;
+        jy += cy_of(i) * v;
+        jz += cz_of(i) * v;
+    }
+    u[idx] = jx / r;
+    u[(size_t)n + idx] = jy / r;
+    u[2 * (size_t)n + idx] = jz / r;
+}
+
+// One axis of the forward DFT over a [3][n][n][n] field; AXIS 0 = x (stride
+// 1), 1 = y (stride n), 2 = z (stride n^2).  REAL_IN reads a real field.
+template <int AXIS, bool REAL_IN>
+__global__ __launch_bounds__(256) void k_dft_axis(const void* __restrict__ in_, double2* __restrict__ out,
+                                                  const double2* __restrict__ tw, int n) {
+    const size_t n3 = (size_t)n * n * n;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 3 * n3) return;
+    const size_t stride = AXIS == 0 ? 1 : AXIS == 1 ? (size_t)n : (size_t)n * n;
+    const int k = (int)((gid / stride) % n);
+    const size_t base = gid - (size_t)k * stride;
+    double re = 0.0, im = 0.0;
+    int m = 0;
+    for (int j = 0; j < n; ++j) {
+        const double2 w = tw[m];
+        if constexpr (REAL_IN) {
+            const double v = static_cast<const double*>(in_)[base + (size_t)j * stride];
+            re = fma(v, w.x, re);
+            im = fma(v, w.y, im);
+        } else {
+            const double2 v = static_cast<const double2*>(in_)[base + (size_t)j * stride];
+            re = fma(v.x, w.x, fma(-v.y, w.y, re));
+            im = fma(v.x, w.y, fma(v.y, w.x, im));
+        }
+        m += k;
+        if (m >= n) m -= n;
+    }
+    out[gid] = make_double2(re, im);
+}
+
+__device__ __forceinline__ int wavenumber(int idx, int n) { return idx < n - n / 2 ? idx : idx - n; }
+
+// Partial shell sums of one (kz, ky) row; partial is [nbins][n*n], zeroed.
+__global__ __launch_bounds__(256) void k_shell_rows(const double2* __restrict__ uh, int n,
+                                                    double* __restrict__ partial, int nbins) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nn = n * n;
+    if (row >= nn) return;
+    const int kz = wavenumber(row / n, n), ky = wavenumber(row % n, n);
+    const size_t n3 = (size_t)n * nn;
+    const double scale = 0.5 / ((double)n3 * (double)n3);
+    const int c2 = kz * kz + ky * ky;
+    int cur = -1;
+    double acc = 0.0;
+    for (int a = 0; a <= n / 2; ++a) {           // |kx| = a, both signs
+        const int b = (int)floor(sqrt((double)(c2 + a * a)) + 0.5);
+        if (b != cur) {
+            if (cur >= 0 && cur < nbins) partial[(size_t)cur * nn + row] = acc;
+            cur = b;
+            acc = 0.0;
+        }
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            if (sgn == 1 && a == 0) continue;
+            const int kx = sgn ? -a : a;
+            if (kx >= n - n / 2 || kx < -(n / 2)) continue;
+            const int ix = kx >= 0 ? kx : kx + n;
+            const size_t e = (size_t)row * n + ix;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double2 v = uh[(size_t)c * n3 + e];
+                acc += (v.x * v.x + v.y * v.y) * scale;
+            }
+        }
+    }
+    if (cur >= 0 && cur < nbins) partial[(size_t)cur * nn + row] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0;
+}
+
+// One block per shell: fixed-order strided sums, then a fixed tree.
+__global__ __launch_bounds__(256) void k_shell_final(const double* __restrict__ partial, int rows,
+                                                     double* __restrict__ E) {
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) s += partial[(size_t)b * rows + r];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) E[b] = red[0];
+}
+
+struct SpecLayout {
+    size_t u, a, b, part, tw, total;
+};
+
+SpecLayout spec_layout(int n, int nbins) {
+    const size_t n3 = (size_t)n * n * n;
+    SpecLayout L;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    L.u = 0;
+    L.a = up(L.u + 3 * n3 * sizeof(double));
+    L.b = up(L.a + 3 * n3 * sizeof(double2));
+    L.part = up(L.b + 3 * n3 * sizeof(double2));
+    L.tw = up(L.part + (size_t)nbins * n * n * sizeof(double));
+    L.total = up(L.tw + (size_t)n * sizeof(double2));
+    return L;
+}
+
+}  // namespace
+
+int spectrum_bins(int n) { return (int)floor(sqrt(3.0) * (n / 2) + 0.5) + 1; }
+
+size_t spectrum_workspace_bytes(int n) { return spec_layout(n, spectrum_bins(n)).total; }
+
+hipError_t launch_energy_spectrum(int storage, const void* f, int n, void* work, double* E_dev,
+                                  int nbins, hipStream_t st) {
+    const SpecLayout L = spec_layout(n, nbins);
+    char* w = static_cast<char*>(work);
+    double* u = reinterpret_cast<double*>(w + L.u);
+    double2* A = reinterpret_cast<double2*>(w + L.a);
+    double2* B = reinterpret_cast<double2*>(w + L.b);
+    double* part = reinterpret_cast<double*>(w + L.part);
+    double2* tw = reinterpret_cast<double2*>(w + L.tw);
+    const int n3 = n * n * n;
+    // Twiddles exp(-2 pi i m / n), computed on the host in float64.
+    {
+        double2* h = static_cast<double2*>(malloc(sizeof(double2) * n));
+        if (!h) return hipErrorOutOfMemory;
+        for (int m = 0; m < n; ++m) {
+            const double ang = 2.0 * M_PI * (double)m / (double)n;
+            h[m] = make_double2(cos(ang), -sin(ang));
+        }
+        hipError_t e = hipMemcpyAsync(tw, h, sizeof(double2) * n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        free(h);
+        if (e != hipSuccess) return e;
+    }
+    const int nb = (n3 + 255) / 256;
+    switch (storage) {
+        case ST_F32: hipLaunchKernelGGL(k_velocity<ST_F32>, dim3(nb), dim3(256), 0, st, static_cast<const float*>(f), u, n3); break;
+        case ST_F16: hipLaunchKernelGGL(k_velocity<ST_F16>, dim3(nb), dim3(256), 0, st, static_cast<const __half*>(f), u, n3); break;
+        case ST_BF16: hipLaunchKernelGGL(k_velocity<ST_BF16>, dim3(nb), dim3(256), 0, st, static_cast<const __hip_bfloat16*>(f), u, n3); break;
+        case ST_F64: hipLaunchKernelGGL(k_velocity<ST_F64>, dim3(nb), dim3(256), 0, st, static_cast<const double*>(f), u, n3); break;
+        default: return hipErrorInvalidValue;
+    }
+    const size_t tot = 3 * (size_t)n3;
+    const unsigned nbt = (unsigned)((tot + 255) / 256);
+    hipLaunchKernelGGL((k_dft_axis<0, true>), dim3(nbt), dim3(256), 0, st, (const void*)u, A, tw, n);
+    hipLaunchKernelGGL((k_dft_axis<1, false>), dim3(nbt), dim3(256), 0, st, (const void*)A, B, tw, n);
+    hipLaunchKernelGGL((k_dft_axis<2, false>), dim3(nbt), dim3(256), 0, st, (const void*)B, A, tw, n);
+    const size_t pc = (size_t)nbins * n * n;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((pc + 255) / 256)), dim3(256), 0, st, part, pc);
+    hipLaunchKernelGGL(k_shell_rows, dim3((n * n + 255) / 256), dim3(256), 0, st, A, n, part, nbins);
+    hipLaunchKernelGGL(k_shell_final, dim3(nbins), dim3(256), 0, st, part, n * n, E_dev);
+    return hipGetLastError();
+}
+
+}  // namespace nco

@@ -1,0 +1,99 @@
+"""A thin object wrapper over the C ABI: one ``Lattice`` owns one nco_lattice.
+
+Shapes follow the C ABI: populations (27, nz, ny, nx), velocity (3, nz, ny,
+nx), node order x fastest.  Nothing here computes; it only reshapes arrays
+and forwards calls to libnco.so.
+"""
+import math
+
+import numpy as np
+
+from . import _lib as L
+
+
+def n_bins(n):
+    """Number of spectrum shells for a cubic lattice of edge n."""
+    return int(math.floor(math.sqrt(3.0) * (n // 2) + 0.5)) + 1
+
+
+class Lattice:
+    def __init__(self, shape, storage="f32", op="bgk", tau=0.6, stream=None):
+        """shape = (nz, ny, nx).  stream: an integer hipStream_t (for example
+        ``torch.cuda.current_stream().cuda_stream``) or None."""
+        self.nz, self.ny, self.nx = (int(s) for s in shape)
+        self.n = self.nx * self.ny * self.nz
+        self.storage = storage
+        self.op = op
+        self.tau = float(tau)
+        self._h = L.nco_lattice_create(self.nx, self.ny, self.nz, L.STORAGE[storage], L.OPS[op],
+                                       self.tau, stream)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.nco_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @staticmethod
+    def bytes(shape, storage="f32"):
+        nz, ny, nx = shape
+        return L.nco_lattice_bytes(nx, ny, nz, L.STORAGE[storage])
+
+    def set_op(self, op, tau=None):
+        self.op = op
+        if tau is not None:
+            self.tau = float(tau)
+        L.nco_set_op(self._h, L.OPS[op], self.tau)
+
+    def set_rates(self, omega_high):
+        L.nco_set_rates(self._h, omega_high)
+
+    def set_net_weights(self, params, width, act="tanh", mlp_prec="f32"):
+        L.nco_set_net_weights(self._h, width, L.ACTS[act], L.MLP_PREC[mlp_prec], params)
+
+    def init_equilibrium(self, rho, u):
+        L.nco_init_equilibrium(self._h, self.n, None if rho is None else np.asarray(rho).ravel(),
+                               np.asarray(u).ravel())
+
+    def init_populations(self, f):
+        L.nco_init_populations(self._h, self.n, np.asarray(f).ravel())
+
+    def step(self, nsteps=1):
+        L.nco_step(self._h, int(nsteps))
+
+    def sync(self):
+        L.nco_sync(self._h)
+
+    def populations(self):
+        return L.nco_read_populations(self._h, self.n).reshape((27,) + self.shape)
+
+    def macroscopic(self):
+        rho, u = L.nco_read_macroscopic(self._h, self.n)
+        return rho.reshape(self.shape), u.reshape((3,) + self.shape)
+
+    def rates(self):
+        return L.nco_read_rates(self._h, self.n).reshape((4,) + self.shape)
+
+    def global_sums(self):
+        return L.nco_global_sums(self._h)
+
+    def energy_spectrum(self):
+        return L.nco_energy_spectrum(self._h, n_bins(self.nx))
+
+    def device_populations(self):
+        return L.nco_device_populations(self._h)

@@ -1,0 +1,247 @@
+"""GPU parity of the HIP path against the CPU float64 oracle, through the C ABI.
+
+Tolerances: streaming is bit-exact (a permutation of stored values); float64
+storage agrees with the oracle to rounding (1e-13); the float32 path stays
+within 1e-5 max-abs population error after 100 steps at 16^3.
+"""
+import numpy as np
+import pytest
+
+from oracle import collision, observables, step
+from paper_2412_08229_amd import Lattice, inputs
+from paper_2412_08229_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+WIDTH = 32
+OMEGA = np.array([1.15, 1.35, 1.55, 1.75])
+
+
+def _params(width=WIDTH, seed=0):
+    return inputs.mlp_params(width, seed)
+
+
+def _oracle_op(kind, tau, width=WIDTH, seed=0, act="tanh"):
+    layers = collision.unpack_params(_params(width, seed), width) if kind == "nco" else None
+    return step.Operator(kind, tau, omega_high=OMEGA, layers=layers, act=act)
+
+
+def _lattice(shape, storage, kind, tau, width=WIDTH, seed=0, act="tanh"):
+    lat = Lattice(shape, storage, kind, tau)
+    if kind == "nco":
+        lat.set_net_weights(_params(width, seed), width, act)
+    if kind == "mrt":
+        lat.set_rates(OMEGA)
+    return lat
+
+
+# ------------------------------------------------------------- streaming ----
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
+@pytest.mark.parametrize("shape", [(5, 7, 9), (1, 1, 1), (3, 1, 2), (16, 16, 16), (2, 3, 130)])
+def test_streaming_is_bit_exact(storage, shape):
+    f0 = inputs.random_populations(shape, seed=1)
+    with Lattice(shape, storage, "stream", 0.6) as lat:
+        lat.init_populations(f0)
+        q = lat.populations()          # the stored values, decoded exactly
+        lat.step(1)
+        g = lat.populations()
+        lat.step(2)
+        g3 = lat.populations()
+    assert np.array_equal(g, step.stream(q))
+    assert np.array_equal(g3, step.stream(step.stream(step.stream(q))))
+
+
+# ------------------------------------------------- float32 path, C1 config --
+
+def _tgv16():
+    n, u0 = 16, 0.05
+    rho, u = inputs.tgv3d(n, u0)
+    return n, rho, u
+
+
+@pytest.mark.parametrize("kind", ["bgk", "mrt", "nco"])
+def test_f32_tgv16_100_steps_within_1e5(kind):
+    n, rho, u = _tgv16()
+    tau = inputs.viscosity(n, 0.05, 100.0)[1] if kind == "nco" else 0.6
+    with _lattice((n, n, n), "f32", kind, tau) as lat:
+        lat.init_equilibrium(rho, u)
+        lat.step(100)
+        got = lat.populations()
+    want = step.run(collision.equilibrium(rho, u), _oracle_op(kind, tau), 100)
+    err = np.abs(got - want).max()
+    print("%s f32 16^3 x100: max err %.3e" % (kind, err))
+    assert err < 1e-5
+
+
+# ---------------------------------------------------- float64 storage -------
+
+@pytest.mark.parametrize("kind", ["bgk", "mrt", "nco"])
+@pytest.mark.parametrize("shape", [(6, 5, 7), (1, 4, 3)])
+def test_f64_matches_oracle_to_rounding(kind, shape):
+    f0 = inputs.random_populations(shape, seed=2, lo=0.8, hi=1.2)
+    tau = 0.57
+    with _lattice(shape, "f64", kind, tau, width=20, seed=3) as lat:
+        lat.init_populations(f0)
+        lat.step(3)
+        got = lat.populations()
+    want = step.run(f0, _oracle_op(kind, tau, width=20, seed=3), 3)
+    assert np.abs(got - want).max() < 1e-13
+
+
+@pytest.mark.parametrize("width,act", [(8, "tanh"), (16, "relu"), (20, "relu"), (32, "tanh")])
+def test_network_rates_match_oracle(width, act):
+    shape = (3, 4, 5)
+    rho, u = inputs.random_velocity(shape, seed=4, amp=0.1)
+    f0 = collision.equilibrium(rho, u) + 0.01 * (inputs.random_populations(shape, seed=5) - 1.0 / 27)
+    layers = collision.unpack_params(_params(width, 6), width)
+    want = collision.nco_rates(f0, layers, act)
+    for storage, tol in (("f64", 1e-13), ("f32", 2e-6)):
+        with _lattice(shape, storage, "nco", 0.6, width=width, seed=6, act=act) as lat:
+            lat.init_populations(f0)
+            got = lat.rates()
+            f_stored = lat.populations()
+        want_s = collision.nco_rates(f_stored, layers, act)
+        assert np.abs(got - want_s).max() < tol, (storage, np.abs(got - want_s).max())
+        assert np.abs(got - want).max() < max(tol, 1e-5)
+
+
+# -------------------------------------------------------- observables -------
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_global_sums_match_oracle(storage):
+    shape = (7, 6, 5)
+    rho, u = inputs.random_velocity(shape, seed=7)
+    with Lattice(shape, storage, "bgk", 0.6) as lat:
+        lat.init_equilibrium(rho, u)
+        s = lat.global_sums()
+        f = lat.populations()
+        r2, u2 = lat.macroscopic()
+    want = observables.global_sums(f)
+    np.testing.assert_allclose(s, want, rtol=1e-13, atol=1e-15)
+    rr, uu = collision.macroscopic(f)
+    np.testing.assert_allclose(r2, rr, rtol=1e-14)
+    np.testing.assert_allclose(u2, uu, atol=1e-16)
+
+
+@pytest.mark.parametrize("n", [8, 9, 12, 16])
+def test_energy_spectrum_matches_oracle(n):
+    rho, u = inputs.turbulence(n, seed=8, k0=2.0, urms=0.05)
+    with Lattice((n, n, n), "f64", "bgk", 0.6) as lat:
+        lat.init_equilibrium(rho, u)
+        E = lat.energy_spectrum()
+        f = lat.populations()
+    want = observables.spectrum(f)
+    assert E.shape == want.shape
+    np.testing.assert_allclose(E, want, rtol=1e-11, atol=1e-18)
+
+
+def test_conservation_on_gpu():
+    n = 16
+    rho, u = inputs.random_velocity((n, n, n), seed=9, amp=0.05)
+    for storage, tol in (("f64", 1e-12), ("f32", 1e-6)):
+        with _lattice((n, n, n), storage, "nco", 0.52) as lat:
+            lat.init_equilibrium(rho, u)
+            s0 = lat.global_sums()
+            lat.step(100)
+            s1 = lat.global_sums()
+        assert abs(s1[0] - s0[0]) / s0[0] < tol
+        assert np.abs(s1[1:4] - s0[1:4]).max() / s0[0] < tol
+
+
+def test_lattice_rotation_equivariance_on_gpu():
+    """Rotating the whole field by 90 degrees about z commutes with a step."""
+    n = 8
+    f0 = inputs.random_populations((n, n, n), seed=10, lo=0.9, hi=1.1)
+    C = np.array([(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)])
+    R = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]])
+    index = {tuple(c): i for i, c in enumerate(C)}
+    perm = [index[tuple(R @ c)] for c in C]
+
+    def rotate(f):
+        out = np.empty_like(f)
+        for j in range(27):
+            # node (x, y) -> (-y, x): array axes [z, y, x]
+            out[perm[j]] = np.rot90(f[j], k=1, axes=(2, 1))
+        return out
+    for storage, tol in (("f64", 1e-13), ("f32", 1e-6)):
+        res = []
+        for start in (f0, rotate(f0)):
+            with _lattice((n, n, n), storage, "nco", 0.55) as lat:
+                lat.init_populations(start)
+                lat.step(2)
+                res.append(lat.populations())
+        assert np.abs(rotate(res[0]) - res[1]).max() < tol
+
+
+def test_bench_size_sampled_against_oracle():
+    """128^3 float32 NCO in the benchmark's launch configuration: one step
+    checked node by node on a sample of 256 nodes."""
+    n = 128
+    _, tau = inputs.viscosity(n, 0.1 / np.sqrt(3.0), 1600.0)
+    rho, u = inputs.tgv3d(n, 0.1 / np.sqrt(3.0))
+    with _lattice((n, n, n), "f32", "nco", tau) as lat:
+        lat.init_equilibrium(rho, u)
+        lat.step(3)
+        before = lat.populations()
+        lat.step(1)
+        after = lat.populations()
+    assert np.isfinite(after).all()
+    rng = np.random.Generator(np.random.PCG64(11))
+    pts = rng.integers(0, n, size=(256, 3))
+    C = np.array([(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)])
+    pulled = np.empty((27, len(pts)))
+    for i, (cx, cy, cz) in enumerate(C):
+        pulled[i] = before[i, (pts[:, 0] - cz) % n, (pts[:, 1] - cy) % n, (pts[:, 2] - cx) % n]
+    want = _oracle_op("nco", tau).collide(pulled)
+    got = after[:, pts[:, 0], pts[:, 1], pts[:, 2]]
+    assert np.abs(got - want).max() < 1e-6
+
+
+def test_repeatable_bitwise():
+    n = 12
+    rho, u = inputs.random_velocity((n, n, n), seed=12)
+    out = []
+    for _ in range(2):
+        with _lattice((n, n, n), "f32", "nco", 0.55) as lat:
+            lat.init_equilibrium(rho, u)
+            lat.step(5)
+            out.append((lat.populations(), lat.global_sums(), lat.energy_spectrum()))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_state_and_argument_errors():
+    with Lattice((4, 4, 4), "f32", "nco", 0.6) as lat:
+        with pytest.raises(L.NCOError) as e:
+            lat.step(1)
+        assert e.value.status == L.NCO_E_STATE
+        with pytest.raises(L.NCOError) as e:
+            lat.rates()
+        assert e.value.status == L.NCO_E_STATE
+        with pytest.raises(L.NCOError) as e:
+            lat.set_net_weights(np.zeros(10), 32)
+        assert e.value.status == L.NCO_E_INVALID
+        with pytest.raises(L.NCOError) as e:
+            lat.set_net_weights(np.zeros(inputs.n_params(12)), 12)
+        assert e.value.status == L.NCO_E_INVALID
+        with pytest.raises(L.NCOError) as e:
+            lat.set_rates([1.0, 2.5, 1.0, 1.0])
+        assert e.value.status == L.NCO_E_INVALID
+        with pytest.raises(L.NCOError):
+            lat.set_op("bgk", 0.5)
+    with Lattice((4, 5, 4), "f32", "bgk", 0.6) as lat:
+        with pytest.raises(L.NCOError):
+            lat.energy_spectrum()
+
+
+def test_zero_steps_and_rest_state():
+    """A new lattice holds the rest state w_i, which every operator keeps."""
+    with _lattice((3, 3, 3), "f64", "nco", 0.7) as lat:
+        f = lat.populations()
+        lat.step(0)
+        assert np.array_equal(lat.populations(), f)
+        lat.step(4)
+        g = lat.populations()
+    w = collision.equilibrium(np.ones((3, 3, 3)), np.zeros((3, 3, 3, 3)))
+    assert np.abs(f - w).max() < 1e-16 and np.abs(g - w).max() < 1e-15
