@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--ops", default="nco,bgk,mrt")
+    ap.add_argument("--ops", default="nco,nco_valu,bgk,mrt")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the lattice path runs on a single MI355X; "
@@ -104,9 +104,12 @@ def main():
     nodes = n ** 3
     results = {}
     for op in args.ops.split(","):
-        lat = Lattice((n, n, n), "f32", op, tau, stream=stream)
+        kind = "nco" if op.startswith("nco") else op
+        lat = Lattice((n, n, n), "f32", kind, tau, stream=stream)
         if op == "nco":
-            lat.set_net_weights(params, width, "tanh")
+            lat.set_net_weights(params, width, "tanh", "f32_mfma")
+        if op == "nco_valu":
+            lat.set_net_weights(params, width, "tanh", "f32")
         if op == "mrt":
             lat.set_rates([4.0 / 3.0] * 4)
         lat.init_equilibrium(rho, u)
@@ -128,9 +131,9 @@ def main():
     if main_op == "nco":
         flops = nco_flops_per_node(width) * nodes
         achieved = flops / (r["ms_per_step"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                "kernel": "k_stream_collide<f32, NCO, W=32, tanh>",
+                "kernel": "k_nco_mfma_f32<f32 storage, tanh>",
                 "algorithmic_per_node": "%d flop (network) + %d B" % (nco_flops_per_node(width),
                                                                      bytes_per_node("f32"))}
     else:

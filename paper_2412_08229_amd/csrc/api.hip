@@ -108,6 +108,7 @@ struct nco_lattice {
     size_t pop_bytes = 0;
     double omega_high[4] = {1.0, 1.0, 1.0, 1.0};
     float* net = nullptr;
+    void* mfma_tab = nullptr;     // per-lane operand table + group gather table
     int width = 0, act = 0, mlp_prec = 0;
     double* staging = nullptr;    // 27N doubles, allocated on first use
     double* partial = nullptr;    // global-sum partials
@@ -131,6 +132,15 @@ int set_device(nco_lattice* lat) {
 int ensure_staging(nco_lattice* lat) {
     if (!lat->staging) HIP_TRY(hipMalloc(&lat->staging, sizeof(double) * 27 * (size_t)lat->n));
     return NCO_OK;
+}
+
+bool use_mfma(const nco_lattice* lat) {
+    return lat->op == NCO_OP_NCO && lat->mlp_prec == NCO_MLP_F32_MFMA && lat->mfma_tab;
+}
+const float* mfma_lane_tab(const nco_lattice* lat) { return static_cast<const float*>(lat->mfma_tab); }
+const int* mfma_group_tab(const nco_lattice* lat) {
+    return reinterpret_cast<const int*>(static_cast<const char*>(lat->mfma_tab) +
+                                        sizeof(float) * mfma_lane_table_floats());
 }
 
 StepArgs step_args(const nco_lattice* lat) {
@@ -225,6 +235,7 @@ int nco_lattice_destroy(nco_lattice* lat) {
     for (int b = 0; b < 2; ++b)
         if (lat->f[b]) hipFree(lat->f[b]);
     if (lat->net) hipFree(lat->net);
+    if (lat->mfma_tab) hipFree(lat->mfma_tab);
     if (lat->staging) hipFree(lat->staging);
     if (lat->partial) hipFree(lat->partial);
     if (lat->small) hipFree(lat->small);
@@ -260,7 +271,10 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
     if (int rc = check_lat(lat)) return rc;
     if (!width_ok(width)) return fail(NCO_E_INVALID, "width %d not supported (8, 16, 20, 32)", width);
     if (act != NCO_ACT_TANH && act != NCO_ACT_RELU) return fail(NCO_E_INVALID, "unknown activation %d", act);
-    if (mlp_prec != NCO_MLP_F32) return fail(NCO_E_UNSUPPORTED, "network precision %d not built", mlp_prec);
+    if (mlp_prec != NCO_MLP_F32 && mlp_prec != NCO_MLP_F32_MFMA)
+        return fail(NCO_E_UNSUPPORTED, "network precision %d not built", mlp_prec);
+    if (mlp_prec == NCO_MLP_F32_MFMA && (width != 32 || lat->storage == NCO_F64))
+        return fail(NCO_E_UNSUPPORTED, "the matrix-core network needs width 32 and float storage");
     if (!params) return fail(NCO_E_INVALID, "null parameters");
     if (n_params != n_params_for(width))
         return fail(NCO_E_INVALID, "expected %zu parameters for width %d, got %zu", n_params_for(width),
@@ -296,6 +310,15 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
     lat->width = W;
     lat->act = act;
     lat->mlp_prec = mlp_prec;
+    if (mlp_prec == NCO_MLP_F32_MFMA) {
+        const size_t nf = mfma_lane_table_floats(), ni = mfma_group_table_ints();
+        std::vector<char> tab(sizeof(float) * nf + sizeof(int) * ni);
+        mfma_prepare_tables(params, act, G.src, G.sign, reinterpret_cast<float*>(tab.data()),
+                            reinterpret_cast<int*>(tab.data() + sizeof(float) * nf));
+        if (!lat->mfma_tab) HIP_TRY(hipMalloc(&lat->mfma_tab, tab.size()));
+        HIP_TRY(hipMemcpyAsync(lat->mfma_tab, tab.data(), tab.size(), hipMemcpyHostToDevice, lat->stream));
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+    }
     return NCO_OK;
 }
 
@@ -333,7 +356,11 @@ int nco_step(nco_lattice* lat, int nsteps) {
     if (int rc = set_device(lat)) return rc;
     const StepArgs a = step_args(lat);
     for (int s = 0; s < nsteps; ++s) {
-        HIP_TRY(launch_step(lat->storage, lat->f[lat->cur], lat->f[1 - lat->cur], a, lat->stream));
+        if (use_mfma(lat))
+            HIP_TRY(launch_nco_mfma(lat->storage, lat->f[lat->cur], lat->f[1 - lat->cur], a,
+                                    mfma_lane_tab(lat), mfma_group_tab(lat), nullptr, lat->stream));
+        else
+            HIP_TRY(launch_step(lat->storage, lat->f[lat->cur], lat->f[1 - lat->cur], a, lat->stream));
         lat->cur = 1 - lat->cur;
     }
     return NCO_OK;
@@ -378,7 +405,11 @@ int nco_read_rates(nco_lattice* lat, double* omega) {
     if (int rc = set_device(lat)) return rc;
     if (int rc = ensure_staging(lat)) return rc;
     const StepArgs a = step_args(lat);
-    HIP_TRY(launch_rates(lat->storage, lat->f[lat->cur], lat->staging, a, lat->stream));
+    if (use_mfma(lat))
+        HIP_TRY(launch_nco_mfma(lat->storage, lat->f[lat->cur], nullptr, a, mfma_lane_tab(lat),
+                                mfma_group_tab(lat), lat->staging, lat->stream));
+    else
+        HIP_TRY(launch_rates(lat->storage, lat->f[lat->cur], lat->staging, a, lat->stream));
     HIP_TRY(hipMemcpyAsync(omega, lat->staging, sizeof(double) * 4 * (size_t)lat->n, hipMemcpyDeviceToHost,
                            lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));

@@ -106,46 +106,43 @@ __device__ __forceinline__ R meq2(int t, const R (&m)[Q], R inv_rho) {
     return a * inv_rho;
 }
 
-// Moment-space relaxation with per-order rates and optional Kupershtokh force.
+// Moment-space change of one collision (with the optional Kupershtokh source):
+// f_post = f - M^{-1} dm with dm = S (m - m^eq) - dm_source.  dm vanishes in
+// the conserved moments (orders 0 and 1 relax with rate 1 onto themselves),
+// so forming the update as a correction keeps mass and momentum to rounding
+// of the (small) non-equilibrium part instead of the populations themselves.
 template <typename R, bool FORCED>
-__device__ __forceinline__ void relax_moments(R (&m)[Q], R omega_nu, const R (&omega)[4],
-                                              R Fx, R Fy, R Fz) {
+__device__ __forceinline__ void collision_delta(const R (&m)[Q], R omega_nu, const R (&omega)[4],
+                                                R Fx, R Fy, R Fz, R (&dm)[Q]) {
     const R inv_rho = R(1) / m[0];
-    R dm2[Q];
-    if constexpr (FORCED) {
-        // Equilibrium shift of the source term, computed before relaxation.
-        const R jx = m[1] * R(1.0 / 1.7320508075688772), jy = m[3] * R(1.0 / 1.7320508075688772),
-                jz = m[9] * R(1.0 / 1.7320508075688772);
-        const R j[3] = {jx, jy, jz}, F[3] = {Fx, Fy, Fz};
-#pragma unroll
-        for (int t = 0; t < Q; ++t) {
-            dm2[t] = R(0);
-            if (order_of(t) == 2) {
-                const int nx = t % 3, ny = (t / 3) % 3, nz = t / 9;
-                int a = -1, b = -1;
-                if (nx == 2) { a = 0; b = 0; } else if (ny == 2) { a = 1; b = 1; }
-                else if (nz == 2) { a = 2; b = 2; } else if (nx == 1 && ny == 1) { a = 0; b = 1; }
-                else if (nx == 1 && nz == 1) { a = 0; b = 2; } else { a = 1; b = 2; }
-                dm2[t] = R(3) * (j[a] * F[b] + j[b] * F[a] + F[a] * F[b]) * inv_rho;
-            }
-        }
-    }
 #pragma unroll
     for (int t = 0; t < Q; ++t) {
         const int n = order_of(t);
-        if (n == 2) {
-            m[t] -= omega_nu * (m[t] - meq2(t, m, inv_rho));
-        } else if (n >= 3) {
-            m[t] *= (R(1) - omega[n - 3]);
+        if (n <= 1) {
+            dm[t] = R(0);
+        } else if (n == 2) {
+            dm[t] = omega_nu * (m[t] - meq2(t, m, inv_rho));
+        } else {
+            dm[t] = omega[n - 3] * m[t];
         }
     }
     if constexpr (FORCED) {
+        const R is3 = R(1.0 / 1.7320508075688772);
+        const R j[3] = {m[1] * is3, m[3] * is3, m[9] * is3}, F[3] = {Fx, Fy, Fz};
 #pragma unroll
-        for (int t = 0; t < Q; ++t)
-            if (order_of(t) == 2) m[t] += dm2[t];
-        m[1] += Sqrt3<R>::v * Fx;
-        m[3] += Sqrt3<R>::v * Fy;
-        m[9] += Sqrt3<R>::v * Fz;
+        for (int t = 0; t < Q; ++t) {
+            if (order_of(t) == 2) {
+                const int nx = t % 3, ny = (t / 3) % 3, nz = t / 9;
+                int a, b;
+                if (nx == 2) { a = 0; b = 0; } else if (ny == 2) { a = 1; b = 1; }
+                else if (nz == 2) { a = 2; b = 2; } else if (nx == 1 && ny == 1) { a = 0; b = 1; }
+                else if (nx == 1 && nz == 1) { a = 0; b = 2; } else { a = 1; b = 2; }
+                dm[t] -= R(3) * (j[a] * F[b] + j[b] * F[a] + F[a] * F[b]) * inv_rho;
+            }
+        }
+        dm[1] = -Sqrt3<R>::v * Fx;
+        dm[3] = -Sqrt3<R>::v * Fy;
+        dm[9] = -Sqrt3<R>::v * Fz;
     }
 }
 
@@ -169,16 +166,29 @@ __device__ __forceinline__ void bgk(R (&f)[Q], R omega_nu, R Fx, R Fy, R Fz) {
         vz = uz + Fz * inv_rho;
         base2 = R(1) - R(1.5) * (vx * vx + vy * vy + vz * vz);
     }
+    // The rest population's equilibrium is closed as rho minus the others, so
+    // the rounded weights do not bias the mass of every step.
+    R feq_sum = R(0), src_sum = R(0);
+    R feq[Q], src[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
+        if (i == 13) continue;
         const R cu = R(cx_of(i)) * ux + R(cy_of(i)) * uy + R(cz_of(i)) * uz;
         const R wr = R(weight_of(i)) * rho;
-        const R feq = wr * (base + cu * (R(3) + R(4.5) * cu));
-        f[i] += (feq - f[i]) * omega_nu;
+        feq[i] = wr * (base + cu * (R(3) + R(4.5) * cu));
+        feq_sum += feq[i];
         if constexpr (FORCED) {
             const R cv = R(cx_of(i)) * vx + R(cy_of(i)) * vy + R(cz_of(i)) * vz;
-            f[i] += wr * (base2 + cv * (R(3) + R(4.5) * cv)) - feq;
+            src[i] = wr * (base2 + cv * (R(3) + R(4.5) * cv)) - feq[i];
+            src_sum += src[i];
         }
+    }
+    feq[13] = rho - feq_sum;
+    src[13] = -src_sum;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        f[i] += (feq[i] - f[i]) * omega_nu;
+        if constexpr (FORCED) f[i] += src[i];
     }
 }
 

@@ -62,14 +62,17 @@ __device__ __forceinline__ void fwd3(R fm, R f0, R fp, R& a0, R& a1, R& a2) {
     a2 = R(2) * (fm + fp) - f0;
 }
 
-// Inverse of fwd3: f(c) = w1(c) sum_n h_n(c) a_n / norm_n.
+// Inverse of fwd3: f(c) = w1(c) sum_n h_n(c) a_n / norm_n.  The rest value
+// is formed as a0 - (f(-1) + f(+1)) (algebraically (2/3)(a0 - a2/2)), so the
+// zeroth moment of the three outputs is a0 up to one unbiased rounding; the
+// rounded constant 1/6 would otherwise scale the mass of every pass.
 template <typename R>
 __device__ __forceinline__ void inv3(R a0, R a1, R a2, R& fm, R& f0, R& fp) {
     const R s = a0 + a2;
     const R d = Sqrt3<R>::v * a1;
     fm = (s - d) * R(1.0 / 6.0);
     fp = (s + d) * R(1.0 / 6.0);
-    f0 = (a0 - R(0.5) * a2) * R(2.0 / 3.0);
+    f0 = a0 - (fm + fp);
 }
 
 // m = M f in tensor order (f in velocity order).

@@ -26,10 +26,10 @@ def _oracle_op(kind, tau, width=WIDTH, seed=0, act="tanh"):
     return step.Operator(kind, tau, omega_high=OMEGA, layers=layers, act=act)
 
 
-def _lattice(shape, storage, kind, tau, width=WIDTH, seed=0, act="tanh"):
+def _lattice(shape, storage, kind, tau, width=WIDTH, seed=0, act="tanh", mlp="f32"):
     lat = Lattice(shape, storage, kind, tau)
     if kind == "nco":
-        lat.set_net_weights(_params(width, seed), width, act)
+        lat.set_net_weights(_params(width, seed), width, act, mlp)
     if kind == "mrt":
         lat.set_rates(OMEGA)
     return lat
@@ -60,17 +60,17 @@ def _tgv16():
     return n, rho, u
 
 
-@pytest.mark.parametrize("kind", ["bgk", "mrt", "nco"])
-def test_f32_tgv16_100_steps_within_1e5(kind):
+@pytest.mark.parametrize("kind,mlp", [("bgk", "f32"), ("mrt", "f32"), ("nco", "f32"), ("nco", "f32_mfma")])
+def test_f32_tgv16_100_steps_within_1e5(kind, mlp):
     n, rho, u = _tgv16()
     tau = inputs.viscosity(n, 0.05, 100.0)[1] if kind == "nco" else 0.6
-    with _lattice((n, n, n), "f32", kind, tau) as lat:
+    with _lattice((n, n, n), "f32", kind, tau, mlp=mlp) as lat:
         lat.init_equilibrium(rho, u)
         lat.step(100)
         got = lat.populations()
     want = step.run(collision.equilibrium(rho, u), _oracle_op(kind, tau), 100)
     err = np.abs(got - want).max()
-    print("%s f32 16^3 x100: max err %.3e" % (kind, err))
+    print("%s/%s f32 16^3 x100: max err %.3e" % (kind, mlp, err))
     assert err < 1e-5
 
 
@@ -136,17 +136,18 @@ def test_energy_spectrum_matches_oracle(n):
     np.testing.assert_allclose(E, want, rtol=1e-11, atol=1e-18)
 
 
-def test_conservation_on_gpu():
+@pytest.mark.parametrize("storage,mlp,tol", [("f64", "f32", 1e-12), ("f32", "f32", 1e-7),
+                                             ("f32", "f32_mfma", 1e-7)])
+def test_conservation_on_gpu(storage, mlp, tol):
     n = 16
     rho, u = inputs.random_velocity((n, n, n), seed=9, amp=0.05)
-    for storage, tol in (("f64", 1e-12), ("f32", 1e-6)):
-        with _lattice((n, n, n), storage, "nco", 0.52) as lat:
-            lat.init_equilibrium(rho, u)
-            s0 = lat.global_sums()
-            lat.step(100)
-            s1 = lat.global_sums()
-        assert abs(s1[0] - s0[0]) / s0[0] < tol
-        assert np.abs(s1[1:4] - s0[1:4]).max() / s0[0] < tol
+    with _lattice((n, n, n), storage, "nco", 0.52, mlp=mlp) as lat:
+        lat.init_equilibrium(rho, u)
+        s0 = lat.global_sums()
+        lat.step(100)
+        s1 = lat.global_sums()
+    assert abs(s1[0] - s0[0]) / s0[0] < tol
+    assert np.abs(s1[1:4] - s0[1:4]).max() / s0[0] < tol
 
 
 def test_lattice_rotation_equivariance_on_gpu():
@@ -174,13 +175,14 @@ def test_lattice_rotation_equivariance_on_gpu():
         assert np.abs(rotate(res[0]) - res[1]).max() < tol
 
 
-def test_bench_size_sampled_against_oracle():
+@pytest.mark.parametrize("mlp", ["f32", "f32_mfma"])
+def test_bench_size_sampled_against_oracle(mlp):
     """128^3 float32 NCO in the benchmark's launch configuration: one step
     checked node by node on a sample of 256 nodes."""
     n = 128
     _, tau = inputs.viscosity(n, 0.1 / np.sqrt(3.0), 1600.0)
     rho, u = inputs.tgv3d(n, 0.1 / np.sqrt(3.0))
-    with _lattice((n, n, n), "f32", "nco", tau) as lat:
+    with _lattice((n, n, n), "f32", "nco", tau, mlp=mlp) as lat:
         lat.init_equilibrium(rho, u)
         lat.step(3)
         before = lat.populations()
@@ -198,12 +200,13 @@ def test_bench_size_sampled_against_oracle():
     assert np.abs(got - want).max() < 1e-6
 
 
-def test_repeatable_bitwise():
+@pytest.mark.parametrize("mlp", ["f32", "f32_mfma"])
+def test_repeatable_bitwise(mlp):
     n = 12
     rho, u = inputs.random_velocity((n, n, n), seed=12)
     out = []
     for _ in range(2):
-        with _lattice((n, n, n), "f32", "nco", 0.55) as lat:
+        with _lattice((n, n, n), "f32", "nco", 0.55, mlp=mlp) as lat:
             lat.init_equilibrium(rho, u)
             lat.step(5)
             out.append((lat.populations(), lat.global_sums(), lat.energy_spectrum()))
@@ -245,3 +248,48 @@ def test_zero_steps_and_rest_state():
         g = lat.populations()
     w = collision.equilibrium(np.ones((3, 3, 3)), np.zeros((3, 3, 3, 3)))
     assert np.abs(f - w).max() < 1e-16 and np.abs(g - w).max() < 1e-15
+
+
+# ------------------------------------------------- matrix-core network -------
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("act", ["tanh", "relu"])
+def test_mfma_network_rates_match_oracle(storage, act):
+    """Rates of the matrix-core network path on a ragged node count (315 =
+    one full block and a partial one) against the oracle on the stored state."""
+    shape = (5, 7, 9)
+    rho, u = inputs.random_velocity(shape, seed=13, amp=0.1)
+    f0 = collision.equilibrium(rho, u) + 0.01 * (inputs.random_populations(shape, seed=14) - 1.0 / 27)
+    layers = collision.unpack_params(_params(32, 15), 32)
+    with _lattice(shape, storage, "nco", 0.6, width=32, seed=15, act=act, mlp="f32_mfma") as lat:
+        lat.init_populations(f0)
+        got = lat.rates()
+        f_stored = lat.populations()
+    want = collision.nco_rates(f_stored, layers, act)
+    err = np.abs(got - want).max()
+    print("mfma rates %s/%s: %.3e" % (storage, act, err))
+    assert err < 2e-6
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (1, 1, 1), (16, 16, 16)])
+def test_mfma_step_matches_oracle_ragged(shape):
+    f0 = inputs.random_populations(shape, seed=16, lo=0.9, hi=1.1)
+    tau = 0.56
+    with _lattice(shape, "f32", "nco", tau, mlp="f32_mfma") as lat:
+        lat.init_populations(f0)
+        f_stored = lat.populations()
+        lat.step(2)
+        got = lat.populations()
+    want = step.run(f_stored, _oracle_op("nco", tau), 2)
+    assert np.abs(got - want).max() < 2e-6
+
+
+def test_mfma_requires_width_32_and_float_storage():
+    with Lattice((4, 4, 4), "f64", "nco", 0.6) as lat:
+        with pytest.raises(L.NCOError) as e:
+            lat.set_net_weights(_params(32), 32, "tanh", "f32_mfma")
+        assert e.value.status == L.NCO_E_UNSUPPORTED
+    with Lattice((4, 4, 4), "f32", "nco", 0.6) as lat:
+        with pytest.raises(L.NCOError) as e:
+            lat.set_net_weights(_params(16), 16, "tanh", "f32_mfma")
+        assert e.value.status == L.NCO_E_UNSUPPORTED
