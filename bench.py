@@ -26,6 +26,11 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
 FP32_PEAK_TFLOPS = 157.3         # MI355X float32 (vector and dense matrix)
 METRIC = "NCO stream-collide GLUPS & % HBM peak, FP32 vs low-precision; p99 solve latency"
 
+# HBM bytes per launch at 128^3 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# scaled by a plain copy of known size (profiles/*_hbm_counters.md).  An entry
+# is removed whenever its kernel changes, until the counters are taken again.
+TRAFFIC_BYTES = {"nco": 446.9e6 + 226.5e6, "bgk": 228.0e6 + 226.5e6}
+
 
 def nco_flops_per_node(width):
     """Multiply-adds of the group-averaged network, counted as 2 flops each:
@@ -38,16 +43,17 @@ def bytes_per_node(storage):
     return 2 * 27 * {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}[storage]
 
 
-def time_op(lat, steps, warmup, torch):
-    """Average wall time of one step (one kernel launch) from HIP events on the
-    lattice's stream, which is torch's current stream."""
+def time_op(lat, steps, warmup, torch, stream):
+    """Average time of one step (one kernel launch) from HIP events recorded
+    on the stream the lattice launches on (a torch stream handed to the
+    library), bracketed by device synchronisation."""
     lat.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    start.record()
+    start.record(stream)
     lat.step(steps)
-    end.record()
+    end.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(end) / steps
 
@@ -98,7 +104,10 @@ def main():
     u0 = 0.1 / math.sqrt(3.0)
     _, tau = inputs.viscosity(n, u0, 1600.0)
     rho, u = inputs.tgv3d(n, u0)
-    stream = torch.cuda.current_stream().cuda_stream
+    tstream = torch.cuda.Stream()          # default priority
+    stream = tstream.cuda_stream
+    if not stream:
+        raise RuntimeError("expected a non-null HIP stream handle")
     width = 32
     params = inputs.mlp_params(width, seed=0)
     nodes = n ** 3
@@ -113,8 +122,10 @@ def main():
         if op == "mrt":
             lat.set_rates([4.0 / 3.0] * 4)
         lat.init_equilibrium(rho, u)
-        steps = args.steps
-        ms = time_op(lat, steps, args.warmup, torch)
+        # The per-node vector-unit network is kept as a reference variant; it
+        # is two orders slower, so it is timed on fewer steps.
+        steps = min(args.steps, 10) if op == "nco_valu" else args.steps
+        ms = time_op(lat, steps, min(args.warmup, 2) if op == "nco_valu" else args.warmup, torch, tstream)
         s = lat.global_sums()
         if not np.all(np.isfinite(s)):
             raise RuntimeError("non-finite state after the %s run" % op)
@@ -122,9 +133,27 @@ def main():
         glups = nodes / (ms * 1e-3) / 1e9
         gbs = bytes_per_node("f32") * nodes / (ms * 1e-3) / 1e9
         results[op] = {"ms_per_step": ms, "glups": glups, "hbm_gbs": gbs,
-                       "hbm_frac": gbs / HBM_PEAK_GBS}
+                       "hbm_frac": gbs / HBM_PEAK_GBS, "steps": steps}
         print("# %s: %.4f ms/step, %.3f GLUPS, %.0f GB/s" % (op, ms, glups, gbs), file=sys.stderr,
               flush=True)
+
+    # Attainable HBM bandwidth on this device: a plain device-to-device copy of
+    # the bytes one float32 step moves (27 reads + 27 writes per node).
+    nbytes = bytes_per_node("f32") * nodes // 2
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(tstream):
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(tstream)
+        for _ in range(20):
+            dst.copy_(src)
+        t1.record(tstream)
+        torch.cuda.synchronize()
+    copy_gbs = 2 * nbytes / (t0.elapsed_time(t1) / 20 * 1e-3) / 1e9
+    del src, dst
 
     main_op = "nco" if "nco" in results else list(results)[0]
     r = results[main_op]
@@ -132,13 +161,13 @@ def main():
         flops = nco_flops_per_node(width) * nodes
         achieved = flops / (r["ms_per_step"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": TRAFFIC_BYTES.get("nco"),
                 "kernel": "k_nco_mfma_f32<f32 storage, tanh>",
                 "algorithmic_per_node": "%d flop (network) + %d B" % (nco_flops_per_node(width),
                                                                      bytes_per_node("f32"))}
     else:
         roof = {"bound": "hbm", "achieved": r["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": r["hbm_frac"], "traffic": None}
+                "frac": r["hbm_frac"], "traffic": TRAFFIC_BYTES.get(main_op)}
     out = {
         "metric": METRIC,
         "value": r["glups"],
@@ -157,6 +186,7 @@ def main():
                    "lattice": [n, n, n], "operator": main_op, "storage": "f32", "width": width},
         "roofline": roof,
         "operators": results,
+        "copy_gbs": copy_gbs,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
