@@ -1,32 +1,38 @@
 // NCO stream-collide with the invariant network on the matrix cores (gfx950).
 //
-// The network of Eq. gconv_m is evaluated for a tile of 16 nodes at a time as
-// a chain of transposed GEMMs, hidden x nodes:
-//     Z1 = W1^T X_g          (32 x 28) (28 x 16), X_g = m^(g) plus a 1 row
-//     H1 = act(Z1)                                 (bias b1 rides on the 1 row)
-//     Z2 = W2^T H1 + b2      (32 x 32) (32 x 16)
-//     acc += act(Z2)         summed over the 48 group elements g
-//     tilde tau = W3^T acc / 48 + b3               (vector units)
-// With v_mfma_f32_16x16x4f32 the accumulator of one product is laid out as
-// lane (q, c) = (lane / 16, lane % 16) holding rows 4q..4q+3 of column c,
-// which is exactly the B-operand layout of the next product's K-step when the
-// K index is ordered (t, r) -> hidden 16 t + 4 q + r.  Layer 1 therefore
-// feeds layer 2 from registers, with no LDS round trip.
+// Network of Eq. gconv_m, evaluated for tiles of 16 nodes as transposed
+// GEMMs (hidden x nodes) on v_mfma_f32_16x16x4f32:
+//     Z1_g = W1^T m^(g) + b1     (32 x 28) (28 x 16)
+//     H1   = act(Z1_g)
+//     Z2_g = W2^T H1 + b2        (32 x 32) (32 x 16)
+//     acc += act(Z2_g)           summed over the 48 elements g of O_h
+//     tilde tau = W3^T acc / 48 + b3
 //
-// The group action m^(g) = M Pi_g f is a signed permutation of the moment
-// vector (the rows of M are products of one-dimensional Hermite polynomials,
-// so a rotation/reflection of the velocities permutes the rows and flips the
-// sign of odd ones).  It is applied while gathering the B operand from the
-// LDS moment tile: a per-group table gives, for each lane group q and K-step,
-// the source row and the sign bit.  W1, W2, b2 and W3 stay in registers for
-// the whole kernel.
+// Group structure of the first layer.  An element g of O_h is an axis
+// permutation pi followed by axis reflections s in {+-1}^3.  Because every row
+// of M is a product of one-dimensional Hermite polynomials, m^(g) = M Pi_g f
+// is the permuted moment vector (Q_pi m) with row k multiplied by
+// prod_r s_r^(n_kr): the sign depends only on the parity class
+// c(k) = (n_kx, n_ky, n_kz) mod 2 of the row.  Hence
+//     Z1_(pi,s) = sum_c chi_s(c) Y_(pi,c),   Y_(pi,c) = W1_c^T (Q_pi m)_c,
+// with chi_s(c) = prod_r s_r^(c_r): the eight sign patterns of one permutation
+// are a 3-point Walsh-Hadamard transform of eight class partial products.
+// The class products cost 10 K-steps (class sizes 9 incl. the bias row, 4, 4,
+// 4, 2, 2, 2, 1) per permutation instead of 8 x 7 K-steps for the eight
+// elements separately; the moment operand is gathered from LDS once per
+// permutation, without signs.
+//
+// Register chaining.  The accumulator of 16x16x4f32 holds, in lane (q, c) =
+// (lane / 16, lane % 16), rows 4q..4q+3 of column c.  That is the B-operand
+// layout of a K-step whose K index is ordered (t, r) -> hidden 16 t + 4 q + r,
+// so layer 2 consumes act(Z1) straight from registers.
 //
 // Block = 256 threads = 256 nodes.  Phase A: each thread pulls its 27
-// populations and writes its moments to LDS.  Phase B: each wavefront runs the
-// network for its 64 nodes (4 tiles of 16) and writes the four rates per node
-// to LDS.  Phase C: each thread pulls its populations again (the kernel is
-// compute bound; the second read is cheap), relaxes in moment space with the
-// rates and stores.
+// populations and writes its 27 moments (plus the constant 1 of the bias row)
+// to LDS.  Phase B: each wavefront runs the network for its 64 nodes, 16 at a
+// time, and writes the four rates per node to LDS.  Phase C: each thread pulls
+// its populations again (the kernel is compute bound; the second read is
+// cheap), relaxes with the rates and stores.
 #include "kernels.h"
 #include "stream.h"
 
@@ -34,30 +40,45 @@ namespace nco {
 
 namespace {
 
-constexpr int MW = 32;             // network width on this path
-constexpr int NODE_STRIDE = 29;    // LDS floats per node: 27 moments, 1.0, pad
-constexpr int GT_ENTRIES = NGROUP * 4 * 8;
+constexpr int MW = 32;              // network width on this path
+constexpr int NODE_STRIDE = 29;     // LDS floats per node: 27 moments, 1.0, 0.0
+constexpr int KSTEPS = 10;          // K-steps of the eight parity-class products
+constexpr int GT_STRIDE = 12;       // ints per (pi, q) in the gather table
+constexpr int GT_ENTRIES = 6 * 4 * GT_STRIDE;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Offsets in the per-lane weight table (floats per lane: LANE_FLOATS).
-constexpr int LT_A1 = 0;           // [t 2][s 7]      W1/b1 rows as A operand
-constexpr int LT_A2 = 14;          // [u 2][t 2][r 4] W2 as A operand
-constexpr int LT_B2 = 30;          // [u 2][r 4]      b2 as accumulator init
-constexpr int LT_W3 = 38;          // [u 2][r 4][n 4] W3 / 48
-constexpr int LT_B3 = 70;          // [n 4]
-constexpr int LANE_FLOATS = 76;
+// K-step -> parity class ci = cx + 2 cy + 4 cz of the W1 rows it holds.
+__host__ __device__ constexpr int step_class(int st) {
+    constexpr int c[KSTEPS] = {0, 0, 0, 1, 2, 4, 3, 5, 6, 7};
+    return c[st];
+}
 
-// Activation of a pre-activation that was scaled by kappa = 2 log2(e) for
-// tanh: tanh(z) = 1 - 2 / (1 + 2^(kappa z)); saturates correctly at +-inf.
+// Offsets in the per-lane weight table (floats per lane: LANE_FLOATS).
+constexpr int LT_A1 = 0;            // [t 2][st 10]    W1 rows / b1 as A operand
+constexpr int LT_A2 = 20;           // [u 2][t 2][r 4] W2 as A operand
+constexpr int LT_B2 = 36;           // [u 2][r 4]      b2 as accumulator init
+constexpr int LT_W3 = 44;           // [u 2][r 4][n 4] W3 / 48
+constexpr int LT_B3 = 76;           // [n 4]
+constexpr int LANE_FLOATS = 80;
+
+// Activation as evaluated on this path.  For tanh the pre-activation arrives
+// scaled by kappa = 2 log2(e) and the function returns r = 1 / (1 + 2^(kappa z)),
+// so that tanh(z) = 1 - 2 r; the affine map 1 - 2 r is folded into the next
+// layer's weights and bias on the host (and into W3, b3 for the group sum),
+// which leaves exp2, add and reciprocal per value.  r saturates correctly
+// (2^+inf = inf gives 0).
 template <int ACT>
 __device__ __forceinline__ float act_scaled(float x) {
     if constexpr (ACT == ACT_RELU) {
         return fmaxf(x, 0.0f);
     } else {
-        const float t = __builtin_amdgcn_exp2f(x);
-        return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + t), 1.0f);
+        return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x));
     }
+}
+
+__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 // RATES = true: no streaming, the rates of the stored state are written to
@@ -103,11 +124,11 @@ __global__ __launch_bounds__(256) void k_nco_mfma_f32(const typename Codec<S>::s
     {
         const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, c = lane & 15;
         const float* __restrict__ lt = lane_tab + lane * LANE_FLOATS;
-        float A1[2][7], A2[2][2][4], B2[2][4];
+        float A1[2][KSTEPS], A2[2][2][4], B2[2][4];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int s = 0; s < 7; ++s) A1[t][s] = lt[LT_A1 + t * 7 + s];
+            for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -125,41 +146,61 @@ __global__ __launch_bounds__(256) void k_nco_mfma_f32(const typename Codec<S>::s
             const float* __restrict__ mrow = sm + node * NODE_STRIDE;
             f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll 1
-            for (int g = 0; g < NGROUP; ++g) {
-                const int* __restrict__ ge = sg + (g * 4 + q) * 8;
-                float b[7];
+            for (int p = 0; p < 6; ++p) {
+                // Moment operand of this permutation, one K-step per register.
+                const int* __restrict__ ge = sg + (p * 4 + q) * GT_STRIDE;
+                float b[KSTEPS];
 #pragma unroll
-                for (int s = 0; s < 7; ++s) {
-                    const int e = ge[s];
-                    b[s] = __int_as_float(__float_as_int(mrow[e & 31]) ^ (e & (int)0x80000000));
+                for (int st = 0; st < KSTEPS; ++st) b[st] = mrow[ge[st]];
+                // Eight parity-class partial products.
+                f32x4 Y[8][2];
+#pragma unroll
+                for (int ci = 0; ci < 8; ++ci) {
+                    Y[ci][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    Y[ci][1] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
-                f32x4 c1[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-                for (int s = 0; s < 7; ++s)
+                for (int st = 0; st < KSTEPS; ++st)
 #pragma unroll
                     for (int t = 0; t < 2; ++t)
-                        c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A1[t][s], b[s], c1[t], 0, 0, 0);
+                        Y[step_class(st)][t] = mfma(A1[t][st], b[st], Y[step_class(st)][t]);
+                // Walsh-Hadamard transform over the class index: Y[s] becomes
+                // the layer-1 pre-activation of reflection pattern s.
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int bit = 1; bit < 8; bit <<= 1)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) c1[t][r] = act_scaled<ACT>(c1[t][r]);
-                f32x4 c2[2];
+                    for (int ci = 0; ci < 8; ++ci)
+                        if (!(ci & bit))
 #pragma unroll
-                for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
+                            for (int t = 0; t < 2; ++t) {
+                                const f32x4 u0 = Y[ci][t], u1 = Y[ci | bit][t];
+                                Y[ci][t] = u0 + u1;
+                                Y[ci | bit][t] = u0 - u1;
+                            }
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int s = 0; s < 8; ++s) {
+                    f32x4 h1[2];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
+                    for (int t = 0; t < 2; ++t)
 #pragma unroll
-                        for (int u = 0; u < 2; ++u)
-                            c2[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(A2[u][t][r], c1[t][r], c2[u], 0, 0, 0);
+                        for (int r = 0; r < 4; ++r) h1[t][r] = act_scaled<ACT>(Y[s][t][r]);
+                    f32x4 c2[2];
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                    for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2[u][r]);
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int u = 0; u < 2; ++u) c2[u] = mfma(A2[u][t][r], h1[t][r], c2[u]);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2[u][r]);
+                }
             }
             // Output layer on the group mean, reduced over the 4 lane groups.
-            float p[4];
+            float pn[4];
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
                 float v = 0.0f;
@@ -169,12 +210,12 @@ __global__ __launch_bounds__(256) void k_nco_mfma_f32(const typename Codec<S>::s
                     for (int r = 0; r < 4; ++r) v = fmaf(lt[LT_W3 + (u * 4 + r) * 4 + n], acc[u][r], v);
                 v += __shfl_xor(v, 16, 64);
                 v += __shfl_xor(v, 32, 64);
-                p[n] = v;
+                pn[n] = v;
             }
             if (q == 0) {
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
-                    const float t = p[n] + lt[LT_B3 + n];
+                    const float t = pn[n] + lt[LT_B3 + n];
                     sw[node * 4 + n] = 1.0f / (0.5f + 0.5f / (1.0f + expf(t)));
                 }
             }
@@ -208,15 +249,39 @@ __global__ __launch_bounds__(256) void k_nco_mfma_f32(const typename Codec<S>::s
     }
 }
 
+// Parity class of row k of M.
+int row_class(int k) {
+    const int t = row_tensor(k);
+    return (t % 3) % 2 + 2 * (((t / 3) % 3) % 2) + 4 * ((t / 9) % 2);
+}
+
+// Canonical placement of the 28 K rows (27 moments + bias row 27) into the
+// 10 K-steps x 4 slots, grouped by parity class; -1 marks an empty slot.
+void class_slots(int slot_row[KSTEPS][4]) {
+    int fill[KSTEPS] = {0};
+    for (int st = 0; st < KSTEPS; ++st)
+        for (int q = 0; q < 4; ++q) slot_row[st][q] = -1;
+    for (int k = 0; k < 28; ++k) {
+        const int ci = k < 27 ? row_class(k) : 0;      // the bias row joins class 0
+        for (int st = 0; st < KSTEPS; ++st)
+            if (step_class(st) == ci && fill[st] < 4) {
+                slot_row[st][fill[st]++] = k;
+                break;
+            }
+    }
+}
+
 }  // namespace
 
 size_t mfma_lane_table_floats() { return 64 * LANE_FLOATS; }
 size_t mfma_group_table_ints() { return GT_ENTRIES; }
 
 // Host-side preparation of the per-lane operand tables from the flat
-// parameters (W1[27][W], b1, W2[W][W], b2, W3[W][4], b3) and of the group
-// gather table from (src, sign) of every group element and row.
-void mfma_prepare_tables(const float* params, int act, const int (*gsrc)[27], const float (*gsign)[27],
+// parameters (W1[27][W], b1, W2[W][W], b2, W3[W][4], b3) and of the gather
+// table: for axis permutation p and slot (st, q) holding W1 row k, the moment
+// row that m^(g) places at k.  gsrc/gsign are indexed by group element g =
+// 8 p + reflection mask; the reflection-free elements g = 8 p give Q_p.
+void mfma_prepare_tables(const float* params, int act, const int (*gsrc)[27], const float (*)[27],
                          float* lane_tab, int* gtab) {
     const int W = MW;
     const float* W1 = params;
@@ -225,41 +290,58 @@ void mfma_prepare_tables(const float* params, int act, const int (*gsrc)[27], co
     const float* b2 = W2 + W * W;
     const float* W3 = b2 + W;
     const float* b3 = W3 + 4 * W;
-    const float kappa = act == ACT_TANH ? (float)(2.0 / 0.69314718055994530942) : 1.0f;
+    const bool th = act == ACT_TANH;
+    const float kappa = th ? (float)(2.0 / 0.69314718055994530942) : 1.0f;
+    // tanh = 1 - 2 r folded into the consumer of each activation:
+    // W2 -> -2 W2, b2 -> b2 + sum_h W2[h][:], W3 -> -2 W3, b3 -> b3 + sum_h W3[h][:]
+    // (the group mean turns 1 into 48 / 48).
+    const float fold = th ? -2.0f : 1.0f;
+    float b2f[MW], b3f[4];
+    for (int o = 0; o < W; ++o) {
+        double s = b2[o];
+        if (th)
+            for (int h = 0; h < W; ++h) s += W2[h * W + o];
+        b2f[o] = (float)s;
+    }
+    for (int n = 0; n < 4; ++n) {
+        double s = b3[n];
+        if (th)
+            for (int h = 0; h < W; ++h) s += W3[h * 4 + n];
+        b3f[n] = (float)s;
+    }
+    int slot_row[KSTEPS][4];
+    class_slots(slot_row);
     for (int lane = 0; lane < 64; ++lane) {
         const int q = lane >> 4, c = lane & 15;
         float* lt = lane_tab + lane * LANE_FLOATS;
         for (int i = 0; i < LANE_FLOATS; ++i) lt[i] = 0.0f;
         for (int t = 0; t < 2; ++t)
-            for (int s = 0; s < 7; ++s) {
-                const int k = 4 * s + q, h = 16 * t + c;
-                lt[LT_A1 + t * 7 + s] = kappa * (k < 27 ? W1[k * W + h] : b1[h]);
+            for (int st = 0; st < KSTEPS; ++st) {
+                const int k = slot_row[st][q], h = 16 * t + c;
+                const float w = k < 0 ? 0.0f : k < 27 ? W1[k * W + h] : b1[h];
+                lt[LT_A1 + t * KSTEPS + st] = kappa * w;
             }
         for (int u = 0; u < 2; ++u)
             for (int t = 0; t < 2; ++t)
                 for (int r = 0; r < 4; ++r)
-                    lt[LT_A2 + u * 8 + t * 4 + r] = kappa * W2[(16 * t + 4 * q + r) * W + 16 * u + c];
+                    lt[LT_A2 + u * 8 + t * 4 + r] = kappa * fold * W2[(16 * t + 4 * q + r) * W + 16 * u + c];
         for (int u = 0; u < 2; ++u)
-            for (int r = 0; r < 4; ++r) lt[LT_B2 + u * 4 + r] = kappa * b2[16 * u + 4 * q + r];
+            for (int r = 0; r < 4; ++r) lt[LT_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
         for (int u = 0; u < 2; ++u)
             for (int r = 0; r < 4; ++r)
                 for (int n = 0; n < 4; ++n)
-                    lt[LT_W3 + (u * 4 + r) * 4 + n] = W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
-        for (int n = 0; n < 4; ++n) lt[LT_B3 + n] = b3[n];
+                    lt[LT_W3 + (u * 4 + r) * 4 + n] = fold * W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
+        for (int n = 0; n < 4; ++n) lt[LT_B3 + n] = b3f[n];
     }
-    for (int g = 0; g < NGROUP; ++g)
+    for (int p = 0; p < 6; ++p)
         for (int q = 0; q < 4; ++q)
-            for (int s = 0; s < 8; ++s) {
-                const int k = 4 * s + q;
-                int e;
-                if (k < 27) {
-                    e = gsrc[g][k] | (gsign[g][k] < 0.0f ? (int)0x80000000 : 0);
-                } else if (k == 27) {
-                    e = 27;          // the constant-1 row carrying b1
-                } else {
-                    e = 28;          // zero pad (unused K slot)
+            for (int st = 0; st < GT_STRIDE; ++st) {
+                int e = 28;                                   // the zero slot of a node's LDS row
+                if (st < KSTEPS) {
+                    const int k = slot_row[st][q];
+                    if (k >= 0) e = k < 27 ? gsrc[8 * p][k] : 27;
                 }
-                gtab[(g * 4 + q) * 8 + s] = e;
+                gtab[(p * 4 + q) * GT_STRIDE + st] = e;
             }
 }
 
@@ -271,17 +353,17 @@ hipError_t launch_nco_mfma(int storage, const void* fin, void* fout, const StepA
 #define MFMA_LAUNCH(SS, AA, RR)                                                                       \
     hipLaunchKernelGGL((k_nco_mfma_f32<SS, AA, RR>), grid, block, 0, st, static_cast<const T*>(fin), \
                        static_cast<T*>(fout), a, lane_tab, gtab, omega_out)
-#define MFMA_CASE(SS)                                                         \
-    case SS: {                                                                \
-        using T = typename Codec<SS>::store_t;                                \
-        if (omega_out) {                                                      \
-            if (a.act == ACT_TANH) MFMA_LAUNCH(SS, ACT_TANH, true);           \
-            else MFMA_LAUNCH(SS, ACT_RELU, true);                             \
-        } else {                                                              \
-            if (a.act == ACT_TANH) MFMA_LAUNCH(SS, ACT_TANH, false);          \
-            else MFMA_LAUNCH(SS, ACT_RELU, false);                            \
-        }                                                                     \
-        return hipGetLastError();                                             \
+#define MFMA_CASE(SS)                                                \
+    case SS: {                                                       \
+        using T = typename Codec<SS>::store_t;                       \
+        if (omega_out) {                                             \
+            if (a.act == ACT_TANH) MFMA_LAUNCH(SS, ACT_TANH, true);  \
+            else MFMA_LAUNCH(SS, ACT_RELU, true);                    \
+        } else {                                                     \
+            if (a.act == ACT_TANH) MFMA_LAUNCH(SS, ACT_TANH, false); \
+            else MFMA_LAUNCH(SS, ACT_RELU, false);                   \
+        }                                                            \
+        return hipGetLastError();                                    \
     }
     switch (storage) {
         MFMA_CASE(ST_F32)
