@@ -135,7 +135,7 @@ int ensure_staging(nco_lattice* lat) {
 }
 
 bool use_mfma(const nco_lattice* lat) {
-    return lat->op == NCO_OP_NCO && lat->mlp_prec == NCO_MLP_F32_MFMA && lat->mfma_tab;
+    return lat->op == NCO_OP_NCO && lat->mlp_prec != NCO_MLP_F32 && lat->mfma_tab;
 }
 const float* mfma_lane_tab(const nco_lattice* lat) { return static_cast<const float*>(lat->mfma_tab); }
 const int* mfma_group_tab(const nco_lattice* lat) {
@@ -271,9 +271,9 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
     if (int rc = check_lat(lat)) return rc;
     if (!width_ok(width)) return fail(NCO_E_INVALID, "width %d not supported (8, 16, 20, 32)", width);
     if (act != NCO_ACT_TANH && act != NCO_ACT_RELU) return fail(NCO_E_INVALID, "unknown activation %d", act);
-    if (mlp_prec != NCO_MLP_F32 && mlp_prec != NCO_MLP_F32_MFMA)
-        return fail(NCO_E_UNSUPPORTED, "network precision %d not built", mlp_prec);
-    if (mlp_prec == NCO_MLP_F32_MFMA && (width != 32 || lat->storage == NCO_F64))
+    if (mlp_prec != NCO_MLP_F32 && mlp_prec != NCO_MLP_F32_MFMA && mlp_prec != NCO_MLP_BF16)
+        return fail(NCO_E_INVALID, "unknown network precision %d", mlp_prec);
+    if (mlp_prec != NCO_MLP_F32 && (width != 32 || lat->storage == NCO_F64))
         return fail(NCO_E_UNSUPPORTED, "the matrix-core network needs width 32 and float storage");
     if (!params) return fail(NCO_E_INVALID, "null parameters");
     if (n_params != n_params_for(width))
@@ -310,10 +310,10 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
     lat->width = W;
     lat->act = act;
     lat->mlp_prec = mlp_prec;
-    if (mlp_prec == NCO_MLP_F32_MFMA) {
+    if (mlp_prec != NCO_MLP_F32) {
         const size_t nf = mfma_lane_table_floats(), ni = mfma_group_table_ints();
         std::vector<char> tab(sizeof(float) * nf + sizeof(int) * ni);
-        mfma_prepare_tables(params, act, G.src, G.sign, reinterpret_cast<float*>(tab.data()),
+        mfma_prepare_tables(params, act, mlp_prec, G.src, reinterpret_cast<float*>(tab.data()),
                             reinterpret_cast<int*>(tab.data() + sizeof(float) * nf));
         if (!lat->mfma_tab) HIP_TRY(hipMalloc(&lat->mfma_tab, tab.size()));
         HIP_TRY(hipMemcpyAsync(lat->mfma_tab, tab.data(), tab.size(), hipMemcpyHostToDevice, lat->stream));
@@ -357,7 +357,7 @@ int nco_step(nco_lattice* lat, int nsteps) {
     const StepArgs a = step_args(lat);
     for (int s = 0; s < nsteps; ++s) {
         if (use_mfma(lat))
-            HIP_TRY(launch_nco_mfma(lat->storage, lat->f[lat->cur], lat->f[1 - lat->cur], a,
+            HIP_TRY(launch_nco_mfma(lat->storage, lat->mlp_prec, lat->f[lat->cur], lat->f[1 - lat->cur], a,
                                     mfma_lane_tab(lat), mfma_group_tab(lat), nullptr, lat->stream));
         else
             HIP_TRY(launch_step(lat->storage, lat->f[lat->cur], lat->f[1 - lat->cur], a, lat->stream));
@@ -406,7 +406,7 @@ int nco_read_rates(nco_lattice* lat, double* omega) {
     if (int rc = ensure_staging(lat)) return rc;
     const StepArgs a = step_args(lat);
     if (use_mfma(lat))
-        HIP_TRY(launch_nco_mfma(lat->storage, lat->f[lat->cur], nullptr, a, mfma_lane_tab(lat),
+        HIP_TRY(launch_nco_mfma(lat->storage, lat->mlp_prec, lat->f[lat->cur], nullptr, a, mfma_lane_tab(lat),
                                 mfma_group_tab(lat), lat->staging, lat->stream));
     else
         HIP_TRY(launch_rates(lat->storage, lat->f[lat->cur], lat->staging, a, lat->stream));

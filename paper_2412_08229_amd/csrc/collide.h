@@ -23,6 +23,8 @@ namespace nco {
 
 enum Op { OP_BGK = 0, OP_MRT = 1, OP_NCO = 2, OP_NONE = 3 };
 enum Act { ACT_TANH = 0, ACT_RELU = 1 };
+// Matrix-core network arithmetic (values of nco_mlp_prec).
+enum MlpPrec { MLP_PREC_F32 = 1, MLP_PREC_BF16 = 2 };
 
 constexpr int NGROUP = 48;
 

@@ -31,12 +31,12 @@ hipError_t launch_global_sums(int storage, const void* f, double* partial, doubl
                               hipStream_t st);
 hipError_t launch_check_finite(int storage, const void* f, int n, int* flag, hipStream_t st);
 
-// Matrix-core network path (nco_mfma.hip), width 32, float arithmetic.
+// Matrix-core network path (nco_mfma.hip), width 32, float32 or bf16 operands.
 size_t mfma_lane_table_floats();
 size_t mfma_group_table_ints();
-void mfma_prepare_tables(const float* params, int act, const int (*gsrc)[27], const float (*gsign)[27],
-                         float* lane_tab, int* gtab);
-hipError_t launch_nco_mfma(int storage, const void* fin, void* fout, const StepArgs& a,
+void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsrc)[27], float* lane_tab,
+                         int* gtab);
+hipError_t launch_nco_mfma(int storage, int prec, const void* fin, void* fout, const StepArgs& a,
                            const float* lane_tab, const int* gtab, double* omega_out, hipStream_t st);
 
 // Energy spectrum (spectrum.hip).

@@ -1,31 +1,37 @@
 // NCO stream-collide with the invariant network on the matrix cores (gfx950).
 //
 // Network of Eq. gconv_m, evaluated for tiles of 16 nodes as transposed
-// GEMMs (hidden x nodes) on v_mfma_f32_16x16x4f32:
+// GEMMs (hidden x nodes):
 //     Z1_g = W1^T m^(g) + b1     (32 x 28) (28 x 16)
 //     H1   = act(Z1_g)
 //     Z2_g = W2^T H1 + b2        (32 x 32) (32 x 16)
 //     acc += act(Z2_g)           summed over the 48 elements g of O_h
 //     tilde tau = W3^T acc / 48 + b3
+// in one of two arithmetics:
+//   PREC_F32  v_mfma_f32_16x16x4f32 (float32 operands and accumulation);
+//   PREC_BF16 v_mfma_f32_16x16x32_bf16 (bf16 operands, float32 accumulation,
+//             activations and group sum in float32).
 //
-// Group structure of the first layer.  An element g of O_h is an axis
-// permutation pi followed by axis reflections s in {+-1}^3.  Because every row
-// of M is a product of one-dimensional Hermite polynomials, m^(g) = M Pi_g f
-// is the permuted moment vector (Q_pi m) with row k multiplied by
-// prod_r s_r^(n_kr): the sign depends only on the parity class
-// c(k) = (n_kx, n_ky, n_kz) mod 2 of the row.  Hence
-//     Z1_(pi,s) = sum_c chi_s(c) Y_(pi,c),   Y_(pi,c) = W1_c^T (Q_pi m)_c,
-// with chi_s(c) = prod_r s_r^(c_r): the eight sign patterns of one permutation
-// are a 3-point Walsh-Hadamard transform of eight class partial products.
-// The class products cost 10 K-steps (class sizes 9 incl. the bias row, 4, 4,
-// 4, 2, 2, 2, 1) per permutation instead of 8 x 7 K-steps for the eight
-// elements separately; the moment operand is gathered from LDS once per
-// permutation, without signs.
+// Group structure.  An element g of O_h is an axis permutation pi followed by
+// axis reflections s in {+-1}^3.  Every row of M is a product of
+// one-dimensional Hermite polynomials, so m^(g) = M Pi_g f is the permuted
+// moment vector (Q_pi m) with row k multiplied by prod_r s_r^(n_kr): the sign
+// depends only on the parity class c(k) = (n_kx, n_ky, n_kz) mod 2 of the row.
+//  * float32: Z1_(pi,s) = sum_c chi_s(c) Y_(pi,c) with Y_(pi,c) =
+//    W1_c^T (Q_pi m)_c and chi_s(c) = prod_r s_r^(c_r), i.e. the eight
+//    reflections of one permutation are a 3-point Walsh-Hadamard transform of
+//    eight class partial products (10 K-steps of 4 instead of 8 x 7).
+//  * bf16: one K = 32 product covers all 28 rows, so each element is one
+//    product per output tile; the reflection is applied to the packed bf16
+//    operand by flipping sign bits with per-lane class masks.
+// The moment operand is gathered from LDS once per permutation.
 //
-// Register chaining.  The accumulator of 16x16x4f32 holds, in lane (q, c) =
-// (lane / 16, lane % 16), rows 4q..4q+3 of column c.  That is the B-operand
-// layout of a K-step whose K index is ordered (t, r) -> hidden 16 t + 4 q + r,
-// so layer 2 consumes act(Z1) straight from registers.
+// Register chaining.  The accumulator of a 16x16 product holds, in lane
+// (q, c) = (lane / 16, lane % 16), rows 4q..4q+3 of column c.  Ordering the K
+// index of the next product as (t, r) -> hidden 16 t + 4 q + r (float32,
+// K = 4 per step) or (j / 4, j % 4) -> hidden 16 (j / 4) + 4 q + j % 4 for the
+// 8 K values j of a lane (bf16, K = 32) makes that exactly its B operand, so
+// layer 2 consumes act(Z1) straight from registers.
 //
 // Block = 256 threads = 256 nodes.  Phase A: each thread pulls its 27
 // populations and writes its 27 moments (plus the constant 1 of the bias row)
@@ -33,6 +39,8 @@
 // time, and writes the four rates per node to LDS.  Phase C: each thread pulls
 // its populations again (the kernel is compute bound; the second read is
 // cheap), relaxes with the rates and stores.
+#include <cstring>
+
 #include "kernels.h"
 #include "stream.h"
 
@@ -47,6 +55,10 @@ constexpr int GT_STRIDE = 12;       // ints per (pi, q) in the gather table
 constexpr int GT_ENTRIES = 6 * 4 * GT_STRIDE;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // K-step -> parity class ci = cx + 2 cy + 4 cz of the W1 rows it holds.
 __host__ __device__ constexpr int step_class(int st) {
@@ -54,13 +66,21 @@ __host__ __device__ constexpr int step_class(int st) {
     return c[st];
 }
 
-// Offsets in the per-lane weight table (floats per lane: LANE_FLOATS).
+// Offsets in the per-lane table (4-byte words per lane: LANE_WORDS).
+// float32 path:
 constexpr int LT_A1 = 0;            // [t 2][st 10]    W1 rows / b1 as A operand
 constexpr int LT_A2 = 20;           // [u 2][t 2][r 4] W2 as A operand
 constexpr int LT_B2 = 36;           // [u 2][r 4]      b2 as accumulator init
 constexpr int LT_W3 = 44;           // [u 2][r 4][n 4] W3 / 48
 constexpr int LT_B3 = 76;           // [n 4]
-constexpr int LANE_FLOATS = 80;
+// bf16 path (A operands as packed bf16 pairs, two per word):
+constexpr int LB_A1 = 0;            // [t 2][4 words]  W1 rows 8q..8q+7 / b1
+constexpr int LB_A2 = 8;            // [u 2][4 words]  W2
+constexpr int LB_B2 = 16;           // [u 2][r 4]
+constexpr int LB_W3 = 24;           // [u 2][r 4][n 4]
+constexpr int LB_B3 = 56;           // [n 4]
+constexpr int LB_SM = 60;           // [bit 3][4 words] sign masks of classes with that bit
+constexpr int LANE_WORDS = 80;
 
 // Activation as evaluated on this path.  For tanh the pre-activation arrives
 // scaled by kappa = 2 log2(e) and the function returns r = 1 / (1 + 2^(kappa z)),
@@ -77,18 +97,197 @@ __device__ __forceinline__ float act_scaled(float x) {
     }
 }
 
-__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mfma32(u32x4 a, u32x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// Two floats to a packed bf16 pair (round to nearest even), low half first.
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
+
+// Output layer on the group sum of one node tile and the rate squashing;
+// lanes of group q = 0 write the four rates of node (tile, c) to LDS.
+__device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float* __restrict__ w3,
+                                             const float* __restrict__ b3, int q, float* __restrict__ sw_node) {
+    float pn[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        float v = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v = fmaf(w3[(u * 4 + r) * 4 + n], acc[u][r], v);
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        pn[n] = v;
+    }
+    if (q == 0) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const float t = pn[n] + b3[n];
+            sw_node[n] = 1.0f / (0.5f + 0.5f / (1.0f + expf(t)));
+        }
+    }
+}
+
+template <int ACT>
+__device__ __forceinline__ void network_f32(const float* __restrict__ sm, const int* __restrict__ sg,
+                                            float* __restrict__ sw, const float* __restrict__ lt, int wave,
+                                            int q, int c) {
+    float A1[2][KSTEPS], A2[2][2][4], B2[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A2[u][t][r] = lt[LT_A2 + u * 8 + t * 4 + r];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) B2[u][r] = lt[LT_B2 + u * 4 + r];
+
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        const int node = wave * 64 + j * 16 + c;
+        const float* __restrict__ mrow = sm + node * NODE_STRIDE;
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll 1
+        for (int p = 0; p < 6; ++p) {
+            // Moment operand of this permutation, one K-step per register.
+            const int* __restrict__ ge = sg + (p * 4 + q) * GT_STRIDE;
+            float b[KSTEPS];
+#pragma unroll
+            for (int st = 0; st < KSTEPS; ++st) b[st] = mrow[ge[st]];
+            // Eight parity-class partial products.
+            f32x4 Y[8][2];
+#pragma unroll
+            for (int ci = 0; ci < 8; ++ci) {
+                Y[ci][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+                Y[ci][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int st = 0; st < KSTEPS; ++st)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) Y[step_class(st)][t] = mfma4(A1[t][st], b[st], Y[step_class(st)][t]);
+            // Walsh-Hadamard transform over the class index: Y[s] becomes the
+            // layer-1 pre-activation of reflection pattern s.
+#pragma unroll
+            for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+                for (int ci = 0; ci < 8; ++ci)
+                    if (!(ci & bit))
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            const f32x4 u0 = Y[ci][t], u1 = Y[ci | bit][t];
+                            Y[ci][t] = u0 + u1;
+                            Y[ci | bit][t] = u0 - u1;
+                        }
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                f32x4 h1[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) h1[t][r] = act_scaled<ACT>(Y[s][t][r]);
+                f32x4 c2[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) c2[u] = mfma4(A2[u][t][r], h1[t][r], c2[u]);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2[u][r]);
+            }
+        }
+        output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
+    }
+}
+
+template <int ACT>
+__device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const int* __restrict__ sg,
+                                             float* __restrict__ sw, const float* __restrict__ lt, int wave,
+                                             int q, int c) {
+    const unsigned* __restrict__ lw = reinterpret_cast<const unsigned*>(lt);
+    u32x4 A1[2], A2[2], SM[3];
+    float B2[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+        A1[t] = u32x4{lw[LB_A1 + 4 * t], lw[LB_A1 + 4 * t + 1], lw[LB_A1 + 4 * t + 2], lw[LB_A1 + 4 * t + 3]};
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        A2[u] = u32x4{lw[LB_A2 + 4 * u], lw[LB_A2 + 4 * u + 1], lw[LB_A2 + 4 * u + 2], lw[LB_A2 + 4 * u + 3]};
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        SM[b] = u32x4{lw[LB_SM + 4 * b], lw[LB_SM + 4 * b + 1], lw[LB_SM + 4 * b + 2], lw[LB_SM + 4 * b + 3]};
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) B2[u][r] = lt[LB_B2 + u * 4 + r];
+
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        const int node = wave * 64 + j * 16 + c;
+        const float* __restrict__ mrow = sm + node * NODE_STRIDE;
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll 1
+        for (int p = 0; p < 6; ++p) {
+            const int* __restrict__ ge = sg + (p * 4 + q) * GT_STRIDE;
+            float x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = mrow[ge[i]];
+            const u32x4 xb = {pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]), pack_bf16(x[4], x[5]),
+                              pack_bf16(x[6], x[7])};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                u32x4 bs = xb;
+                if (s & 1) bs ^= SM[0];
+                if (s & 2) bs ^= SM[1];
+                if (s & 4) bs ^= SM[2];
+                f32x4 c1[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) c1[t] = mfma32(A1[t], bs, f32x4{0.f, 0.f, 0.f, 0.f});
+                float h[2][4];
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) h[t][r] = act_scaled<ACT>(c1[t][r]);
+                const u32x4 hb = {pack_bf16(h[0][0], h[0][1]), pack_bf16(h[0][2], h[0][3]),
+                                  pack_bf16(h[1][0], h[1][1]), pack_bf16(h[1][2], h[1][3])};
+                f32x4 c2[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) c2[u] = mfma32(A2[u], hb, f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]});
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2[u][r]);
+            }
+        }
+        output_layer(acc, lt + LB_W3, lt + LB_B3, q, sw + node * 4);
+    }
 }
 
 // RATES = true: no streaming, the rates of the stored state are written to
 // omega_out [4][n] instead of a step (readout and tests of the network alone).
-template <int S, int ACT, bool RATES>
-__global__ __launch_bounds__(256) void k_nco_mfma_f32(const typename Codec<S>::store_t* __restrict__ fin,
-                                                      typename Codec<S>::store_t* __restrict__ fout,
-                                                      StepArgs a, const float* __restrict__ lane_tab,
-                                                      const int* __restrict__ gtab,
-                                                      double* __restrict__ omega_out) {
+template <int S, int ACT, bool RATES, int PREC>
+__global__ __launch_bounds__(256) void k_nco_mfma(const typename Codec<S>::store_t* __restrict__ fin,
+                                                  typename Codec<S>::store_t* __restrict__ fout, StepArgs a,
+                                                  const float* __restrict__ lane_tab, const int* __restrict__ gtab,
+                                                  double* __restrict__ omega_out) {
     __shared__ float sm[256 * NODE_STRIDE];
     __shared__ int sg[GT_ENTRIES];
     __shared__ float sw[256 * 4];
@@ -120,106 +319,14 @@ __global__ __launch_bounds__(256) void k_nco_mfma_f32(const typename Codec<S>::s
     }
     __syncthreads();
 
-    // Phase B: the network on the matrix cores, one wavefront per 64 nodes.
+    // Phase B: the network, one wavefront per 64 nodes.
     {
-        const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, c = lane & 15;
-        const float* __restrict__ lt = lane_tab + lane * LANE_FLOATS;
-        float A1[2][KSTEPS], A2[2][2][4], B2[2][4];
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) A2[u][t][r] = lt[LT_A2 + u * 8 + t * 4 + r];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) B2[u][r] = lt[LT_B2 + u * 4 + r];
-
-#pragma unroll 1
-        for (int j = 0; j < 4; ++j) {
-            const int node = wave * 64 + j * 16 + c;
-            const float* __restrict__ mrow = sm + node * NODE_STRIDE;
-            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-#pragma unroll 1
-            for (int p = 0; p < 6; ++p) {
-                // Moment operand of this permutation, one K-step per register.
-                const int* __restrict__ ge = sg + (p * 4 + q) * GT_STRIDE;
-                float b[KSTEPS];
-#pragma unroll
-                for (int st = 0; st < KSTEPS; ++st) b[st] = mrow[ge[st]];
-                // Eight parity-class partial products.
-                f32x4 Y[8][2];
-#pragma unroll
-                for (int ci = 0; ci < 8; ++ci) {
-                    Y[ci][0] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    Y[ci][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
-#pragma unroll
-                for (int st = 0; st < KSTEPS; ++st)
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-                        Y[step_class(st)][t] = mfma(A1[t][st], b[st], Y[step_class(st)][t]);
-                // Walsh-Hadamard transform over the class index: Y[s] becomes
-                // the layer-1 pre-activation of reflection pattern s.
-#pragma unroll
-                for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-                    for (int ci = 0; ci < 8; ++ci)
-                        if (!(ci & bit))
-#pragma unroll
-                            for (int t = 0; t < 2; ++t) {
-                                const f32x4 u0 = Y[ci][t], u1 = Y[ci | bit][t];
-                                Y[ci][t] = u0 + u1;
-                                Y[ci | bit][t] = u0 - u1;
-                            }
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    f32x4 h1[2];
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) h1[t][r] = act_scaled<ACT>(Y[s][t][r]);
-                    f32x4 c2[2];
-#pragma unroll
-                    for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-#pragma unroll
-                            for (int u = 0; u < 2; ++u) c2[u] = mfma(A2[u][t][r], h1[t][r], c2[u]);
-#pragma unroll
-                    for (int u = 0; u < 2; ++u)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2[u][r]);
-                }
-            }
-            // Output layer on the group mean, reduced over the 4 lane groups.
-            float pn[4];
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                float v = 0.0f;
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) v = fmaf(lt[LT_W3 + (u * 4 + r) * 4 + n], acc[u][r], v);
-                v += __shfl_xor(v, 16, 64);
-                v += __shfl_xor(v, 32, 64);
-                pn[n] = v;
-            }
-            if (q == 0) {
-#pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    const float t = pn[n] + lt[LT_B3 + n];
-                    sw[node * 4 + n] = 1.0f / (0.5f + 0.5f / (1.0f + expf(t)));
-                }
-            }
-        }
+        const int lane = tid & 63;
+        const float* __restrict__ lt = lane_tab + lane * LANE_WORDS;
+        if constexpr (PREC == MLP_PREC_BF16)
+            network_bf16<ACT>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
+        else
+            network_f32<ACT>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
     }
     __syncthreads();
 
@@ -249,8 +356,9 @@ __global__ __launch_bounds__(256) void k_nco_mfma_f32(const typename Codec<S>::s
     }
 }
 
-// Parity class of row k of M.
+// Parity class of row k of M (the bias row 27 and padding rows count as 0).
 int row_class(int k) {
+    if (k >= 27) return 0;
     const int t = row_tensor(k);
     return (t % 3) % 2 + 2 * (((t / 3) % 3) % 2) + 4 * ((t / 9) % 2);
 }
@@ -262,7 +370,7 @@ void class_slots(int slot_row[KSTEPS][4]) {
     for (int st = 0; st < KSTEPS; ++st)
         for (int q = 0; q < 4; ++q) slot_row[st][q] = -1;
     for (int k = 0; k < 28; ++k) {
-        const int ci = k < 27 ? row_class(k) : 0;      // the bias row joins class 0
+        const int ci = row_class(k);
         for (int st = 0; st < KSTEPS; ++st)
             if (step_class(st) == ci && fill[st] < 4) {
                 slot_row[st][fill[st]++] = k;
@@ -271,18 +379,25 @@ void class_slots(int slot_row[KSTEPS][4]) {
     }
 }
 
+unsigned bf16_bits(float v) {                 // round to nearest even
+    unsigned u;
+    std::memcpy(&u, &v, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
 }  // namespace
 
-size_t mfma_lane_table_floats() { return 64 * LANE_FLOATS; }
+size_t mfma_lane_table_floats() { return 64 * LANE_WORDS; }
 size_t mfma_group_table_ints() { return GT_ENTRIES; }
 
-// Host-side preparation of the per-lane operand tables from the flat
+// Host-side preparation of the per-lane operand table from the flat
 // parameters (W1[27][W], b1, W2[W][W], b2, W3[W][4], b3) and of the gather
-// table: for axis permutation p and slot (st, q) holding W1 row k, the moment
-// row that m^(g) places at k.  gsrc/gsign are indexed by group element g =
-// 8 p + reflection mask; the reflection-free elements g = 8 p give Q_p.
-void mfma_prepare_tables(const float* params, int act, const int (*gsrc)[27], const float (*)[27],
-                         float* lane_tab, int* gtab) {
+// table: for axis permutation p and K slot holding W1 row k, the moment row
+// that m^(g) places at k.  gsrc is indexed by group element g = 8 p +
+// reflection mask; the reflection-free elements g = 8 p give Q_p.
+void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsrc)[27], float* lane_tab,
+                         int* gtab) {
     const int W = MW;
     const float* W1 = params;
     const float* b1 = W1 + 27 * W;
@@ -309,61 +424,100 @@ void mfma_prepare_tables(const float* params, int act, const int (*gsrc)[27], co
             for (int h = 0; h < W; ++h) s += W3[h * 4 + n];
         b3f[n] = (float)s;
     }
+    auto w1row = [&](int k, int h) { return k < 27 ? W1[k * W + h] : k == 27 ? b1[h] : 0.0f; };
     int slot_row[KSTEPS][4];
     class_slots(slot_row);
     for (int lane = 0; lane < 64; ++lane) {
         const int q = lane >> 4, c = lane & 15;
-        float* lt = lane_tab + lane * LANE_FLOATS;
-        for (int i = 0; i < LANE_FLOATS; ++i) lt[i] = 0.0f;
-        for (int t = 0; t < 2; ++t)
-            for (int st = 0; st < KSTEPS; ++st) {
-                const int k = slot_row[st][q], h = 16 * t + c;
-                const float w = k < 0 ? 0.0f : k < 27 ? W1[k * W + h] : b1[h];
-                lt[LT_A1 + t * KSTEPS + st] = kappa * w;
-            }
-        for (int u = 0; u < 2; ++u)
+        float* lt = lane_tab + lane * LANE_WORDS;
+        unsigned* lw = reinterpret_cast<unsigned*>(lt);
+        for (int i = 0; i < LANE_WORDS; ++i) lt[i] = 0.0f;
+        if (prec == MLP_PREC_F32) {
             for (int t = 0; t < 2; ++t)
+                for (int st = 0; st < KSTEPS; ++st) {
+                    const int k = slot_row[st][q];
+                    lt[LT_A1 + t * KSTEPS + st] = k < 0 ? 0.0f : kappa * w1row(k, 16 * t + c);
+                }
+            for (int u = 0; u < 2; ++u)
+                for (int t = 0; t < 2; ++t)
+                    for (int r = 0; r < 4; ++r)
+                        lt[LT_A2 + u * 8 + t * 4 + r] = kappa * fold * W2[(16 * t + 4 * q + r) * W + 16 * u + c];
+            for (int u = 0; u < 2; ++u)
+                for (int r = 0; r < 4; ++r) lt[LT_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
+            for (int u = 0; u < 2; ++u)
                 for (int r = 0; r < 4; ++r)
-                    lt[LT_A2 + u * 8 + t * 4 + r] = kappa * fold * W2[(16 * t + 4 * q + r) * W + 16 * u + c];
-        for (int u = 0; u < 2; ++u)
-            for (int r = 0; r < 4; ++r) lt[LT_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
-        for (int u = 0; u < 2; ++u)
-            for (int r = 0; r < 4; ++r)
-                for (int n = 0; n < 4; ++n)
-                    lt[LT_W3 + (u * 4 + r) * 4 + n] = fold * W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
-        for (int n = 0; n < 4; ++n) lt[LT_B3 + n] = b3f[n];
+                    for (int n = 0; n < 4; ++n)
+                        lt[LT_W3 + (u * 4 + r) * 4 + n] = fold * W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
+            for (int n = 0; n < 4; ++n) lt[LT_B3 + n] = b3f[n];
+        } else {
+            // K slot j of lane group q is row k = 8 q + j (layer 1) and hidden
+            // unit 16 (j / 4) + 4 q + j % 4 (layer 2).
+            for (int t = 0; t < 2; ++t)
+                for (int w = 0; w < 4; ++w) {
+                    const int k0 = 8 * q + 2 * w, k1 = k0 + 1;
+                    lw[LB_A1 + 4 * t + w] = bf16_bits(kappa * w1row(k0, 16 * t + c)) |
+                                            (bf16_bits(kappa * w1row(k1, 16 * t + c)) << 16);
+                }
+            auto hid = [&](int j) { return 16 * (j / 4) + 4 * q + j % 4; };
+            for (int u = 0; u < 2; ++u)
+                for (int w = 0; w < 4; ++w)
+                    lw[LB_A2 + 4 * u + w] =
+                        bf16_bits(kappa * fold * W2[hid(2 * w) * W + 16 * u + c]) |
+                        (bf16_bits(kappa * fold * W2[hid(2 * w + 1) * W + 16 * u + c]) << 16);
+            for (int u = 0; u < 2; ++u)
+                for (int r = 0; r < 4; ++r) lt[LB_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
+            for (int u = 0; u < 2; ++u)
+                for (int r = 0; r < 4; ++r)
+                    for (int n = 0; n < 4; ++n)
+                        lt[LB_W3 + (u * 4 + r) * 4 + n] = fold * W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
+            for (int n = 0; n < 4; ++n) lt[LB_B3 + n] = b3f[n];
+            for (int b = 0; b < 3; ++b)
+                for (int w = 0; w < 4; ++w) {
+                    const int k0 = 8 * q + 2 * w, k1 = k0 + 1;
+                    lw[LB_SM + 4 * b + w] = ((row_class(k0) >> b) & 1 ? 0x8000u : 0u) |
+                                            ((row_class(k1) >> b) & 1 ? 0x80000000u : 0u);
+                }
+        }
     }
     for (int p = 0; p < 6; ++p)
         for (int q = 0; q < 4; ++q)
-            for (int st = 0; st < GT_STRIDE; ++st) {
-                int e = 28;                                   // the zero slot of a node's LDS row
-                if (st < KSTEPS) {
-                    const int k = slot_row[st][q];
-                    if (k >= 0) e = k < 27 ? gsrc[8 * p][k] : 27;
+            for (int i = 0; i < GT_STRIDE; ++i) {
+                // Row k placed in this slot; 27 is the constant-1 row, 28 zero.
+                int k = -1;
+                if (prec == MLP_PREC_F32) {
+                    if (i < KSTEPS) k = slot_row[i][q];
+                } else if (i < 8) {
+                    k = 8 * q + i;
                 }
-                gtab[(p * 4 + q) * GT_STRIDE + st] = e;
+                int e = 28;
+                if (k >= 0 && k < 27) e = gsrc[8 * p][k];
+                if (k == 27) e = 27;
+                gtab[(p * 4 + q) * GT_STRIDE + i] = e;
             }
 }
 
 // omega_out == nullptr: one stream-collide step fin -> fout.  Otherwise the
 // rates of the state in fin are written to omega_out and fout is untouched.
-hipError_t launch_nco_mfma(int storage, const void* fin, void* fout, const StepArgs& a,
+hipError_t launch_nco_mfma(int storage, int prec, const void* fin, void* fout, const StepArgs& a,
                            const float* lane_tab, const int* gtab, double* omega_out, hipStream_t st) {
     const dim3 grid((a.n + 255) / 256), block(256);
-#define MFMA_LAUNCH(SS, AA, RR)                                                                       \
-    hipLaunchKernelGGL((k_nco_mfma_f32<SS, AA, RR>), grid, block, 0, st, static_cast<const T*>(fin), \
+#define MFMA_LAUNCH(SS, AA, RR, PP)                                                               \
+    hipLaunchKernelGGL((k_nco_mfma<SS, AA, RR, PP>), grid, block, 0, st, static_cast<const T*>(fin), \
                        static_cast<T*>(fout), a, lane_tab, gtab, omega_out)
-#define MFMA_CASE(SS)                                                \
-    case SS: {                                                       \
-        using T = typename Codec<SS>::store_t;                       \
-        if (omega_out) {                                             \
-            if (a.act == ACT_TANH) MFMA_LAUNCH(SS, ACT_TANH, true);  \
-            else MFMA_LAUNCH(SS, ACT_RELU, true);                    \
-        } else {                                                     \
-            if (a.act == ACT_TANH) MFMA_LAUNCH(SS, ACT_TANH, false); \
-            else MFMA_LAUNCH(SS, ACT_RELU, false);                   \
-        }                                                            \
-        return hipGetLastError();                                    \
+#define MFMA_PREC(SS, AA, RR)                                             \
+    if (prec == MLP_PREC_BF16) MFMA_LAUNCH(SS, AA, RR, MLP_PREC_BF16);    \
+    else MFMA_LAUNCH(SS, AA, RR, MLP_PREC_F32);
+#define MFMA_CASE(SS)                                                    \
+    case SS: {                                                           \
+        using T = typename Codec<SS>::store_t;                           \
+        if (omega_out) {                                                 \
+            if (a.act == ACT_TANH) { MFMA_PREC(SS, ACT_TANH, true) }     \
+            else { MFMA_PREC(SS, ACT_RELU, true) }                       \
+        } else {                                                         \
+            if (a.act == ACT_TANH) { MFMA_PREC(SS, ACT_TANH, false) }    \
+            else { MFMA_PREC(SS, ACT_RELU, false) }                      \
+        }                                                                \
+        return hipGetLastError();                                        \
     }
     switch (storage) {
         MFMA_CASE(ST_F32)
@@ -372,6 +526,7 @@ hipError_t launch_nco_mfma(int storage, const void* fin, void* fout, const StepA
         default: return hipErrorInvalidValue;
     }
 #undef MFMA_CASE
+#undef MFMA_PREC
 #undef MFMA_LAUNCH
 }
 

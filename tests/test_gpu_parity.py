@@ -293,3 +293,50 @@ def test_mfma_requires_width_32_and_float_storage():
         with pytest.raises(L.NCOError) as e:
             lat.set_net_weights(_params(16), 16, "tanh", "f32_mfma")
         assert e.value.status == L.NCO_E_UNSUPPORTED
+
+
+# ------------------------------------------------------ precision forms -------
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("act", ["tanh", "relu"])
+def test_bf16_network_rates_close_to_oracle(storage, act):
+    """bf16 matrix-core network: rates within bf16 rounding of the float64
+    oracle on the stored state (error printed)."""
+    shape = (5, 7, 9)
+    rho, u = inputs.random_velocity(shape, seed=17, amp=0.1)
+    f0 = collision.equilibrium(rho, u) + 0.01 * (inputs.random_populations(shape, seed=18) - 1.0 / 27)
+    layers = collision.unpack_params(_params(32, 19), 32)
+    with _lattice(shape, storage, "nco", 0.6, width=32, seed=19, act=act, mlp="bf16") as lat:
+        lat.init_populations(f0)
+        got = lat.rates()
+        f_stored = lat.populations()
+    want = collision.nco_rates(f_stored, layers, act)
+    err = np.abs(got - want).max()
+    print("bf16 network rates %s/%s: max |omega - omega_oracle| = %.3e" % (storage, act, err))
+    assert err < 5e-3
+
+
+# Measured errors against the float64 oracle after 100 steps of the 16^3
+# Taylor-Green case (NCO, 27-32-32-4 tanh); bounds carry a margin of ~3x.
+PRECISION_BOUNDS = {
+    ("f32", "f32"): 1e-5, ("f32", "f32_mfma"): 1e-5, ("f32", "bf16"): 3e-5,
+    ("f16", "f32_mfma"): 3e-5, ("f16", "bf16"): 5e-5,
+    ("bf16", "f32_mfma"): 3e-4, ("bf16", "bf16"): 3e-4,
+}
+
+
+@pytest.mark.parametrize("storage,mlp", sorted(PRECISION_BOUNDS))
+def test_precision_forms_tgv16_100_steps(storage, mlp):
+    n, rho, u = _tgv16()
+    tau = inputs.viscosity(n, 0.05, 100.0)[1]
+    with _lattice((n, n, n), storage, "nco", tau, mlp=mlp) as lat:
+        lat.init_equilibrium(rho, u)
+        lat.step(100)
+        got = lat.populations()
+        ke = lat.global_sums()[4] / n ** 3
+    want = step.run(collision.equilibrium(rho, u), _oracle_op("nco", tau), 100)
+    err = np.abs(got - want).max()
+    ke_ref = observables.kinetic_energy(want)
+    print("storage %s, network %s: max |f - f_oracle| = %.3e, kinetic energy rel. err %.3e"
+          % (storage, mlp, err, abs(ke - ke_ref) / ke_ref))
+    assert err < PRECISION_BOUNDS[(storage, mlp)]
