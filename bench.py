@@ -32,6 +32,23 @@ METRIC = "NCO stream-collide GLUPS & % HBM peak, FP32 vs low-precision; p99 solv
 TRAFFIC_BYTES = {"bgk": 228.0e6 + 226.5e6}
 
 
+# Timed variants: name -> (operator, population storage, network arithmetic,
+# activation).  "nco" is the headline (float32 storage and network).
+VARIANTS = {
+    "nco": ("nco", "f32", "f32_mfma", "tanh"),
+    "nco_bf16net": ("nco", "f32", "bf16", "tanh"),
+    "nco_f16store_bf16net": ("nco", "f16", "bf16", "tanh"),
+    "nco_bf16store_bf16net": ("nco", "bf16", "bf16", "tanh"),
+    "nco_relu_bf16net": ("nco", "f32", "bf16", "relu"),
+    "nco_valu": ("nco", "f32", "f32", "tanh"),
+    "bgk": ("bgk", "f32", None, None),
+    "bgk_f16store": ("bgk", "f16", None, None),
+    "bgk_bf16store": ("bgk", "bf16", None, None),
+    "mrt": ("mrt", "f32", None, None),
+    "mrt_f16store": ("mrt", "f16", None, None),
+}
+
+
 def nco_flops_per_node(width):
     """Multiply-adds of the group-averaged network, counted as 2 flops each:
     48 x (27 W + W^2) for the two hidden layers of every group element plus
@@ -90,7 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--ops", default="nco,nco_valu,bgk,mrt")
+    ap.add_argument("--ops", default=",".join(VARIANTS))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the lattice path runs on a single MI355X; "
@@ -113,27 +130,28 @@ def main():
     nodes = n ** 3
     results = {}
     for op in args.ops.split(","):
-        kind = "nco" if op.startswith("nco") else op
-        lat = Lattice((n, n, n), "f32", kind, tau, stream=stream)
-        if op == "nco":
-            lat.set_net_weights(params, width, "tanh", "f32_mfma")
-        if op == "nco_valu":
-            lat.set_net_weights(params, width, "tanh", "f32")
-        if op == "mrt":
+        kind, storage, mlp, act = VARIANTS[op]
+        lat = Lattice((n, n, n), storage, kind, tau, stream=stream)
+        if kind == "nco":
+            lat.set_net_weights(params, width, act, mlp)
+        if kind == "mrt":
             lat.set_rates([4.0 / 3.0] * 4)
         lat.init_equilibrium(rho, u)
         # The per-node vector-unit network is kept as a reference variant; it
         # is two orders slower, so it is timed on fewer steps.
-        steps = min(args.steps, 10) if op == "nco_valu" else args.steps
-        ms = time_op(lat, steps, min(args.warmup, 2) if op == "nco_valu" else args.warmup, torch, tstream)
+        slow = kind == "nco" and mlp == "f32"
+        steps = min(args.steps, 10) if slow else args.steps
+        ms = time_op(lat, steps, min(args.warmup, 2) if slow else args.warmup, torch, tstream)
         s = lat.global_sums()
         if not np.all(np.isfinite(s)):
             raise RuntimeError("non-finite state after the %s run" % op)
         lat.close()
         glups = nodes / (ms * 1e-3) / 1e9
-        gbs = bytes_per_node("f32") * nodes / (ms * 1e-3) / 1e9
+        gbs = bytes_per_node(storage) * nodes / (ms * 1e-3) / 1e9
         results[op] = {"ms_per_step": ms, "glups": glups, "hbm_gbs": gbs,
-                       "hbm_frac": gbs / HBM_PEAK_GBS, "steps": steps}
+                       "hbm_frac": gbs / HBM_PEAK_GBS, "steps": steps, "storage": storage,
+                       "network": mlp if kind == "nco" else None,
+                       "activation": act if kind == "nco" else None}
         print("# %s: %.4f ms/step, %.3f GLUPS, %.0f GB/s" % (op, ms, glups, gbs), file=sys.stderr,
               flush=True)
 
