@@ -1,0 +1,134 @@
+"""Pins of the oracle's hand-written reverse mode against central finite
+differences of the (separately pinned) forward oracle, in float64."""
+import numpy as np
+import pytest
+
+from oracle import adjoint, collision, observables, step
+from paper_2412_08229_amd import inputs
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _layers(width=8, seed=0):
+    return collision.unpack_params(inputs.mlp_params(width, seed), width)
+
+
+def _perturb(layers, v, h):
+    out, pos = [], 0
+    for W, b in layers:
+        dW = v[pos:pos + W.size].reshape(W.shape)
+        pos += W.size
+        db = v[pos:pos + b.size]
+        pos += b.size
+        out.append((W + h * dW, b + h * db))
+    return out
+
+
+def test_equilibrium_vjp_matches_finite_differences():
+    rng = _rng(1)
+    f = inputs.random_populations((5,), seed=2)
+    v = rng.standard_normal((27, 5))
+    d = rng.standard_normal((27, 5))
+    rho = f.sum(0)
+    j = adjoint._C.T @ f
+
+    def feq(g):
+        r, u = collision.macroscopic(g)
+        return collision.equilibrium(r, u)
+    h = 1e-6
+    fd = ((feq(f + h * d) - feq(f - h * d)) / (2 * h) * v).sum()
+    an = (adjoint.equilibrium_vjp(rho, j, v) * d).sum()
+    assert abs(fd - an) < 1e-8 * max(1.0, abs(an))
+
+
+@pytest.mark.parametrize("act", ["tanh", "relu"])
+@pytest.mark.parametrize("forced", [False, True])
+def test_collision_vjp_matches_finite_differences(act, forced):
+    rng = _rng(3)
+    f = inputs.random_populations((6,), seed=4, lo=0.8, hi=1.2)
+    lam = rng.standard_normal((27, 6))
+    layers = _layers(8, 5)
+    force = 1e-3 * rng.standard_normal((3, 6)) if forced else None
+    tau = 0.56
+
+    def post(g, lay):
+        out = collision.nco(g, tau, lay, act)
+        if forced:
+            out = out + collision.kupershtokh_source(g, force)
+        return out
+    g_f, g_p = adjoint.nco_collide_vjp(f, lam, tau, layers, act, force)
+    # ReLU is piecewise linear: a pre-activation lies 7e-6 from its kink
+    # here, so the step must stay below that.
+    h, tol = (1e-6, 1e-7) if act == "tanh" else (1e-8, 1e-6)
+    d = rng.standard_normal((27, 6))
+    fd = ((post(f + h * d, layers) - post(f - h * d, layers)) / (2 * h) * lam).sum()
+    assert abs(fd - (g_f * d).sum()) < tol * max(1.0, abs(fd))
+    v = rng.standard_normal(collision.n_params(8))
+    fd = ((post(f, _perturb(layers, v, h)) - post(f, _perturb(layers, v, -h))) / (2 * h) * lam).sum()
+    an = adjoint.flatten(g_p) @ v
+    assert abs(fd - an) < tol * max(1.0, abs(an))
+
+
+def test_spectrum_vjp_matches_finite_differences():
+    rng = _rng(6)
+    n = 6
+    rho, u = inputs.random_velocity((n, n, n), seed=7)
+    f = collision.equilibrium(rho, u)
+    dE = rng.standard_normal(observables.n_bins(n))
+    d = 1e-3 * rng.standard_normal(f.shape)
+    h = 1e-6
+    fd = ((observables.spectrum(f + h * d) - observables.spectrum(f - h * d)) / (2 * h) * dE).sum()
+    an = (adjoint.spectrum_vjp(f, dE) * d).sum()
+    assert abs(fd - an) < 1e-8 * max(abs(an), 1e-12)
+
+
+def test_unrolled_gradient_matches_finite_differences():
+    """Loss on log E(k) after 4 forced NCO steps on 6^3: gradient with respect
+    to the network parameters and to the initial populations."""
+    n, width, tau, T = 6, 8, 0.55, 4
+    rng = _rng(8)
+    layers = _layers(width, 9)
+    _, u = inputs.turbulence(n, seed=10, k0=2.0, urms=0.05)
+    f0 = collision.equilibrium(np.ones((n, n, n)), u)
+    Et = observables.spectrum(f0) * 0.8 + 1e-9
+    forces = [1e-4 * rng.standard_normal((3, n, n, n)) for _ in range(T)]
+
+    def loss_grad(x):
+        L, dE = adjoint.log_spectrum_loss(observables.spectrum(x), Et, 1, 3)
+        return L, adjoint.spectrum_vjp(x, dE)
+
+    def loss(lay, g0):
+        op = step.Operator("nco", tau, layers=lay, act="tanh")
+        return loss_grad(step.run(g0, op, T, forces=lambda t: forces[t]))[0]
+    L, gp, gf0 = adjoint.run_and_grad(f0, tau, layers, "tanh", T, loss_grad, forces=lambda t: forces[t])
+    assert abs(L - loss(layers, f0)) < 1e-14
+    h = 1e-6
+    v = rng.standard_normal(collision.n_params(width))
+    fd = (loss(_perturb(layers, v, h), f0) - loss(_perturb(layers, v, -h), f0)) / (2 * h)
+    an = adjoint.flatten(gp) @ v
+    assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12), (fd, an)
+    d = 1e-3 * rng.standard_normal(f0.shape)
+    fd = (loss(layers, f0 + h * d) - loss(layers, f0 - h * d)) / (2 * h)
+    an = (gf0 * d).sum()
+    assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12), (fd, an)
+
+
+def test_adjoint_negative_control():
+    """A wrong streaming transpose (pull instead of push) breaks the check."""
+    n, width, tau, T = 4, 8, 0.55, 2
+    layers = _layers(width, 11)
+    f0 = inputs.random_populations((n, n, n), seed=12, lo=0.9, hi=1.1)
+    w = _rng(13).standard_normal(f0.shape)
+
+    def loss_grad(x):
+        return float((w * x).sum()), w
+    _, _, good = adjoint.run_and_grad(f0, tau, layers, "tanh", T, loss_grad)
+    saved = step.unstream
+    try:
+        step.unstream = step.stream
+        _, _, bad = adjoint.run_and_grad(f0, tau, layers, "tanh", T, loss_grad)
+    finally:
+        step.unstream = saved
+    assert np.abs(good - bad).max() > 1e-3
