@@ -142,6 +142,37 @@ int nco_energy_spectrum(nco_lattice* lat, double* E, int nbins);
  * bytes; valid until the next step or destroy. */
 int nco_device_populations(nco_lattice* lat, void** dev_ptr, size_t* bytes);
 
+/* Alvelius spectral forcing (Sec. "Training Data - Forced Isotropic
+ * Turbulence"), applied through the Kupershtokh exact-difference source
+ * (Sec. II.A) in every following step.  k: n_modes integer wavevectors
+ * (3 ints each, one of each +-k pair); the force is
+ * F(x) = sum_m 2 Re(F_hat_m exp(i k_m . x)), x = 2 pi (node / extent), with
+ * F_hat = A_ran e1 + B_ran e2, A_ran, B_ran = sqrt(F(|k|) / (2 pi |k|^2))
+ * exp(i theta1, i (theta1 + psi)) (sin 2 phi, cos 2 phi),
+ * F(|k|) = amplitude exp(-(|k| - kf)^2 / c), e1 the unit normal of k in the
+ * x-y plane and e2 = (k_x k_z, k_y k_z, -(k_x^2 + k_y^2)) / (|k| sqrt(k_x^2 + k_y^2))
+ * ((1,0,0) and (0,1,0) when k_x = k_y = 0).  draws: [n_steps][n_modes][3]
+ * uniform numbers in [0, 1) giving phi / pi, psi / 2 pi and theta1 / 2 pi;
+ * the t-th step after this call uses draws[t mod n_steps].  n_modes = 0
+ * switches forcing off. */
+int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
+                    double amplitude, double kf, double c);
+
+/* Run nsteps steps (NCO operator, width 32, float storage) keeping a
+ * checkpoint of the state every ckpt_every steps in device memory, for a
+ * following nco_backward (the gradient of Adam in Sec. "Learning Task"). */
+int nco_forward_record(nco_lattice* lat, int nsteps, int ckpt_every);
+
+/* Reverse mode through the recorded run (no step may come in between).  The
+ * loss gradient at the final state is dL_dE (nbins values: dL/dE(k) of the
+ * spectrum defined by nco_energy_spectrum, or NULL) plus dL_df (27N values,
+ * or NULL).  Writes grad (n_params = 2084 values, the parameter order of
+ * nco_set_net_weights) in float64 and, if dL_df0 is not NULL, dL/d(initial
+ * populations) (27N values).  Segments are recomputed from their checkpoints;
+ * the result is deterministic (fixed-order reductions). */
+int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double* dL_df, double* grad,
+                 size_t n_params, double* dL_df0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,70 @@
+"""Alvelius spectral forcing (Sec. "Training Data - Forced Isotropic
+Turbulence"), in float64.
+
+Test infrastructure (see ``oracle/__init__``): never used by the product path.
+
+For a wavevector k with |k| = kk the force coefficient is
+    F_hat(k) = A_ran e1(k) + B_ran e2(k),
+    A_ran = (F(kk) / (2 pi kk^2))^(1/2) exp(i theta1) g_A(phi),
+    B_ran = (F(kk) / (2 pi kk^2))^(1/2) exp(i theta2) g_B(phi),
+    g_A = sin 2 phi, g_B = cos 2 phi, theta2 = theta1 + psi,
+    F(kk) = amplitude exp(-(kk - k_f)^2 / c),
+with phi uniform in [0, pi), psi and theta1 uniform in [0, 2 pi).
+
+Readings: the printed e1 = (k_x k_y, -k_x k_y, 0)/sqrt(k_x^2 + k_y^2) is not
+normal to k; the unit vector normal to k in the x-y plane,
+e1 = (k_y, -k_x, 0)/sqrt(k_x^2 + k_y^2), is used, with e2 as printed; for
+k_x = k_y = 0, e1 = (1, 0, 0) and e2 = (0, 1, 0).  theta1 is drawn from the
+random numbers like phi and psi instead of the velocity-dependent rule, so
+the force is a known function of time.  The amplitude A of F(kk) is given
+directly (lattice units) instead of through the power input.  The force
+field is real: one wavevector of each +-k pair carries F_hat and
+F(x) = sum 2 Re(F_hat(k) exp(i k.x)), x in [0, 2 pi)^3.
+"""
+import numpy as np
+
+
+def basis(k):
+    """(e1, e2) for an integer wavevector k = (kx, ky, kz)."""
+    kx, ky, kz = (float(v) for v in k)
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    kp = np.sqrt(kx * kx + ky * ky)
+    if kp == 0.0:
+        return np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    e1 = np.array([ky, -kx, 0.0]) / kp
+    e2 = np.array([kx * kz / kk, ky * kz / kk, -kp * kp / kk]) / kp
+    return e1, e2
+
+
+def coefficients(ks, draws, amplitude, kf, c):
+    """F_hat for every step and mode: ks (n_modes, 3) integers, draws
+    (n_steps, n_modes, 3) uniform in [0, 1) as (phi, psi, theta1) / range.
+    Returns complex (n_steps, n_modes, 3)."""
+    ks = np.asarray(ks)
+    draws = np.asarray(draws, dtype=np.float64)
+    out = np.zeros(draws.shape[:2] + (3,), dtype=np.complex128)
+    for mi, k in enumerate(ks):
+        kk = np.sqrt(float((k * k).sum()))
+        e1, e2 = basis(k)
+        Fk = amplitude * np.exp(-(kk - kf) ** 2 / c)
+        mag = np.sqrt(Fk / (2.0 * np.pi * kk * kk))
+        phi = np.pi * draws[:, mi, 0]
+        psi = 2.0 * np.pi * draws[:, mi, 1]
+        th1 = 2.0 * np.pi * draws[:, mi, 2]
+        A = mag * np.exp(1j * th1) * np.sin(2.0 * phi)
+        B = mag * np.exp(1j * (th1 + psi)) * np.cos(2.0 * phi)
+        out[:, mi, :] = A[:, None] * e1[None, :] + B[:, None] * e2[None, :]
+    return out
+
+
+def field(ks, fhat, shape):
+    """Real force field (3, nz, ny, nx) of one step from its coefficients."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    F = np.zeros((3,) + tuple(shape))
+    for k, fh in zip(np.asarray(ks), fhat):
+        th = 2.0 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz)
+        e = np.exp(1j * th)
+        for a in range(3):
+            F[a] += 2.0 * np.real(fh[a] * e)
+    return F

@@ -51,6 +51,10 @@ SIGNATURES = {
     "nco_global_sums": (_I, [_P, _D]),
     "nco_energy_spectrum": (_I, [_P, _D, _I]),
     "nco_device_populations": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
+    "nco_set_forcing": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), _D, _I, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double]),
+    "nco_forward_record": (_I, [_P, _I, _I]),
+    "nco_backward": (_I, [_P, _D, _I, _D, _D, _SZ, _D]),
 }
 
 
@@ -185,6 +189,34 @@ def nco_energy_spectrum(h, nbins):
     out = np.empty(nbins)
     check(lib().nco_energy_spectrum(h, dptr(out), nbins))
     return out
+
+
+def nco_set_forcing(h, k, draws, amplitude, kf, c):
+    if k is None or len(k) == 0:
+        check(lib().nco_set_forcing(h, 0, None, None, 0, 0.0, 0.0, 1.0))
+        return
+    kk = np.ascontiguousarray(k, dtype=np.int32)
+    d = np.ascontiguousarray(draws, dtype=np.float64)
+    n_modes = kk.shape[0]
+    if d.ndim != 3 or d.shape[1] != n_modes or d.shape[2] != 3:
+        raise ValueError("draws must have shape (n_steps, n_modes, 3)")
+    check(lib().nco_set_forcing(h, n_modes, kk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dptr(d),
+                                d.shape[0], amplitude, kf, c))
+
+
+def nco_forward_record(h, nsteps, ckpt_every):
+    check(lib().nco_forward_record(h, nsteps, ckpt_every))
+
+
+def nco_backward(h, n, n_params, dL_dE=None, dL_df=None, want_df0=False):
+    grad = np.empty(n_params)
+    e = None if dL_dE is None else as_f64(dL_dE)
+    df = None if dL_df is None else as_f64(dL_df, 27 * n)
+    df0 = np.empty(27 * n) if want_df0 else None
+    check(lib().nco_backward(h, None if e is None else dptr(e), 0 if e is None else e.size,
+                             None if df is None else dptr(df), dptr(grad), n_params,
+                             None if df0 is None else dptr(df0)))
+    return grad, df0
 
 
 def nco_device_populations(h):

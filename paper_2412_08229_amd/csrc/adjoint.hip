@@ -1,0 +1,492 @@
+// Adjoint (reverse mode) of one stream-collide step with the NCO collision.
+//
+// The forward step is y = stream(x_t) (pull), x_t+1 = y - M^{-1} dm(y; theta)
+// with dm = S (m - m^eq) - dm_source (Eq. omegatheta, Kupershtokh source of
+// Sec. II.A).  Given lambda = dL/dx_t+1 at every node, this kernel computes,
+// per node, the pre-collision adjoint
+//     lambda_y = lambda + M^T g_m,   g_m = (d dm / d m)^T nu,  nu = -M^{-T} lambda,
+// including the path through the rates omega_n(theta, m) of the invariant
+// network (Eq. gconv_m and the sigmoid squashing), and scatters it back along
+// the streaming direction: dL/dx_t,i(x - c_i) = lambda_y,i(x).  The network
+// is re-evaluated per node and group element (no activations are stored);
+// its parameter gradient
+//     dL/dW1 = sum_(nodes, g) x_g dz1^T, dL/dW2 = sum h1 dz2^T, ...
+// is reduced over the 64 nodes of a block in LDS, each lane owning a fixed
+// block of gradient entries, and written as one partial per block; a second
+// kernel adds the partials in a fixed order (deterministic, no atomics).
+#include "kernels.h"
+#include "stream.h"
+
+namespace nco {
+
+namespace {
+
+constexpr int AW = 32;                    // network width of the adjoint path
+constexpr int NPAR = AW * (27 + AW + 4) + 2 * AW + 4;
+constexpr int OFF_W1 = 0, OFF_B1 = 27 * AW, OFF_W2 = OFF_B1 + AW, OFF_B2 = OFF_W2 + AW * AW;
+constexpr int OFF_W3 = OFF_B2 + AW, OFF_B3 = OFF_W3 + 4 * AW;
+
+// One-dimensional pieces of M^T (transpose of fwd3) and M^{-T} (transpose
+// of inv3), applied along each axis like the transforms themselves.
+template <typename R>
+__device__ __forceinline__ void fwd3_t(R g0, R g1, R g2, R& fm, R& f0, R& fp) {
+    const R s3 = Sqrt3<R>::v;
+    fm = g0 - s3 * g1 + R(2) * g2;
+    f0 = g0 - g2;
+    fp = g0 + s3 * g1 + R(2) * g2;
+}
+
+template <typename R>
+__device__ __forceinline__ void inv3_t(R lm, R l0, R lp, R& a0, R& a1, R& a2) {
+    const R s3 = Sqrt3<R>::v;
+    a0 = (lm + R(4) * l0 + lp) * R(1.0 / 6.0);
+    a1 = s3 * (lp - lm) * R(1.0 / 6.0);
+    a2 = (lm - R(2) * l0 + lp) * R(1.0 / 6.0);
+}
+
+// out = M^T g (g in tensor moment order, out in velocity order).
+template <typename R>
+__device__ __forceinline__ void moments_T(const R (&g)[Q], R (&out)[Q]) {
+    R s[Q], t[Q];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) fwd3_t(g[p], g[9 + p], g[18 + p], s[p], s[9 + p], s[18 + p]);
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+            fwd3_t(s[9 * z + n], s[9 * z + 3 + n], s[9 * z + 6 + n], t[9 * z + n], t[9 * z + 3 + n],
+                   t[9 * z + 6 + n]);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) fwd3_t(t[3 * r], t[3 * r + 1], t[3 * r + 2], out[3 * r], out[3 * r + 1], out[3 * r + 2]);
+}
+
+// mu = M^{-T} lam (lam in velocity order, mu in tensor moment order).
+template <typename R>
+__device__ __forceinline__ void inverse_T(const R (&lam)[Q], R (&mu)[Q]) {
+    R t[Q], s[Q];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) inv3_t(lam[3 * r], lam[3 * r + 1], lam[3 * r + 2], t[3 * r], t[3 * r + 1], t[3 * r + 2]);
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+            inv3_t(t[9 * z + n], t[9 * z + 3 + n], t[9 * z + 6 + n], s[9 * z + n], s[9 * z + 3 + n],
+                   s[9 * z + 6 + n]);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) inv3_t(s[p], s[9 + p], s[18 + p], mu[p], mu[9 + p], mu[18 + p]);
+}
+
+template <int ACT>
+__device__ __forceinline__ float act_f(float z) {
+    return ACT == ACT_RELU ? fmaxf(z, 0.0f) : tanhf(z);
+}
+// Derivative from the activation's output.
+template <int ACT>
+__device__ __forceinline__ float act_d(float h) {
+    return ACT == ACT_RELU ? (h > 0.0f ? 1.0f : 0.0f) : 1.0f - h * h;
+}
+
+// Index of the two first-order factors of a second-order tensor index t
+// (moment m_a m_b / rho): a, b in {0, 1, 2} as tensor indices 1, 3, 9.
+__device__ __forceinline__ void pair_of(int t, int& ta, int& tb) {
+    const int nx = t % 3, ny = (t / 3) % 3, nz = t / 9;
+    const int idx[3] = {1, 3, 9};
+    int k = 0, ab[2];
+    for (int r = 0; r < 3; ++r) {
+        const int n = r == 0 ? nx : r == 1 ? ny : nz;
+        for (int c = 0; c < n; ++c) ab[k++] = idx[r];
+    }
+    ta = ab[0];
+    tb = ab[1];
+}
+
+template <int S, int ACT>
+__global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t* __restrict__ xin,
+                                                const float* __restrict__ lam_in, float* __restrict__ lam_out,
+                                                StepArgs a, const int* __restrict__ gsrc,
+                                                float* __restrict__ partial) {
+    constexpr int W = AW;
+    // Network (unstacked W1 [27][W], b1, W2 [W][W], b2, W3 [W][4], b3), read
+    // by every lane with the same address (LDS broadcast).
+    __shared__ float s_w1[27 * W], s_b1[W], s_w2[W * W], s_b2[W], s_w3[W * 4], s_b3[4];
+    // Per-node rows: moments (paper order, [27] = 1), dL/dm, and the vectors
+    // of the current group element for the parameter-gradient reduction.
+    __shared__ float s_m[64][28];
+    __shared__ float s_dm[64][28];
+    __shared__ float s_h1[64][W];
+    __shared__ float s_d1[64][W];
+    __shared__ float s_d2[64][W];
+    const int lane = threadIdx.x;
+    const int idx = blockIdx.x * 64 + lane;
+    const bool live = idx < a.n;
+    {
+        // Unstacked W1 is the identity element's slice (g = 0, no permutation).
+        const float* __restrict__ net = a.net;
+        for (int e = lane; e < 27 * W; e += 64) s_w1[e] = net[e];
+        for (int e = lane; e < W * W; e += 64) s_w2[e] = net[net_off_w2(W) + e];
+        for (int e = lane; e < W * 4; e += 64) s_w3[e] = net[net_off_w3(W) + e];
+        if (lane < W) {
+            s_b1[lane] = net[net_off_b1(W) + lane];
+            s_b2[lane] = net[net_off_b2(W) + lane];
+        }
+        if (lane < 4) s_b3[lane] = net[net_off_b3(W) + lane];
+    }
+
+    // Forward quantities of the node: pulled populations and moments.
+    float m[Q];
+    const NodeIdx p = node_of(live ? idx : 0, a.nx, a.ny);
+    {
+        float f[Q];
+        if (live) {
+            pull<S>(xin, a, p, f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[i] = (float)weight_of(i);
+        }
+        to_moments(f, m);
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        s_m[lane][k] = m[row_tensor(k)];
+        s_dm[lane][k] = 0.0f;
+    }
+    s_m[lane][27] = 1.0f;
+    __syncthreads();
+
+    // Pass 1: network forward for the rates; sum over g of act(z2).
+    float S2[W];
+#pragma unroll
+    for (int o = 0; o < W; ++o) S2[o] = 0.0f;
+#pragma unroll 1
+    for (int g = 0; g < NGROUP; ++g) {
+        const int* __restrict__ gs = gsrc + g * 27;
+        float h[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) h[j] = s_b1[j];
+#pragma unroll 3
+        for (int k = 0; k < Q; ++k) {
+            const int e = gs[k];
+            const float xk = __int_as_float(__float_as_int(s_m[lane][e & 31]) ^ (e & (int)0x80000000));
+#pragma unroll
+            for (int j = 0; j < W; ++j) h[j] = fmaf(s_w1[k * W + j], xk, h[j]);
+        }
+        float z[W];
+#pragma unroll
+        for (int o = 0; o < W; ++o) z[o] = s_b2[o];
+#pragma unroll 4
+        for (int j = 0; j < W; ++j) {
+            const float hj = act_f<ACT>(h[j]);
+#pragma unroll
+            for (int o = 0; o < W; ++o) z[o] = fmaf(s_w2[j * W + o], hj, z[o]);
+        }
+#pragma unroll
+        for (int o = 0; o < W; ++o) S2[o] += act_f<ACT>(z[o]);
+    }
+    float tt[4], omega[4], tau[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        float t = 0.0f;
+#pragma unroll
+        for (int o = 0; o < W; ++o) t = fmaf(s_w3[o * 4 + n], S2[o], t);
+        tt[n] = t * (1.0f / NGROUP) + s_b3[n];
+        tau[n] = 0.5f + 0.5f / (1.0f + expf(tt[n]));
+        omega[n] = 1.0f / tau[n];
+    }
+
+    // Adjoint of dm: nu = dL/d(dm) = -M^{-T} lambda.
+    float lam[Q], nu[Q];
+    if (live) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[i] = lam_in[(size_t)i * a.n + idx];
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[i] = 0.0f;
+    }
+    inverse_T(lam, nu);
+    const float wnu = a.omega_nu_f;
+    const float inv_rho = 1.0f / m[0];
+    float gm[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) gm[t] = 0.0f;
+    float domega[4] = {0.f, 0.f, 0.f, 0.f};
+    double Fd[3] = {0.0, 0.0, 0.0};
+    if (a.n_modes > 0 && live) force_at(a, p.x, p.y, p.z, Fd[0], Fd[1], Fd[2]);
+    const float F[3] = {(float)Fd[0], (float)Fd[1], (float)Fd[2]};
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+        const int n = order_of(t);
+        const float v = -nu[t];
+        if (n == 2) {
+            int ta, tb;
+            pair_of(t, ta, tb);
+            // dm_t = w_nu (m_t - m_a m_b / rho) - (sqrt3 (m_a F_b + m_b F_a) + 3 F_a F_b) / rho
+            const int a_ = ta == 1 ? 0 : ta == 3 ? 1 : 2, b_ = tb == 1 ? 0 : tb == 3 ? 1 : 2;
+            gm[t] += v * wnu;
+            gm[ta] -= v * wnu * m[tb] * inv_rho;
+            gm[tb] -= v * wnu * m[ta] * inv_rho;
+            gm[0] += v * wnu * m[ta] * m[tb] * inv_rho * inv_rho;
+            if (a.n_modes > 0) {
+                const float s3 = 1.7320508075688772f;
+                const float src = (s3 * (m[ta] * F[b_] + m[tb] * F[a_]) + 3.0f * F[a_] * F[b_]) * inv_rho;
+                gm[ta] -= v * s3 * F[b_] * inv_rho;
+                gm[tb] -= v * s3 * F[a_] * inv_rho;
+                gm[0] += v * src * inv_rho;
+            }
+        } else if (n >= 3) {
+            gm[t] += v * omega[n - 3];
+            domega[n - 3] += v * m[t];
+        }
+    }
+    // Through the squashing: omega = 1 / tau, tau = 1/2 + 1/(2 (1 + e^t)).
+    float dtt[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const float e = expf(tt[n]);
+        dtt[n] = domega[n] * 0.5f * e / ((1.0f + e) * (1.0f + e) * tau[n] * tau[n]);
+    }
+    // The output layer's adjoint is the same for every group element.
+    float dh2[W];
+#pragma unroll
+    for (int o = 0; o < W; ++o) {
+        float s = 0.0f;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) s = fmaf(s_w3[o * 4 + n], dtt[n], s);
+        dh2[o] = s * (1.0f / NGROUP);
+    }
+
+    // Gradient accumulators owned by this lane.
+    const int r1 = 7 * (lane >> 4), c1 = 2 * (lane & 15);        // W1 rows r1..r1+6 (27 = b1), cols c1, c1+1
+    const int r2 = 4 * (lane >> 3), c2 = 4 * (lane & 7);         // W2 rows r2..r2+3, cols c2..c2+3
+    float acc1[7][2], acc2[4][4], accb2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc1[i][0] = acc1[i][1] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc2[i][j] = 0.0f;
+
+    // Pass 2: per group element, recompute, back-propagate, reduce.
+#pragma unroll 1
+    for (int g = 0; g < NGROUP; ++g) {
+        const int* __restrict__ gs = gsrc + g * 27;
+        float h1[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) h1[j] = s_b1[j];
+#pragma unroll 3
+        for (int k = 0; k < Q; ++k) {
+            const int e = gs[k];
+            const float xk = __int_as_float(__float_as_int(s_m[lane][e & 31]) ^ (e & (int)0x80000000));
+#pragma unroll
+            for (int j = 0; j < W; ++j) h1[j] = fmaf(s_w1[k * W + j], xk, h1[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            h1[j] = act_f<ACT>(h1[j]);
+            s_h1[lane][j] = h1[j];
+        }
+        float dz2[W];
+#pragma unroll
+        for (int o = 0; o < W; ++o) dz2[o] = s_b2[o];
+#pragma unroll 4
+        for (int j = 0; j < W; ++j)
+#pragma unroll
+            for (int o = 0; o < W; ++o) dz2[o] = fmaf(s_w2[j * W + o], h1[j], dz2[o]);
+#pragma unroll
+        for (int o = 0; o < W; ++o) {
+            dz2[o] = dh2[o] * act_d<ACT>(act_f<ACT>(dz2[o]));
+            s_d2[lane][o] = dz2[o];
+        }
+        float dz1[W];
+#pragma unroll 4
+        for (int j = 0; j < W; ++j) {
+            float s = 0.0f;
+#pragma unroll
+            for (int o = 0; o < W; ++o) s = fmaf(s_w2[j * W + o], dz2[o], s);
+            dz1[j] = s * act_d<ACT>(s_h1[lane][j]);
+            s_d1[lane][j] = dz1[j];
+        }
+        // dL/dm^(g) = W1 dz1, scattered back through the signed permutation.
+#pragma unroll 3
+        for (int k = 0; k < Q; ++k) {
+            float s = 0.0f;
+#pragma unroll
+            for (int j = 0; j < W; ++j) s = fmaf(s_w1[k * W + j], dz1[j], s);
+            const int e = gs[k];
+            s_dm[lane][e & 31] += __int_as_float(__float_as_int(s) ^ (e & (int)0x80000000));
+        }
+        __syncthreads();
+        // Block reduction of this group element's parameter gradients.
+        int er[7];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) er[i] = r1 + i < 27 ? gs[r1 + i] : 27;
+#pragma unroll 4
+        for (int nd = 0; nd < 64; ++nd) {
+            float xv[7], hv[4], d1v[2], d2v[4];
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                xv[i] = r1 + i < 28
+                            ? __int_as_float(__float_as_int(s_m[nd][er[i] & 31]) ^ (er[i] & (int)0x80000000))
+                            : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) d1v[c] = s_d1[nd][c1 + c];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) hv[i] = s_h1[nd][r2 + i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) d2v[c] = s_d2[nd][c2 + c];
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc1[i][c] = fmaf(xv[i], d1v[c], acc1[i][c]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc2[i][c] = fmaf(hv[i], d2v[c], acc2[i][c]);
+            if (lane < W) accb2 += s_d2[nd][lane];
+        }
+        __syncthreads();
+    }
+
+    // dL/dy = lambda + M^T g_m, with the network's share of g_m from s_dm.
+#pragma unroll
+    for (int k = 0; k < Q; ++k) gm[row_tensor(k)] += s_dm[lane][k];
+    float gf[Q];
+    moments_T(gm, gf);
+    // Scatter back along the streaming: position x - c_i.
+    if (live) {
+        const int xs[3] = {p.x == a.nx - 1 ? 0 : p.x + 1, p.x, p.x == 0 ? a.nx - 1 : p.x - 1};
+        const int ys[3] = {(p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx, p.y * a.nx,
+                           (p.y == 0 ? a.ny - 1 : p.y - 1) * a.nx};
+        const int nxy = a.nx * a.ny;
+        const int zs[3] = {(p.z == a.nz - 1 ? 0 : p.z + 1) * nxy, p.z * nxy,
+                           (p.z == 0 ? a.nz - 1 : p.z - 1) * nxy};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int dst = zs[cz_of(i) + 1] + ys[cy_of(i) + 1] + xs[cx_of(i) + 1];
+            lam_out[(size_t)i * a.n + dst] = lam[i] + gf[i];
+        }
+    }
+
+    // Output-layer gradients: dW3 = sum (S2/48) dtt^T, db3 = sum dtt.
+#pragma unroll
+    for (int o = 0; o < W; ++o) s_h1[lane][o] = S2[o] * (1.0f / NGROUP);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) s_d2[lane][n] = dtt[n];
+    __syncthreads();
+    float* __restrict__ out = partial + (size_t)blockIdx.x * NPAR;
+    {
+        float w3a = 0.0f, w3b = 0.0f, b3a = 0.0f;
+        const int e0 = 2 * lane, e1 = 2 * lane + 1;              // W3 entries [o][n] = e / 4, e % 4
+        for (int nd = 0; nd < 64; ++nd) {
+            w3a = fmaf(s_h1[nd][e0 >> 2], s_d2[nd][e0 & 3], w3a);
+            w3b = fmaf(s_h1[nd][e1 >> 2], s_d2[nd][e1 & 3], w3b);
+            if (lane < 4) b3a += s_d2[nd][lane];
+        }
+        out[OFF_W3 + e0] = w3a;
+        out[OFF_W3 + e1] = w3b;
+        if (lane < 4) out[OFF_B3 + lane] = b3a;
+    }
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const int r = r1 + i;
+        if (r < 27) {
+            out[OFF_W1 + r * W + c1] = acc1[i][0];
+            out[OFF_W1 + r * W + c1 + 1] = acc1[i][1];
+        } else if (r == 27) {
+            out[OFF_B1 + c1] = acc1[i][0];
+            out[OFF_B1 + c1 + 1] = acc1[i][1];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[OFF_W2 + (r2 + i) * W + c2 + c] = acc2[i][c];
+    if (lane < W) out[OFF_B2 + lane] = accb2;
+}
+
+
+// grad[p] += sum over blocks of partial[b][p], in block order, in float64.
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial, int nblocks,
+                                                     double* __restrict__ grad) {
+    const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pidx >= NPAR) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += (double)partial[(size_t)b * NPAR + pidx];
+    grad[pidx] += s;
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, size_t count, float v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_f64(double* __restrict__ p, size_t count, double v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_add_f64_to_f32(float* __restrict__ dst, const double* __restrict__ src,
+                                                       size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] += (float)src[i];
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_f64(const float* __restrict__ src, double* __restrict__ dst,
+                                                   size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = (double)src[i];
+}
+
+}  // namespace
+
+int adjoint_param_count() { return NPAR; }
+int adjoint_blocks(int n) { return (n + 63) / 64; }
+
+hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
+                          const int* gsrc, float* partial, hipStream_t st) {
+    const dim3 grid((a.n + 63) / 64), block(64);
+#define ADJ_CASE(SS)                                                                                         \
+    case SS: {                                                                                               \
+        using T = typename Codec<SS>::store_t;                                                               \
+        if (a.act == ACT_TANH)                                                                               \
+            hipLaunchKernelGGL((k_adjoint<SS, ACT_TANH>), grid, block, 0, st, static_cast<const T*>(xin),    \
+                               lam_in, lam_out, a, gsrc, partial);                                           \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_adjoint<SS, ACT_RELU>), grid, block, 0, st, static_cast<const T*>(xin),    \
+                               lam_in, lam_out, a, gsrc, partial);                                           \
+        return hipGetLastError();                                                                            \
+    }
+    switch (storage) {
+        ADJ_CASE(ST_F32)
+        ADJ_CASE(ST_F16)
+        ADJ_CASE(ST_BF16)
+        default: return hipErrorInvalidValue;
+    }
+#undef ADJ_CASE
+}
+
+hipError_t launch_grad_reduce(const float* partial, int nblocks, double* grad, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_reduce, dim3((NPAR + 255) / 256), dim3(256), 0, st, partial, nblocks, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, size_t count, float v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, size_t count, double v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_f64_to_f32(float* dst, const double* src, size_t count, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_f64_to_f32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, dst, src, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_f32_to_f64(const float* src, double* dst, size_t count, hipStream_t st) {
+    hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count);
+    return hipGetLastError();
+}
+
+}  // namespace nco

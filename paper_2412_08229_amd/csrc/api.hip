@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "../../include/nco.h"
@@ -115,6 +117,21 @@ struct nco_lattice {
     double* small = nullptr;      // 64 doubles of results
     int* flag = nullptr;
     void* spec_work = nullptr;
+    // Spectral forcing: coefficients of every step of the forcing period.
+    int n_modes = 0, force_steps = 0;
+    long force_t = 0;             // forcing step of the next lattice step
+    int* d_fk = nullptr;
+    double* d_fhat = nullptr;
+    // Recorded forward run (checkpoints) for the adjoint.
+    int rec_steps = -1, rec_every = 0;
+    long rec_force_t0 = 0;
+    long steps_since_record = 0;
+    std::vector<void*> ckpt, seg;
+    float* lam[2] = {nullptr, nullptr};
+    float* adj_partial = nullptr;
+    double* d_grad = nullptr;
+    double* d_dE = nullptr;
+    int* d_gsrc = nullptr;        // [48][27] group source row | sign bit
 };
 
 namespace {
@@ -159,7 +176,32 @@ StepArgs step_args(const nco_lattice* lat) {
         a.omega_high_f[k] = (float)lat->omega_high[k];
     }
     a.net = lat->net;
+    a.n_modes = 0;
+    a.fk = nullptr;
+    a.fhat = nullptr;
     return a;
+}
+
+// Arguments of the step that uses forcing step t.
+StepArgs step_args_at(const nco_lattice* lat, long t) {
+    StepArgs a = step_args(lat);
+    if (lat->n_modes > 0) {
+        a.n_modes = lat->n_modes;
+        a.fk = lat->d_fk;
+        a.fhat = lat->d_fhat + (size_t)(t % lat->force_steps) * lat->n_modes * 6;
+    }
+    return a;
+}
+
+// One forward step from buffer fin to fout with the given forcing step.
+int launch_one(nco_lattice* lat, const void* fin, void* fout, long t) {
+    const StepArgs a = step_args_at(lat, t);
+    if (use_mfma(lat))
+        HIP_TRY(launch_nco_mfma(lat->storage, lat->mlp_prec, fin, fout, a, mfma_lane_tab(lat), mfma_group_tab(lat),
+                                nullptr, lat->stream));
+    else
+        HIP_TRY(launch_step(lat->storage, fin, fout, a, lat->stream));
+    return NCO_OK;
 }
 
 }  // namespace
@@ -241,6 +283,16 @@ int nco_lattice_destroy(nco_lattice* lat) {
     if (lat->small) hipFree(lat->small);
     if (lat->flag) hipFree(lat->flag);
     if (lat->spec_work) hipFree(lat->spec_work);
+    if (lat->d_fk) hipFree(lat->d_fk);
+    if (lat->d_fhat) hipFree(lat->d_fhat);
+    for (void* p : lat->ckpt) hipFree(p);
+    for (void* p : lat->seg) hipFree(p);
+    for (int b = 0; b < 2; ++b)
+        if (lat->lam[b]) hipFree(lat->lam[b]);
+    if (lat->adj_partial) hipFree(lat->adj_partial);
+    if (lat->d_grad) hipFree(lat->d_grad);
+    if (lat->d_dE) hipFree(lat->d_dE);
+    if (lat->d_gsrc) hipFree(lat->d_gsrc);
     if (lat->own_stream && lat->stream) hipStreamDestroy(lat->stream);
     delete lat;
     return NCO_OK;
@@ -310,6 +362,16 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
     lat->width = W;
     lat->act = act;
     lat->mlp_prec = mlp_prec;
+    {
+        // Group table of the adjoint: source row | sign bit per element and row.
+        int gs[48 * 27];
+        for (int g = 0; g < NGROUP; ++g)
+            for (int k = 0; k < 27; ++k)
+                gs[g * 27 + k] = G.src[g][k] | (G.sign[g][k] < 0.0f ? (int)0x80000000 : 0);
+        if (!lat->d_gsrc) HIP_TRY(hipMalloc(&lat->d_gsrc, sizeof(gs)));
+        HIP_TRY(hipMemcpyAsync(lat->d_gsrc, gs, sizeof(gs), hipMemcpyHostToDevice, lat->stream));
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+    }
     if (mlp_prec != NCO_MLP_F32) {
         const size_t nf = mfma_lane_table_floats(), ni = mfma_group_table_ints();
         std::vector<char> tab(sizeof(float) * nf + sizeof(int) * ni);
@@ -334,6 +396,7 @@ int nco_init_equilibrium(nco_lattice* lat, const double* rho, const double* u) {
     if (rho) HIP_TRY(hipMemcpyAsync(d_rho, rho, sizeof(double) * n, hipMemcpyHostToDevice, lat->stream));
     HIP_TRY(launch_init_equilibrium(lat->storage, lat->f[lat->cur], d_rho, d_u, lat->n, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->rec_steps = -1;            // a recorded run no longer ends in this state
     return NCO_OK;
 }
 
@@ -346,6 +409,7 @@ int nco_init_populations(nco_lattice* lat, const double* f) {
                            lat->stream));
     HIP_TRY(launch_from_double(lat->storage, lat->f[lat->cur], lat->staging, lat->n, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->rec_steps = -1;
     return NCO_OK;
 }
 
@@ -354,15 +418,167 @@ int nco_step(nco_lattice* lat, int nsteps) {
     if (nsteps < 0) return fail(NCO_E_INVALID, "nsteps must be >= 0");
     if (lat->op == NCO_OP_NCO && !lat->net) return fail(NCO_E_STATE, "NCO operator needs network weights");
     if (int rc = set_device(lat)) return rc;
-    const StepArgs a = step_args(lat);
     for (int s = 0; s < nsteps; ++s) {
-        if (use_mfma(lat))
-            HIP_TRY(launch_nco_mfma(lat->storage, lat->mlp_prec, lat->f[lat->cur], lat->f[1 - lat->cur], a,
-                                    mfma_lane_tab(lat), mfma_group_tab(lat), nullptr, lat->stream));
-        else
-            HIP_TRY(launch_step(lat->storage, lat->f[lat->cur], lat->f[1 - lat->cur], a, lat->stream));
+        if (int rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t)) return rc;
         lat->cur = 1 - lat->cur;
+        ++lat->force_t;
+        ++lat->steps_since_record;
     }
+    return NCO_OK;
+}
+
+int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
+                    double amplitude, double kf, double c) {
+    if (int rc = check_lat(lat)) return rc;
+    if (n_modes < 0 || (n_modes > 0 && (!k || !draws || n_steps < 1 || !(c > 0.0))))
+        return fail(NCO_E_INVALID, "bad forcing arguments");
+    if (int rc = set_device(lat)) return rc;
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    if (lat->d_fk) HIP_TRY(hipFree(lat->d_fk));
+    if (lat->d_fhat) HIP_TRY(hipFree(lat->d_fhat));
+    lat->d_fk = nullptr;
+    lat->d_fhat = nullptr;
+    lat->n_modes = 0;
+    lat->force_t = 0;
+    if (n_modes == 0) return NCO_OK;
+    // Alvelius coefficients (Sec. "Training Data - Forced Isotropic
+    // Turbulence"): F_hat = A_ran e1 + B_ran e2 with A_ran, B_ran =
+    // sqrt(F(k) / (2 pi k^2)) exp(i theta_{1,2}) (sin 2 phi, cos 2 phi),
+    // theta2 = theta1 + psi, F(k) = amplitude exp(-(k - kf)^2 / c); e1 the
+    // unit normal of k in the x-y plane, e2 = k x e1 / |k| as printed.
+    std::vector<double> fh((size_t)n_steps * n_modes * 6);
+    for (int m = 0; m < n_modes; ++m) {
+        const double kx = k[3 * m], ky = k[3 * m + 1], kz = k[3 * m + 2];
+        const double kk = std::sqrt(kx * kx + ky * ky + kz * kz), kp = std::sqrt(kx * kx + ky * ky);
+        if (!(kk > 0.0)) return fail(NCO_E_INVALID, "forcing wavevector %d is zero", m);
+        double e1[3], e2[3];
+        if (kp == 0.0) {
+            e1[0] = 1; e1[1] = 0; e1[2] = 0;
+            e2[0] = 0; e2[1] = 1; e2[2] = 0;
+        } else {
+            e1[0] = ky / kp; e1[1] = -kx / kp; e1[2] = 0.0;
+            e2[0] = kx * kz / (kk * kp); e2[1] = ky * kz / (kk * kp); e2[2] = -kp / kk;
+        }
+        const double Fk = amplitude * std::exp(-(kk - kf) * (kk - kf) / c);
+        const double mag = std::sqrt(Fk / (2.0 * M_PI * kk * kk));
+        for (int t = 0; t < n_steps; ++t) {
+            const double* d = draws + ((size_t)t * n_modes + m) * 3;
+            const double phi = M_PI * d[0], psi = 2.0 * M_PI * d[1], th1 = 2.0 * M_PI * d[2];
+            const double ga = std::sin(2.0 * phi), gb = std::cos(2.0 * phi);
+            const double Ar = mag * std::cos(th1) * ga, Ai = mag * std::sin(th1) * ga;
+            const double Br = mag * std::cos(th1 + psi) * gb, Bi = mag * std::sin(th1 + psi) * gb;
+            double* o = &fh[((size_t)t * n_modes + m) * 6];
+            for (int a3 = 0; a3 < 3; ++a3) {
+                o[2 * a3] = Ar * e1[a3] + Br * e2[a3];
+                o[2 * a3 + 1] = Ai * e1[a3] + Bi * e2[a3];
+            }
+        }
+    }
+    HIP_TRY(hipMalloc(&lat->d_fk, sizeof(int) * 3 * n_modes));
+    HIP_TRY(hipMalloc(&lat->d_fhat, sizeof(double) * fh.size()));
+    HIP_TRY(hipMemcpyAsync(lat->d_fk, k, sizeof(int) * 3 * n_modes, hipMemcpyHostToDevice, lat->stream));
+    HIP_TRY(hipMemcpyAsync(lat->d_fhat, fh.data(), sizeof(double) * fh.size(), hipMemcpyHostToDevice, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->n_modes = n_modes;
+    lat->force_steps = n_steps;
+    return NCO_OK;
+}
+
+int nco_forward_record(nco_lattice* lat, int nsteps, int ckpt_every) {
+    if (int rc = check_lat(lat)) return rc;
+    if (nsteps < 1 || ckpt_every < 1) return fail(NCO_E_INVALID, "nsteps and ckpt_every must be >= 1");
+    if (lat->op != NCO_OP_NCO || !lat->net) return fail(NCO_E_STATE, "recording needs the NCO operator with weights");
+    if (lat->width != 32 || lat->storage == NCO_F64)
+        return fail(NCO_E_UNSUPPORTED, "the adjoint needs width 32 and float storage");
+    if (int rc = set_device(lat)) return rc;
+    const int ncp = (nsteps + ckpt_every - 1) / ckpt_every;
+    while ((int)lat->ckpt.size() < ncp) {
+        void* p = nullptr;
+        HIP_TRY(hipMalloc(&p, lat->pop_bytes));
+        lat->ckpt.push_back(p);
+    }
+    lat->rec_force_t0 = lat->force_t;
+    for (int s = 0; s < nsteps; ++s) {
+        if (s % ckpt_every == 0)
+            HIP_TRY(hipMemcpyAsync(lat->ckpt[s / ckpt_every], lat->f[lat->cur], lat->pop_bytes,
+                                   hipMemcpyDeviceToDevice, lat->stream));
+        if (int rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t)) return rc;
+        lat->cur = 1 - lat->cur;
+        ++lat->force_t;
+    }
+    lat->rec_steps = nsteps;
+    lat->rec_every = ckpt_every;
+    lat->steps_since_record = 0;
+    return NCO_OK;
+}
+
+int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double* dL_df, double* grad,
+                 size_t n_params, double* dL_df0) {
+    if (int rc = check_lat(lat)) return rc;
+    if (lat->rec_steps < 1 || lat->steps_since_record != 0)
+        return fail(NCO_E_STATE, "backward needs nco_forward_record immediately before it");
+    if (!grad || n_params != (size_t)adjoint_param_count())
+        return fail(NCO_E_INVALID, "grad must hold %d values", adjoint_param_count());
+    if (!dL_dE && !dL_df) return fail(NCO_E_INVALID, "give dL_dE, dL_df or both");
+    if (int rc = set_device(lat)) return rc;
+    const size_t n = lat->n, nf = 27 * n;
+    if (dL_dE) {
+        if (lat->nx != lat->ny || lat->nx != lat->nz) return fail(NCO_E_INVALID, "spectrum needs a cubic lattice");
+        if (nbins != spectrum_bins(lat->nx)) return fail(NCO_E_INVALID, "nbins must be %d", spectrum_bins(lat->nx));
+    }
+    for (int b = 0; b < 2; ++b)
+        if (!lat->lam[b]) HIP_TRY(hipMalloc(&lat->lam[b], sizeof(float) * nf));
+    const int nblk = adjoint_blocks(lat->n);
+    if (!lat->adj_partial) HIP_TRY(hipMalloc(&lat->adj_partial, sizeof(float) * (size_t)nblk * adjoint_param_count()));
+    if (!lat->d_grad) HIP_TRY(hipMalloc(&lat->d_grad, sizeof(double) * adjoint_param_count()));
+    while ((int)lat->seg.size() < lat->rec_every) {
+        void* p = nullptr;
+        HIP_TRY(hipMalloc(&p, lat->pop_bytes));
+        lat->seg.push_back(p);
+    }
+    // Adjoint of the final state.
+    float* lin = lat->lam[0];
+    float* lout = lat->lam[1];
+    HIP_TRY(launch_fill_f32(lin, nf, 0.0f, lat->stream));
+    if (dL_dE) {
+        const int nn = lat->nx;
+        if (!lat->spec_work) HIP_TRY(hipMalloc(&lat->spec_work, spectrum_workspace_bytes(nn) + 256 * sizeof(double) * 8));
+        if (!lat->d_dE) HIP_TRY(hipMalloc(&lat->d_dE, sizeof(double) * 2048));
+        if (nbins > 2048) return fail(NCO_E_UNSUPPORTED, "too many shells");
+        HIP_TRY(hipMemcpyAsync(lat->d_dE, dL_dE, sizeof(double) * nbins, hipMemcpyHostToDevice, lat->stream));
+        HIP_TRY(launch_spectrum_adjoint(lat->storage, lat->f[lat->cur], nn, lat->spec_work, lat->d_dE, nbins, lin,
+                                        lat->stream));
+    }
+    if (dL_df) {
+        if (int rc = ensure_staging(lat)) return rc;
+        HIP_TRY(hipMemcpyAsync(lat->staging, dL_df, sizeof(double) * nf, hipMemcpyHostToDevice, lat->stream));
+        HIP_TRY(launch_add_f64_to_f32(lin, lat->staging, nf, lat->stream));
+    }
+    HIP_TRY(launch_fill_f64(lat->d_grad, adjoint_param_count(), 0.0, lat->stream));
+    const int T = lat->rec_steps, K = lat->rec_every;
+    const int ncp = (T + K - 1) / K;
+    for (int sgi = ncp - 1; sgi >= 0; --sgi) {
+        const int t0 = sgi * K, len = std::min(K, T - t0);
+        // Recompute the states of this segment from its checkpoint.
+        HIP_TRY(hipMemcpyAsync(lat->seg[0], lat->ckpt[sgi], lat->pop_bytes, hipMemcpyDeviceToDevice, lat->stream));
+        for (int i = 1; i < len; ++i)
+            if (int rc = launch_one(lat, lat->seg[i - 1], lat->seg[i], lat->rec_force_t0 + t0 + i - 1)) return rc;
+        for (int t = t0 + len - 1; t >= t0; --t) {
+            const StepArgs a = step_args_at(lat, lat->rec_force_t0 + t);
+            HIP_TRY(launch_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_gsrc, lat->adj_partial,
+                                   lat->stream));
+            HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, lat->d_grad, lat->stream));
+            std::swap(lin, lout);
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(grad, lat->d_grad, sizeof(double) * adjoint_param_count(), hipMemcpyDeviceToHost,
+                           lat->stream));
+    if (dL_df0) {
+        if (int rc = ensure_staging(lat)) return rc;
+        HIP_TRY(launch_f32_to_f64(lin, lat->staging, nf, lat->stream));
+        HIP_TRY(hipMemcpyAsync(dL_df0, lat->staging, sizeof(double) * nf, hipMemcpyDeviceToHost, lat->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(lat->stream));
     return NCO_OK;
 }
 

@@ -17,7 +17,30 @@ struct StepArgs {
     double omega_high[4];    // fixed rates of orders 3..6 (OP_MRT)
     float omega_high_f[4];
     const float* net;        // device network buffer (OP_NCO), see net_off_*()
+    // Spectral forcing of this step: F(x) = sum_m 2 Re(Fhat_m exp(i k_m.x)),
+    // x in [0, 2 pi)^3; n_modes = 0 disables the Kupershtokh source.
+    int n_modes;
+    const int* fk;           // [n_modes][3] integer wavevectors
+    const double* fhat;      // [n_modes][6] Re/Im of Fhat_x, Fhat_y, Fhat_z for this step
 };
+
+// Force density at node (x, y, z) for the current step (float64 synthesis).
+__device__ __forceinline__ void force_at(const StepArgs& a, int x, int y, int z, double& Fx, double& Fy,
+                                         double& Fz) {
+    Fx = Fy = Fz = 0.0;
+    for (int m = 0; m < a.n_modes; ++m) {
+        const int* k = a.fk + 3 * m;
+        // Phase as a fraction of a turn, reduced exactly in integers.
+        const long px = ((long)k[0] * x) % a.nx, py = ((long)k[1] * y) % a.ny, pz = ((long)k[2] * z) % a.nz;
+        const double turn = (double)px / a.nx + (double)py / a.ny + (double)pz / a.nz;
+        double s, c;
+        sincospi(2.0 * turn, &s, &c);
+        const double* fh = a.fhat + 6 * m;
+        Fx += 2.0 * (fh[0] * c - fh[1] * s);
+        Fy += 2.0 * (fh[2] * c - fh[3] * s);
+        Fz += 2.0 * (fh[4] * c - fh[5] * s);
+    }
+}
 
 hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs& a, hipStream_t st);
 hipError_t launch_rates(int storage, const void* fin, double* omega, const StepArgs& a, hipStream_t st);
@@ -38,6 +61,19 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
                          int* gtab);
 hipError_t launch_nco_mfma(int storage, int prec, const void* fin, void* fout, const StepArgs& a,
                            const float* lane_tab, const int* gtab, double* omega_out, hipStream_t st);
+
+// Adjoint of a step (adjoint.hip), network width 32, float arithmetic.
+int adjoint_param_count();
+int adjoint_blocks(int n);
+hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
+                          const int* gsrc, float* partial, hipStream_t st);
+hipError_t launch_grad_reduce(const float* partial, int nblocks, double* grad, hipStream_t st);
+hipError_t launch_fill_f32(float* p, size_t count, float v, hipStream_t st);
+hipError_t launch_fill_f64(double* p, size_t count, double v, hipStream_t st);
+hipError_t launch_add_f64_to_f32(float* dst, const double* src, size_t count, hipStream_t st);
+hipError_t launch_f32_to_f64(const float* src, double* dst, size_t count, hipStream_t st);
+hipError_t launch_spectrum_adjoint(int storage, const void* f, int n, void* work, const double* dE, int nbins,
+                                   float* lam, hipStream_t st);
 
 // Energy spectrum (spectrum.hip).
 size_t spectrum_workspace_bytes(int n);

@@ -13,12 +13,13 @@ template <typename R> __device__ __forceinline__ R pick(float f, double d);
 template <> __device__ __forceinline__ float pick<float>(float f, double) { return f; }
 template <> __device__ __forceinline__ double pick<double>(float, double d) { return d; }
 
-// Collision of one node in place; OP and W/ACT select the operator.
-template <typename R, int OP, int W, int ACT>
-__device__ __forceinline__ void collide_node(R (&f)[Q], const StepArgs& a) {
+// Collision of one node in place (plus the Kupershtokh source of force F when
+// FORCED); OP and W/ACT select the operator.
+template <typename R, int OP, int W, int ACT, bool FORCED>
+__device__ __forceinline__ void collide_node(R (&f)[Q], const StepArgs& a, R Fx, R Fy, R Fz) {
     const R omega_nu = pick<R>(a.omega_nu_f, a.omega_nu);
     if constexpr (OP == OP_BGK) {
-        bgk<R, false>(f, omega_nu, R(0), R(0), R(0));
+        bgk<R, FORCED>(f, omega_nu, Fx, Fy, Fz);
     } else {
         R m[Q];
         to_moments(f, m);
@@ -30,7 +31,7 @@ __device__ __forceinline__ void collide_node(R (&f)[Q], const StepArgs& a) {
             for (int n = 0; n < 4; ++n) omega[n] = pick<R>(a.omega_high_f[n], a.omega_high[n]);
         }
         R dm[Q], df[Q];
-        collision_delta<R, false>(m, omega_nu, omega, R(0), R(0), R(0), dm);
+        collision_delta<R, FORCED>(m, omega_nu, omega, Fx, Fy, Fz, dm);
         from_moments(dm, df);
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] -= df[i];
@@ -45,8 +46,15 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Codec<S>:
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.n) return;
     R f[Q];
-    pull<S>(fin, a, node_of(idx, a.nx, a.ny), f);
-    collide_node<R, OP, W, ACT>(f, a);
+    const NodeIdx p = node_of(idx, a.nx, a.ny);
+    pull<S>(fin, a, p, f);
+    if (a.n_modes > 0) {
+        double Fx, Fy, Fz;
+        force_at(a, p.x, p.y, p.z, Fx, Fy, Fz);
+        collide_node<R, OP, W, ACT, true>(f, a, (R)Fx, (R)Fy, (R)Fz);
+    } else {
+        collide_node<R, OP, W, ACT, false>(f, a, R(0), R(0), R(0));
+    }
     store_local<S>(fout, a.n, idx, f);
 }
 

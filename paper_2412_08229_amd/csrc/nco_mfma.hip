@@ -348,7 +348,14 @@ __global__ __launch_bounds__(256) void k_nco_mfma(const typename Codec<S>::store
 #pragma unroll
         for (int n = 0; n < 4; ++n) omega[n] = sw[tid * 4 + n];
         float dm[Q], df[Q];
-        collision_delta<float, false>(m, a.omega_nu_f, omega, 0.f, 0.f, 0.f, dm);
+        if (a.n_modes > 0) {
+            const NodeIdx p = node_of(idx, a.nx, a.ny);
+            double Fx, Fy, Fz;
+            force_at(a, p.x, p.y, p.z, Fx, Fy, Fz);
+            collision_delta<float, true>(m, a.omega_nu_f, omega, (float)Fx, (float)Fy, (float)Fz, dm);
+        } else {
+            collision_delta<float, false>(m, a.omega_nu_f, omega, 0.f, 0.f, 0.f, dm);
+        }
         from_moments(dm, df);
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] -= df[i];

@@ -37,7 +37,8 @@ __global__ __launch_bounds__(256) void k_velocity(const typename Codec<S>::store
 
 // One axis of the forward DFT over a [3][n][n][n] field; AXIS 0 = x (stride
 // 1), 1 = y (stride n), 2 = z (stride n^2).  REAL_IN reads a real field.
-template <int AXIS, bool REAL_IN>
+// CONJ = true applies the conjugate twiddles (the unnormalised inverse DFT).
+template <int AXIS, bool REAL_IN, bool CONJ = false>
 __global__ __launch_bounds__(256) void k_dft_axis(const void* __restrict__ in_, double2* __restrict__ out,
                                                   const double2* __restrict__ tw, int n) {
     const size_t n3 = (size_t)n * n * n;
@@ -49,7 +50,8 @@ __global__ __launch_bounds__(256) void k_dft_axis(const void* __restrict__ in_, 
     double re = 0.0, im = 0.0;
     int m = 0;
     for (int j = 0; j < n; ++j) {
-        const double2 w = tw[m];
+        double2 w = tw[m];
+        if constexpr (CONJ) w.y = -w.y;
         if constexpr (REAL_IN) {
             const double v = static_cast<const double*>(in_)[base + (size_t)j * stride];
             re = fma(v, w.x, re);
@@ -123,8 +125,69 @@ __global__ __launch_bounds__(256) void k_shell_final(const double* __restrict__ 
     if (threadIdx.x == 0) E[b] = red[0];
 }
 
+// dL/dE at every wavevector: A[c][e] *= dL/dE(shell of e).
+__global__ __launch_bounds__(256) void k_scale_shells(double2* __restrict__ A, int n,
+                                                      const double* __restrict__ dE, int nbins) {
+    const size_t n3 = (size_t)n * n * n;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n3) return;
+    const int kx = wavenumber((int)(e % n), n), ky = wavenumber((int)((e / n) % n), n),
+              kz = wavenumber((int)(e / ((size_t)n * n)), n);
+    const int b = (int)floor(sqrt((double)(kx * kx + ky * ky + kz * kz)) + 0.5);
+    const double s = b < nbins ? dE[b] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double2 v = A[(size_t)c * n3 + e];
+        v.x *= s;
+        v.y *= s;
+        A[(size_t)c * n3 + e] = v;
+    }
+}
+
+// rho and u = j / rho of every node (float64).
+template <int S>
+__global__ __launch_bounds__(256) void k_rho_u(const typename Codec<S>::store_t* __restrict__ f, double* __restrict__ u,
+                                               double* __restrict__ rho, int n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = Codec<S>::to_double(f[(size_t)i * n + idx], i);
+        r += v;
+        jx += cx_of(i) * v;
+        jy += cy_of(i) * v;
+        jz += cz_of(i) * v;
+    }
+    u[idx] = jx / r;
+    u[(size_t)n + idx] = jy / r;
+    u[2 * (size_t)n + idx] = jz / r;
+    rho[idx] = r;
+}
+
+// lambda_f = lambda_rho + c . lambda_j with lambda_u = Re(B) / n^6 (B the
+// unnormalised inverse DFT of the shell-weighted spectrum), lambda_j =
+// lambda_u / rho, lambda_rho = -lambda_u . u / rho.
+__global__ __launch_bounds__(256) void k_lambda_from_u(const double2* __restrict__ B, const double* __restrict__ u,
+                                                       const double* __restrict__ rho, int n3, double scale,
+                                                       float* __restrict__ lam) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n3) return;
+    double lu[3], lr = 0.0;
+    const double ir = 1.0 / rho[idx];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lu[c] = B[(size_t)c * n3 + idx].x * scale;
+        lr -= lu[c] * u[(size_t)c * n3 + idx];
+    }
+    lr *= ir;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        lam[(size_t)i * n3 + idx] = (float)(lr + (cx_of(i) * lu[0] + cy_of(i) * lu[1] + cz_of(i) * lu[2]) * ir);
+}
+
 struct SpecLayout {
-    size_t u, a, b, part, tw, total;
+    size_t u, a, b, part, tw, rho, total;
 };
 
 SpecLayout spec_layout(int n, int nbins) {
@@ -136,13 +199,64 @@ SpecLayout spec_layout(int n, int nbins) {
     L.b = up(L.a + 3 * n3 * sizeof(double2));
     L.part = up(L.b + 3 * n3 * sizeof(double2));
     L.tw = up(L.part + (size_t)nbins * n * n * sizeof(double));
-    L.total = up(L.tw + (size_t)n * sizeof(double2));
+    L.rho = up(L.tw + (size_t)n * sizeof(double2));
+    L.total = up(L.rho + n3 * sizeof(double));
     return L;
+}
+
+// Twiddles exp(-2 pi i m / n), computed on the host in float64.
+hipError_t upload_twiddles(double2* tw, int n, hipStream_t st) {
+    double2* h = static_cast<double2*>(malloc(sizeof(double2) * n));
+    if (!h) return hipErrorOutOfMemory;
+    for (int m = 0; m < n; ++m) {
+        const double ang = 2.0 * M_PI * (double)m / (double)n;
+        h[m] = make_double2(cos(ang), -sin(ang));
+    }
+    hipError_t e = hipMemcpyAsync(tw, h, sizeof(double2) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    free(h);
+    return e;
 }
 
 }  // namespace
 
 int spectrum_bins(int n) { return (int)floor(sqrt(3.0) * (n / 2) + 0.5) + 1; }
+
+// lam (float [27][n^3]) = (dE/df)^T dL/dE for the spectrum of f; dE lives on
+// the device (nbins doubles).  Forward DFT, weight each wavevector by the
+// derivative of its shell, inverse DFT, then the chain rule through u = j/rho.
+hipError_t launch_spectrum_adjoint(int storage, const void* f, int n, void* work, const double* dE,
+                                   int nbins, float* lam, hipStream_t st) {
+    const SpecLayout L = spec_layout(n, nbins);
+    char* w = static_cast<char*>(work);
+    double* u = reinterpret_cast<double*>(w + L.u);
+    double2* A = reinterpret_cast<double2*>(w + L.a);
+    double2* B = reinterpret_cast<double2*>(w + L.b);
+    double2* tw = reinterpret_cast<double2*>(w + L.tw);
+    double* rho = reinterpret_cast<double*>(w + L.rho);
+    const int n3 = n * n * n;
+    if (hipError_t e = upload_twiddles(tw, n, st); e != hipSuccess) return e;
+    const int nb = (n3 + 255) / 256;
+    switch (storage) {
+        case ST_F32: hipLaunchKernelGGL(k_rho_u<ST_F32>, dim3(nb), dim3(256), 0, st, static_cast<const float*>(f), u, rho, n3); break;
+        case ST_F16: hipLaunchKernelGGL(k_rho_u<ST_F16>, dim3(nb), dim3(256), 0, st, static_cast<const __half*>(f), u, rho, n3); break;
+        case ST_BF16: hipLaunchKernelGGL(k_rho_u<ST_BF16>, dim3(nb), dim3(256), 0, st, static_cast<const __hip_bfloat16*>(f), u, rho, n3); break;
+        case ST_F64: hipLaunchKernelGGL(k_rho_u<ST_F64>, dim3(nb), dim3(256), 0, st, static_cast<const double*>(f), u, rho, n3); break;
+        default: return hipErrorInvalidValue;
+    }
+    const size_t tot = 3 * (size_t)n3;
+    const unsigned nbt = (unsigned)((tot + 255) / 256);
+    hipLaunchKernelGGL((k_dft_axis<0, true>), dim3(nbt), dim3(256), 0, st, (const void*)u, A, tw, n);
+    hipLaunchKernelGGL((k_dft_axis<1, false>), dim3(nbt), dim3(256), 0, st, (const void*)A, B, tw, n);
+    hipLaunchKernelGGL((k_dft_axis<2, false>), dim3(nbt), dim3(256), 0, st, (const void*)B, A, tw, n);
+    hipLaunchKernelGGL(k_scale_shells, dim3(nb), dim3(256), 0, st, A, n, dE, nbins);
+    hipLaunchKernelGGL((k_dft_axis<0, false, true>), dim3(nbt), dim3(256), 0, st, (const void*)A, B, tw, n);
+    hipLaunchKernelGGL((k_dft_axis<1, false, true>), dim3(nbt), dim3(256), 0, st, (const void*)B, A, tw, n);
+    hipLaunchKernelGGL((k_dft_axis<2, false, true>), dim3(nbt), dim3(256), 0, st, (const void*)A, B, tw, n);
+    const double scale = 1.0 / ((double)n3 * (double)n3);
+    hipLaunchKernelGGL(k_lambda_from_u, dim3(nb), dim3(256), 0, st, B, u, rho, n3, scale, lam);
+    return hipGetLastError();
+}
 
 size_t spectrum_workspace_bytes(int n) { return spec_layout(n, spectrum_bins(n)).total; }
 
@@ -156,19 +270,7 @@ hipError_t launch_energy_spectrum(int storage, const void* f, int n, void* work,
     double* part = reinterpret_cast<double*>(w + L.part);
     double2* tw = reinterpret_cast<double2*>(w + L.tw);
     const int n3 = n * n * n;
-    // Twiddles exp(-2 pi i m / n), computed on the host in float64.
-    {
-        double2* h = static_cast<double2*>(malloc(sizeof(double2) * n));
-        if (!h) return hipErrorOutOfMemory;
-        for (int m = 0; m < n; ++m) {
-            const double ang = 2.0 * M_PI * (double)m / (double)n;
-            h[m] = make_double2(cos(ang), -sin(ang));
-        }
-        hipError_t e = hipMemcpyAsync(tw, h, sizeof(double2) * n, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        free(h);
-        if (e != hipSuccess) return e;
-    }
+    if (hipError_t e = upload_twiddles(tw, n, st); e != hipSuccess) return e;
     const int nb = (n3 + 255) / 256;
     switch (storage) {
         case ST_F32: hipLaunchKernelGGL(k_velocity<ST_F32>, dim3(nb), dim3(256), 0, st, static_cast<const float*>(f), u, n3); break;

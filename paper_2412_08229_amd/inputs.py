@@ -136,3 +136,18 @@ def alvelius_modes(kmax=2.0):
     ks = [(kx, ky, kz) for kz in range(-r, r + 1) for ky in range(-r, r + 1) for kx in range(-r, r + 1)
           if 0 < kx * kx + ky * ky + kz * kz <= kmax * kmax]
     return np.array(ks, dtype=np.int64)
+
+
+def forcing_half_modes(kmax=2.0):
+    """One wavevector of each +-k pair of ``alvelius_modes`` (the one whose
+    first nonzero component, in the order z, y, x, is positive)."""
+    ks = alvelius_modes(kmax)
+    keep = [(kz > 0) or (kz == 0 and ky > 0) or (kz == 0 and ky == 0 and kx > 0) for kx, ky, kz in ks]
+    return ks[np.array(keep)]
+
+
+def uniform_draws(n_steps, n_modes, seed):
+    """Uniform numbers in [0, 1), shape (n_steps, n_modes, 3): the random
+    angles (phi, psi, theta1) of the spectral forcing, scaled to [0, 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.random((n_steps, n_modes, 3))

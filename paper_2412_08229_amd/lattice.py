@@ -97,3 +97,16 @@ class Lattice:
 
     def device_populations(self):
         return L.nco_device_populations(self._h)
+
+    def set_forcing(self, k, draws, amplitude, kf, c):
+        """Spectral forcing for the following steps; k=None switches it off."""
+        L.nco_set_forcing(self._h, k, draws, amplitude, kf, c)
+
+    def forward_record(self, nsteps, ckpt_every):
+        L.nco_forward_record(self._h, int(nsteps), int(ckpt_every))
+
+    def backward(self, dL_dE=None, dL_df=None, n_params=2084, want_df0=False):
+        """Gradient of the recorded run: (dL/dtheta, dL/df0 or None)."""
+        g, df0 = L.nco_backward(self._h, self.n, n_params, dL_dE,
+                                None if dL_df is None else np.asarray(dL_df).ravel(), want_df0)
+        return g, (None if df0 is None else df0.reshape((27,) + self.shape))

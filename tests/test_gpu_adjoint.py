@@ -1,0 +1,123 @@
+"""GPU forcing and reverse mode against the float64 oracle, through the C ABI.
+
+The GPU gradient is float32 arithmetic; it is compared with the oracle's
+float64 gradient of the same run in relative 2-norm."""
+import numpy as np
+import pytest
+
+from oracle import adjoint, collision, forcing, observables, step
+from paper_2412_08229_amd import Lattice, inputs
+from paper_2412_08229_amd import _lib as L
+from paper_2412_08229_amd.training import log_spectrum_loss
+
+pytestmark = pytest.mark.gpu
+
+AMP, KF, CW = 2e-6, 1.5, 1.0
+
+
+def _forcing(n_steps, seed):
+    ks = inputs.forcing_half_modes(2.0)
+    draws = inputs.uniform_draws(n_steps, len(ks), seed)
+    return ks, draws
+
+
+def _oracle_forces(ks, draws, shape):
+    fh = forcing.coefficients(ks, draws, AMP, KF, CW)
+    return lambda t: forcing.field(ks, fh[t % len(fh)], shape)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-13), ("f32", 2e-6)])
+def test_forced_steps_match_oracle(storage, tol):
+    n, T = 8, 5
+    ks, draws = _forcing(3, seed=1)
+    f0 = inputs.random_populations((n, n, n), seed=2, lo=0.9, hi=1.1)
+    with Lattice((n, n, n), storage, "bgk", 0.6) as lat:
+        lat.set_forcing(ks, draws, AMP, KF, CW)
+        lat.init_populations(f0)
+        fs = lat.populations()
+        lat.step(T)
+        got = lat.populations()
+    want = step.run(fs, step.Operator("bgk", 0.6), T, forces=_oracle_forces(ks, draws, (n, n, n)))
+    assert np.abs(got - want).max() < tol
+
+
+def _setup(n, width, seed, act):
+    params = inputs.mlp_params(width, seed)
+    _, u = inputs.turbulence(n, seed=seed + 1, k0=2.0, urms=0.04)
+    rho = np.ones((n, n, n))
+    f0 = collision.equilibrium(rho, u)
+    Et = observables.spectrum(f0) * np.linspace(0.7, 1.3, observables.n_bins(n)) + 1e-12
+    return params, rho, u, f0, Et
+
+
+@pytest.mark.parametrize("act,mlp,forced", [("tanh", "f32", False), ("tanh", "f32_mfma", True),
+                                            ("relu", "f32", False)])
+def test_spectrum_loss_gradient_matches_oracle(act, mlp, forced):
+    n, width, tau, T, K = 8, 32, 0.56, 6, 4
+    params, rho, u, f0, Et = _setup(n, width, 4, act)
+    ks, draws = _forcing(T, seed=5)
+    kmin, kmax = 1, 3
+    with Lattice((n, n, n), "f32", "nco", tau) as lat:
+        lat.set_net_weights(params, width, act, mlp)
+        if forced:
+            lat.set_forcing(ks, draws, AMP, KF, CW)
+        lat.init_equilibrium(rho, u)
+        fs = lat.populations()
+        lat.forward_record(T, K)
+        E = lat.energy_spectrum()
+        Lg, dE = log_spectrum_loss(E, Et, kmin, kmax)
+        g, df0 = lat.backward(dL_dE=dE, want_df0=True)
+    layers = collision.unpack_params(params, width)
+    forces = _oracle_forces(ks, draws, (n, n, n)) if forced else None
+
+    def loss_grad(x):
+        Lx, d = adjoint.log_spectrum_loss(observables.spectrum(x), Et, kmin, kmax)
+        return Lx, adjoint.spectrum_vjp(x, d)
+    Lo, go, gfo = adjoint.run_and_grad(fs, tau, layers, act, T, loss_grad, forces=forces)
+    go = adjoint.flatten(go)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    relf = np.linalg.norm(df0 - gfo) / np.linalg.norm(gfo)
+    print("%s/%s forced=%s: loss %.6e vs %.6e, grad rel err %.2e, dL/df0 rel err %.2e"
+          % (act, mlp, forced, Lg, Lo, rel, relf))
+    assert abs(Lg - Lo) < 1e-4 * abs(Lo)
+    assert rel < 2e-3 and relf < 2e-3
+
+
+def test_population_loss_gradient_and_determinism():
+    """Loss <w, x_T> given as dL/df; two backward passes agree bitwise."""
+    n, width, tau, T, K = 6, 32, 0.57, 5, 2
+    params = inputs.mlp_params(width, 7)
+    f0 = inputs.random_populations((n, n, n), seed=8, lo=0.95, hi=1.05)
+    w = np.random.Generator(np.random.PCG64(9)).standard_normal(f0.shape)
+    grads = []
+    with Lattice((n, n, n), "f32", "nco", tau) as lat:
+        lat.set_net_weights(params, width, "tanh", "f32")
+        for _ in range(2):
+            lat.init_populations(f0)
+            fs = lat.populations()
+            lat.forward_record(T, K)
+            grads.append(lat.backward(dL_df=w, want_df0=True))
+    assert np.array_equal(grads[0][0], grads[1][0]) and np.array_equal(grads[0][1], grads[1][1])
+    layers = collision.unpack_params(params, width)
+    _, go, gfo = adjoint.run_and_grad(fs, tau, layers, "tanh", T, lambda x: (float((w * x).sum()), w))
+    go = adjoint.flatten(go)
+    assert np.linalg.norm(grads[0][0] - go) / np.linalg.norm(go) < 2e-3
+    assert np.linalg.norm(grads[0][1] - gfo) / np.linalg.norm(gfo) < 1e-4
+
+
+def test_backward_state_errors():
+    with Lattice((4, 4, 4), "f32", "nco", 0.6) as lat:
+        lat.set_net_weights(inputs.mlp_params(32, 0), 32)
+        with pytest.raises(L.NCOError) as e:
+            lat.backward(dL_df=np.zeros((27, 4, 4, 4)))
+        assert e.value.status == L.NCO_E_STATE
+        lat.forward_record(3, 2)
+        lat.step(1)
+        with pytest.raises(L.NCOError) as e:
+            lat.backward(dL_df=np.zeros((27, 4, 4, 4)))
+        assert e.value.status == L.NCO_E_STATE
+    with Lattice((4, 4, 4), "f32", "nco", 0.6) as lat:
+        lat.set_net_weights(inputs.mlp_params(16, 0), 16)
+        with pytest.raises(L.NCOError) as e:
+            lat.forward_record(3, 2)
+        assert e.value.status == L.NCO_E_UNSUPPORTED
