@@ -97,7 +97,7 @@ def train(unrolls, params0, epochs, lr=1e-3, log=None):
             opt.step()
             with torch.no_grad():
                 p.copy_(p.float().double())          # parameters live as float32 values
-            total += float(loss)
+            total += float(loss.detach())
         history.append(total / len(fns))
         if log:
             log("epoch %d: loss %.6f" % (ep, history[-1]))
