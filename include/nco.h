@@ -113,6 +113,16 @@ int nco_init_populations(nco_lattice* lat, const double* f);
 /* Advance nsteps >= 0 time steps; asynchronous on the lattice's stream. */
 int nco_step(nco_lattice* lat, int nsteps);
 
+/* Advance several lattices at once: lattice i by nsteps[i] steps.  Every
+ * step is one grouped dispatch per kernel kind (operator, storage, network
+ * arithmetic), each covering up to 16 lattices, so that small lattices share
+ * the device instead of queueing one behind another.  All lattices must live
+ * on the same device and stream and appear once; NCO lattices must use a
+ * matrix-core network (nco_set_net_weights with NCO_MLP_F32_MFMA or
+ * NCO_MLP_BF16).  Each lattice's result is the same as from nco_step.
+ * Asynchronous on the shared stream. */
+int nco_batch_step(nco_lattice** lats, int n, const int* nsteps);
+
 /* Block until the lattice's stream has finished its work. */
 int nco_sync(nco_lattice* lat);
 

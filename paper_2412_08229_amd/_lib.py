@@ -54,6 +54,7 @@ SIGNATURES = {
     "nco_set_forcing": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), _D, _I, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double]),
     "nco_forward_record": (_I, [_P, _I, _I]),
+    "nco_batch_step": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(ctypes.c_int)]),
     "nco_backward": (_I, [_P, _D, _I, _D, _D, _SZ, _D]),
 }
 
@@ -202,6 +203,13 @@ def nco_set_forcing(h, k, draws, amplitude, kf, c):
         raise ValueError("draws must have shape (n_steps, n_modes, 3)")
     check(lib().nco_set_forcing(h, n_modes, kk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dptr(d),
                                 d.shape[0], amplitude, kf, c))
+
+
+def nco_batch_step(handles, nsteps):
+    n = len(handles)
+    arr = (_P * max(n, 1))(*[h.value if isinstance(h, _P) else h for h in handles])
+    steps = (ctypes.c_int * max(n, 1))(*[int(s) for s in nsteps])
+    check(lib().nco_batch_step(arr, n, steps))
 
 
 def nco_forward_record(h, nsteps, ckpt_every):

@@ -427,6 +427,73 @@ int nco_step(nco_lattice* lat, int nsteps) {
     return NCO_OK;
 }
 
+int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
+    if (!lats || !nsteps || n < 0) return fail(NCO_E_INVALID, "null arguments");
+    if (n == 0) return NCO_OK;
+    nco_lattice* first = lats[0];
+    int max_steps = 0;
+    for (int i = 0; i < n; ++i) {
+        nco_lattice* lat = lats[i];
+        if (!lat) return fail(NCO_E_INVALID, "lattice %d is null", i);
+        if (nsteps[i] < 0) return fail(NCO_E_INVALID, "nsteps[%d] < 0", i);
+        if (lat->stream != first->stream || lat->device != first->device)
+            return fail(NCO_E_INVALID, "all lattices of a batch must share one device and stream");
+        for (int j = 0; j < i; ++j)
+            if (lats[j] == lat) return fail(NCO_E_INVALID, "lattice %d appears twice", i);
+        if (lat->op == NCO_OP_NCO && !use_mfma(lat))
+            return fail(NCO_E_UNSUPPORTED, "batched NCO lattices need the matrix-core network (width 32)");
+        if (lat->op == NCO_OP_STREAM) return fail(NCO_E_UNSUPPORTED, "batched streaming-only lattices");
+        max_steps = std::max(max_steps, nsteps[i]);
+    }
+    if (int rc = set_device(first)) return rc;
+    // Kernel kind of each lattice: one grouped dispatch per kind and step.
+    auto kind = [](const nco_lattice* l) {
+        return l->op == NCO_OP_NCO ? 1000 + 100 * l->storage + 10 * l->mlp_prec + l->act : 10 * l->storage + l->op;
+    };
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return kind(lats[x]) < kind(lats[y]); });
+    for (int s = 0; s < max_steps; ++s) {
+        int pos = 0;
+        while (pos < n) {
+            LaunchGroup g;
+            g.count = 0;
+            g.prefix[0] = 0;
+            // Up to GROUP_MAX lattices of one kind that still have steps to run.
+            const int k0 = kind(lats[order[pos]]);
+            std::vector<int> members;
+            while (pos < n && kind(lats[order[pos]]) == k0 && (int)members.size() < GROUP_MAX) {
+                const int idx = order[pos++];
+                if (nsteps[idx] > s) members.push_back(idx);
+            }
+            for (int idx : members) {
+                nco_lattice* lat = lats[idx];
+                GroupDesc& d = g.d[g.count];
+                d.fin = lat->f[lat->cur];
+                d.fout = lat->f[1 - lat->cur];
+                d.a = step_args_at(lat, lat->force_t);
+                d.lane_tab = lat->op == NCO_OP_NCO ? mfma_lane_tab(lat) : nullptr;
+                d.gtab = lat->op == NCO_OP_NCO ? mfma_group_tab(lat) : nullptr;
+                g.prefix[g.count + 1] = g.prefix[g.count] + (lat->n + 255) / 256;
+                ++g.count;
+            }
+            if (g.count == 0) continue;
+            const nco_lattice* l0 = lats[members[0]];
+            if (l0->op == NCO_OP_NCO)
+                HIP_TRY(launch_nco_mfma_grouped(l0->storage, l0->mlp_prec, l0->act, g, first->stream));
+            else
+                HIP_TRY(launch_step_grouped(l0->storage, l0->op, g, first->stream));
+            for (int idx : members) {
+                nco_lattice* lat = lats[idx];
+                lat->cur = 1 - lat->cur;
+                ++lat->force_t;
+                ++lat->steps_since_record;
+            }
+        }
+    }
+    return NCO_OK;
+}
+
 int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
                     double amplitude, double kf, double c) {
     if (int rc = check_lat(lat)) return rc;

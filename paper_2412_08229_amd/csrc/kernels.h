@@ -42,7 +42,33 @@ __device__ __forceinline__ void force_at(const StepArgs& a, int x, int y, int z,
     }
 }
 
+// Grouped launch: one dispatch advancing up to GROUP_MAX lattices of the same
+// kernel kind by one step; blocks [prefix[i], prefix[i+1]) serve lattice i.
+// Passed by value (kernel argument segment, read with scalar loads).
+constexpr int GROUP_MAX = 16;
+struct GroupDesc {
+    const void* fin;
+    void* fout;
+    StepArgs a;
+    const float* lane_tab;
+    const int* gtab;
+};
+struct LaunchGroup {
+    int count;
+    int prefix[GROUP_MAX + 1];
+    GroupDesc d[GROUP_MAX];
+};
+
+// Lattice of block b of a grouped launch (count <= 16: a linear scan).
+__device__ __forceinline__ int group_member(const LaunchGroup& g, int b) {
+    int i = 0;
+    while (i + 1 < g.count && g.prefix[i + 1] <= b) ++i;
+    return i;
+}
+
 hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs& a, hipStream_t st);
+// BGK and fixed-rate lattices (op in a.op of every member, same storage).
+hipError_t launch_step_grouped(int storage, int op, const LaunchGroup& g, hipStream_t st);
 hipError_t launch_rates(int storage, const void* fin, double* omega, const StepArgs& a, hipStream_t st);
 hipError_t launch_init_equilibrium(int storage, void* f, const double* rho, const double* u, int n,
                                    hipStream_t st);
@@ -61,6 +87,7 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
                          int* gtab);
 hipError_t launch_nco_mfma(int storage, int prec, const void* fin, void* fout, const StepArgs& a,
                            const float* lane_tab, const int* gtab, double* omega_out, hipStream_t st);
+hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchGroup& g, hipStream_t st);
 
 // Adjoint of a step (adjoint.hip), network width 32, float arithmetic.
 int adjoint_param_count();

@@ -39,11 +39,32 @@ __device__ __forceinline__ void collide_node(R (&f)[Q], const StepArgs& a, R Fx,
 }
 
 template <int S, int OP, int W, int ACT>
+__device__ __forceinline__ void stream_collide_node(const typename Codec<S>::store_t* __restrict__ fin,
+                                                    typename Codec<S>::store_t* __restrict__ fout,
+                                                    const StepArgs& a, int idx);
+
+template <int S, int OP, int W, int ACT>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename Codec<S>::store_t* __restrict__ fin,
                                                         typename Codec<S>::store_t* __restrict__ fout,
                                                         StepArgs a) {
+    stream_collide_node<S, OP, W, ACT>(fin, fout, a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// One step of several lattices of the same kind in one dispatch.
+template <int S, int OP>
+__global__ __launch_bounds__(256) void k_stream_collide_grouped(LaunchGroup g) {
+    using T = typename Codec<S>::store_t;
+    const int i = group_member(g, blockIdx.x);
+    const GroupDesc& d = g.d[i];
+    stream_collide_node<S, OP, 8, ACT_TANH>(static_cast<const T*>(d.fin), static_cast<T*>(d.fout), d.a,
+                                            (blockIdx.x - g.prefix[i]) * blockDim.x + threadIdx.x);
+}
+
+template <int S, int OP, int W, int ACT>
+__device__ __forceinline__ void stream_collide_node(const typename Codec<S>::store_t* __restrict__ fin,
+                                                    typename Codec<S>::store_t* __restrict__ fout,
+                                                    const StepArgs& a, int idx) {
     using R = typename Codec<S>::real;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.n) return;
     R f[Q];
     const NodeIdx p = node_of(idx, a.nx, a.ny);
@@ -309,6 +330,23 @@ hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs&
         case OP_MRT: DISPATCH_STORAGE(storage, return (launch_step_op<SS, OP_MRT>(fin, fout, a, st)))
         case OP_NCO: DISPATCH_STORAGE(storage, return (launch_step_op<SS, OP_NCO>(fin, fout, a, st)))
         case OP_NONE: DISPATCH_STORAGE(storage, return (launch_step_op<SS, OP_NONE>(fin, fout, a, st)))
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_grouped(int storage, int op, const LaunchGroup& g, hipStream_t st) {
+    const dim3 grid(g.prefix[g.count]), block(256);
+    switch (op) {
+        case OP_BGK:
+            DISPATCH_STORAGE(storage, {
+                hipLaunchKernelGGL((k_stream_collide_grouped<SS, OP_BGK>), grid, block, 0, st, g);
+                return hipGetLastError();
+            })
+        case OP_MRT:
+            DISPATCH_STORAGE(storage, {
+                hipLaunchKernelGGL((k_stream_collide_grouped<SS, OP_MRT>), grid, block, 0, st, g);
+                return hipGetLastError();
+            })
         default: return hipErrorInvalidValue;
     }
 }

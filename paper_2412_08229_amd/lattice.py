@@ -16,6 +16,14 @@ def n_bins(n):
     return int(math.floor(math.sqrt(3.0) * (n // 2) + 0.5)) + 1
 
 
+def batch_step(lattices, nsteps):
+    """Advance lattice i by nsteps[i] steps in grouped dispatches
+    (nco_batch_step); all lattices share one device and stream."""
+    if len(nsteps) != len(lattices):
+        raise ValueError("one step count per lattice")
+    L.nco_batch_step([lat._h for lat in lattices], [int(s) for s in nsteps])
+
+
 class Lattice:
     def __init__(self, shape, storage="f32", op="bgk", tau=0.6, stream=None):
         """shape = (nz, ny, nx).  stream: an integer hipStream_t (for example
