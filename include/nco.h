@@ -113,14 +113,19 @@ int nco_init_populations(nco_lattice* lat, const double* f);
 /* Advance nsteps >= 0 time steps; asynchronous on the lattice's stream. */
 int nco_step(nco_lattice* lat, int nsteps);
 
-/* Advance several lattices at once: lattice i by nsteps[i] steps.  Every
- * step is one grouped dispatch per kernel kind (operator, storage, network
- * arithmetic), each covering up to 16 lattices, so that small lattices share
- * the device instead of queueing one behind another.  All lattices must live
- * on the same device and stream and appear once; NCO lattices must use a
- * matrix-core network (nco_set_net_weights with NCO_MLP_F32_MFMA or
- * NCO_MLP_BF16).  Each lattice's result is the same as from nco_step.
- * Asynchronous on the shared stream. */
+/* Advance several lattices at once: lattice i by nsteps[i] steps.  Lattices
+ * of one kernel kind (operator, storage, network arithmetic, activation) are
+ * taken in chunks of up to 16; every step of a chunk is one grouped dispatch
+ * over its lattices, so that small lattices share the device instead of
+ * queueing one behind another.  The first chunk runs on the shared stream,
+ * the others on up to three side streams the library keeps per device,
+ * forked from the shared stream and joined back to it before the call
+ * returns, so that chunks run concurrently; work queued on the shared
+ * stream afterwards sees every result.  All lattices must live on the same
+ * device and stream and appear once; NCO lattices must use a matrix-core
+ * network (nco_set_net_weights with NCO_MLP_F32_MFMA or NCO_MLP_BF16);
+ * streaming-only lattices are not batched.  Each lattice's result is the
+ * same, bit for bit, as from nco_step.  Asynchronous on the shared stream. */
 int nco_batch_step(nco_lattice** lats, int n, const int* nsteps);
 
 /* Block until the lattice's stream has finished its work. */

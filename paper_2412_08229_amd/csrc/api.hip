@@ -6,6 +6,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -150,6 +151,36 @@ int ensure_staging(nco_lattice* lat) {
     if (!lat->staging) HIP_TRY(hipMalloc(&lat->staging, sizeof(double) * 27 * (size_t)lat->n));
     return NCO_OK;
 }
+
+// Side streams and fork/join events of nco_batch_step, one set per device,
+// created on first use (default priority) and kept until the process ends.
+// g_side_mutex is held while a batch is enqueued, so that batches issued from
+// several threads do not interleave their records of the shared events.
+constexpr int BATCH_SIDE_STREAMS = 3;
+constexpr int MAX_DEVICES = 64;
+struct BatchSide {
+    hipStream_t st[BATCH_SIDE_STREAMS] = {};
+    hipEvent_t ev[1 + BATCH_SIDE_STREAMS] = {};
+    bool ready = false;
+};
+BatchSide g_side[MAX_DEVICES];
+std::mutex g_side_mutex;
+
+int side_streams(int device, hipStream_t (&out)[BATCH_SIDE_STREAMS]) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(NCO_E_UNSUPPORTED, "device index %d", device);
+    BatchSide& b = g_side[device];
+    if (!b.ready) {
+        for (int k = 0; k < BATCH_SIDE_STREAMS; ++k)
+            HIP_TRY(hipStreamCreateWithFlags(&b.st[k], hipStreamNonBlocking));
+        for (int k = 0; k < 1 + BATCH_SIDE_STREAMS; ++k)
+            HIP_TRY(hipEventCreateWithFlags(&b.ev[k], hipEventDisableTiming));
+        b.ready = true;
+    }
+    for (int k = 0; k < BATCH_SIDE_STREAMS; ++k) out[k] = b.st[k];
+    return NCO_OK;
+}
+
+hipEvent_t batch_event(int device, int k) { return g_side[device].ev[k]; }
 
 bool use_mfma(const nco_lattice* lat) {
     return lat->op == NCO_OP_NCO && lat->mlp_prec != NCO_MLP_F32 && lat->mfma_tab;
@@ -446,27 +477,48 @@ int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
         max_steps = std::max(max_steps, nsteps[i]);
     }
     if (int rc = set_device(first)) return rc;
-    // Kernel kind of each lattice: one grouped dispatch per kind and step.
+    // Kernel kind of each lattice; chunks of up to GROUP_MAX lattices of one
+    // kind share a dispatch per step.
     auto kind = [](const nco_lattice* l) {
         return l->op == NCO_OP_NCO ? 1000 + 100 * l->storage + 10 * l->mlp_prec + l->act : 10 * l->storage + l->op;
     };
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return kind(lats[x]) < kind(lats[y]); });
-    for (int s = 0; s < max_steps; ++s) {
-        int pos = 0;
-        while (pos < n) {
+    std::vector<std::vector<int>> chunks;
+    for (int pos = 0; pos < n;) {
+        std::vector<int> c;
+        const int k0 = kind(lats[order[pos]]);
+        while (pos < n && kind(lats[order[pos]]) == k0 && (int)c.size() < GROUP_MAX) {
+            if (nsteps[order[pos]] > 0) c.push_back(order[pos]);
+            ++pos;
+        }
+        if (!c.empty()) chunks.push_back(std::move(c));
+    }
+    if (chunks.empty()) return NCO_OK;
+    // Chunk 0 runs on the shared stream; the others on side streams forked
+    // from it and joined back, so that chunks of different kinds (and the
+    // chunks of a large batch) proceed concurrently.
+    std::lock_guard<std::mutex> lock(g_side_mutex);
+    hipStream_t side[BATCH_SIDE_STREAMS] = {};
+    const int n_side = std::min((int)chunks.size() - 1, BATCH_SIDE_STREAMS);
+    if (n_side > 0) {
+        if (int rc = side_streams(first->device, side)) return rc;
+        HIP_TRY(hipEventRecord(batch_event(first->device, 0), first->stream));
+        for (int k = 0; k < n_side; ++k) HIP_TRY(hipStreamWaitEvent(side[k], batch_event(first->device, 0), 0));
+    }
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        hipStream_t st = c == 0 ? first->stream : side[(c - 1) % BATCH_SIDE_STREAMS];
+        const std::vector<int>& mem = chunks[c];
+        const nco_lattice* l0 = lats[mem[0]];
+        int chunk_steps = 0;
+        for (int idx : mem) chunk_steps = std::max(chunk_steps, nsteps[idx]);
+        for (int s = 0; s < chunk_steps; ++s) {
             LaunchGroup g;
             g.count = 0;
             g.prefix[0] = 0;
-            // Up to GROUP_MAX lattices of one kind that still have steps to run.
-            const int k0 = kind(lats[order[pos]]);
-            std::vector<int> members;
-            while (pos < n && kind(lats[order[pos]]) == k0 && (int)members.size() < GROUP_MAX) {
-                const int idx = order[pos++];
-                if (nsteps[idx] > s) members.push_back(idx);
-            }
-            for (int idx : members) {
+            for (int idx : mem) {
+                if (nsteps[idx] <= s) continue;
                 nco_lattice* lat = lats[idx];
                 GroupDesc& d = g.d[g.count];
                 d.fin = lat->f[lat->cur];
@@ -476,20 +528,19 @@ int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
                 d.gtab = lat->op == NCO_OP_NCO ? mfma_group_tab(lat) : nullptr;
                 g.prefix[g.count + 1] = g.prefix[g.count] + (lat->n + 255) / 256;
                 ++g.count;
-            }
-            if (g.count == 0) continue;
-            const nco_lattice* l0 = lats[members[0]];
-            if (l0->op == NCO_OP_NCO)
-                HIP_TRY(launch_nco_mfma_grouped(l0->storage, l0->mlp_prec, l0->act, g, first->stream));
-            else
-                HIP_TRY(launch_step_grouped(l0->storage, l0->op, g, first->stream));
-            for (int idx : members) {
-                nco_lattice* lat = lats[idx];
                 lat->cur = 1 - lat->cur;
                 ++lat->force_t;
                 ++lat->steps_since_record;
             }
+            if (l0->op == NCO_OP_NCO)
+                HIP_TRY(launch_nco_mfma_grouped(l0->storage, l0->mlp_prec, l0->act, g, st));
+            else
+                HIP_TRY(launch_step_grouped(l0->storage, l0->op, g, st));
         }
+    }
+    for (int k = 0; k < n_side; ++k) {
+        HIP_TRY(hipEventRecord(batch_event(first->device, 1 + k), side[k]));
+        HIP_TRY(hipStreamWaitEvent(first->stream, batch_event(first->device, 1 + k), 0));
     }
     return NCO_OK;
 }

@@ -283,38 +283,58 @@ __device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const
 
 // RATES = true: no streaming, the rates of the stored state are written to
 // omega_out [4][n] instead of a step (readout and tests of the network alone).
+// Work space of one block in LDS, declared by each kernel.
+struct BlockLds {
+    float* sm;      // [256][NODE_STRIDE] moments, then hidden activations
+    int* sg;        // [GT_ENTRIES] gather table
+    float* sw;      // [256][4] rates
+};
+
 template <int S, int ACT, bool RATES, int PREC>
 __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t* __restrict__ fin,
                                                typename Codec<S>::store_t* __restrict__ fout, const StepArgs& a,
                                                const float* __restrict__ lane_tab, const int* __restrict__ gtab,
-                                               double* __restrict__ omega_out, int blk);
+                                               double* __restrict__ omega_out, int blk, BlockLds lds);
+
+#define NCO_BLOCK_LDS                              \
+    __shared__ float lds_sm[256 * NODE_STRIDE];    \
+    __shared__ int lds_sg[GT_ENTRIES];             \
+    __shared__ float lds_sw[256 * 4];              \
+    const BlockLds lds{lds_sm, lds_sg, lds_sw};
 
 template <int S, int ACT, bool RATES, int PREC>
 __global__ __launch_bounds__(256) void k_nco_mfma(const typename Codec<S>::store_t* __restrict__ fin,
                                                   typename Codec<S>::store_t* __restrict__ fout, StepArgs a,
                                                   const float* __restrict__ lane_tab, const int* __restrict__ gtab,
                                                   double* __restrict__ omega_out) {
-    nco_mfma_block<S, ACT, RATES, PREC>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x);
+    NCO_BLOCK_LDS
+    nco_mfma_block<S, ACT, RATES, PREC>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x, lds);
 }
 
-// One step of several lattices (same storage, activation and arithmetic).
+template <int S, int ACT, int PREC>
+__device__ __forceinline__ void grouped_block(const GroupDesc& d, int blk, BlockLds lds) {
+    using T = typename Codec<S>::store_t;
+    nco_mfma_block<S, ACT, false, PREC>(static_cast<const T*>(d.fin), static_cast<T*>(d.fout), d.a, d.lane_tab,
+                                        d.gtab, nullptr, blk, lds);
+}
+
+// One step of several lattices with the same storage, activation and
+// network arithmetic.
 template <int S, int ACT, int PREC>
 __global__ __launch_bounds__(256) void k_nco_mfma_grouped(LaunchGroup g) {
-    using T = typename Codec<S>::store_t;
+    NCO_BLOCK_LDS
     const int i = group_member(g, blockIdx.x);
-    const GroupDesc& d = g.d[i];
-    nco_mfma_block<S, ACT, false, PREC>(static_cast<const T*>(d.fin), static_cast<T*>(d.fout), d.a, d.lane_tab,
-                                        d.gtab, nullptr, blockIdx.x - g.prefix[i]);
+    grouped_block<S, ACT, PREC>(g.d[i], blockIdx.x - g.prefix[i], lds);
 }
 
 template <int S, int ACT, bool RATES, int PREC>
 __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t* __restrict__ fin,
                                                typename Codec<S>::store_t* __restrict__ fout, const StepArgs& a,
                                                const float* __restrict__ lane_tab, const int* __restrict__ gtab,
-                                               double* __restrict__ omega_out, int blk) {
-    __shared__ float sm[256 * NODE_STRIDE];
-    __shared__ int sg[GT_ENTRIES];
-    __shared__ float sw[256 * 4];
+                                               double* __restrict__ omega_out, int blk, BlockLds lds) {
+    float* __restrict__ sm = lds.sm;
+    int* __restrict__ sg = lds.sg;
+    float* __restrict__ sw = lds.sw;
     const int tid = threadIdx.x;
     const int idx = blk * 256 + tid;
     const bool live = idx < a.n;
@@ -532,15 +552,15 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
 hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchGroup& g, hipStream_t st) {
     const dim3 grid(g.prefix[g.count]), block(256);
 #define GRP_LAUNCH(SS, AA, PP) hipLaunchKernelGGL((k_nco_mfma_grouped<SS, AA, PP>), grid, block, 0, st, g)
-#define GRP_CASE(SS)                                                                      \
-    case SS:                                                                              \
-        if (prec == MLP_PREC_BF16) {                                                      \
-            if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_BF16);                 \
-            else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_BF16);                                 \
-        } else {                                                                          \
-            if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_F32);                  \
-            else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_F32);                                  \
-        }                                                                                 \
+#define GRP_CASE(SS)                                                      \
+    case SS:                                                              \
+        if (prec == MLP_PREC_BF16) {                                      \
+            if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_BF16); \
+            else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_BF16);                 \
+        } else {                                                          \
+            if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_F32);  \
+            else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_F32);                  \
+        }                                                                 \
         return hipGetLastError();
     switch (storage) {
         GRP_CASE(ST_F32)

@@ -15,10 +15,12 @@ scheduling logic use a simulated engine on the CPU.
 """
 import argparse
 import collections
+import itertools
 import json
 import math
 import sys
 import time
+from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -125,13 +127,25 @@ class Server:
     """FIFO admission by device-memory budget and slots, rounds of ``chunk``
     steps over every active solve."""
 
-    def __init__(self, engine, budget_bytes, max_slots=16, chunk=50):
+    def __init__(self, engine, budget_bytes, max_slots=16, chunk=50, prep_workers=0):
+        """prep_workers > 0: host-side set-up of arrived requests runs on that
+        many threads, concurrently with the device rounds; 0: it runs on the
+        calling thread while a round is in flight."""
         self.engine = engine
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.chunk = int(chunk)
+        self.prep_workers = int(prep_workers)
 
     def run(self, requests, clock=time.perf_counter, sleep=time.sleep, log=None):
+        pool = ThreadPoolExecutor(self.prep_workers) if self.prep_workers > 0 else None
+        try:
+            return self._run(requests, clock, sleep, log, pool)
+        finally:
+            if pool is not None:
+                pool.shutdown(wait=True)
+
+    def _run(self, requests, clock, sleep, log, pool):
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         active = []           # [request, handle, remaining steps, bytes]
         used = 0
@@ -139,17 +153,31 @@ class Server:
         t0 = clock()
         done = []
         node_steps = 0
-        prepared = {}
+        prepared = {}         # rid -> set-up result (or its Future)
 
         def prepare_arrived():
+            # Set up the arrived head of the queue (at most one slot's worth
+            # of requests ahead) before it is admitted.
             now = clock() - t0
-            for req in pending:
-                if req.arrival > now or len(prepared) >= self.max_slots:
+            for req in itertools.islice(pending, 0, self.max_slots):
+                if req.arrival > now:
                     break
                 if req.rid not in prepared:
-                    prepared[req.rid] = self.engine.prepare(req)
+                    prepared[req.rid] = pool.submit(self.engine.prepare, req) if pool else self.engine.prepare(req)
+
+        def ready(req, wait):
+            p = prepared.get(req.rid)
+            if isinstance(p, Future) and not p.done() and not wait:
+                return False
+            return True
+
+        def take(req):
+            p = prepared.pop(req.rid, None)
+            return p.result() if isinstance(p, Future) else p
 
         while pending or active:
+            if pool is not None:
+                prepare_arrived()
             now = clock() - t0
             # Admission: the head of the queue, as long as a slot and memory are free.
             while pending and pending[0].arrival <= now and len(active) < self.max_slots:
@@ -157,14 +185,14 @@ class Server:
                 nb = self.engine.bytes(req)
                 if nb > self.budget:
                     pending.popleft()
-                    prepared.pop(req.rid, None)
+                    take(req)
                     req.status, req.finished = "rejected", clock() - t0
                     done.append(req)
                     continue
-                if used + nb > self.budget:
+                if used + nb > self.budget or not ready(req, wait=not active):
                     break
                 pending.popleft()
-                handle = self.engine.create(req, prepared.pop(req.rid, None))
+                handle = self.engine.create(req, take(req))
                 req.admitted, req.status = clock() - t0, "running"
                 active.append([req, handle, req.steps, nb])
                 used += nb
@@ -174,7 +202,7 @@ class Server:
                     sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.05)))
                 continue
             steps = [min(self.chunk, a[2]) for a in active]
-            self.engine.step_batch([a[1] for a in active], steps, overlap=prepare_arrived)
+            self.engine.step_batch([a[1] for a in active], steps, overlap=None if pool else prepare_arrived)
             node_steps += sum(a[0].n ** 3 * s for a, s in zip(active, steps))
             still = []
             for a, s in zip(active, steps):
@@ -231,10 +259,11 @@ def main(argv=None):
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--loads", default="0.5,0.9")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="0: the device's free memory")
-    ap.add_argument("--small-budget-gb", type=float, default=8.0)
+    ap.add_argument("--small-budget-gb", type=float, default=2.0)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=50)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--prep-workers", type=int, default=2)
     args = ap.parse_args(argv)
     import torch
     stream = torch.cuda.Stream()
@@ -249,7 +278,7 @@ def main(argv=None):
     for load, bud in runs:
         rate = load * cap * 1e9 / mean_work
         reqs = poisson_requests(args.requests, rate, args.seed)
-        srv = Server(engine, bud, max_slots=args.slots, chunk=args.chunk)
+        srv = Server(engine, bud, max_slots=args.slots, chunk=args.chunk, prep_workers=args.prep_workers)
         rep = srv.run(reqs, log=lambda s: print("# " + s, file=sys.stderr, flush=True))
         rep.update({"offered_load": load, "arrival_rate_per_s": rate})
         print(json.dumps(rep), flush=True)

@@ -56,7 +56,7 @@ class SimEngine:
         del self.live[h]
 
 
-def _run(reqs, budget, slots=16, chunk=50, rate=1e9):
+def _run(reqs, budget, slots=16, chunk=50, rate=1e9, workers=0):
     clk = Clock()
     eng = SimEngine(clk, rate)
     peak = {"bytes": 0, "slots": 0}
@@ -67,7 +67,8 @@ def _run(reqs, budget, slots=16, chunk=50, rate=1e9):
         peak["slots"] = max(peak["slots"], len(handles))
         orig(handles, steps, overlap)
     eng.step_batch = watch
-    rep = serve.Server(eng, budget, max_slots=slots, chunk=chunk).run(reqs, clock=clk, sleep=clk.sleep)
+    rep = serve.Server(eng, budget, max_slots=slots, chunk=chunk, prep_workers=workers).run(
+        reqs, clock=clk, sleep=clk.sleep)
     return rep, eng, peak
 
 
@@ -156,3 +157,14 @@ def test_batching_beats_serial_latency():
     rep_b, _, _ = _run(reqs(), budget=1 << 30, slots=8, chunk=20)
     rep_s, _, _ = _run(reqs(), budget=1 << 30, slots=1, chunk=20)
     assert rep_b["latency_s"]["all"]["mean"] < rep_s["latency_s"]["all"]["mean"]
+
+
+def test_threaded_preparation():
+    reqs = serve.poisson_requests(25, rate=40.0, seed=4, grids=(16, 32), steps=(10, 80))
+    clk = Clock()
+    eng = SimEngine(clk)
+    rep = serve.Server(eng, 1 << 30, max_slots=4, chunk=10, prep_workers=2).run(reqs, clock=clk, sleep=clk.sleep)
+    assert rep["status"] == {"done": 25}
+    assert sorted(eng.prepared) == list(range(25))
+    adm = [r.admitted for r in sorted(reqs, key=lambda r: r.arrival)]
+    assert adm == sorted(adm) and not eng.live
