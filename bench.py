@@ -29,7 +29,7 @@ METRIC = "NCO stream-collide GLUPS & % HBM peak, FP32 vs low-precision; p99 solv
 # HBM bytes per launch at 128^3 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain copy of known size (profiles/*_hbm_counters.md).  An entry
 # is removed whenever its kernel changes, until the counters are taken again.
-TRAFFIC_BYTES = {"bgk": 228.0e6 + 226.5e6}
+TRAFFIC_BYTES = {"nco": 313.1e6 + 226.5e6, "bgk": 226.9e6 + 226.5e6}
 
 
 # Timed variants: name -> (operator, population storage, network arithmetic,
@@ -75,7 +75,7 @@ def time_op(lat, steps, warmup, torch, stream):
     return start.elapsed_time(end) / steps
 
 
-def cpu_baseline(n_sample=64, nsteps=2):
+def cpu_baseline(n_sample=64, nsteps=6):
     """The float64 oracle timed on the host, on a bounded sample: the same
     workload at n_sample^3 for nsteps steps."""
     from oracle import collision, step
@@ -129,6 +129,7 @@ def main():
     params = inputs.mlp_params(width, seed=0)
     nodes = n ** 3
     results = {}
+    spectra = {}
     for op in args.ops.split(","):
         kind, storage, mlp, act = VARIANTS[op]
         lat = Lattice((n, n, n), storage, kind, tau, stream=stream)
@@ -145,6 +146,7 @@ def main():
         s = lat.global_sums()
         if not np.all(np.isfinite(s)):
             raise RuntimeError("non-finite state after the %s run" % op)
+        spectra[op] = (steps, lat.energy_spectrum(), s[4])
         lat.close()
         glups = nodes / (ms * 1e-3) / 1e9
         gbs = bytes_per_node(storage) * nodes / (ms * 1e-3) / 1e9
@@ -154,6 +156,26 @@ def main():
                        "activation": act if kind == "nco" else None}
         print("# %s: %.4f ms/step, %.3f GLUPS, %.0f GB/s" % (op, ms, glups, gbs), file=sys.stderr,
               flush=True)
+
+    # Reduced-precision forms against the float32 run of the same operator
+    # after the same number of steps: energy-weighted spectrum error
+    # sum_k |E - E_f32| / sum_k E_f32, the largest relative error of one shell
+    # over 1 <= k <= n/4, the kinetic-energy error and the speedup.
+    for op, r in results.items():
+        ref = VARIANTS[op][0]
+        if (op == ref or ref not in spectra or spectra[ref][0] != spectra[op][0]
+                or VARIANTS[op][3] != VARIANTS[ref][3]):
+            continue
+        _, e_ref, k_ref = spectra[ref]
+        _, e, k = spectra[op]
+        # Shells 1..n/4 that hold energy (symmetry leaves some of the
+        # Taylor-Green shells empty).
+        sh = np.arange(len(e_ref))
+        sh = sh[(sh >= 1) & (sh <= n // 4) & (e_ref > 1e-10 * e_ref.max())]
+        r["vs_f32"] = {"spectrum_err": float(np.abs(e - e_ref).sum() / e_ref.sum()),
+                       "spectrum_max_shell_err": float(np.max(np.abs(e[sh] - e_ref[sh]) / e_ref[sh])),
+                       "kinetic_energy_err": float(abs(k - k_ref) / k_ref),
+                       "speedup": r["glups"] / results[ref]["glups"]}
 
     # Attainable HBM bandwidth on this device: a plain device-to-device copy of
     # the bytes one float32 step moves (27 reads + 27 writes per node).
@@ -180,7 +202,7 @@ def main():
         achieved = flops / (r["ms_per_step"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS, "traffic": TRAFFIC_BYTES.get("nco"),
-                "kernel": "k_nco_mfma_f32<f32 storage, tanh>",
+                "kernel": "k_nco_mfma<f32 storage, tanh, float32 matrix cores>",
                 "algorithmic_per_node": "%d flop (network) + %d B" % (nco_flops_per_node(width),
                                                                      bytes_per_node("f32"))}
     else:

@@ -75,6 +75,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libnco.so not built: run __graft_entry__.build() "
                               "(or python paper_2412_08229_amd/build.py)")
+        # PyTorch wheels carry their own HIP runtime under the same soname as
+        # the system one libnco.so links.  Whichever loads first serves the
+        # whole process, and torch does not work on a runtime other than its
+        # own, so torch (when installed) is loaded first: the library and
+        # torch then share one runtime, and torch streams are valid handles.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -1,0 +1,134 @@
+"""Precision form: 16-bit deviation storage and bf16 matrix-core network
+against float32 and float64 runs of the same Taylor-Green vortex.
+
+Workload: the 3-D Taylor-Green vortex of Sec. "Three-dimensional
+Taylor-Green Vortex" at Re = 1600, Ma = 0.1 (u0 = 0.1/sqrt(3)), NCO with a
+seeded 27-32-32-4 tanh network.  Observables (Sec. "Learning Task" and the
+Taylor-Green section): the mean kinetic energy k(t) = <|u|^2>/2 from the
+float64 global sums, the dissipation rate -dk/dt (centred differences of
+k sampled every ``every`` steps) and the energy spectrum E(k) at the end.
+
+Errors per result:
+* kinetic energy: max_t |k - k_ref| / k_ref(t);
+* mean dissipation: |(k(0) - k(T)) - (k_ref(0) - k_ref(T))| / (k_ref(0) - k_ref(T));
+* dissipation: max_t |eps - eps_ref| / max_t eps_ref, eps = -dk/dt from
+  samples ``every`` steps apart (at 256^3 k changes by only ~1e-4 of itself
+  over 50 steps, so this figure shows the storage noise of 16-bit formats);
+* spectrum: sum_k |E - E_ref| / sum_k E_ref (energy-weighted), and the
+  largest relative error of one shell over the shells 1 <= k <= n/4 holding
+  at least 1e-6 of the largest shell energy.
+
+References: at 64^3 the float64 path of the library (float64 storage and
+arithmetic, pinned to the oracle to 1e-13 by the parity tests) over five
+convective times, and the oracle itself for the first 20 steps at 32^3; at
+256^3 the float32 path (float32 storage and float32 matrix-core network).
+The bound the reduced-precision form must meet is a spectrum error of at
+most 2 %: the bf16 network with float32 or FP16-deviation storage meets it;
+BF16-deviation storage (8-bit significand) does not at 256^3 and is held to
+the looser bounds below.
+"""
+import json
+import math
+import time
+
+import numpy as np
+import pytest
+
+from oracle import collision, observables, step
+from paper_2412_08229_amd import Lattice, inputs
+
+pytestmark = pytest.mark.gpu
+
+U0 = 0.1 / math.sqrt(3.0)
+WIDTH = 32
+FP32 = ("f32", "f32_mfma")
+LOW = [("f32", "bf16"), ("f16", "bf16"), ("bf16", "bf16")]
+
+
+def _run(n, storage, mlp, nsteps, every, stream=None):
+    _, tau = inputs.viscosity(n, U0, 1600.0)
+    rho, u = inputs.tgv3d(n, U0)
+    with Lattice((n, n, n), storage, "nco", tau, stream=stream) as lat:
+        lat.set_net_weights(inputs.mlp_params(WIDTH, 0), WIDTH, "tanh", mlp)
+        lat.init_equilibrium(rho, u)
+        ke = [lat.global_sums()[4] / lat.n]
+        t0 = time.perf_counter()
+        for _ in range(nsteps // every):
+            lat.step(every)
+            ke.append(lat.global_sums()[4] / lat.n)     # synchronises
+        wall = time.perf_counter() - t0
+        spec = lat.energy_spectrum()
+    return np.array(ke), spec, wall
+
+
+def _errors(run, ref, n, every):
+    ke, spec, _ = run
+    ke_r, spec_r, _ = ref
+    eps = -np.gradient(ke, every)
+    eps_r = -np.gradient(ke_r, every)
+    sh = np.arange(len(spec_r))
+    sh = sh[(sh >= 1) & (sh <= n // 4) & (spec_r >= 1e-6 * spec_r.max())]
+    d, d_r = ke[0] - ke[-1], ke_r[0] - ke_r[-1]
+    return {"kinetic_energy_err": float(np.max(np.abs(ke - ke_r) / ke_r)),
+            "mean_dissipation_err": float(abs(d - d_r) / abs(d_r)),
+            "dissipation_err": float(np.max(np.abs(eps - eps_r)) / np.max(np.abs(eps_r))),
+            "spectrum_err": float(np.abs(spec - spec_r).sum() / spec_r.sum()),
+            "spectrum_max_shell_err": float(np.max(np.abs(spec[sh] - spec_r[sh]) / spec_r[sh]))}
+
+
+def test_oracle_start_32():
+    """First 20 steps at 32^3: every precision form against the oracle."""
+    n, nsteps = 32, 20
+    _, tau = inputs.viscosity(n, U0, 1600.0)
+    rho, u = inputs.tgv3d(n, U0)
+    op = step.Operator("nco", tau, layers=collision.unpack_params(inputs.mlp_params(WIDTH, 0), WIDTH), act="tanh")
+    f = collision.equilibrium(rho, u)
+    ke_o = [observables.kinetic_energy(f)]
+    for _ in range(nsteps // 5):
+        f = step.run(f, op, 5)
+        ke_o.append(observables.kinetic_energy(f))
+    ke_o = np.array(ke_o)
+    out = {}
+    for storage, mlp in [FP32] + LOW:
+        ke, _, _ = _run(n, storage, mlp, nsteps, 5)
+        out["%s/%s" % (storage, mlp)] = float(np.max(np.abs(ke - ke_o) / ke_o))
+    print("PRECISION32", json.dumps(out))
+    assert out["f32/f32_mfma"] < 1e-6
+    for k, v in out.items():
+        assert v < 1e-3, k
+
+
+def test_precision_64_full_horizon():
+    n = 64
+    every = 16
+    nsteps = 5 * int(round(n / (2 * math.pi) / U0 / every)) * every      # five convective times
+    ref = _run(n, "f64", "f32", nsteps, every)
+    out = {"steps": nsteps}
+    for storage, mlp in [FP32] + LOW:
+        out["%s/%s" % (storage, mlp)] = _errors(_run(n, storage, mlp, nsteps, every), ref, n, every)
+    print("PRECISION64", json.dumps(out))
+    assert out["f32/f32_mfma"]["kinetic_energy_err"] < 1e-5
+    for storage, mlp in LOW:
+        e = out["%s/%s" % (storage, mlp)]
+        assert e["spectrum_err"] < 0.02 and e["kinetic_energy_err"] < 0.01, (storage, mlp, e)
+    assert out["f16/bf16"]["mean_dissipation_err"] < 1e-3
+
+
+def test_precision_256_speedup():
+    import torch
+    stream = torch.cuda.Stream().cuda_stream
+    n, nsteps, every = 256, 1000, 50
+    ref = _run(n, *FP32, nsteps, every, stream)
+    out = {"steps": nsteps, "f32/f32_mfma": {"wall_s": ref[2]}}
+    for storage, mlp in LOW:
+        r = _run(n, storage, mlp, nsteps, every, stream)
+        e = _errors(r, ref, n, every)
+        e.update({"wall_s": r[2], "speedup": ref[2] / r[2]})
+        out["%s/%s" % (storage, mlp)] = e
+    print("PRECISION256", json.dumps(out))
+    for storage, mlp in LOW:
+        e = out["%s/%s" % (storage, mlp)]
+        assert e["speedup"] > 1.5, (storage, mlp, e)
+    for key in ("f32/bf16", "f16/bf16"):
+        assert out[key]["spectrum_err"] < 0.02 and out[key]["kinetic_energy_err"] < 1e-3, key
+    assert out["bf16/bf16"]["spectrum_err"] < 0.1 and out["bf16/bf16"]["kinetic_energy_err"] < 0.05
