@@ -192,13 +192,17 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
                             Y[ci][t] = u0 + u1;
                             Y[ci | bit][t] = u0 - u1;
                         }
+            // Layer 2 and the two activations, software-pipelined over the
+            // reflections: while the 16 products of reflection s run on the
+            // matrix cores, the vector units activate layer 1 of reflection
+            // s + 1 and layer 2 of reflection s - 1 (independent of them).
+            f32x4 h1[2], c2p[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h1[t][r] = act_scaled<ACT>(Y[0][t][r]);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                f32x4 h1[2];
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) h1[t][r] = act_scaled<ACT>(Y[s][t][r]);
                 f32x4 c2[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
@@ -208,11 +212,25 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
                     for (int r = 0; r < 4; ++r)
 #pragma unroll
                         for (int u = 0; u < 2; ++u) c2[u] = mfma4(A2[u][t][r], h1[t][r], c2[u]);
+                if (s > 0) {
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                    for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2[u][r]);
+                        for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2p[u][r]);
+                }
+                if (s < 7) {
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h1[t][r] = act_scaled<ACT>(Y[s + 1][t][r]);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) c2p[u] = c2[u];
             }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2p[u][r]);
         }
         output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
     }
