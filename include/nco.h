@@ -49,7 +49,7 @@ typedef enum {
     NCO_E_INVALID = -1,     /* bad argument (size, tau <= 1/2, weight count, ...) */
     NCO_E_OOM = -2,         /* device allocation failed */
     NCO_E_HIP = -3,         /* a HIP runtime call failed */
-    NCO_E_UNSTABLE = -4,    /* non-finite populations detected */
+    NCO_E_UNSTABLE = -4,    /* non-finite state or failed stability check */
     NCO_E_STATE = -5,       /* call not valid in the lattice's current state */
     NCO_E_UNSUPPORTED = -6  /* valid request this build does not implement */
 } nco_status;
@@ -128,7 +128,19 @@ int nco_step(nco_lattice* lat, int nsteps);
  * same, bit for bit, as from nco_step.  Asynchronous on the shared stream. */
 int nco_batch_step(nco_lattice** lats, int n, const int* nsteps);
 
-/* Block until the lattice's stream has finished its work. */
+/* Stability check.  Every `every` steps (0: off, the default) the float64
+ * global sums of the state are computed on the device, after the step, on
+ * the stream that ran it, and compared with the mass of the state at the
+ * last nco_init_* or nco_set_check call: a sum that is not finite (a NaN or
+ * infinity anywhere in the lattice) or a mass drift beyond
+ * mass_rel_tol |mass| marks the lattice unstable.  The collision conserves
+ * mass exactly (the zeroth moment relaxes with rate 1, Sec. II.B), so a
+ * drift can only come from rounding or from a blow-up.  The check adds no
+ * synchronisation; nco_sync reports it.  A new initialisation clears it. */
+int nco_set_check(nco_lattice* lat, int every, double mass_rel_tol);
+
+/* Block until the lattice's stream has finished its work.  Returns
+ * NCO_E_UNSTABLE if a stability check (nco_set_check) has failed. */
 int nco_sync(nco_lattice* lat);
 
 /* Copy the populations (27N values) to the host. */

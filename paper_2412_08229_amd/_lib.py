@@ -45,6 +45,7 @@ SIGNATURES = {
     "nco_init_populations": (_I, [_P, _D]),
     "nco_step": (_I, [_P, _I]),
     "nco_sync": (_I, [_P]),
+    "nco_set_check": (_I, [_P, _I, ctypes.c_double]),
     "nco_read_populations": (_I, [_P, _D]),
     "nco_read_macroscopic": (_I, [_P, _D, _D]),
     "nco_read_rates": (_I, [_P, _D]),
@@ -168,6 +169,10 @@ def nco_step(h, nsteps):
 
 def nco_sync(h):
     check(lib().nco_sync(h))
+
+
+def nco_set_check(h, every, mass_rel_tol):
+    check(lib().nco_set_check(h, int(every), float(mass_rel_tol)))
 
 
 def nco_read_populations(h, n):

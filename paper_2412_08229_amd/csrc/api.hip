@@ -133,6 +133,13 @@ struct nco_lattice {
     double* d_grad = nullptr;
     double* d_dE = nullptr;
     int* d_gsrc = nullptr;        // [48][27] group source row | sign bit
+    // Stability check: every check_every steps, the global sums are checked
+    // on the device against the mass at the last initialisation; a failure
+    // sets *flag, which nco_sync reports.
+    int check_every = 0;
+    double check_tol = 0.0;
+    double mass0 = 0.0;
+    long steps_since_check = 0;
 };
 
 namespace {
@@ -144,6 +151,29 @@ int check_lat(nco_lattice* lat) {
 
 int set_device(nco_lattice* lat) {
     HIP_TRY(hipSetDevice(lat->device));
+    return NCO_OK;
+}
+
+// Reference mass of the stability check (float64 sum of the state just set)
+// and a cleared flag.  Synchronous.
+int record_mass(nco_lattice* lat) {
+    const int zero = 0;
+    double sums[5];
+    HIP_TRY(launch_global_sums(lat->storage, lat->f[lat->cur], lat->partial, lat->small, lat->n, lat->stream));
+    HIP_TRY(hipMemcpyAsync(sums, lat->small, sizeof sums, hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipMemcpyAsync(lat->flag, &zero, sizeof zero, hipMemcpyHostToDevice, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->mass0 = sums[0];
+    lat->steps_since_check = 0;
+    return NCO_OK;
+}
+
+// After a step queued on stream st: the stability check when it is due.
+int maybe_check(nco_lattice* lat, hipStream_t st) {
+    if (lat->check_every <= 0 || ++lat->steps_since_check < lat->check_every) return NCO_OK;
+    lat->steps_since_check = 0;
+    HIP_TRY(launch_check_state(lat->storage, lat->f[lat->cur], lat->partial, lat->small + 8, lat->n, lat->mass0,
+                               lat->check_tol, lat->flag, st));
     return NCO_OK;
 }
 
@@ -428,7 +458,7 @@ int nco_init_equilibrium(nco_lattice* lat, const double* rho, const double* u) {
     HIP_TRY(launch_init_equilibrium(lat->storage, lat->f[lat->cur], d_rho, d_u, lat->n, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
     lat->rec_steps = -1;            // a recorded run no longer ends in this state
-    return NCO_OK;
+    return record_mass(lat);
 }
 
 int nco_init_populations(nco_lattice* lat, const double* f) {
@@ -441,7 +471,7 @@ int nco_init_populations(nco_lattice* lat, const double* f) {
     HIP_TRY(launch_from_double(lat->storage, lat->f[lat->cur], lat->staging, lat->n, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
     lat->rec_steps = -1;
-    return NCO_OK;
+    return record_mass(lat);
 }
 
 int nco_step(nco_lattice* lat, int nsteps) {
@@ -454,8 +484,18 @@ int nco_step(nco_lattice* lat, int nsteps) {
         lat->cur = 1 - lat->cur;
         ++lat->force_t;
         ++lat->steps_since_record;
+        if (int rc = maybe_check(lat, lat->stream)) return rc;
     }
     return NCO_OK;
+}
+
+int nco_set_check(nco_lattice* lat, int every, double mass_rel_tol) {
+    if (int rc = check_lat(lat)) return rc;
+    if (every < 0 || !(mass_rel_tol >= 0.0)) return fail(NCO_E_INVALID, "every must be >= 0 and tolerance >= 0");
+    if (int rc = set_device(lat)) return rc;
+    lat->check_every = every;
+    lat->check_tol = mass_rel_tol;
+    return record_mass(lat);
 }
 
 int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
@@ -536,6 +576,9 @@ int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
                 HIP_TRY(launch_nco_mfma_grouped(l0->storage, l0->mlp_prec, l0->act, g, st));
             else
                 HIP_TRY(launch_step_grouped(l0->storage, l0->op, g, st));
+            for (int idx : mem)
+                if (nsteps[idx] > s)
+                    if (int rc = maybe_check(lats[idx], st)) return rc;
         }
     }
     for (int k = 0; k < n_side; ++k) {
@@ -704,6 +747,14 @@ int nco_sync(nco_lattice* lat) {
     if (int rc = check_lat(lat)) return rc;
     if (int rc = set_device(lat)) return rc;
     HIP_TRY(hipStreamSynchronize(lat->stream));
+    if (lat->check_every > 0) {
+        int flag = 0;
+        HIP_TRY(hipMemcpyAsync(&flag, lat->flag, sizeof flag, hipMemcpyDeviceToHost, lat->stream));
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        if (flag)
+            return fail(NCO_E_UNSTABLE, "stability check failed: non-finite state or mass drift above %g",
+                        lat->check_tol);
+    }
     return NCO_OK;
 }
 

@@ -78,7 +78,10 @@ hipError_t launch_macroscopic(int storage, const void* f, double* rho, double* u
 int sums_partial_count(int n);
 hipError_t launch_global_sums(int storage, const void* f, double* partial, double* out, int n,
                               hipStream_t st);
-hipError_t launch_check_finite(int storage, const void* f, int n, int* flag, hipStream_t st);
+// Global sums into sums[0..4], then flag = 1 if they are not finite or the
+// mass left [mass0 (1 - tol), mass0 (1 + tol)].
+hipError_t launch_check_state(int storage, const void* f, double* partial, double* sums, int n, double mass0,
+                              double tol, int* flag, hipStream_t st);
 
 // Matrix-core network path (nco_mfma.hip), width 32, float32 or bf16 operands.
 size_t mfma_lane_table_floats();

@@ -256,19 +256,15 @@ __global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ p
         for (int s = 0; s < 5; ++s) out[s] = part[s][0] + part[s][1] + part[s][2] + part[s][3];
 }
 
-// Non-finite detector: any NaN/Inf population sets *flag (plain store of 1,
-// idempotent, no atomics).
-template <int S>
-__global__ __launch_bounds__(256) void k_check_finite(const typename Codec<S>::store_t* __restrict__ f,
-                                                      int n, int* __restrict__ flag) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
+// Stability check on the float64 global sums (mass, momentum, energy):
+// *flag = 1 if any is not finite (a NaN or infinity anywhere in the lattice
+// reaches every sum) or the mass has drifted from mass0 by more than
+// tol |mass0|.  One thread; a plain store, idempotent.
+__global__ void k_check_sums(const double* __restrict__ sums, double mass0, double tol, int* __restrict__ flag) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     bool bad = false;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double v = Codec<S>::to_double(f[(size_t)i * n + idx], i);
-        bad |= !(v == v) || v > 1e300 || v < -1e300;
-    }
+    for (int s = 0; s < 5; ++s) bad |= !(sums[s] - sums[s] == 0.0);
+    bad |= !(fabs(sums[0] - mass0) <= tol * fabs(mass0));
     if (bad) *flag = 1;
 }
 
@@ -401,12 +397,11 @@ hipError_t launch_global_sums(int storage, const void* f, double* partial, doubl
     })
 }
 
-hipError_t launch_check_finite(int storage, const void* f, int n, int* flag, hipStream_t st) {
-    DISPATCH_STORAGE(storage, {
-        hipLaunchKernelGGL(k_check_finite<SS>, dim3(nblocks(n)), dim3(256), 0, st,
-                           static_cast<const typename Codec<SS>::store_t*>(f), n, flag);
-        return hipGetLastError();
-    })
+hipError_t launch_check_state(int storage, const void* f, double* partial, double* sums, int n, double mass0,
+                              double tol, int* flag, hipStream_t st) {
+    if (hipError_t e = launch_global_sums(storage, f, partial, sums, n, st)) return e;
+    hipLaunchKernelGGL(k_check_sums, dim3(1), dim3(64), 0, st, sums, mass0, tol, flag);
+    return hipGetLastError();
 }
 
 }  // namespace nco

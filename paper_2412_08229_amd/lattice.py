@@ -87,6 +87,11 @@ class Lattice:
     def sync(self):
         L.nco_sync(self._h)
 
+    def set_check(self, every, mass_rel_tol):
+        """Stability check every ``every`` steps (0: off); ``sync`` raises
+        NCOError(NCO_E_UNSTABLE) once it has failed."""
+        L.nco_set_check(self._h, every, mass_rel_tol)
+
     def populations(self):
         return L.nco_read_populations(self._h, self.n).reshape((27,) + self.shape)
 

@@ -76,12 +76,15 @@ def poisson_requests(count, rate, seed, grids=GRIDS, re=(400.0, 3000.0), steps=(
 class GpuEngine:
     """libnco.so lattices on one stream, batched with nco_batch_step."""
 
-    def __init__(self, width=32, seed=0, stream=None):
+    def __init__(self, width=32, seed=0, stream=None, check_every=50, mass_tol=1e-3):
+        """check_every, mass_tol: the library's stability check on every
+        solve (a request whose state blows up ends as "unstable")."""
         from . import _lib
         self._lib = _lib
         self.params = inputs.mlp_params(width, seed)
         self.width = width
         self.stream = stream
+        self.check_every, self.mass_tol = check_every, mass_tol
 
     def bytes(self, req):
         storage = CLASSES[req.cls][0]
@@ -104,18 +107,32 @@ class GpuEngine:
         lat = Lattice((req.n, req.n, req.n), storage, "nco", tau, stream=self.stream)
         lat.set_net_weights(self.params, self.width, "tanh", mlp)
         lat.init_equilibrium(rho, u)
+        lat.set_check(self.check_every, self.mass_tol)
         return lat
 
     def step_batch(self, lats, steps, overlap=None):
-        """Queue one round, run ``overlap`` on the host meanwhile, then wait."""
+        """Queue one round, run ``overlap`` on the host meanwhile, then wait.
+        Returns the indices of lattices whose stability check failed."""
         batch_step(lats, steps)
         if overlap is not None:
             overlap()
-        if lats:
-            lats[0].sync()
+        unstable = []
+        for i, lat in enumerate(lats):
+            try:
+                lat.sync()
+            except self._lib.NCOError as e:
+                if e.status != self._lib.NCO_E_UNSTABLE:
+                    raise
+                unstable.append(i)
+        return unstable
 
     def result(self, lat):
-        s = lat.global_sums()
+        try:
+            s = lat.global_sums()
+        except self._lib.NCOError as e:
+            if e.status != self._lib.NCO_E_UNSTABLE:
+                raise
+            return {}
         return {"mass": float(s[0]), "momentum": [float(v) for v in s[1:4]],
                 "kinetic_energy": float(s[4] / lat.n)}
 
@@ -202,19 +219,25 @@ class Server:
                     sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.05)))
                 continue
             steps = [min(self.chunk, a[2]) for a in active]
-            self.engine.step_batch([a[1] for a in active], steps, overlap=None if pool else prepare_arrived)
+            unstable = self.engine.step_batch([a[1] for a in active], steps,
+                                              overlap=None if pool else prepare_arrived)
+            unstable = set(unstable or ())
             node_steps += sum(a[0].n ** 3 * s for a, s in zip(active, steps))
             still = []
-            for a, s in zip(active, steps):
+            for i, (a, s) in enumerate(zip(active, steps)):
                 a[2] -= s
-                if a[2] > 0:
+                if a[2] > 0 and i not in unstable:
                     still.append(a)
                     continue
                 req = a[0]
-                res = self.engine.result(a[1])
-                req.result = res
-                vals = np.hstack([np.ravel(v) for v in res.values()])
-                req.status = "done" if np.all(np.isfinite(vals)) else "unstable"
+                if i in unstable:
+                    # Failed stability check: the request ends here and frees its slot.
+                    req.result, req.status = {}, "unstable"
+                else:
+                    res = self.engine.result(a[1])
+                    req.result = res
+                    vals = np.hstack([np.ravel(v) for v in res.values()]) if res else np.array([np.nan])
+                    req.status = "done" if np.all(np.isfinite(vals)) else "unstable"
                 req.finished = clock() - t0
                 self.engine.destroy(a[1])
                 used -= a[3]

@@ -168,3 +168,24 @@ def test_threaded_preparation():
     assert sorted(eng.prepared) == list(range(25))
     adm = [r.admitted for r in sorted(reqs, key=lambda r: r.arrival)]
     assert adm == sorted(adm) and not eng.live
+
+
+class UnstableEngine(SimEngine):
+    """Reports request 1 unstable after its first round."""
+
+    def step_batch(self, handles, steps, overlap=None):
+        super().step_batch(handles, steps, overlap)
+        return [i for i, h in enumerate(handles) if self.live[h][0].rid == 1]
+
+
+def test_unstable_request_frees_its_slot():
+    reqs = [serve.Request(rid=i, arrival=0.0, n=16, re=1000.0, steps=100, flow="tgv", cls="f32") for i in range(3)]
+    clk = Clock()
+    eng = UnstableEngine(clk)
+    one = eng.bytes(reqs[0])
+    rep = serve.Server(eng, 2 * one, max_slots=2, chunk=10).run(reqs, clock=clk, sleep=clk.sleep)
+    assert rep["status"] == {"done": 2, "unstable": 1}
+    assert reqs[1].status == "unstable" and reqs[1].result == {}
+    # Its slot went to request 2 after one round, not after 100 steps.
+    assert reqs[2].admitted < reqs[0].finished
+    assert rep["latency_s"]["all"]["count"] == 2 and not eng.live
