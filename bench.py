@@ -52,6 +52,11 @@ VARIANTS = {
     "mrt_256": ("mrt", "f32", None, None),
 }
 GRID = {"bgk_256": 256, "mrt_256": 256}
+# The paper's own network, 27-20-20-4 with ReLU (zero-padded to width 32 on
+# the matrix cores).
+VARIANTS["nco_w20_relu"] = ("nco", "f32", "f32_mfma", "relu")
+VARIANTS["nco_w20_relu_bf16net"] = ("nco", "f32", "bf16", "relu")
+NET_WIDTH = {"nco_w20_relu": 20, "nco_w20_relu_bf16net": 20}
 
 
 def nco_flops_per_node(width):
@@ -144,7 +149,8 @@ def main():
         tau_op, rho_op, u_op = fields[n_op]
         lat = Lattice((n_op, n_op, n_op), storage, kind, tau_op, stream=stream)
         if kind == "nco":
-            lat.set_net_weights(params, width, act, mlp)
+            w_op = NET_WIDTH.get(op, width)
+            lat.set_net_weights(params if w_op == width else inputs.mlp_params(w_op, seed=0), w_op, act, mlp)
         if kind == "mrt":
             lat.set_rates([4.0 / 3.0] * 4)
         lat.init_equilibrium(rho_op, u_op)
@@ -164,6 +170,7 @@ def main():
         results[op] = {"ms_per_step": ms, "glups": glups, "hbm_gbs": gbs, "lattice": n_op,
                        "hbm_frac": gbs / HBM_PEAK_GBS, "steps": steps, "storage": storage,
                        "network": mlp if kind == "nco" else None,
+                       "width": NET_WIDTH.get(op, width) if kind == "nco" else None,
                        "activation": act if kind == "nco" else None}
         print("# %s: %.4f ms/step, %.3f GLUPS, %.0f GB/s" % (op, ms, glups, gbs), file=sys.stderr,
               flush=True)

@@ -99,7 +99,10 @@ int nco_set_rates(nco_lattice* lat, const double omega_high[4]);
  * W1[27][width], b1[width], W2[width][width], b2[width], W3[width][4], b3[4]
  * (each W stored [in][out] row-major).  The input is the full moment vector
  * m^(g) = M Pi_g f in the row order of M; the output is tilde tau_n for the
- * orders 3..6.  width must be 8, 16, 20 or 32. */
+ * orders 3..6.  width must be 8, 16, 20 or 32 (the paper's network is
+ * width 20 with ReLU).  The matrix-core arithmetics (NCO_MLP_F32_MFMA,
+ * NCO_MLP_BF16) need float32 or 16-bit storage and run narrower networks
+ * zero-padded to width 32, at the cost of width 32. */
 int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec,
                         const float* params, size_t n_params);
 

@@ -386,8 +386,8 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
     if (act != NCO_ACT_TANH && act != NCO_ACT_RELU) return fail(NCO_E_INVALID, "unknown activation %d", act);
     if (mlp_prec != NCO_MLP_F32 && mlp_prec != NCO_MLP_F32_MFMA && mlp_prec != NCO_MLP_BF16)
         return fail(NCO_E_INVALID, "unknown network precision %d", mlp_prec);
-    if (mlp_prec != NCO_MLP_F32 && (width != 32 || lat->storage == NCO_F64))
-        return fail(NCO_E_UNSUPPORTED, "the matrix-core network needs width 32 and float storage");
+    if (mlp_prec != NCO_MLP_F32 && lat->storage == NCO_F64)
+        return fail(NCO_E_UNSUPPORTED, "the matrix-core network needs float32 or 16-bit storage");
     if (!params) return fail(NCO_E_INVALID, "null parameters");
     if (n_params != n_params_for(width))
         return fail(NCO_E_INVALID, "expected %zu parameters for width %d, got %zu", n_params_for(width),
@@ -436,7 +436,32 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
     if (mlp_prec != NCO_MLP_F32) {
         const size_t nf = mfma_lane_table_floats(), ni = mfma_group_table_ints();
         std::vector<char> tab(sizeof(float) * nf + sizeof(int) * ni);
-        mfma_prepare_tables(params, act, mlp_prec, G.src, reinterpret_cast<float*>(tab.data()),
+        // Narrower networks run zero-padded to width 32: a padded hidden unit
+        // has zero weights and bias and zero outgoing weights, so it adds
+        // nothing to the next layer for either activation.
+        std::vector<float> padded;
+        const float* p32 = params;
+        if (W < 32) {
+            const int P = 32;
+            padded.assign(n_params_for(P), 0.0f);
+            float* q = padded.data();
+            for (int k = 0; k < 27; ++k)
+                for (int h = 0; h < W; ++h) q[k * P + h] = W1[k * W + h];
+            q += 27 * P;
+            for (int h = 0; h < W; ++h) q[h] = b1[h];
+            q += P;
+            for (int i = 0; i < W; ++i)
+                for (int o = 0; o < W; ++o) q[i * P + o] = W2[i * W + o];
+            q += P * P;
+            for (int o = 0; o < W; ++o) q[o] = b2[o];
+            q += P;
+            for (int i = 0; i < W; ++i)
+                for (int n = 0; n < 4; ++n) q[i * 4 + n] = W3[i * 4 + n];
+            q += 4 * P;
+            for (int n = 0; n < 4; ++n) q[n] = b3[n];
+            p32 = padded.data();
+        }
+        mfma_prepare_tables(p32, act, mlp_prec, G.src, reinterpret_cast<float*>(tab.data()),
                             reinterpret_cast<int*>(tab.data() + sizeof(float) * nf));
         if (!lat->mfma_tab) HIP_TRY(hipMalloc(&lat->mfma_tab, tab.size()));
         HIP_TRY(hipMemcpyAsync(lat->mfma_tab, tab.data(), tab.size(), hipMemcpyHostToDevice, lat->stream));
