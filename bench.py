@@ -110,8 +110,69 @@ def cpu_baseline(n_sample=64, nsteps=6):
                       % (n_sample, nsteps, dt)}
 
 
+def precision_horizon(n, convective_times, every, f64_steps):
+    """Reduced-precision forms over a long Taylor-Green run (Re 1600, Ma 0.1)
+    against the float32 path: kinetic energy k(t) every ``every`` steps, the
+    mean dissipation rate over each tenth of the run, the energy spectrum at
+    the end, and wall time.  The float32 path itself is compared with the
+    library's float64 path (float64 storage and arithmetic) over the first
+    ``f64_steps`` steps.  Prints one JSON line."""
+    import torch
+    from paper_2412_08229_amd import Lattice, inputs
+
+    u0 = 0.1 / math.sqrt(3.0)
+    _, tau = inputs.viscosity(n, u0, 1600.0)
+    rho, u = inputs.tgv3d(n, u0)
+    t_c = n / (2 * math.pi) / u0                       # steps per convective time L / u0
+    nsteps = int(round(convective_times * t_c / every)) * every
+    stream = torch.cuda.Stream().cuda_stream
+    params = inputs.mlp_params(32, seed=0)
+
+    def run(storage, mlp, steps, samples):
+        with Lattice((n, n, n), storage, "nco", tau, stream=stream) as lat:
+            lat.set_net_weights(params, 32, "tanh", mlp)
+            lat.init_equilibrium(rho, u)
+            ke = [lat.global_sums()[4] / lat.n]
+            t0 = time.perf_counter()
+            for i in range(steps // samples):
+                lat.step(samples)
+                ke.append(lat.global_sums()[4] / lat.n)
+                if (i + 1) % 10 == 0:
+                    print("# %s/%s: step %d" % (storage, mlp, (i + 1) * samples), file=sys.stderr, flush=True)
+            wall = time.perf_counter() - t0
+            print("# %s/%s: %d steps in %.1f s" % (storage, mlp, steps, wall), file=sys.stderr, flush=True)
+            return np.array(ke), lat.energy_spectrum(), wall
+
+    out = {"workload": "Taylor-Green vortex %d^3, Re 1600, Ma 0.1, NCO 27-32-32-4 tanh" % n,
+           "steps": nsteps, "convective_times": nsteps / t_c, "sample_every": every}
+    if f64_steps > 0:
+        k64, e64, _ = run("f64", "f32", f64_steps, f64_steps // 4)
+        k32, e32, _ = run("f32", "f32_mfma", f64_steps, f64_steps // 4)
+        out["f32_vs_f64"] = {"steps": f64_steps, "kinetic_energy_err": float(np.max(np.abs(k32 - k64) / k64)),
+                             "spectrum_err": float(np.abs(e32 - e64).sum() / e64.sum())}
+    ref = run("f32", "f32_mfma", nsteps, every)
+    out["f32/f32_mfma"] = {"wall_s": ref[2], "kinetic_energy_final": float(ref[0][-1] / ref[0][0])}
+    seg = len(ref[0]) // 10
+    for storage, mlp in [("f32", "bf16"), ("f16", "bf16"), ("bf16", "bf16")]:
+        ke, spec, wall = run(storage, mlp, nsteps, every)
+        d = [(ke[i * seg] - ke[(i + 1) * seg]) for i in range(10)]
+        d_r = [(ref[0][i * seg] - ref[0][(i + 1) * seg]) for i in range(10)]
+        sh = np.arange(len(spec))
+        sh = sh[(sh >= 1) & (sh <= n // 4) & (ref[1] >= 1e-6 * ref[1].max())]
+        out["%s/%s" % (storage, mlp)] = {
+            "kinetic_energy_err": float(np.max(np.abs(ke - ref[0]) / ref[0])),
+            "dissipation_err_per_tenth": float(max(abs(a - b) / abs(b) for a, b in zip(d, d_r))),
+            "spectrum_err": float(np.abs(spec - ref[1]).sum() / ref[1].sum()),
+            "spectrum_max_shell_err": float(np.max(np.abs(spec[sh] - ref[1][sh]) / ref[1][sh])),
+            "wall_s": wall, "speedup": ref[2] / wall}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--precision-horizon", type=float, default=0.0,
+                    help="instead of the benchmark: the reduced-precision study over this many convective times")
+    ap.add_argument("--f64-steps", type=int, default=20)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
@@ -123,6 +184,9 @@ def main():
         print("bench.py measures one GPU only: the lattice path runs on a single MI355X; "
               "multi-GPU domain decomposition is not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.precision_horizon > 0:
+        precision_horizon(args.n, args.precision_horizon, 100, args.f64_steps)
+        return
 
     import torch
     from paper_2412_08229_amd import Lattice, inputs
