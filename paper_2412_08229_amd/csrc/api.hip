@@ -133,6 +133,10 @@ struct nco_lattice {
     double* d_grad = nullptr;
     double* d_dE = nullptr;
     int* d_gsrc = nullptr;        // [48][27] group source row | sign bit
+    // Matrix-core adjoint: float32 forward tables and the adjoint table
+    // (width-32 networks on matrix cores), float64 per-block gradient rows.
+    void* adj_tab = nullptr;
+    double* adj_partial64 = nullptr;
     // Stability check: every check_every steps, the global sums are checked
     // on the device against the mass at the last initialisation; a failure
     // sets *flag, which nco_sync reports.
@@ -343,6 +347,8 @@ int nco_lattice_destroy(nco_lattice* lat) {
     if (lat->partial) hipFree(lat->partial);
     if (lat->small) hipFree(lat->small);
     if (lat->flag) hipFree(lat->flag);
+    if (lat->adj_tab) hipFree(lat->adj_tab);
+    if (lat->adj_partial64) hipFree(lat->adj_partial64);
     if (lat->spec_work) hipFree(lat->spec_work);
     if (lat->d_fk) hipFree(lat->d_fk);
     if (lat->d_fhat) hipFree(lat->d_fhat);
@@ -466,6 +472,20 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
         if (!lat->mfma_tab) HIP_TRY(hipMalloc(&lat->mfma_tab, tab.size()));
         HIP_TRY(hipMemcpyAsync(lat->mfma_tab, tab.data(), tab.size(), hipMemcpyHostToDevice, lat->stream));
         HIP_TRY(hipStreamSynchronize(lat->stream));
+        if (W == 32) {
+            // Reverse mode on the matrix cores: the float32 forward tables
+            // (also for a bf16 network) and the adjoint's own table.
+            const size_t na = mfma_adjoint_table_floats();
+            std::vector<char> at(sizeof(float) * (nf + na) + sizeof(int) * ni);
+            float* lt32 = reinterpret_cast<float*>(at.data());
+            int* gt32 = reinterpret_cast<int*>(at.data() + sizeof(float) * nf);
+            float* adj = reinterpret_cast<float*>(at.data() + sizeof(float) * nf + sizeof(int) * ni);
+            mfma_prepare_tables(params, act, NCO_MLP_F32_MFMA, G.src, lt32, gt32);
+            mfma_prepare_adjoint_table(params, adj);
+            if (!lat->adj_tab) HIP_TRY(hipMalloc(&lat->adj_tab, at.size()));
+            HIP_TRY(hipMemcpyAsync(lat->adj_tab, at.data(), at.size(), hipMemcpyHostToDevice, lat->stream));
+            HIP_TRY(hipStreamSynchronize(lat->stream));
+        }
     }
     return NCO_OK;
 }
@@ -714,8 +734,19 @@ int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double*
     }
     for (int b = 0; b < 2; ++b)
         if (!lat->lam[b]) HIP_TRY(hipMalloc(&lat->lam[b], sizeof(float) * nf));
-    const int nblk = adjoint_blocks(lat->n);
-    if (!lat->adj_partial) HIP_TRY(hipMalloc(&lat->adj_partial, sizeof(float) * (size_t)nblk * adjoint_param_count()));
+    // Matrix-core adjoint for matrix-core networks, vector-unit adjoint for
+    // the vector-unit network.
+    const bool mfma = lat->mlp_prec != NCO_MLP_F32 && lat->adj_tab;
+    const int npar = adjoint_param_count();
+    const int nblk = mfma ? adjoint_mfma_blocks(lat->n) : adjoint_blocks(lat->n);
+    const int ngrp = (nblk + 63) / 64;
+    if (mfma) {
+        if (!lat->adj_partial64)
+            HIP_TRY(hipMalloc(&lat->adj_partial64, sizeof(double) * (size_t)(nblk + ngrp) * npar));
+        HIP_TRY(launch_fill_f64(lat->adj_partial64, (size_t)nblk * npar, 0.0, lat->stream));
+    } else if (!lat->adj_partial) {
+        HIP_TRY(hipMalloc(&lat->adj_partial, sizeof(float) * (size_t)nblk * npar));
+    }
     if (!lat->d_grad) HIP_TRY(hipMalloc(&lat->d_grad, sizeof(double) * adjoint_param_count()));
     while ((int)lat->seg.size() < lat->rec_every) {
         void* p = nullptr;
@@ -751,12 +782,25 @@ int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double*
             if (int rc = launch_one(lat, lat->seg[i - 1], lat->seg[i], lat->rec_force_t0 + t0 + i - 1)) return rc;
         for (int t = t0 + len - 1; t >= t0; --t) {
             const StepArgs a = step_args_at(lat, lat->rec_force_t0 + t);
-            HIP_TRY(launch_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_gsrc, lat->adj_partial,
-                                   lat->stream));
-            HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, lat->d_grad, lat->stream));
+            if (mfma) {
+                const char* tab = static_cast<const char*>(lat->adj_tab);
+                const float* lt32 = reinterpret_cast<const float*>(tab);
+                const int* gt32 = reinterpret_cast<const int*>(tab + sizeof(float) * mfma_lane_table_floats());
+                const float* adj = reinterpret_cast<const float*>(tab + sizeof(float) * mfma_lane_table_floats() +
+                                                                  sizeof(int) * mfma_group_table_ints());
+                HIP_TRY(launch_adjoint_mfma(lat->storage, lat->act, lat->seg[t - t0], lin, lout, a, lt32, gt32, adj,
+                                            lat->d_gsrc, lat->adj_partial64, lat->stream));
+            } else {
+                HIP_TRY(launch_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_gsrc, lat->adj_partial,
+                                       lat->stream));
+                HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, lat->d_grad, lat->stream));
+            }
             std::swap(lin, lout);
         }
     }
+    if (mfma)
+        HIP_TRY(launch_grad_reduce_f64(lat->adj_partial64, nblk, lat->adj_partial64 + (size_t)nblk * npar,
+                                       lat->d_grad, lat->stream));
     HIP_TRY(hipMemcpyAsync(grad, lat->d_grad, sizeof(double) * adjoint_param_count(), hipMemcpyDeviceToHost,
                            lat->stream));
     if (dL_df0) {

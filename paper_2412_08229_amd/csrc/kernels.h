@@ -98,6 +98,20 @@ int adjoint_blocks(int n);
 hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
                           const int* gsrc, float* partial, hipStream_t st);
 hipError_t launch_grad_reduce(const float* partial, int nblocks, double* grad, hipStream_t st);
+// grad = sum over rows of partial[nblocks][NPAR] (float64) in row order, in
+// two passes over groups of 64 rows; stage holds ceil(nblocks / 64) rows.
+hipError_t launch_grad_reduce_f64(const double* partial, int nblocks, double* stage, double* grad, hipStream_t st);
+
+// The same adjoint on the matrix cores (nco_mfma.hip): 256 nodes per block;
+// lane_tab and gtab are the float32 forward tables of mfma_prepare_tables,
+// adj_tab the table of mfma_prepare_adjoint_table; the step's parameter
+// gradient is added to partial[block][NPAR].
+size_t mfma_adjoint_table_floats();
+void mfma_prepare_adjoint_table(const float* params, float* tab);
+int adjoint_mfma_blocks(int n);
+hipError_t launch_adjoint_mfma(int storage, int act, const void* xin, const float* lam_in, float* lam_out,
+                               const StepArgs& a, const float* lane_tab, const int* gtab, const float* adj_tab,
+                               const int* gsrc, double* partial, hipStream_t st);
 hipError_t launch_fill_f32(float* p, size_t count, float v, hipStream_t st);
 hipError_t launch_fill_f64(double* p, size_t count, double v, hipStream_t st);
 hipError_t launch_add_f64_to_f32(float* dst, const double* src, size_t count, hipStream_t st);

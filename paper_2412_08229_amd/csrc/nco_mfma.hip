@@ -41,6 +41,7 @@
 // cheap), relaxes with the rates and stores.
 #include <cstring>
 
+#include "adjoint.h"
 #include "kernels.h"
 #include "stream.h"
 
@@ -112,7 +113,9 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
 }
 
 // Output layer on the group sum of one node tile and the rate squashing;
-// lanes of group q = 0 write the four rates of node (tile, c) to LDS.
+// lanes of group q = 0 write the four rates of node (tile, c) to LDS, or with
+// RAW the pre-squash outputs tilde tau_n (for the adjoint).
+template <bool RAW = false>
 __device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float* __restrict__ w3,
                                              const float* __restrict__ b3, int q, float* __restrict__ sw_node) {
     float pn[4];
@@ -131,15 +134,18 @@ __device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float*
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             const float t = pn[n] + b3[n];
-            sw_node[n] = 1.0f / (0.5f + 0.5f / (1.0f + expf(t)));
+            sw_node[n] = RAW ? t : 1.0f / (0.5f + 0.5f / (1.0f + expf(t)));
         }
     }
 }
 
+// s2 != nullptr (adjoint): sw receives tilde tau instead of the rates and
+// s2[node][32] the group sum of the folded second-layer activations (row
+// 16 u + 4 q + r in lane (q, c)).
 template <int ACT>
 __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const int* __restrict__ sg,
                                             float* __restrict__ sw, const float* __restrict__ lt, int wave,
-                                            int q, int c) {
+                                            int q, int c, float* __restrict__ s2 = nullptr) {
     float A1[2][KSTEPS], A2[2][2][4], B2[2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -232,7 +238,15 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(c2p[u][r]);
         }
-        output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
+        if (s2) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) s2[node * 32 + 16 * u + 4 * q + r] = acc[u][r];
+            output_layer<true>(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
+        } else {
+            output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
+        }
     }
 }
 
@@ -425,6 +439,447 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
     }
 }
 
+// ---------------------------------------------------------------- adjoint --
+//
+// Reverse mode of one step on the matrix cores (float32), the same
+// computation as the vector-unit adjoint (adjoint.hip): given lambda =
+// dL/dx_t+1, the pre-collision adjoint M^T g_m + lambda is scattered back
+// along the streaming, and the parameter gradient of this step is added to
+// the block's row of `partial` (float64, one row per block, each row touched
+// by its block only, so the sum over steps is in a fixed order).
+//
+// Per node tile of 16 and group element g = (pi, s), in the layout of the
+// forward network (hidden x nodes, lane (q, c) holding rows 4q..4q+3 of
+// node c):
+//   forward recompute   r1 = act(Z1), r2 = act(Z2)          (forward tables)
+//   dz2 = dh2 (.) act'(z2),   dh2 = W3 dtt / 48 (the same for every g)
+//   dh1 = W2 dz2,   dz1 = dh1 (.) act'(z1),   dx = W1 dz1   (three products
+//         whose B operands are the previous accumulators, as in the forward)
+//   dL/dm[src_pi(k)] += sum_s chi_s(class k) dx_s[k]        (through LDS)
+//   dW2 += h1 dz2^T, dW1 += x_g dz1^T (the bias row of x_g gives db1),
+//   db2 += dz2                                               (products over
+//         the 16 nodes of the tile: h1, dz2 and dz1 are transposed through
+//         a per-wave LDS buffer so that the node index becomes K)
+// For tanh, with r = 1 / (1 + 2^(kappa z)): h = 1 - 2 r, act' = 4 r (1 - r).
+
+// Per-lane table of the adjoint (4-byte words per lane).
+constexpr int AT_W2T = 0;           // [t 2][u 2][r 4]  W2[16 t + c][16 u + 4 q + r]
+constexpr int AT_W1T = 16;          // [kt 2][t 2][r 4] W1[16 kt + c][16 t + 4 q + r] (rows >= 27: 0)
+constexpr int AT_W3 = 32;           // [u 2][r 4][n 4]  W3[16 u + 4 q + r][n] / 48
+constexpr int AT_CLS = 64;          // [kt 2][r 4]      parity class of row 16 kt + 4 q + r (int)
+constexpr int AT_CLSC = 72;         // [kt 2]           parity class of row 16 kt + c (int)
+constexpr int ADJ_WORDS = 76;
+constexpr int TB = 33;              // row stride of the per-wave transpose buffers
+
+// chi_s(cls) = (-1)^popcount(s & cls) as a float sign.
+__device__ __forceinline__ float refl_sign(int s, int cls) {
+    return (__builtin_popcount(s & cls) & 1) ? -1.0f : 1.0f;
+}
+
+template <int ACT>
+__device__ __forceinline__ float act_grad(float r) {
+    if constexpr (ACT == ACT_RELU)
+        return r > 0.0f ? 1.0f : 0.0f;
+    else
+        return 4.0f * r * (1.0f - r);
+}
+
+template <int ACT>
+__device__ __forceinline__ float act_value(float r) {
+    if constexpr (ACT == ACT_RELU)
+        return r;
+    else
+        return 1.0f - 2.0f * r;
+}
+
+template <int S, int ACT>
+__global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::store_t* __restrict__ xin,
+                                                      const float* __restrict__ lam_in, float* __restrict__ lam_out,
+                                                      StepArgs a, const float* __restrict__ lane_tab,
+                                                      const int* __restrict__ gtab, const float* __restrict__ adj_tab,
+                                                      const int* __restrict__ gsrc, double* __restrict__ partial) {
+    __shared__ float sm[256 * NODE_STRIDE];     // moments (row order of M; [27] = 1, [28] = 0)
+    __shared__ int sg[GT_ENTRIES];              // forward gather table
+    __shared__ int sgs[6 * 27];                 // source rows of the reflection-free elements g = 8 pi
+    __shared__ float sw[256 * 4];               // tilde tau, then dL/d tilde tau
+    __shared__ float som[256 * 4];              // rates omega_3..omega_6
+    __shared__ float sF[256 * 3];               // body force
+    __shared__ float sdm[256 * 32];             // group sums of the second layer, then dL/dm (network part)
+    __shared__ float sbuf[4][3][16 * TB];       // per-wave transposes
+    const int tid = threadIdx.x;
+    const int idx = blockIdx.x * 256 + tid;
+    const bool live = idx < a.n;
+    const NodeIdx p = node_of(live ? idx : 0, a.nx, a.ny);
+
+    for (int e = tid; e < GT_ENTRIES; e += 256) sg[e] = gtab[e];
+    for (int e = tid; e < 6 * 27; e += 256) sgs[e] = gsrc[(e / 27) * 8 * 27 + e % 27] & 31;
+    // Phase A: moments of the pulled state, body force.
+    {
+        float f[Q], m[Q];
+        if (live) {
+            pull<S>(xin, a, p, f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[i] = (float)weight_of(i);
+        }
+        to_moments(f, m);
+        float* row = sm + tid * NODE_STRIDE;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) row[k] = m[row_tensor(k)];
+        row[27] = 1.0f;
+        row[28] = 0.0f;
+        double Fd[3] = {0.0, 0.0, 0.0};
+        if (a.n_modes > 0 && live) force_at(a, p.x, p.y, p.z, Fd[0], Fd[1], Fd[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sF[tid * 3 + d] = (float)Fd[d];
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
+    // Phase B1: the network forward for tilde tau and the group sums.
+    network_f32<ACT>(sm, sg, sw, lane_tab + lane * LANE_WORDS, wave, q, c, sdm);
+    __syncthreads();
+
+    // Phase B2: per node, dL/d tilde tau from the node-local collision adjoint.
+    {
+        float m[Q], lam[Q], nu[Q], gm[Q], omega[4], tau[4], e[4], domega[4];
+        const float* row = sm + tid * NODE_STRIDE;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) m[row_tensor(k)] = row[k];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            e[n] = expf(sw[tid * 4 + n]);
+            tau[n] = 0.5f + 0.5f / (1.0f + e[n]);
+            omega[n] = 1.0f / tau[n];
+            som[tid * 4 + n] = omega[n];
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[i] = live ? lam_in[(size_t)i * a.n + idx] : 0.0f;
+        inverse_T(lam, nu);
+        const float F[3] = {sF[tid * 3], sF[tid * 3 + 1], sF[tid * 3 + 2]};
+        collision_vjp_local(m, nu, a.omega_nu_f, omega, a.n_modes > 0, F, gm, domega);
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+            sw[tid * 4 + n] = domega[n] * 0.5f * e[n] / ((1.0f + e[n]) * (1.0f + e[n]) * tau[n] * tau[n]);
+    }
+    __syncthreads();
+
+    // Output layer: dW3 = sum (H2 / 48) dtt^T with H2 the group sum of the
+    // (unfolded) second-layer activations, db3 = sum dtt.
+    double* __restrict__ out = partial + (size_t)blockIdx.x * NPAR;
+    if (tid < 132) {
+        double sacc = 0.0;
+        if (tid < 128) {
+            const int o = tid >> 2, n = tid & 3;
+            float v = 0.0f;
+            for (int nd = 0; nd < 256; ++nd) {
+                const float acc = sdm[nd * 32 + o];
+                const float h2 = ACT == ACT_RELU ? acc : (float)NGROUP - 2.0f * acc;
+                v = fmaf(h2 * (1.0f / NGROUP), sw[nd * 4 + n], v);
+            }
+            sacc = v;
+            out[OFF_W3 + o * 4 + n] += sacc;
+        } else {
+            const int n = tid - 128;
+            float v = 0.0f;
+            for (int nd = 0; nd < 256; ++nd) v += sw[nd * 4 + n];
+            out[OFF_B3 + n] += (double)v;
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < 32; ++k) sdm[tid * 32 + k] = 0.0f;
+    __syncthreads();
+
+    // Phase B3: the network adjoint on the matrix cores.
+    f32x4 gW2[2][2], gW1[2][2];
+    float gb2[2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            gW2[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+            gW1[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gb2[u][r] = 0.0f;
+    {
+        const float* __restrict__ lt = lane_tab + lane * LANE_WORDS;
+        const float* __restrict__ at = adj_tab + lane * ADJ_WORDS;
+        const int* __restrict__ ati = reinterpret_cast<const int*>(at);
+        float A1[2][KSTEPS], A2[2][2][4], B2[2][4], W2T[2][2][4], W1T[2][2][4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    A2[u][t][r] = lt[LT_A2 + u * 8 + t * 4 + r];
+                    W2T[t][u][r] = at[AT_W2T + t * 8 + u * 4 + r];
+                    W1T[u][t][r] = at[AT_W1T + u * 8 + t * 4 + r];
+                }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) B2[u][r] = lt[LT_B2 + u * 4 + r];
+        int cls[2][4], clsc[2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            clsc[kt] = ati[AT_CLSC + kt];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cls[kt][r] = ati[AT_CLS + kt * 4 + r];
+        }
+        float* __restrict__ bh = sbuf[wave][0];
+        float* __restrict__ bz2 = sbuf[wave][1];
+        float* __restrict__ bz1 = sbuf[wave][2];
+
+#pragma unroll 1
+        for (int j = 0; j < 4; ++j) {
+            const int base = wave * 64 + j * 16;
+            const int node = base + c;
+            const float* __restrict__ mrow = sm + node * NODE_STRIDE;
+            // dh2 = W3 dtt / 48 for this lane's rows.
+            float dh2[2][4];
+            {
+                float dt[4];
+#pragma unroll
+                for (int n = 0; n < 4; ++n) dt[n] = sw[node * 4 + n];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float v = 0.0f;
+#pragma unroll
+                        for (int n = 0; n < 4; ++n) v = fmaf(at[AT_W3 + (u * 4 + r) * 4 + n], dt[n], v);
+                        dh2[u][r] = v;
+                    }
+            }
+#pragma unroll 1
+            for (int pi = 0; pi < 6; ++pi) {
+                // Layer 1 of the eight reflections (as in the forward).
+                const int* __restrict__ ge = sg + (pi * 4 + q) * GT_STRIDE;
+                float b[KSTEPS];
+#pragma unroll
+                for (int st = 0; st < KSTEPS; ++st) b[st] = mrow[ge[st]];
+                f32x4 Y[8][2];
+#pragma unroll
+                for (int ci = 0; ci < 8; ++ci) {
+                    Y[ci][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    Y[ci][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+                for (int st = 0; st < KSTEPS; ++st)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) Y[step_class(st)][t] = mfma4(A1[t][st], b[st], Y[step_class(st)][t]);
+#pragma unroll
+                for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+                    for (int ci = 0; ci < 8; ++ci)
+                        if (!(ci & bit))
+#pragma unroll
+                            for (int t = 0; t < 2; ++t) {
+                                const f32x4 u0 = Y[ci][t], u1 = Y[ci | bit][t];
+                                Y[ci][t] = u0 + u1;
+                                Y[ci | bit][t] = u0 - u1;
+                            }
+                // x_pi (reflection-free input) in the A layout of the dW1
+                // product: row 16 kt + c, node 4 st + q of the tile.
+                float xa[2][4];
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) {
+                    const int k = 16 * kt + c;
+                    const int src = k < 27 ? sgs[pi * 27 + k] : (k == 27 ? 27 : 28);
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) xa[kt][st] = sm[(base + 4 * st + q) * NODE_STRIDE + src];
+                }
+                float D[2][4];
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) D[kt][r] = 0.0f;
+
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    float r1[2][4], d1[2][4];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            r1[t][r] = act_scaled<ACT>(Y[s][t][r]);
+                            d1[t][r] = act_grad<ACT>(r1[t][r]);
+                        }
+                    f32x4 c2[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int u = 0; u < 2; ++u) c2[u] = mfma4(A2[u][t][r], r1[t][r], c2[u]);
+                    float dz2[2][4];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            dz2[u][r] = dh2[u][r] * act_grad<ACT>(act_scaled<ACT>(c2[u][r]));
+                            gb2[u][r] += dz2[u][r];
+                        }
+                    // dh1 = W2 dz2, dz1 = dh1 act'(z1).
+                    f32x4 h[2];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        h[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) h[t] = mfma4(W2T[t][u][r], dz2[u][r], h[t]);
+                    }
+                    float dz1[2][4];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) dz1[t][r] = h[t][r] * d1[t][r];
+                    // dx = W1 dz1, summed over the reflections with their signs.
+#pragma unroll
+                    for (int kt = 0; kt < 2; ++kt) {
+                        f32x4 dx = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) dx = mfma4(W1T[kt][t][r], dz1[t][r], dx);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) D[kt][r] = fmaf(refl_sign(s, cls[kt][r]), dx[r], D[kt][r]);
+                    }
+                    // Transposes: [node c][hidden] from the accumulator layout.
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            bh[c * TB + 16 * t + 4 * q + r] = act_value<ACT>(r1[t][r]);
+                            bz2[c * TB + 16 * t + 4 * q + r] = dz2[t][r];
+                            bz1[c * TB + 16 * t + 4 * q + r] = dz1[t][r];
+                        }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    float ha[2][4], zb2[2][4], zb1[2][4];
+#pragma unroll
+                    for (int x = 0; x < 2; ++x)
+#pragma unroll
+                        for (int st = 0; st < 4; ++st) {
+                            const int o = (4 * st + q) * TB + 16 * x + c;
+                            ha[x][st] = bh[o];
+                            zb2[x][st] = bz2[o];
+                            zb1[x][st] = bz1[o];
+                        }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    // dW2[j][o] += sum over the tile's nodes h1[j] dz2[o];
+                    // dW1[k][j] += x_g[k] dz1[j], x_g = chi_s x_pi.
+#pragma unroll
+                    for (int x = 0; x < 2; ++x)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y)
+#pragma unroll
+                            for (int st = 0; st < 4; ++st) {
+                                gW2[x][y] = mfma4(ha[x][st], zb2[y][st], gW2[x][y]);
+                                gW1[x][y] = mfma4(refl_sign(s, clsc[x]) * xa[x][st], zb1[y][st], gW1[x][y]);
+                            }
+                }
+                // dL/dm of this permutation: row k feeds from moment src_pi(k).
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = 16 * kt + 4 * q + r;
+                        if (k < 27) sdm[node * 32 + sgs[pi * 27 + k]] += D[kt][r];
+                    }
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase C: the full collision adjoint per node, scattered along the streaming.
+    {
+        float m[Q], lam[Q], nu[Q], gm[Q], omega[4], domega[4];
+        const float* row = sm + tid * NODE_STRIDE;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) m[row_tensor(k)] = row[k];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) omega[n] = som[tid * 4 + n];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[i] = live ? lam_in[(size_t)i * a.n + idx] : 0.0f;
+        inverse_T(lam, nu);
+        const float F[3] = {sF[tid * 3], sF[tid * 3 + 1], sF[tid * 3 + 2]};
+        collision_vjp_local(m, nu, a.omega_nu_f, omega, a.n_modes > 0, F, gm, domega);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) gm[row_tensor(k)] += sdm[tid * 32 + k];
+        float gf[Q];
+        moments_T(gm, gf);
+        if (live) {
+            const int xs[3] = {p.x == a.nx - 1 ? 0 : p.x + 1, p.x, p.x == 0 ? a.nx - 1 : p.x - 1};
+            const int ys[3] = {(p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx, p.y * a.nx,
+                               (p.y == 0 ? a.ny - 1 : p.y - 1) * a.nx};
+            const int nxy = a.nx * a.ny;
+            const int zs[3] = {(p.z == a.nz - 1 ? 0 : p.z + 1) * nxy, p.z * nxy,
+                               (p.z == 0 ? a.nz - 1 : p.z - 1) * nxy};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int dst = zs[cz_of(i) + 1] + ys[cy_of(i) + 1] + xs[cx_of(i) + 1];
+                lam_out[(size_t)i * a.n + dst] = lam[i] + gf[i];
+            }
+        }
+    }
+    __syncthreads();
+
+    // Block sums of the waves' gradients, in wave order, added to the block's row.
+    float* red = sm;                            // 4 waves x 1024 floats (reuses the moment tile)
+    // dW2: lane (q, c) holds [j = 16 x + 4 q + r][o = 16 y + c].
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wave * 1024 + (16 * x + 4 * q + r) * 32 + 16 * y + c] = gW2[x][y][r];
+    __syncthreads();
+    for (int e = tid; e < 1024; e += 256) {
+        const float v = red[e] + red[1024 + e] + red[2048 + e] + red[3072 + e];
+        out[OFF_W2 + e] += (double)v;
+    }
+    __syncthreads();
+    // dW1 and db1: lane (q, c) holds [k = 16 x + 4 q + r][j = 16 y + c]; row 27 is b1.
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wave * 1024 + (16 * x + 4 * q + r) * 32 + 16 * y + c] = gW1[x][y][r];
+    __syncthreads();
+    for (int e = tid; e < 28 * 32; e += 256) {
+        const float v = red[e] + red[1024 + e] + red[2048 + e] + red[3072 + e];
+        out[(e < 27 * 32 ? OFF_W1 + e : OFF_B1 + e - 27 * 32)] += (double)v;
+    }
+    __syncthreads();
+    // db2: lane (q, c) holds rows o = 16 u + 4 q + r summed over its nodes c.
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(wave * 16 + c) * 32 + 16 * u + 4 * q + r] = gb2[u][r];
+    __syncthreads();
+    if (tid < 32) {
+        float v = 0.0f;
+        for (int w = 0; w < 64; ++w) v += red[w * 32 + tid];
+        out[OFF_B2 + tid] += (double)v;
+    }
+}
+
 // Parity class of row k of M (the bias row 27 and padding rows count as 0).
 int row_class(int k) {
     if (k >= 27) return 0;
@@ -563,6 +1018,65 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
                 if (k == 27) e = 27;
                 gtab[(p * 4 + q) * GT_STRIDE + i] = e;
             }
+}
+
+size_t mfma_adjoint_table_floats() { return 64 * ADJ_WORDS; }
+
+// Per-lane table of the matrix-core adjoint from the flat parameters of a
+// width-32 network (unfolded weights: the adjoint works with h = tanh(z)).
+void mfma_prepare_adjoint_table(const float* params, float* tab) {
+    const int W = MW;
+    const float* W1 = params;
+    const float* W2 = W1 + 27 * W + W;
+    const float* W3 = W2 + W * W + W;
+    for (int lane = 0; lane < 64; ++lane) {
+        const int q = lane >> 4, c = lane & 15;
+        float* at = tab + lane * ADJ_WORDS;
+        int* ai = reinterpret_cast<int*>(at);
+        for (int t = 0; t < 2; ++t)
+            for (int u = 0; u < 2; ++u)
+                for (int r = 0; r < 4; ++r) at[AT_W2T + t * 8 + u * 4 + r] = W2[(16 * t + c) * W + 16 * u + 4 * q + r];
+        for (int kt = 0; kt < 2; ++kt)
+            for (int t = 0; t < 2; ++t)
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * kt + c;
+                    at[AT_W1T + kt * 8 + t * 4 + r] = k < 27 ? W1[k * W + 16 * t + 4 * q + r] : 0.0f;
+                }
+        for (int u = 0; u < 2; ++u)
+            for (int r = 0; r < 4; ++r)
+                for (int n = 0; n < 4; ++n)
+                    at[AT_W3 + (u * 4 + r) * 4 + n] = W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
+        for (int kt = 0; kt < 2; ++kt) {
+            for (int r = 0; r < 4; ++r) ai[AT_CLS + kt * 4 + r] = row_class(16 * kt + 4 * q + r);
+            ai[AT_CLSC + kt] = row_class(16 * kt + c);
+        }
+    }
+}
+
+int adjoint_mfma_blocks(int n) { return (n + 255) / 256; }
+
+hipError_t launch_adjoint_mfma(int storage, int act, const void* xin, const float* lam_in, float* lam_out,
+                               const StepArgs& a, const float* lane_tab, const int* gtab, const float* adj_tab,
+                               const int* gsrc, double* partial, hipStream_t st) {
+    const dim3 grid(adjoint_mfma_blocks(a.n)), block(256);
+#define ADJM_CASE(SS)                                                                                            \
+    case SS: {                                                                                                   \
+        using T = typename Codec<SS>::store_t;                                                                   \
+        if (act == ACT_TANH)                                                                                     \
+            hipLaunchKernelGGL((k_adjoint_mfma<SS, ACT_TANH>), grid, block, 0, st, static_cast<const T*>(xin),   \
+                               lam_in, lam_out, a, lane_tab, gtab, adj_tab, gsrc, partial);                     \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_adjoint_mfma<SS, ACT_RELU>), grid, block, 0, st, static_cast<const T*>(xin),   \
+                               lam_in, lam_out, a, lane_tab, gtab, adj_tab, gsrc, partial);                     \
+        return hipGetLastError();                                                                                \
+    }
+    switch (storage) {
+        ADJM_CASE(ST_F32)
+        ADJM_CASE(ST_F16)
+        ADJM_CASE(ST_BF16)
+        default: return hipErrorInvalidValue;
+    }
+#undef ADJM_CASE
 }
 
 // omega_out == nullptr: one stream-collide step fin -> fout.  Otherwise the

@@ -280,9 +280,10 @@ def capacity_glups(engine, chunk=50, grids=GRIDS):
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Poisson stream of periodic-box solves on one GPU")
     ap.add_argument("--requests", type=int, default=24)
-    ap.add_argument("--loads", default="0.5,0.9")
-    ap.add_argument("--budget-gb", type=float, default=0.0, help="0: the device's free memory")
-    ap.add_argument("--small-budget-gb", type=float, default=2.0)
+    ap.add_argument("--loads", default="0.5,0.9", help="offered loads, fractions of the measured capacity")
+    ap.add_argument("--budgets", default="free,2",
+                    help="device-memory budgets in GB ('free': 90 %% of the free memory); every load runs "
+                         "with the first, the last load also with the others")
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=50)
     ap.add_argument("--seed", type=int, default=0)
@@ -292,12 +293,12 @@ def main(argv=None):
     stream = torch.cuda.Stream()
     engine = GpuEngine(stream=stream.cuda_stream)
     free = torch.cuda.mem_get_info()[0]
-    budget = int(args.budget_gb * 2 ** 30) if args.budget_gb > 0 else int(0.9 * free)
+    budgets = [int(0.9 * free) if b == "free" else int(float(b) * 2 ** 30) for b in args.budgets.split(",")]
     cap = capacity_glups(engine, chunk=args.chunk)
     mean_work = np.mean([n ** 3 for n in GRIDS]) * 1250.0
     print(json.dumps({"capacity_glups": cap, "mean_request_node_steps": mean_work}), flush=True)
-    runs = [(float(x), budget) for x in args.loads.split(",")]
-    runs.append((float(args.loads.split(",")[-1]), int(args.small_budget_gb * 2 ** 30)))
+    loads = [float(x) for x in args.loads.split(",")]
+    runs = [(x, budgets[0]) for x in loads] + [(loads[-1], b) for b in budgets[1:]]
     for load, bud in runs:
         rate = load * cap * 1e9 / mean_work
         reqs = poisson_requests(args.requests, rate, args.seed)

@@ -51,7 +51,8 @@ def _setup(n, width, seed, act):
 
 
 @pytest.mark.parametrize("act,mlp,forced", [("tanh", "f32", False), ("tanh", "f32_mfma", True),
-                                            ("relu", "f32", False)])
+                                            ("relu", "f32", False), ("tanh", "f32_mfma", False),
+                                            ("relu", "f32_mfma", True)])
 def test_spectrum_loss_gradient_matches_oracle(act, mlp, forced):
     n, width, tau, T, K = 8, 32, 0.56, 6, 4
     params, rho, u, f0, Et = _setup(n, width, 4, act)
@@ -83,15 +84,19 @@ def test_spectrum_loss_gradient_matches_oracle(act, mlp, forced):
     assert rel < 2e-3 and relf < 2e-3
 
 
-def test_population_loss_gradient_and_determinism():
-    """Loss <w, x_T> given as dL/df; two backward passes agree bitwise."""
-    n, width, tau, T, K = 6, 32, 0.57, 5, 2
+@pytest.mark.parametrize("shape,mlp", [((6, 6, 6), "f32"), ((6, 6, 6), "f32_mfma"), ((7, 6, 9), "f32_mfma"),
+                                       ((3, 11, 17), "f32_mfma")])
+def test_population_loss_gradient_and_determinism(shape, mlp):
+    """Loss <w, x_T> given as dL/df; two backward passes agree bitwise.  The
+    lattices with 378 and 561 nodes end in a partial block of the
+    matrix-core adjoint."""
+    width, tau, T, K = 32, 0.57, 5, 2
     params = inputs.mlp_params(width, 7)
-    f0 = inputs.random_populations((n, n, n), seed=8, lo=0.95, hi=1.05)
+    f0 = inputs.random_populations(shape, seed=8, lo=0.95, hi=1.05)
     w = np.random.Generator(np.random.PCG64(9)).standard_normal(f0.shape)
     grads = []
-    with Lattice((n, n, n), "f32", "nco", tau) as lat:
-        lat.set_net_weights(params, width, "tanh", "f32")
+    with Lattice(shape, "f32", "nco", tau) as lat:
+        lat.set_net_weights(params, width, "tanh", mlp)
         for _ in range(2):
             lat.init_populations(f0)
             fs = lat.populations()
@@ -121,3 +126,22 @@ def test_backward_state_errors():
         with pytest.raises(L.NCOError) as e:
             lat.forward_record(3, 2)
         assert e.value.status == L.NCO_E_UNSUPPORTED
+
+
+def test_bf16_network_gradient_close_to_float32():
+    """A bf16 network runs its forward in bf16 and its reverse mode in
+    float32: the gradient stays within bf16 rounding of the float32
+    network's."""
+    n, width, tau, T, K = 8, 32, 0.56, 6, 3
+    params, rho, u, f0, Et = _setup(n, width, 4, "tanh")
+    out = {}
+    for mlp in ("f32_mfma", "bf16"):
+        with Lattice((n, n, n), "f32", "nco", tau) as lat:
+            lat.set_net_weights(params, width, "tanh", mlp)
+            lat.init_equilibrium(rho, u)
+            lat.forward_record(T, K)
+            _, dE = log_spectrum_loss(lat.energy_spectrum(), Et, 1, 3)
+            out[mlp] = lat.backward(dL_dE=dE)[0]
+    rel = np.linalg.norm(out["bf16"] - out["f32_mfma"]) / np.linalg.norm(out["f32_mfma"])
+    print("bf16 vs float32 network gradient: rel %.2e" % rel)
+    assert rel < 5e-2
