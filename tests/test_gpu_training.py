@@ -69,3 +69,32 @@ def test_training_reduces_loss_below_untrained_fixed_rate_and_bgk():
           % (L_untrained, L_trained, others["mrt"], others["bgk"], np.round(hist, 5).tolist()))
     assert L_trained < 0.9 * L_untrained
     assert L_trained < others["mrt"] and L_trained < others["bgk"]
+
+
+def test_c4_training_gain_64():
+    """The forced-turbulence case at its full size: 64^3, 200-step unrolls,
+    checkpoints every 20, loss on the log-spectrum gap over 2 <= k <= 16.
+    30 Adam epochs on the GPU's own forward and reverse kernels lower the
+    loss below the untrained network's, the fixed-rate operator's (the NCO
+    with tilde tau = 0) and BGK's (measured: 60.48 -> 59.43 against 60.48
+    and 61.21; the higher-order rates move the high shells only a little)."""
+    n, T, K, tau = 64, 200, 20, 0.52
+    rho, u, frc, target = forced_turbulence(n, T, seed=31, tau=tau)
+    params0 = inputs.mlp_params(32, 1)
+    run = Unroll((n, n, n), tau, ("eq", rho, u), T, K, target, 2, 16, forcing=frc)
+    L_untrained = run.loss(params0)
+    params, hist = train([run], params0, epochs=30, lr=1e-2)
+    L_trained = run.loss(params)
+    run.close()
+    others = {}
+    for kind in ("mrt", "bgk"):
+        with Lattice((n, n, n), "f32", kind, tau) as lat:
+            lat.set_rates([4.0 / 3.0] * 4)
+            lat.set_forcing(*frc)
+            lat.init_equilibrium(rho, u)
+            lat.step(T)
+            others[kind] = log_spectrum_loss(lat.energy_spectrum(), target, 2, 16)[0]
+    print("64^3 loss: untrained NCO %.5f, trained NCO %.5f, fixed-rate %.5f, BGK %.5f"
+          % (L_untrained, L_trained, others["mrt"], others["bgk"]))
+    assert L_trained < L_untrained - 0.5
+    assert L_trained < others["mrt"] - 0.5 and L_trained < others["bgk"]
