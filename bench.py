@@ -85,6 +85,31 @@ def time_op(lat, steps, warmup, torch, stream):
     return start.elapsed_time(end) / steps
 
 
+def train_step(n, tau, rho, u, params, width, stream, T=40, K=10):
+    """One training step of the float32 matrix-core NCO on the benchmark
+    lattice: a T-step recorded forward (checkpoints every K) and the reverse
+    pass (segment recompute + matrix-core adjoint) for a population loss."""
+    from paper_2412_08229_amd import Lattice
+    w = np.random.Generator(np.random.PCG64(1)).standard_normal((27, n, n, n)) * 1e-3
+    with Lattice((n, n, n), "f32", "nco", tau, stream=stream) as lat:
+        lat.set_net_weights(params, width, "tanh", "f32_mfma")
+        for rep in range(2):                    # the first pass allocates the checkpoints
+            lat.init_equilibrium(rho, u)
+            t0 = time.perf_counter()
+            lat.forward_record(T, K)
+            lat.sync()
+            t1 = time.perf_counter()
+            g, _ = lat.backward(dL_df=w)
+            t2 = time.perf_counter()
+        if not np.all(np.isfinite(g)):
+            raise RuntimeError("non-finite gradient")
+    fwd = (t1 - t0) / T * 1e3
+    rev = (t2 - t1) / T * 1e3
+    return {"forward_ms_per_step": fwd, "reverse_ms_per_step": rev,
+            "train_glups": n ** 3 / ((t2 - t0) / T * 1e-3) / 1e9, "steps": T, "checkpoint_every": K,
+            "lattice": n, "network": "f32_mfma", "activation": "tanh"}
+
+
 def cpu_baseline(n_sample=64, nsteps=6):
     """The float64 oracle timed on the host, on a bounded sample: the same
     workload at n_sample^3 for nsteps steps."""
@@ -178,7 +203,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--ops", default=",".join(VARIANTS))
+    ap.add_argument("--ops", default=",".join(list(VARIANTS) + ["nco_train"]))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the lattice path runs on a single MI355X; "
@@ -206,6 +231,11 @@ def main():
     spectra = {}
     fields = {n: (tau, rho, u)}
     for op in args.ops.split(","):
+        if op == "nco_train":
+            results[op] = train_step(n, tau, rho, u, params, width, stream)
+            print("# nco_train: forward %.4f ms/step, reverse %.4f ms/step" % (
+                results[op]["forward_ms_per_step"], results[op]["reverse_ms_per_step"]), file=sys.stderr, flush=True)
+            continue
         kind, storage, mlp, act = VARIANTS[op]
         n_op = GRID.get(op, n)
         if n_op not in fields:
@@ -244,6 +274,8 @@ def main():
     # sum_k |E - E_f32| / sum_k E_f32, the largest relative error of one shell
     # over 1 <= k <= n/4, the kinetic-energy error and the speedup.
     for op, r in results.items():
+        if op not in VARIANTS:
+            continue
         ref = VARIANTS[op][0]
         if (op == ref or ref not in spectra or op not in spectra or spectra[ref][0] != spectra[op][0]
                 or VARIANTS[op][3] != VARIANTS[ref][3]):

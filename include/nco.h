@@ -75,8 +75,14 @@ int nco_version(void);
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* nco_last_error(void);
 
-/* Device bytes a lattice of this size and storage needs (both population
- * buffers plus per-lattice work space); used for admission decisions. */
+/* Device bytes a lattice of this size and storage holds once created and
+ * initialised with nco_init_equilibrium: both population buffers, per-lattice
+ * work space and the 4 doubles per node of host-transfer staging that call
+ * uses; used for admission decisions.  Not included: calls that move all
+ * populations to or from the host (nco_init_populations,
+ * nco_read_populations, nco_backward) grow the staging to 27 doubles per node
+ * on first use, and network tables, forcing tables and reverse-mode
+ * checkpoints are allocated by the calls that need them. */
 int nco_lattice_bytes(int nx, int ny, int nz, int storage, size_t* bytes);
 
 /* Create a lattice of nx*ny*nz nodes (each >= 1) on the current device.

@@ -113,7 +113,8 @@ struct nco_lattice {
     float* net = nullptr;
     void* mfma_tab = nullptr;     // per-lane operand table + group gather table
     int width = 0, act = 0, mlp_prec = 0;
-    double* staging = nullptr;    // 27N doubles, allocated on first use
+    double* staging = nullptr;    // host-transfer staging, allocated on first use
+    int staging_per_node = 0;     // its size in doubles per node
     double* partial = nullptr;    // global-sum partials
     double* small = nullptr;      // 64 doubles of results
     int* flag = nullptr;
@@ -181,8 +182,18 @@ int maybe_check(nco_lattice* lat, hipStream_t st) {
     return NCO_OK;
 }
 
-int ensure_staging(nco_lattice* lat) {
-    if (!lat->staging) HIP_TRY(hipMalloc(&lat->staging, sizeof(double) * 27 * (size_t)lat->n));
+// Host-transfer staging of at least `per_node` doubles per node, grown on
+// demand (4 for velocity and density fields, 27 for populations).
+int ensure_staging(nco_lattice* lat, int per_node) {
+    if (lat->staging_per_node >= per_node) return NCO_OK;
+    if (lat->staging) {
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        HIP_TRY(hipFree(lat->staging));
+        lat->staging = nullptr;
+        lat->staging_per_node = 0;
+    }
+    HIP_TRY(hipMalloc(&lat->staging, sizeof(double) * per_node * (size_t)lat->n));
+    lat->staging_per_node = per_node;
     return NCO_OK;
 }
 
@@ -282,8 +293,9 @@ int nco_lattice_bytes(int nx, int ny, int nz, int storage, size_t* bytes) {
     const size_t sb = store_bytes(storage);
     if (!sb) return fail(NCO_E_INVALID, "unknown storage %d", storage);
     const size_t n = (size_t)nx * ny * nz;
-    // Two population buffers, the global-sum partials and the small result area.
-    *bytes = 2 * 27 * n * sb + 5 * sizeof(double) * ((n + 255) / 256) + 4096;
+    // Two population buffers, the global-sum partials, the small result
+    // area and the staging nco_init_equilibrium uses (4 doubles per node).
+    *bytes = 2 * 27 * n * sb + 5 * sizeof(double) * ((n + 255) / 256) + 4096 + 4 * sizeof(double) * n;
     return NCO_OK;
 }
 
@@ -327,9 +339,10 @@ int nco_lattice_create(int nx, int ny, int nz, int storage, int op, double tau, 
         hipMalloc(&lat->small, 64 * sizeof(double)) != hipSuccess ||
         hipMalloc(&lat->flag, sizeof(int)) != hipSuccess)
         return bail(fail(NCO_E_OOM, "cannot allocate lattice work space"));
-    // Rest state f = w.
-    std::vector<double> zero(3 * n, 0.0);
-    rc = nco_init_equilibrium(lat, nullptr, zero.data());
+    // Rest state f = w (no host transfer, no staging).
+    if (hipError_t e = launch_init_equilibrium(storage, lat->f[0], nullptr, nullptr, lat->n, lat->stream))
+        return bail(fail(NCO_E_HIP, "rest state: %s", hipGetErrorString(e)));
+    rc = record_mass(lat);
     if (rc != NCO_OK) return bail(rc);
     *out = lat;
     return NCO_OK;
@@ -494,7 +507,7 @@ int nco_init_equilibrium(nco_lattice* lat, const double* rho, const double* u) {
     if (int rc = check_lat(lat)) return rc;
     if (!u) return fail(NCO_E_INVALID, "null velocity");
     if (int rc = set_device(lat)) return rc;
-    if (int rc = ensure_staging(lat)) return rc;
+    if (int rc = ensure_staging(lat, 4)) return rc;
     const size_t n = lat->n;
     double* d_u = lat->staging;
     double* d_rho = rho ? lat->staging + 3 * n : nullptr;
@@ -510,7 +523,7 @@ int nco_init_populations(nco_lattice* lat, const double* f) {
     if (int rc = check_lat(lat)) return rc;
     if (!f) return fail(NCO_E_INVALID, "null populations");
     if (int rc = set_device(lat)) return rc;
-    if (int rc = ensure_staging(lat)) return rc;
+    if (int rc = ensure_staging(lat, 27)) return rc;
     HIP_TRY(hipMemcpyAsync(lat->staging, f, sizeof(double) * 27 * (size_t)lat->n, hipMemcpyHostToDevice,
                            lat->stream));
     HIP_TRY(launch_from_double(lat->storage, lat->f[lat->cur], lat->staging, lat->n, lat->stream));
@@ -767,7 +780,7 @@ int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double*
                                         lat->stream));
     }
     if (dL_df) {
-        if (int rc = ensure_staging(lat)) return rc;
+        if (int rc = ensure_staging(lat, 27)) return rc;
         HIP_TRY(hipMemcpyAsync(lat->staging, dL_df, sizeof(double) * nf, hipMemcpyHostToDevice, lat->stream));
         HIP_TRY(launch_add_f64_to_f32(lin, lat->staging, nf, lat->stream));
     }
@@ -804,7 +817,7 @@ int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double*
     HIP_TRY(hipMemcpyAsync(grad, lat->d_grad, sizeof(double) * adjoint_param_count(), hipMemcpyDeviceToHost,
                            lat->stream));
     if (dL_df0) {
-        if (int rc = ensure_staging(lat)) return rc;
+        if (int rc = ensure_staging(lat, 27)) return rc;
         HIP_TRY(launch_f32_to_f64(lin, lat->staging, nf, lat->stream));
         HIP_TRY(hipMemcpyAsync(dL_df0, lat->staging, sizeof(double) * nf, hipMemcpyDeviceToHost, lat->stream));
     }
@@ -831,7 +844,7 @@ int nco_read_populations(nco_lattice* lat, double* f) {
     if (int rc = check_lat(lat)) return rc;
     if (!f) return fail(NCO_E_INVALID, "null output");
     if (int rc = set_device(lat)) return rc;
-    if (int rc = ensure_staging(lat)) return rc;
+    if (int rc = ensure_staging(lat, 27)) return rc;
     HIP_TRY(launch_to_double(lat->storage, lat->f[lat->cur], lat->staging, lat->n, lat->stream));
     HIP_TRY(hipMemcpyAsync(f, lat->staging, sizeof(double) * 27 * (size_t)lat->n, hipMemcpyDeviceToHost,
                            lat->stream));
@@ -842,7 +855,7 @@ int nco_read_populations(nco_lattice* lat, double* f) {
 int nco_read_macroscopic(nco_lattice* lat, double* rho, double* u) {
     if (int rc = check_lat(lat)) return rc;
     if (int rc = set_device(lat)) return rc;
-    if (int rc = ensure_staging(lat)) return rc;
+    if (int rc = ensure_staging(lat, 4)) return rc;
     const size_t n = lat->n;
     HIP_TRY(launch_macroscopic(lat->storage, lat->f[lat->cur], lat->staging, lat->staging + n, lat->n,
                                lat->stream));
@@ -857,7 +870,7 @@ int nco_read_rates(nco_lattice* lat, double* omega) {
     if (!omega) return fail(NCO_E_INVALID, "null output");
     if (!lat->net) return fail(NCO_E_STATE, "no network weights set");
     if (int rc = set_device(lat)) return rc;
-    if (int rc = ensure_staging(lat)) return rc;
+    if (int rc = ensure_staging(lat, 4)) return rc;
     const StepArgs a = step_args(lat);
     if (use_mfma(lat))
         HIP_TRY(launch_nco_mfma(lat->storage, lat->mlp_prec, lat->f[lat->cur], nullptr, a, mfma_lane_tab(lat),

@@ -70,6 +70,7 @@ hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs&
 // BGK and fixed-rate lattices (op in a.op of every member, same storage).
 hipError_t launch_step_grouped(int storage, int op, const LaunchGroup& g, hipStream_t st);
 hipError_t launch_rates(int storage, const void* fin, double* omega, const StepArgs& a, hipStream_t st);
+// f = f^eq(rho, u); rho == nullptr: rho = 1; u == nullptr: u = 0.
 hipError_t launch_init_equilibrium(int storage, void* f, const double* rho, const double* u, int n,
                                    hipStream_t st);
 hipError_t launch_from_double(int storage, void* f, const double* src, int n, hipStream_t st);

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_init_equilibrium(typename Codec<S>::sto
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n) return;
     const double r = rho ? rho[idx] : 1.0;
-    const double ux = u[idx], uy = u[(size_t)n + idx], uz = u[2 * (size_t)n + idx];
+    const double ux = u ? u[idx] : 0.0, uy = u ? u[(size_t)n + idx] : 0.0, uz = u ? u[2 * (size_t)n + idx] : 0.0;
     const double uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {

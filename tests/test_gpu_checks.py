@@ -153,3 +153,24 @@ def test_creation_arguments_outside_the_domain():
         with pytest.raises(L.NCOError) as e:
             lat.set_check(-1, 1e-3)
         assert e.value.status == L.NCO_E_INVALID
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_footprint_matches_device_memory(storage):
+    """nco_lattice_bytes (the serving admission figure) against the device
+    memory a lattice takes once created and initialised with an equilibrium."""
+    import torch
+    n = 96
+    rho, u = inputs.tgv3d(n, 0.05)
+    with Lattice((4, 4, 4), storage, "bgk", 0.6) as warm:      # load the library's code first
+        warm.init_equilibrium(None, np.zeros((3, 4, 4, 4)))
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    lat = Lattice((n, n, n), storage, "bgk", 0.6)
+    lat.init_equilibrium(rho, u)
+    lat.sync()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    want = Lattice.bytes((n, n, n), storage)
+    lat.close()
+    print("%s: reported %d bytes, device memory used %d" % (storage, want, used))
+    assert abs(used - want) < 0.05 * want + (4 << 20)
