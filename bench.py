@@ -106,7 +106,7 @@ def train_step(n, tau, rho, u, params, width, stream, T=40, K=10):
     fwd = (t1 - t0) / T * 1e3
     rev = (t2 - t1) / T * 1e3
     return {"forward_ms_per_step": fwd, "reverse_ms_per_step": rev,
-            "train_glups": n ** 3 / ((t2 - t0) / T * 1e-3) / 1e9, "steps": T, "checkpoint_every": K,
+            "train_glups": n ** 3 / ((t2 - t0) / T) / 1e9, "steps": T, "checkpoint_every": K,
             "lattice": n, "network": "f32_mfma", "activation": "tanh"}
 
 
