@@ -150,29 +150,59 @@ def test_conservation_on_gpu(storage, mlp, tol):
     assert np.abs(s1[1:4] - s0[1:4]).max() / s0[0] < tol
 
 
-def test_lattice_rotation_equivariance_on_gpu():
-    """Rotating the whole field by 90 degrees about z commutes with a step."""
+# Lattice symmetries as (matrix R acting on velocities, the node map as a
+# function on [z][y][x] arrays): a rotation by 90 degrees about z, the
+# reflection x -> -x, and the cyclic axis permutation (x, y, z) -> (y, z, x).
+_SYMMETRIES = {
+    "rot_z": (np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]]), lambda a: np.rot90(a, k=1, axes=(2, 1))),
+    "reflect_x": (np.diag([-1, 1, 1]), lambda a: np.roll(a[:, :, ::-1], 1, axis=2)),
+    "cycle_xyz": (np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]]), lambda a: np.transpose(a, (1, 2, 0))),
+}
+
+
+def _apply_symmetry(f, name):
+    R, nodes = _SYMMETRIES[name]
+    C = np.array([(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)])
+    index = {tuple(c): i for i, c in enumerate(C)}
+    out = np.empty_like(f)
+    for j in range(27):
+        out[index[tuple(R @ C[j])]] = nodes(f[j])
+    return out
+
+
+@pytest.mark.parametrize("sym", sorted(_SYMMETRIES))
+@pytest.mark.parametrize("storage, mlp, tol", [("f64", "f32", 1e-13), ("f32", "f32", 1e-6),
+                                               ("f32", "f32_mfma", 1e-6), ("f32", "bf16", 1e-5)])
+def test_lattice_symmetry_equivariance_on_gpu(sym, storage, mlp, tol):
+    """A lattice symmetry applied to the whole field commutes with two NCO
+    steps (Sec. II.B: the group-averaged rates are invariant, the collision
+    equivariant), on the vector-unit and both matrix-core networks.  Only
+    the order of the group sum changes, so agreement is to rounding."""
     n = 8
     f0 = inputs.random_populations((n, n, n), seed=10, lo=0.9, hi=1.1)
-    C = np.array([(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)])
-    R = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]])
-    index = {tuple(c): i for i, c in enumerate(C)}
-    perm = [index[tuple(R @ c)] for c in C]
+    res = []
+    for start in (f0, _apply_symmetry(f0, sym)):
+        with _lattice((n, n, n), storage, "nco", 0.55, mlp=mlp) as lat:
+            lat.init_populations(start)
+            lat.step(2)
+            res.append(lat.populations())
+    assert np.abs(_apply_symmetry(res[0], sym) - res[1]).max() < tol
 
-    def rotate(f):
-        out = np.empty_like(f)
-        for j in range(27):
-            # node (x, y) -> (-y, x): array axes [z, y, x]
-            out[perm[j]] = np.rot90(f[j], k=1, axes=(2, 1))
-        return out
-    for storage, tol in (("f64", 1e-13), ("f32", 1e-6)):
+
+def test_symmetry_maps_are_lattice_symmetries():
+    """The node maps above move a field the way its velocities say: a single
+    population travelling along c ends, after streaming, where the mapped
+    one travels along R c (checked with the streaming-only operator)."""
+    n = 6
+    for name in _SYMMETRIES:
+        f0 = inputs.random_populations((n, n, n), seed=12, lo=0.9, hi=1.1)
         res = []
-        for start in (f0, rotate(f0)):
-            with _lattice((n, n, n), storage, "nco", 0.55) as lat:
+        for start in (f0, _apply_symmetry(f0, name)):
+            with Lattice((n, n, n), "f64", "stream", 0.6) as lat:
                 lat.init_populations(start)
-                lat.step(2)
+                lat.step(1)
                 res.append(lat.populations())
-        assert np.abs(rotate(res[0]) - res[1]).max() < tol
+        assert np.array_equal(_apply_symmetry(res[0], name), res[1]), name
 
 
 @pytest.mark.parametrize("mlp", ["f32", "f32_mfma"])
