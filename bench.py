@@ -193,8 +193,51 @@ def precision_horizon(n, convective_times, every, f64_steps):
     print(json.dumps(out), flush=True)
 
 
+def convergence(sizes, u0=0.05, re=100.0):
+    """The convergence study of Sec. "Convergence": the extruded 2-D
+    Taylor-Green vortex from its equilibrium, one step, relative L2 errors of
+    velocity and pressure against the analytic solution, at fixed Re and
+    Ma, for BGK, the fixed-rate operator and the NCO (float32 matrix cores).
+    Prints one JSON line."""
+    import torch
+    from paper_2412_08229_amd import Lattice, inputs
+
+    stream = torch.cuda.Stream().cuda_stream
+    params = inputs.mlp_params(32, seed=0)
+    out = {"workload": "Taylor-Green vortex 2-D extruded along z, u0 %g, Re %g, one step from equilibrium" % (u0, re),
+           "errors": {}}
+    for kind in ("bgk", "mrt", "nco"):
+        rows = {}
+        for n in sizes:
+            nu, tau = inputs.viscosity(n, u0, re)
+            rho0, u_0, _ = inputs.tgv2d(n, u0)
+            with Lattice((n, n, n), "f32", kind, tau, stream=stream) as lat:
+                if kind == "nco":
+                    lat.set_net_weights(params, 32, "tanh", "f32_mfma")
+                if kind == "mrt":
+                    lat.set_rates([4.0 / 3.0] * 4)
+                lat.init_equilibrium(rho0, u_0)
+                lat.step(1)
+                rho, u = lat.macroscopic()
+            k2 = (2.0 * math.pi / n) ** 2
+            u_a = u_0 * math.exp(-2.0 * nu * k2)
+            p_a = (rho0 - 1.0) / 3.0 * math.exp(-4.0 * nu * k2)
+            eu = math.sqrt(((u - u_a) ** 2).sum() / (u_a ** 2).sum())
+            ep = math.sqrt((((rho - 1.0) / 3.0 - p_a) ** 2).sum() / (p_a ** 2).sum())
+            rows[n] = {"velocity_l2": eu, "pressure_l2": ep}
+        ns = sorted(rows)
+        for a, b in zip(ns, ns[1:]):
+            rows[b]["velocity_order"] = math.log2(rows[a]["velocity_l2"] / rows[b]["velocity_l2"])
+            rows[b]["pressure_order"] = math.log2(rows[a]["pressure_l2"] / rows[b]["pressure_l2"])
+        out["errors"][kind] = {str(n): r for n, r in rows.items()}
+        print("# convergence %s done" % kind, file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--convergence", default="", help="instead of the benchmark: the TGV2D convergence study "
+                                                      "at these comma-separated sizes")
     ap.add_argument("--precision-horizon", type=float, default=0.0,
                     help="instead of the benchmark: the reduced-precision study over this many convective times")
     ap.add_argument("--f64-steps", type=int, default=20)
@@ -209,6 +252,9 @@ def main():
         print("bench.py measures one GPU only: the lattice path runs on a single MI355X; "
               "multi-GPU domain decomposition is not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.convergence:
+        convergence([int(x) for x in args.convergence.split(",")])
+        return
     if args.precision_horizon > 0:
         precision_horizon(args.n, args.precision_horizon, 100, args.f64_steps)
         return
