@@ -234,8 +234,74 @@ def convergence(sizes, u0=0.05, re=100.0):
     print(json.dumps(out), flush=True)
 
 
+def tgv_dissipation(sizes, ref_n, t_end=20.0, dt=0.1, re=1600.0):
+    """The 3-D Taylor-Green vortex of Sec. "Three-dimensional Taylor-Green
+    Vortex" at Re 1600, Ma 0.1: kinetic energy k(t) and dissipation rate
+    -dk/dt (both in units of u0 and L = n / 2 pi) up to t_end convective
+    times, for BGK, the fixed-rate operator and the NCO (seeded network,
+    float32 matrix cores) at the coarse sizes, against a BGK run at ref_n.
+    A run whose state stops being finite is reported with the time it did.
+    Prints one JSON line."""
+    import torch
+    from paper_2412_08229_amd import Lattice, inputs
+    from paper_2412_08229_amd import _lib as L
+
+    u0 = 0.1 / math.sqrt(3.0)
+    stream = torch.cuda.Stream().cuda_stream
+    params = inputs.mlp_params(32, seed=0)
+
+    def run(kind, n):
+        nu, tau = inputs.viscosity(n, u0, re)
+        t_c = n / (2.0 * math.pi) / u0                  # steps per convective time
+        every = max(1, int(round(dt * t_c)))
+        nsamp = int(round(t_end * t_c / every))
+        rho, u = inputs.tgv3d(n, u0)
+        ts, ks, status = [0.0], [], "stable"
+        with Lattice((n, n, n), "f32", kind, tau, stream=stream) as lat:
+            if kind == "nco":
+                lat.set_net_weights(params, 32, "tanh", "f32_mfma")
+            if kind == "mrt":
+                lat.set_rates([4.0 / 3.0] * 4)
+            lat.init_equilibrium(rho, u)
+            del rho, u
+            ks.append(lat.global_sums()[4] / lat.n / u0 ** 2)
+            for i in range(nsamp):
+                lat.step(every)
+                try:
+                    s = lat.global_sums()
+                except L.NCOError:
+                    status = "unstable at t = %.2f" % ((i + 1) * every / t_c)
+                    break
+                ts.append((i + 1) * every / t_c)
+                ks.append(s[4] / lat.n / u0 ** 2)
+                if (i + 1) % max(1, nsamp // 10) == 0:
+                    print("# %s %d^3: t = %.1f" % (kind, n, ts[-1]), file=sys.stderr, flush=True)
+        ts, ks = np.array(ts), np.array(ks)
+        eps = -np.gradient(ks, ts) if len(ts) > 2 else np.zeros_like(ts)
+        return ts, ks, eps, status
+
+    t_r, k_r, e_r, st_r = run("bgk", ref_n)
+    out = {"workload": "Taylor-Green vortex Re %g, Ma 0.1, t <= %g convective times" % (re, t_end),
+           "reference": {"operator": "bgk", "lattice": ref_n, "status": st_r,
+                         "peak_dissipation": float(e_r.max()), "t_peak": float(t_r[np.argmax(e_r)])},
+           "runs": {}}
+    for n in sizes:
+        for kind in ("bgk", "mrt", "nco"):
+            t, k, e, st = run(kind, n)
+            e_ref = np.interp(t, t_r, e_r)
+            k_ref = np.interp(t, t_r, k_r)
+            out["runs"]["%s_%d" % (kind, n)] = {
+                "status": st, "t_reached": float(t[-1]),
+                "dissipation_err": float(np.max(np.abs(e - e_ref)) / e_r.max()),
+                "kinetic_energy_err": float(np.max(np.abs(k - k_ref) / k_ref)),
+                "peak_dissipation": float(e.max()), "t_peak": float(t[np.argmax(e)])}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--tgv-dissipation", default="",
+                    help="instead of the benchmark: coarse sizes and the reference size last, e.g. 32,64,128,512")
     ap.add_argument("--convergence", default="", help="instead of the benchmark: the TGV2D convergence study "
                                                       "at these comma-separated sizes")
     ap.add_argument("--precision-horizon", type=float, default=0.0,
@@ -252,6 +318,10 @@ def main():
         print("bench.py measures one GPU only: the lattice path runs on a single MI355X; "
               "multi-GPU domain decomposition is not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.tgv_dissipation:
+        sizes = [int(x) for x in args.tgv_dissipation.split(",")]
+        tgv_dissipation(sizes[:-1], sizes[-1])
+        return
     if args.convergence:
         convergence([int(x) for x in args.convergence.split(",")])
         return
