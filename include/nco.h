@@ -199,6 +199,13 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
  * following nco_backward (the gradient of Adam in Sec. "Learning Task"). */
 int nco_forward_record(nco_lattice* lat, int nsteps, int ckpt_every);
 
+/* nco_forward_record, and the mean kinetic energy k(t) = <|u|^2> / 2
+ * (u = j / rho, float64 sums) of the states t = 0, every, 2 every, ... <=
+ * nsteps steps after the start, written to k (nsteps / every + 1 values):
+ * the trajectory the dissipation-rate loss of Sec. "Learning Task" (the
+ * reduced Taylor-Green training) is computed from. */
+int nco_forward_record_energy(nco_lattice* lat, int nsteps, int ckpt_every, int every, double* k);
+
 /* Reverse mode through the recorded run (no step may come in between).  The
  * loss gradient at the final state is dL_dE (nbins values: dL/dE(k) of the
  * spectrum defined by nco_energy_spectrum, or NULL) plus dL_df (27N values,
@@ -208,6 +215,13 @@ int nco_forward_record(nco_lattice* lat, int nsteps, int ckpt_every);
  * the result is deterministic (fixed-order reductions). */
 int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double* dL_df, double* grad,
                  size_t n_params, double* dL_df0);
+
+/* nco_backward with, in addition, a loss on the kinetic-energy trajectory of
+ * nco_forward_record_energy: dL_dk[m] = dL/dk(m every) for the states
+ * t = m every, m = 0 .. rec_steps / every (the same sampling as the
+ * record).  dL_dE and dL_df (terms at the final state) may both be NULL. */
+int nco_backward_energy(nco_lattice* lat, const double* dL_dk, int every, const double* dL_dE, int nbins,
+                        const double* dL_df, double* grad, size_t n_params, double* dL_df0);
 
 #ifdef __cplusplus
 }

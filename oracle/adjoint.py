@@ -155,17 +155,37 @@ def log_spectrum_loss(E, E_target, kmin, kmax):
 
 # ---------------------------------------------------------------- driver ----
 
-def run_and_grad(f0, tau, layers, act, nsteps, loss_grad, forces=None):
+def kinetic_energy_vjp(f):
+    """d k / d f for the mean kinetic energy k = <|u|^2> / 2, u = j / rho:
+    per node, d(|j|^2 / (2 rho^2)) / d f_i = (u . c_i - |u|^2) / rho, divided
+    by the number of nodes."""
+    C = lattice.velocities().astype(float)
+    rho, u = collision.macroscopic(f)
+    uc = np.einsum("ia,a...->i...", C, u)
+    uu = (u * u).sum(axis=0)
+    return (uc - uu) / rho / rho.size
+
+
+def run_and_grad(f0, tau, layers, act, nsteps, loss_grad, forces=None, traj_grad=None):
     """Forward nsteps NCO steps from f0, then the exact gradient of
-    L = loss(x_T) with respect to the network parameters and to f0.
+    L = loss(x_T) (+ terms on the intermediate states) with respect to the
+    network parameters and to f0.
 
     loss_grad(x_T) -> (L, dL/dx_T).  forces: None or callable t -> (3, ...).
-    Returns (L, parameter gradients, dL/df0)."""
+    traj_grad: None or callable (t, x_t) -> dL/dx_t (or None) for the loss
+    terms on the state after t steps, t = 0 .. nsteps, whose values the
+    caller adds to L.  Returns (L, parameter gradients, dL/df0)."""
     op = step.Operator("nco", tau, layers=layers, act=act)
     xs = [f0]
     for t in range(nsteps):
         xs.append(step.step(xs[-1], op, None if forces is None else forces(t)))
     L, lam = loss_grad(xs[-1])
+
+    def add_traj(t, lam):
+        extra = None if traj_grad is None else traj_grad(t, xs[t])
+        return lam if extra is None else lam + extra
+
+    lam = add_traj(nsteps, lam)
     shape = f0.shape
     total = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
     for t in range(nsteps - 1, -1, -1):
@@ -173,5 +193,5 @@ def run_and_grad(f0, tau, layers, act, nsteps, loss_grad, forces=None):
         F = None if forces is None else forces(t).reshape(3, -1)
         g, pg = nco_collide_vjp(y, lam.reshape(27, -1), tau, layers, act, F)
         total = [(a + c, b + d) for (a, b), (c, d) in zip(total, pg)]
-        lam = step.unstream(g.reshape(shape))
+        lam = add_traj(t, step.unstream(g.reshape(shape)))
     return L, total, lam

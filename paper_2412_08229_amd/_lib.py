@@ -55,6 +55,8 @@ SIGNATURES = {
     "nco_set_forcing": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), _D, _I, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double]),
     "nco_forward_record": (_I, [_P, _I, _I]),
+    "nco_forward_record_energy": (_I, [_P, _I, _I, _I, _D]),
+    "nco_backward_energy": (_I, [_P, _D, _I, _D, _I, _D, _D, _SZ, _D]),
     "nco_batch_step": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(ctypes.c_int)]),
     "nco_backward": (_I, [_P, _D, _I, _D, _D, _SZ, _D]),
 }
@@ -228,6 +230,24 @@ def nco_batch_step(handles, nsteps):
 
 def nco_forward_record(h, nsteps, ckpt_every):
     check(lib().nco_forward_record(h, nsteps, ckpt_every))
+
+
+def nco_forward_record_energy(h, nsteps, ckpt_every, every):
+    k = np.empty(nsteps // every + 1)
+    check(lib().nco_forward_record_energy(h, nsteps, ckpt_every, every, dptr(k)))
+    return k
+
+
+def nco_backward_energy(h, n, n_params, dL_dk, every, dL_dE=None, dL_df=None, want_df0=False):
+    grad = np.empty(n_params)
+    k = as_f64(dL_dk)
+    e = None if dL_dE is None else as_f64(dL_dE)
+    df = None if dL_df is None else as_f64(dL_df, 27 * n)
+    df0 = np.empty(27 * n) if want_df0 else None
+    check(lib().nco_backward_energy(h, dptr(k), every, None if e is None else dptr(e), 0 if e is None else e.size,
+                                    None if df is None else dptr(df), dptr(grad), n_params,
+                                    None if df0 is None else dptr(df0)))
+    return grad, df0
 
 
 def nco_backward(h, n, n_params, dL_dE=None, dL_df=None, want_df0=False):

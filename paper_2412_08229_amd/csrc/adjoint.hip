@@ -328,6 +328,30 @@ __global__ __launch_bounds__(256) void k_grad_final(const double* __restrict__ s
     grad[pidx] = s;
 }
 
+// lam_i(x) += coef (u . c_i - |u|^2) / rho: coef times the derivative of
+// rho |u|^2 / (2 rho^2) summed over nodes, i.e. of N k with k = <|u|^2> / 2.
+template <int S>
+__global__ __launch_bounds__(256) void k_add_energy_grad(const typename Codec<S>::store_t* __restrict__ f,
+                                                         float* __restrict__ lam, double coef, int n) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double fv[Q], rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        fv[i] = Codec<S>::to_double(f[(size_t)i * n + idx], i);
+        rho += fv[i];
+        jx += cx_of(i) * fv[i];
+        jy += cy_of(i) * fv[i];
+        jz += cz_of(i) * fv[i];
+    }
+    const double ux = jx / rho, uy = jy / rho, uz = jz / rho, uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double uc = cx_of(i) * ux + cy_of(i) * uy + cz_of(i) * uz;
+        lam[(size_t)i * n + idx] += (float)(coef * (uc - uu) / rho);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, size_t count, float v) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = v;
@@ -389,6 +413,22 @@ hipError_t launch_grad_reduce_f64(const double* partial, int nblocks, double* st
     if (hipError_t e = hipGetLastError()) return e;
     hipLaunchKernelGGL(k_grad_final, dim3((NPAR + 255) / 256), dim3(256), 0, st, stage, groups, grad);
     return hipGetLastError();
+}
+
+hipError_t launch_add_energy_grad(int storage, const void* f, float* lam, double coef, int n, hipStream_t st) {
+    const dim3 grid((n + 255) / 256), block(256);
+#define AEG_CASE(SS)                                                                                           \
+    case SS:                                                                                                   \
+        hipLaunchKernelGGL(k_add_energy_grad<SS>, grid, block, 0, st,                                          \
+                           static_cast<const typename Codec<SS>::store_t*>(f), lam, coef, n);                  \
+        return hipGetLastError();
+    switch (storage) {
+        AEG_CASE(ST_F32)
+        AEG_CASE(ST_F16)
+        AEG_CASE(ST_BF16)
+        default: return hipErrorInvalidValue;
+    }
+#undef AEG_CASE
 }
 
 hipError_t launch_fill_f32(float* p, size_t count, float v, hipStream_t st) {

@@ -703,9 +703,14 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
     return NCO_OK;
 }
 
-int nco_forward_record(nco_lattice* lat, int nsteps, int ckpt_every) {
+namespace {
+
+// Recorded forward run; every > 0: k(t) = <|u|^2> / 2 at t = 0, every, ...
+// into k (host, nsteps / every + 1 values).
+int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, double* k) {
     if (int rc = check_lat(lat)) return rc;
     if (nsteps < 1 || ckpt_every < 1) return fail(NCO_E_INVALID, "nsteps and ckpt_every must be >= 1");
+    if (every < 0 || (every > 0 && !k)) return fail(NCO_E_INVALID, "energy sampling needs every >= 1 and an output");
     if (lat->op != NCO_OP_NCO || !lat->net) return fail(NCO_E_STATE, "recording needs the NCO operator with weights");
     if (lat->width != 32 || lat->storage == NCO_F64)
         return fail(NCO_E_UNSUPPORTED, "the adjoint needs width 32 and float storage");
@@ -716,29 +721,76 @@ int nco_forward_record(nco_lattice* lat, int nsteps, int ckpt_every) {
         HIP_TRY(hipMalloc(&p, lat->pop_bytes));
         lat->ckpt.push_back(p);
     }
+    const int nk = every > 0 ? nsteps / every + 1 : 0;
+    double* d_k = nullptr;
+    if (nk > 0) HIP_TRY(hipMalloc(&d_k, sizeof(double) * 5 * nk));
+    auto sample = [&](int m) -> int {
+        HIP_TRY(launch_global_sums(lat->storage, lat->f[lat->cur], lat->partial, d_k + 5 * m, lat->n, lat->stream));
+        return NCO_OK;
+    };
+    int rc = NCO_OK;
     lat->rec_force_t0 = lat->force_t;
-    for (int s = 0; s < nsteps; ++s) {
-        if (s % ckpt_every == 0)
-            HIP_TRY(hipMemcpyAsync(lat->ckpt[s / ckpt_every], lat->f[lat->cur], lat->pop_bytes,
-                                   hipMemcpyDeviceToDevice, lat->stream));
-        if (int rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t)) return rc;
+    if (nk > 0) rc = sample(0);
+    for (int s = 0; s < nsteps && rc == NCO_OK; ++s) {
+        if (s % ckpt_every == 0) {
+            if (hipMemcpyAsync(lat->ckpt[s / ckpt_every], lat->f[lat->cur], lat->pop_bytes, hipMemcpyDeviceToDevice,
+                               lat->stream) != hipSuccess) {
+                rc = fail(NCO_E_HIP, "checkpoint copy failed");
+                break;
+            }
+        }
+        if ((rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t))) break;
         lat->cur = 1 - lat->cur;
         ++lat->force_t;
+        if (nk > 0 && (s + 1) % every == 0) rc = sample((s + 1) / every);
     }
+    if (rc == NCO_OK && nk > 0) {
+        std::vector<double> sums(5 * (size_t)nk);
+        if (hipMemcpyAsync(sums.data(), d_k, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, lat->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(lat->stream) != hipSuccess)
+            rc = fail(NCO_E_HIP, "reading the energy samples failed");
+        for (int m = 0; m < nk && rc == NCO_OK; ++m) k[m] = sums[5 * m + 4] / lat->n;
+    }
+    if (d_k) {
+        hipStreamSynchronize(lat->stream);
+        hipFree(d_k);
+    }
+    if (rc != NCO_OK) return rc;
     lat->rec_steps = nsteps;
     lat->rec_every = ckpt_every;
     lat->steps_since_record = 0;
     return NCO_OK;
 }
 
-int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double* dL_df, double* grad,
-                 size_t n_params, double* dL_df0) {
+}  // namespace
+
+int nco_forward_record(nco_lattice* lat, int nsteps, int ckpt_every) {
+    return forward_record(lat, nsteps, ckpt_every, 0, nullptr);
+}
+
+int nco_forward_record_energy(nco_lattice* lat, int nsteps, int ckpt_every, int every, double* k) {
+    return forward_record(lat, nsteps, ckpt_every, every, k);
+}
+
+namespace {
+
+int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_dE, int nbins, const double* dL_df,
+             double* grad, size_t n_params, double* dL_df0) {
     if (int rc = check_lat(lat)) return rc;
     if (lat->rec_steps < 1 || lat->steps_since_record != 0)
         return fail(NCO_E_STATE, "backward needs nco_forward_record immediately before it");
     if (!grad || n_params != (size_t)adjoint_param_count())
         return fail(NCO_E_INVALID, "grad must hold %d values", adjoint_param_count());
-    if (!dL_dE && !dL_df) return fail(NCO_E_INVALID, "give dL_dE, dL_df or both");
+    if (!dL_dE && !dL_df && !dL_dk) return fail(NCO_E_INVALID, "give dL_dE, dL_df or dL_dk");
+    if (dL_dk && every < 1) return fail(NCO_E_INVALID, "energy sampling needs every >= 1");
+    // dL/dk(t) enters the adjoint of the state after t steps, t = m every.
+    auto inject = [&](int t, const void* state, float* lam) -> int {
+        if (!dL_dk || t % every != 0) return NCO_OK;
+        const double g = dL_dk[t / every];
+        if (g != 0.0) HIP_TRY(launch_add_energy_grad(lat->storage, state, lam, g / lat->n, lat->n, lat->stream));
+        return NCO_OK;
+    };
     if (int rc = set_device(lat)) return rc;
     const size_t n = lat->n, nf = 27 * n;
     if (dL_dE) {
@@ -784,6 +836,7 @@ int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double*
         HIP_TRY(hipMemcpyAsync(lat->staging, dL_df, sizeof(double) * nf, hipMemcpyHostToDevice, lat->stream));
         HIP_TRY(launch_add_f64_to_f32(lin, lat->staging, nf, lat->stream));
     }
+    if (int rc = inject(lat->rec_steps, lat->f[lat->cur], lin)) return rc;
     HIP_TRY(launch_fill_f64(lat->d_grad, adjoint_param_count(), 0.0, lat->stream));
     const int T = lat->rec_steps, K = lat->rec_every;
     const int ncp = (T + K - 1) / K;
@@ -808,6 +861,7 @@ int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double*
                                        lat->stream));
                 HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, lat->d_grad, lat->stream));
             }
+            if (int rc = inject(t, lat->seg[t - t0], lout)) return rc;
             std::swap(lin, lout);
         }
     }
@@ -823,6 +877,19 @@ int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double*
     }
     HIP_TRY(hipStreamSynchronize(lat->stream));
     return NCO_OK;
+}
+
+}  // namespace
+
+int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double* dL_df, double* grad,
+                 size_t n_params, double* dL_df0) {
+    return backward(lat, nullptr, 0, dL_dE, nbins, dL_df, grad, n_params, dL_df0);
+}
+
+int nco_backward_energy(nco_lattice* lat, const double* dL_dk, int every, const double* dL_dE, int nbins,
+                        const double* dL_df, double* grad, size_t n_params, double* dL_df0) {
+    if (!dL_dk) return fail(NCO_E_INVALID, "null dL_dk");
+    return backward(lat, dL_dk, every, dL_dE, nbins, dL_df, grad, n_params, dL_df0);
 }
 
 int nco_sync(nco_lattice* lat) {

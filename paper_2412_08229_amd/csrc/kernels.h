@@ -99,6 +99,8 @@ int adjoint_blocks(int n);
 hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
                           const int* gsrc, float* partial, hipStream_t st);
 hipError_t launch_grad_reduce(const float* partial, int nblocks, double* grad, hipStream_t st);
+// lam += coef d(sum over nodes of |u|^2 / 2) / df for the state f (float64 arithmetic).
+hipError_t launch_add_energy_grad(int storage, const void* f, float* lam, double coef, int n, hipStream_t st);
 // grad = sum over rows of partial[nblocks][NPAR] (float64) in row order, in
 // two passes over groups of 64 rows; stage holds ceil(nblocks / 64) rows.
 hipError_t launch_grad_reduce_f64(const double* partial, int nblocks, double* stage, double* grad, hipStream_t st);

@@ -115,11 +115,20 @@ class Lattice:
         """Spectral forcing for the following steps; k=None switches it off."""
         L.nco_set_forcing(self._h, k, draws, amplitude, kf, c)
 
-    def forward_record(self, nsteps, ckpt_every):
+    def forward_record(self, nsteps, ckpt_every, energy_every=0):
+        """Recorded run for backward(); with energy_every > 0 it returns the
+        mean kinetic energy k(t) of the states t = 0, energy_every, ..."""
+        if energy_every > 0:
+            return L.nco_forward_record_energy(self._h, int(nsteps), int(ckpt_every), int(energy_every))
         L.nco_forward_record(self._h, int(nsteps), int(ckpt_every))
+        return None
 
-    def backward(self, dL_dE=None, dL_df=None, n_params=2084, want_df0=False):
-        """Gradient of the recorded run: (dL/dtheta, dL/df0 or None)."""
-        g, df0 = L.nco_backward(self._h, self.n, n_params, dL_dE,
-                                None if dL_df is None else np.asarray(dL_df).ravel(), want_df0)
+    def backward(self, dL_dE=None, dL_df=None, n_params=2084, want_df0=False, dL_dk=None, energy_every=0):
+        """Gradient of the recorded run: (dL/dtheta, dL/df0 or None).  dL_dk:
+        loss gradient on the kinetic-energy samples of forward_record."""
+        df = None if dL_df is None else np.asarray(dL_df).ravel()
+        if dL_dk is not None:
+            g, df0 = L.nco_backward_energy(self._h, self.n, n_params, dL_dk, int(energy_every), dL_dE, df, want_df0)
+        else:
+            g, df0 = L.nco_backward(self._h, self.n, n_params, dL_dE, df, want_df0)
         return g, (None if df0 is None else df0.reshape((27,) + self.shape))

@@ -61,6 +61,62 @@ class Unroll:
         self.lat.close()
 
 
+class DissipationUnroll:
+    """One dissipation-rate training sample (the loss of the reduced
+    Taylor-Green training in Sec. "Learning Task", on the periodic box): a
+    recorded run of nsteps steps from the fields (rho, u) whose mean kinetic
+    energy k(t) is sampled every ``every`` steps; the dissipation rate
+    eps = -dk/dt (centred differences, k in units of u0^2, t in convective
+    units L / u0 with L = n / 2 pi) is compared with eps_ref(t) over
+    t_min <= t:  L = mean ((eps - eps_ref) / max eps_ref)^2."""
+
+    def __init__(self, shape, tau, rho, u, u0, nsteps, ckpt_every, every, eps_ref, t_min=1.0,
+                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None):
+        self.lat = Lattice(shape, storage, "nco", tau, stream=stream)
+        self.rho, self.u, self.u0 = rho, u, float(u0)
+        self.nsteps, self.ckpt_every, self.every = int(nsteps), int(ckpt_every), int(every)
+        self.act, self.mlp, self.width = act, mlp, width
+        L = shape[-1] / (2.0 * np.pi)
+        self.dt = self.every * self.u0 / L                       # convective time between samples
+        m = self.nsteps // self.every + 1
+        self.t = np.arange(m) * self.dt
+        self.inner = np.arange(1, m - 1)
+        self.inner = self.inner[self.t[self.inner] >= t_min]
+        self.eps_ref = np.array([eps_ref(t) for t in self.t[self.inner]])
+        self.scale = float(np.max(np.abs(self.eps_ref)))
+
+    def _run(self, params):
+        lat = self.lat
+        lat.set_net_weights(params, self.width, self.act, self.mlp)
+        lat.init_equilibrium(self.rho, self.u)
+        k = lat.forward_record(self.nsteps, self.ckpt_every, energy_every=self.every) / self.u0 ** 2
+        eps = -(k[self.inner + 1] - k[self.inner - 1]) / (2.0 * self.dt)
+        r = (eps - self.eps_ref) / self.scale
+        return k, eps, r
+
+    def curve(self, params):
+        """(t, eps) of the run with these parameters."""
+        _, eps, _ = self._run(params)
+        return self.t[self.inner], eps
+
+    def loss(self, params):
+        return float(np.mean(self._run(params)[2] ** 2))
+
+    def loss_and_grad(self, params):
+        k, eps, r = self._run(params)
+        L = float(np.mean(r ** 2))
+        # dL/deps_m = 2 r_m / (scale |window|); eps_m = -(k_{m+1} - k_{m-1}) / (2 dt); k = k_raw / u0^2.
+        de = 2.0 * r / (self.scale * len(r))
+        dk = np.zeros_like(k)
+        np.add.at(dk, self.inner + 1, -de / (2.0 * self.dt))
+        np.add.at(dk, self.inner - 1, de / (2.0 * self.dt))
+        g, _ = self.lat.backward(dL_dk=dk / self.u0 ** 2, energy_every=self.every)
+        return L, g, None
+
+    def close(self):
+        self.lat.close()
+
+
 def make_autograd(unroll):
     """torch.autograd.Function computing the loss of ``unroll`` from a flat
     float64 parameter tensor, with the hand-written adjoint as backward."""
@@ -104,4 +160,4 @@ def train(unrolls, params0, epochs, lr=1e-3, log=None):
     return p.detach().numpy().copy(), history
 
 
-__all__ = ["log_spectrum_loss", "Unroll", "make_autograd", "train", "n_bins"]
+__all__ = ["log_spectrum_loss", "Unroll", "DissipationUnroll", "make_autograd", "train", "n_bins"]

@@ -145,3 +145,39 @@ def test_bf16_network_gradient_close_to_float32():
     rel = np.linalg.norm(out["bf16"] - out["f32_mfma"]) / np.linalg.norm(out["f32_mfma"])
     print("bf16 vs float32 network gradient: rel %.2e" % rel)
     assert rel < 5e-2
+
+
+@pytest.mark.parametrize("mlp", ["f32", "f32_mfma"])
+def test_energy_trajectory_gradient_matches_oracle(mlp):
+    """Loss on the kinetic-energy trajectory (states t = 0, 2, 4, 6 of a
+    6-step run, checkpoints every 4): the recorded samples match the
+    oracle's k(t), and the gradient of sum_m a_m k(t_m) matches the oracle's
+    reverse mode with the same intermediate terms."""
+    n, width, tau, T, K, every = 8, 32, 0.56, 6, 4, 2
+    params = inputs.mlp_params(width, 21)
+    rho, u = inputs.random_velocity((n, n, n), seed=22, amp=0.08)
+    a = np.random.Generator(np.random.PCG64(23)).standard_normal(T // every + 1)
+    with Lattice((n, n, n), "f32", "nco", tau) as lat:
+        lat.set_net_weights(params, width, "tanh", mlp)
+        lat.init_equilibrium(rho, u)
+        fs = lat.populations()
+        k = lat.forward_record(T, K, energy_every=every)
+        g, df0 = lat.backward(dL_dk=a, energy_every=every, want_df0=True)
+    layers = collision.unpack_params(params, width)
+    op = step.Operator("nco", tau, layers=layers, act="tanh")
+    x, k_o = fs, [observables.kinetic_energy(fs)]
+    for t in range(1, T + 1):
+        x = step.step(x, op)
+        if t % every == 0:
+            k_o.append(observables.kinetic_energy(x))
+    assert np.abs(k - np.array(k_o)).max() < 1e-6 * max(k_o)
+
+    def traj(t, xt):
+        return a[t // every] * adjoint.kinetic_energy_vjp(xt) if t % every == 0 else None
+    _, go, gfo = adjoint.run_and_grad(fs, tau, layers, "tanh", T, lambda xt: (0.0, np.zeros_like(xt)),
+                                      traj_grad=traj)
+    go = adjoint.flatten(go)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    relf = np.linalg.norm(df0 - gfo) / np.linalg.norm(gfo)
+    print("energy trajectory %s: grad rel err %.2e, dL/df0 rel err %.2e" % (mlp, rel, relf))
+    assert rel < 2e-3 and relf < 2e-3

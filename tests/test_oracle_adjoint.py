@@ -132,3 +132,51 @@ def test_adjoint_negative_control():
     finally:
         step.unstream = saved
     assert np.abs(good - bad).max() > 1e-3
+
+
+def test_kinetic_energy_vjp_matches_finite_differences():
+    n = 4
+    rng = _rng(14)
+    rho, u = inputs.random_velocity((n, n, n), seed=15, amp=0.1)
+    f = collision.equilibrium(rho, u) + 1e-3 * rng.standard_normal((27, n, n, n))
+    g = adjoint.kinetic_energy_vjp(f)
+    h = 1e-6
+    for _ in range(3):
+        d = rng.standard_normal(f.shape)
+        fd = (observables.kinetic_energy(f + h * d) - observables.kinetic_energy(f - h * d)) / (2 * h)
+        assert abs(fd - (g * d).sum()) < 1e-8 * abs(fd), (fd, (g * d).sum())
+
+
+def test_trajectory_loss_gradient_matches_finite_differences():
+    """A loss on the kinetic energy of intermediate states (the dissipation
+    training of Sec. "Learning Task"): L = sum_m a_m k(t_m) over the states
+    t = 0, 2, 4 of a 4-step NCO run on 4^3, plus the final-state term 0."""
+    n, width, tau, T, every = 4, 8, 0.55, 4, 2
+    rng = _rng(16)
+    layers = _layers(width, 17)
+    rho, u = inputs.random_velocity((n, n, n), seed=18, amp=0.08)
+    f0 = collision.equilibrium(rho, u)
+    a = rng.standard_normal(T // every + 1)
+
+    def loss(lay, g0):
+        op = step.Operator("nco", tau, layers=lay, act="tanh")
+        x, total = g0, a[0] * observables.kinetic_energy(g0)
+        for t in range(1, T + 1):
+            x = step.step(x, op)
+            if t % every == 0:
+                total += a[t // every] * observables.kinetic_energy(x)
+        return total
+
+    def traj(t, x):
+        return a[t // every] * adjoint.kinetic_energy_vjp(x) if t % every == 0 else None
+    _, gp, gf0 = adjoint.run_and_grad(f0, tau, layers, "tanh", T, lambda x: (0.0, np.zeros_like(x)),
+                                      traj_grad=traj)
+    h = 1e-6
+    v = rng.standard_normal(collision.n_params(width))
+    fd = (loss(_perturb(layers, v, h), f0) - loss(_perturb(layers, v, -h), f0)) / (2 * h)
+    an = adjoint.flatten(gp) @ v
+    assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12), (fd, an)
+    d = 1e-3 * rng.standard_normal(f0.shape)
+    fd = (loss(layers, f0 + h * d) - loss(layers, f0 - h * d)) / (2 * h)
+    an = (gf0 * d).sum()
+    assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12), (fd, an)
