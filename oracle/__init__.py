@@ -23,6 +23,9 @@ paper defines, in float64, with the passage it follows named in its docstring:
                     E(k) (Sec. "Learning Task", loss on E(kappa)).
 * ``brute``       - a second, independent scalar-loop implementation of one
                     step, for brute-force checks on tiny grids.
+* ``reduced``     - the reduced Taylor-Green domain of Appendix A: the cube
+                    [0, pi/2]^3 stepped by unfolding it to the periodic box
+                    through the vortex's symmetry group.
 * ``adjoint``     - reverse-mode derivative of an unrolled run with respect to
                     the network parameters (what Adam consumes in Sec.
                     "Learning Task").

@@ -12,6 +12,8 @@ fields stand in for them with the paper's shapes):
   dimensional Taylor-Green Vortex" on [0, 2 pi)^3 with nodes at x_j = 2 pi j/N.
   The printed pressure is garbled; the standard one is used:
   p = rho0 u0^2 / 16 (cos 2x + cos 2y)(cos 2z + 2), rho = 1 + p / cs^2.
+* ``tgv3d_octant``: the same vortex on the reduced domain of Appendix A,
+  [0, pi/2]^3 with nodes half a spacing from the faces.
 * ``tgv2d``: the two-dimensional Taylor-Green vortex of Sec. "Convergence",
   extruded along z without gradient, with its analytic velocity gradient.
   The printed pressure has the sign of the (sin x cos y, -cos x sin y) form
@@ -30,9 +32,9 @@ import numpy as np
 CS2 = 1.0 / 3.0
 
 
-def grid(n):
-    """Node coordinates x_j = 2 pi j / n of a periodic box of edge 2 pi."""
-    return 2.0 * np.pi * np.arange(n) / n
+def grid(n, offset=0.0):
+    """Node coordinates x_j = 2 pi (j + offset) / n of a periodic box of edge 2 pi."""
+    return 2.0 * np.pi * (np.arange(n) + offset) / n
 
 
 def viscosity(n, u0, re):
@@ -42,16 +44,27 @@ def viscosity(n, u0, re):
     return nu, nu / CS2 + 0.5
 
 
-def tgv3d(n, u0, rho0=1.0):
+def tgv3d(n, u0, rho0=1.0, offset=0.0):
     """(rho, u) of the 3-D Taylor-Green vortex, shapes (n,n,n) and (3,n,n,n),
-    index order [z, y, x]."""
-    x = grid(n)
+    index order [z, y, x]; nodes at 2 pi (j + offset) / n."""
+    x = grid(n, offset)
     Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
     u = np.stack([u0 * np.sin(X) * np.cos(Y) * np.cos(Z),
                   -u0 * np.cos(X) * np.sin(Y) * np.cos(Z),
                   np.zeros_like(X)])
     p = rho0 * u0 * u0 / 16.0 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
     return rho0 + p / CS2, u
+
+
+def tgv3d_octant(n, u0, rho0=1.0):
+    """(rho, u) of the 3-D Taylor-Green vortex on the reduced domain of
+    Appendix A ("Reduced Taylor-Green vortex"): the cube [0, pi/2]^3 with n
+    nodes per edge, half a spacing from its faces, x_j = (j + 1/2) pi / (2 n).
+    These are the first n nodes per axis of the 4n-node box with
+    ``offset=0.5``; the spacing, and so the lattice viscosity of a Reynolds
+    number, is that of the 4n box."""
+    rho, u = tgv3d(4 * n, u0, rho0, offset=0.5)
+    return rho[:n, :n, :n].copy(), u[:, :n, :n, :n].copy()
 
 
 def tgv2d(n, u0, rho0=1.0):
