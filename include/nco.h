@@ -69,6 +69,10 @@ typedef enum { NCO_MLP_F32 = 0, NCO_MLP_F32_MFMA = 1, NCO_MLP_BF16 = 2 } nco_mlp
 
 typedef enum { NCO_ACT_TANH = 0, NCO_ACT_RELU = 1 } nco_act;
 
+/* Lattice domain: the periodic box, or the reduced Taylor-Green cube of
+ * Appendix A ("Reduced Taylor-Green vortex"). */
+typedef enum { NCO_DOMAIN_PERIODIC = 0, NCO_DOMAIN_TGV_OCTANT = 1 } nco_domain;
+
 /* Library version, major * 10000 + minor * 100 + patch. */
 int nco_version(void);
 
@@ -96,6 +100,24 @@ int nco_lattice_destroy(nco_lattice* lat);
 
 /* Switch the collision operator and/or tau of an existing lattice. */
 int nco_set_op(nco_lattice* lat, int op, double tau);
+
+/* Domain of the streaming (Appendix A, "Reduced Taylor-Green vortex").
+ * NCO_DOMAIN_PERIODIC (the default): periodic wrap on every axis.
+ * NCO_DOMAIN_TGV_OCTANT: the n^3 lattice (nx = ny = nz = n) is the cube
+ * [0, pi/2]^3 of the three-dimensional Taylor-Green vortex, node j at
+ * (j + 1/2) pi / (2n), and stands for the symmetric 2 pi box of 4n nodes per
+ * edge; populations that stream out of the cube come back in through the
+ * vortex's symmetries (mirrors in the planes through the origin, the quarter
+ * turns about the vortex axis x = y = pi/2, the half turn about the line
+ * x = y, z = pi/2), with their velocity mapped along.  A state that has
+ * those symmetries evolves exactly as on the 4n box, with 64 times fewer
+ * nodes; global sums and the kinetic energy are those of the box, up to
+ * the factor 64 in the sums.  Valid for every operator, storage and network,
+ * for nco_step, nco_batch_step and the reverse mode; spectral forcing, the
+ * energy spectrum and spectrum losses need the periodic box
+ * (NCO_E_UNSUPPORTED).  NCO_E_INVALID for an unknown domain or a non-cubic
+ * lattice.  Takes effect from the next step; it drops a recorded run. */
+int nco_set_domain(nco_lattice* lat, int domain);
 
 /* Fixed rates omega_3..omega_6 of the four higher-order groups (NCO_OP_MRT). */
 int nco_set_rates(nco_lattice* lat, const double omega_high[4]);

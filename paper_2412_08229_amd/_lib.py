@@ -40,6 +40,7 @@ SIGNATURES = {
     "nco_lattice_destroy": (_I, [_P]),
     "nco_set_op": (_I, [_P, _I, ctypes.c_double]),
     "nco_set_rates": (_I, [_P, _D]),
+    "nco_set_domain": (_I, [_P, _I]),
     "nco_set_net_weights": (_I, [_P, _I, _I, _I, _F, _SZ]),
     "nco_init_equilibrium": (_I, [_P, _D, _D]),
     "nco_init_populations": (_I, [_P, _D]),
@@ -171,6 +172,13 @@ def nco_step(h, nsteps):
 
 def nco_sync(h):
     check(lib().nco_sync(h))
+
+
+DOMAINS = {"periodic": 0, "tgv_octant": 1}
+
+
+def nco_set_domain(h, domain):
+    check(lib().nco_set_domain(h, DOMAINS[domain] if isinstance(domain, str) else int(domain)))
 
 
 def nco_set_check(h, every, mass_rel_tol):

@@ -245,19 +245,12 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
     for (int k = 0; k < Q; ++k) gm[row_tensor(k)] += s_dm[lane][k];
     float gf[Q];
     moments_T(gm, gf);
-    // Scatter back along the streaming: position x - c_i.
+    // Scatter back along the streaming: the slot the pull read.
     if (live) {
-        const int xs[3] = {p.x == a.nx - 1 ? 0 : p.x + 1, p.x, p.x == 0 ? a.nx - 1 : p.x - 1};
-        const int ys[3] = {(p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx, p.y * a.nx,
-                           (p.y == 0 ? a.ny - 1 : p.y - 1) * a.nx};
-        const int nxy = a.nx * a.ny;
-        const int zs[3] = {(p.z == a.nz - 1 ? 0 : p.z + 1) * nxy, p.z * nxy,
-                           (p.z == 0 ? a.nz - 1 : p.z - 1) * nxy};
+        float v[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int dst = zs[cz_of(i) + 1] + ys[cy_of(i) + 1] + xs[cx_of(i) + 1];
-            lam_out[(size_t)i * a.n + dst] = lam[i] + gf[i];
-        }
+        for (int i = 0; i < Q; ++i) v[i] = lam[i] + gf[i];
+        scatter_to_sources(lam_out, a, p, v);
     }
 
     // Output-layer gradients: dW3 = sum (S2/48) dtt^T, db3 = sum dtt.

@@ -102,6 +102,7 @@ GroupAction build_group_action() {
 struct nco_lattice {
     int nx = 0, ny = 0, nz = 0, n = 0;
     int storage = 0, op = 0;
+    int domain = 0;               // DOMAIN_PERIODIC or DOMAIN_TGV_OCTANT
     double tau = 0.0;
     int device = 0;
     hipStream_t stream = nullptr;
@@ -243,6 +244,7 @@ StepArgs step_args(const nco_lattice* lat) {
     a.nz = lat->nz;
     a.n = lat->n;
     a.op = lat->op;
+    a.domain = lat->domain;
     a.width = lat->width;
     a.act = lat->act;
     a.omega_nu = 1.0 / lat->tau;
@@ -384,6 +386,21 @@ int nco_set_op(nco_lattice* lat, int op, double tau) {
     if (!(tau > 0.5) || !std::isfinite(tau)) return fail(NCO_E_INVALID, "tau must be > 1/2 (got %g)", tau);
     lat->op = op;
     lat->tau = tau;
+    return NCO_OK;
+}
+
+int nco_set_domain(nco_lattice* lat, int domain) {
+    if (int rc = check_lat(lat)) return rc;
+    if (domain == NCO_DOMAIN_PERIODIC) {
+        if (lat->domain != domain) lat->rec_steps = -1;
+        lat->domain = domain;
+        return NCO_OK;
+    }
+    if (domain != NCO_DOMAIN_TGV_OCTANT) return fail(NCO_E_INVALID, "unknown domain %d", domain);
+    if (lat->nx != lat->ny || lat->nx != lat->nz) return fail(NCO_E_INVALID, "the reduced domain is a cube");
+    if (lat->n_modes > 0) return fail(NCO_E_UNSUPPORTED, "spectral forcing needs the periodic domain");
+    lat->domain = domain;
+    lat->rec_steps = -1;  // a recorded run used the other streaming
     return NCO_OK;
 }
 
@@ -651,6 +668,8 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
     if (int rc = check_lat(lat)) return rc;
     if (n_modes < 0 || (n_modes > 0 && (!k || !draws || n_steps < 1 || !(c > 0.0))))
         return fail(NCO_E_INVALID, "bad forcing arguments");
+    if (n_modes > 0 && lat->domain != NCO_DOMAIN_PERIODIC)
+        return fail(NCO_E_UNSUPPORTED, "spectral forcing needs the periodic domain");
     if (int rc = set_device(lat)) return rc;
     HIP_TRY(hipStreamSynchronize(lat->stream));
     if (lat->d_fk) HIP_TRY(hipFree(lat->d_fk));
@@ -783,6 +802,8 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
     if (!grad || n_params != (size_t)adjoint_param_count())
         return fail(NCO_E_INVALID, "grad must hold %d values", adjoint_param_count());
     if (!dL_dE && !dL_df && !dL_dk) return fail(NCO_E_INVALID, "give dL_dE, dL_df or dL_dk");
+    if (dL_dE && lat->domain != NCO_DOMAIN_PERIODIC)
+        return fail(NCO_E_UNSUPPORTED, "a spectrum loss needs the periodic domain");
     if (dL_dk && every < 1) return fail(NCO_E_INVALID, "energy sampling needs every >= 1");
     // dL/dk(t) enters the adjoint of the state after t steps, t = m every.
     auto inject = [&](int t, const void* state, float* lam) -> int {
@@ -966,6 +987,7 @@ int nco_energy_spectrum(nco_lattice* lat, double* E, int nbins) {
     if (int rc = check_lat(lat)) return rc;
     if (!E) return fail(NCO_E_INVALID, "null output");
     if (lat->nx != lat->ny || lat->nx != lat->nz) return fail(NCO_E_INVALID, "spectrum needs a cubic lattice");
+    if (lat->domain != NCO_DOMAIN_PERIODIC) return fail(NCO_E_UNSUPPORTED, "spectrum needs the periodic domain");
     const int n = lat->nx;
     if (nbins != spectrum_bins(n)) return fail(NCO_E_INVALID, "nbins must be %d for n = %d", spectrum_bins(n), n);
     if (int rc = set_device(lat)) return rc;

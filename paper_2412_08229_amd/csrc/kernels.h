@@ -7,10 +7,16 @@
 
 namespace nco {
 
+// Lattice domains: the periodic box, or the reduced Taylor-Green cube of
+// Appendix A (n^3 nodes standing for the symmetric 4n box).
+constexpr int DOMAIN_PERIODIC = 0;
+constexpr int DOMAIN_TGV_OCTANT = 1;
+
 // Everything a stream-collide launch needs, passed by value.
 struct StepArgs {
     int nx, ny, nz, n;       // lattice extent and node count
     int op;                  // OP_BGK / OP_MRT / OP_NCO
+    int domain;              // DOMAIN_PERIODIC / DOMAIN_TGV_OCTANT (nx = ny = nz)
     int width, act;          // network shape (OP_NCO)
     double omega_nu;         // 1 / tau
     float omega_nu_f;

@@ -88,6 +88,15 @@ __global__ __launch_bounds__(256) void k_stream_only(const typename Codec<S>::st
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.n) return;
     const NodeIdx p = node_of(idx, a.nx, a.ny);
+    if (on_octant_face(a, p)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const Slot s = fold_octant(a.nx, p.x - cx_of(i), p.y - cy_of(i), p.z - cz_of(i), cx_of(i), cy_of(i),
+                                       cz_of(i));
+            fout[(size_t)i * a.n + idx] = fin[(size_t)s.plane * a.n + s.node];
+        }
+        return;
+    }
     const int xs[3] = {p.x == a.nx - 1 ? 0 : p.x + 1, p.x, p.x == 0 ? a.nx - 1 : p.x - 1};
     const int ys[3] = {(p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx, p.y * a.nx,
                        (p.y == 0 ? a.ny - 1 : p.y - 1) * a.nx};

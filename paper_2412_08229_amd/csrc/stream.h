@@ -21,11 +21,75 @@ __device__ __forceinline__ NodeIdx node_of(int idx, int nx, int ny) {
     return r;
 }
 
-// Pull the 27 populations of node (x, y, z): f_i(x) <- f_i(x - c_i), periodic.
+// Reduced Taylor-Green domain (Appendix A): the lattice is the cube
+// [0, pi/2]^3 of the vortex with n nodes per edge, half a spacing from the
+// faces, and stands for the whole 2 pi box, which the vortex's symmetries
+// fill with images of the cube.  A streaming source outside the cube is
+// mapped inside by one of those symmetries, and the population's velocity is
+// mapped with it:
+//   coordinate < 0 (the planes through the origin): mirror, that velocity
+//     component reversed (S_x, S_y, S_z);
+//   z > pi/2: half turn about the line x = y, z = pi/2,
+//     (x, y, z) -> (y, x, pi - z), c -> (c_y, c_x, -c_z);
+//   x > pi/2: quarter turn about the vortex axis x = y = pi/2,
+//     (x, y) -> (y, pi - x), c -> (c_y, -c_x);
+//   y > pi/2: the opposite quarter turn, (x, y) -> (pi - y, x), c -> (-c_y, c_x).
+// In node indices pi - x is 2n - 1 - j.  Two rounds bring every source with
+// coordinates in [-1, n] inside (checked exhaustively against the unfolded
+// periodic streaming for n = 1..7); the map is a bijection of population
+// slots, so its adjoint is the scatter to the same slot.  The clamp only
+// keeps an impossible input in bounds.
+struct Slot {
+    int plane, node;
+};
+
+__device__ __forceinline__ Slot fold_octant(int n, int sx, int sy, int sz, int cx, int cy, int cz) {
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        if (sx < 0) { sx = -1 - sx; cx = -cx; }
+        if (sy < 0) { sy = -1 - sy; cy = -cy; }
+        if (sz < 0) { sz = -1 - sz; cz = -cz; }
+        if (sz >= n) {
+            int t = sx; sx = sy; sy = t; sz = 2 * n - 1 - sz;
+            t = cx; cx = cy; cy = t; cz = -cz;
+        }
+        if (sx >= n) {
+            int t = sx; sx = sy; sy = 2 * n - 1 - t;
+            t = cx; cx = cy; cy = -t;
+        }
+        if (sy >= n) {
+            int t = sy; sy = sx; sx = 2 * n - 1 - t;
+            t = cy; cy = cx; cx = -t;
+        }
+    }
+    sx = min(max(sx, 0), n - 1);
+    sy = min(max(sy, 0), n - 1);
+    sz = min(max(sz, 0), n - 1);
+    return {9 * (cz + 1) + 3 * (cy + 1) + (cx + 1), (sz * n + sy) * n + sx};
+}
+
+__device__ __forceinline__ bool on_octant_face(const StepArgs& a, NodeIdx p) {
+    return a.domain == DOMAIN_TGV_OCTANT &&
+           (p.x == 0 || p.y == 0 || p.z == 0 || p.x == a.nx - 1 || p.y == a.nx - 1 || p.z == a.nx - 1);
+}
+
+// Pull the 27 populations of node (x, y, z): f_i(x) <- f_i(x - c_i), periodic,
+// or folded into the reduced Taylor-Green cube at its faces.
 template <int S>
 __device__ __forceinline__ void pull(const typename Codec<S>::store_t* __restrict__ fin,
                                      const StepArgs& a, NodeIdx p,
                                      typename Codec<S>::real (&f)[Q]) {
+    if (on_octant_face(a, p)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const Slot s = fold_octant(a.nx, p.x - cx_of(i), p.y - cy_of(i), p.z - cz_of(i), cx_of(i), cy_of(i),
+                                       cz_of(i));
+            f[i] = Codec<S>::load(fin + (size_t)s.plane * a.n + s.node, i);
+        }
+        return;
+    }
+    // Interior nodes of the reduced cube never wrap, so the periodic code
+    // serves them too.
     // Source coordinate for c = -1, 0, +1 is x + 1, x, x - 1.
     const int xs[3] = {p.x == a.nx - 1 ? 0 : p.x + 1, p.x, p.x == 0 ? a.nx - 1 : p.x - 1};
     const int ys[3] = {(p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx, p.y * a.nx,
@@ -37,6 +101,30 @@ __device__ __forceinline__ void pull(const typename Codec<S>::store_t* __restric
     for (int i = 0; i < Q; ++i) {
         const int src = zs[cz_of(i) + 1] + ys[cy_of(i) + 1] + xs[cx_of(i) + 1];
         f[i] = Codec<S>::load(fin + (size_t)i * a.n + src, i);
+    }
+}
+
+// Adjoint of pull: v_i(x) goes to the slot the pull of population i at x
+// read, dL/df_i(x - c_i) = v_i(x) (periodic) or its folded slot.
+__device__ __forceinline__ void scatter_to_sources(float* __restrict__ out, const StepArgs& a, NodeIdx p,
+                                                   const float (&v)[Q]) {
+    if (on_octant_face(a, p)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const Slot s = fold_octant(a.nx, p.x - cx_of(i), p.y - cy_of(i), p.z - cz_of(i), cx_of(i), cy_of(i),
+                                       cz_of(i));
+            out[(size_t)s.plane * a.n + s.node] = v[i];
+        }
+        return;
+    }
+    const int xs[3] = {p.x == a.nx - 1 ? 0 : p.x + 1, p.x, p.x == 0 ? a.nx - 1 : p.x - 1};
+    const int ys[3] = {(p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx, p.y * a.nx, (p.y == 0 ? a.ny - 1 : p.y - 1) * a.nx};
+    const int nxy = a.nx * a.ny;
+    const int zs[3] = {(p.z == a.nz - 1 ? 0 : p.z + 1) * nxy, p.z * nxy, (p.z == 0 ? a.nz - 1 : p.z - 1) * nxy};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int dst = zs[cz_of(i) + 1] + ys[cy_of(i) + 1] + xs[cx_of(i) + 1];
+        out[(size_t)i * a.n + dst] = v[i];
     }
 }
 

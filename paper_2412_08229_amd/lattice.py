@@ -87,6 +87,12 @@ class Lattice:
     def sync(self):
         L.nco_sync(self._h)
 
+    def set_domain(self, domain):
+        """'periodic' (default) or 'tgv_octant': the cube [0, pi/2]^3 of the
+        Taylor-Green vortex standing for the symmetric 4n box (Appendix A);
+        initialise it with ``inputs.tgv3d_octant``."""
+        L.nco_set_domain(self._h, domain)
+
     def set_check(self, every, mass_rel_tol):
         """Stability check every ``every`` steps (0: off); ``sync`` raises
         NCOError(NCO_E_UNSTABLE) once it has failed."""

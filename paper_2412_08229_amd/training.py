@@ -62,21 +62,27 @@ class Unroll:
 
 
 class DissipationUnroll:
-    """One dissipation-rate training sample (the loss of the reduced
-    Taylor-Green training in Sec. "Learning Task", on the periodic box): a
-    recorded run of nsteps steps from the fields (rho, u) whose mean kinetic
-    energy k(t) is sampled every ``every`` steps; the dissipation rate
-    eps = -dk/dt (centred differences, k in units of u0^2, t in convective
-    units L / u0 with L = n / 2 pi) is compared with eps_ref(t) over
-    t_min <= t:  L = mean ((eps - eps_ref) / max eps_ref)^2."""
+    """One dissipation-rate training sample (the loss of the Taylor-Green
+    training of Sec. "Training based on dissipation rates"): a recorded run
+    of nsteps steps from the fields (rho, u) whose mean kinetic energy k(t)
+    is sampled every ``every`` steps; the dissipation rate eps = -dk/dt
+    (centred differences, k in units of u0^2, t in convective units L / u0
+    with L = N / 2 pi for a box of N nodes per edge) is compared with
+    eps_ref(t) over t_min <= t:  L = mean ((eps - eps_ref) / max eps_ref)^2.
+
+    domain: 'periodic' (the box itself) or 'tgv_octant', the reduced cube of
+    Appendix A, whose n nodes per edge stand for the N = 4n box (fields from
+    ``inputs.tgv3d_octant``)."""
 
     def __init__(self, shape, tau, rho, u, u0, nsteps, ckpt_every, every, eps_ref, t_min=1.0,
-                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None):
+                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, domain="periodic"):
         self.lat = Lattice(shape, storage, "nco", tau, stream=stream)
+        if domain != "periodic":
+            self.lat.set_domain(domain)
         self.rho, self.u, self.u0 = rho, u, float(u0)
         self.nsteps, self.ckpt_every, self.every = int(nsteps), int(ckpt_every), int(every)
         self.act, self.mlp, self.width = act, mlp, width
-        L = shape[-1] / (2.0 * np.pi)
+        L = shape[-1] * (4 if domain == "tgv_octant" else 1) / (2.0 * np.pi)
         self.dt = self.every * self.u0 / L                       # convective time between samples
         m = self.nsteps // self.every + 1
         self.t = np.arange(m) * self.dt
