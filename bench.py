@@ -57,6 +57,10 @@ GRID = {"bgk_256": 256, "mrt_256": 256}
 VARIANTS["nco_w20_relu"] = ("nco", "f32", "f32_mfma", "relu")
 VARIANTS["nco_w20_relu_bf16net"] = ("nco", "f32", "bf16", "relu")
 NET_WIDTH = {"nco_w20_relu": 20, "nco_w20_relu_bf16net": 20}
+# The same Taylor-Green vortex on the reduced cube of Appendix A: an n/4
+# cube standing for the n box (the node grid is offset by half a spacing).
+VARIANTS["nco_octant"] = ("nco", "f32", "f32_mfma", "tanh")
+DOMAIN = {"nco_octant": "tgv_octant"}
 
 
 def nco_flops_per_node(width):
@@ -298,6 +302,68 @@ def tgv_dissipation(sizes, ref_n, t_end=20.0, dt=0.1, re=1600.0):
     print(json.dumps(out), flush=True)
 
 
+def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100):
+    """Dissipation-rate training of Sec. "Training based on dissipation
+    rates" on the reduced Taylor-Green cube of Appendix A: every (Re, Ma,
+    cube) of the grid is one sample, its loss the mean squared gap of -dk/dt
+    to a BGK run on the ref_cube cube at ``samples`` points over
+    0 <= t <= t_end; one Adam step per epoch on the mean loss, the samples
+    run concurrently on their own streams.  Reports the loss per sample
+    before and after training, for the fixed-rate operator and BGK (or the
+    time they became unstable), and the time per epoch.  Prints one JSON line."""
+    from paper_2412_08229_amd import inputs
+    from paper_2412_08229_amd.training import DissipationUnroll, tgv_cube_energy, train_batched
+
+    t0 = time.time()
+    refs = {}
+    for re in res:
+        for ma in mas:
+            u0 = ma / math.sqrt(3.0)
+            t, k, st = tgv_cube_energy("bgk", ref_cube, re, u0, t_end, 3 * samples)
+            refs[(re, ma)] = (t, -np.gradient(k, t), st)
+            print("# reference Re %g Ma %g: %s, %.1f s" % (re, ma, st, time.time() - t0), file=sys.stderr, flush=True)
+    p0 = inputs.mlp_params(32, seed=1)
+    runs, keys = [], []
+    for re in res:
+        for ma in mas:
+            u0 = ma / math.sqrt(3.0)
+            tr, er, _ = refs[(re, ma)]
+            for n in cubes:
+                _, tau = inputs.viscosity(4 * n, u0, re)
+                tc = 4 * n / (2.0 * math.pi) / u0
+                every = max(1, int(round(t_end * tc / samples)))
+                nsteps = int(round(t_end * tc / every)) * every
+                rho, u = inputs.tgv3d_octant(n, u0)
+                runs.append(DissipationUnroll((n, n, n), tau, rho, u, u0, nsteps, 50, every,
+                                              lambda t, tr=tr, er=er: float(np.interp(t, tr, er)), t_min=0.0,
+                                              domain="tgv_octant"))
+                keys.append("Re%g_Ma%g_n%d" % (re, ma, n))
+    L0 = [r.loss(p0) for r in runs]
+    t1 = time.time()
+    params, hist = train_batched(runs, p0, epochs, lr=lr,
+                                 log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    t_epoch = (time.time() - t1) / max(1, epochs)
+    L1 = [r.loss(params) for r in runs]
+    out = {"workload": "Taylor-Green dissipation training on the reduced cube, t <= %g, %d points" % (t_end, samples),
+           "reference": {"operator": "bgk", "cube": ref_cube, "box": 4 * ref_cube,
+                         "status": {"Re%g_Ma%g" % k: v[2] for k, v in refs.items()}},
+           "epochs": epochs, "lr": lr, "seconds_per_epoch": t_epoch, "history": hist, "samples": {}}
+    for key, run, l0, l1 in zip(keys, runs, L0, L1):
+        other = {}
+        for kind in ("mrt", "bgk"):
+            n = run.lat.nx
+            t, k, st = tgv_cube_energy(kind, n, None, run.u0, t_end, None, tau=run.lat.tau, every=run.every,
+                                       nsamp=run.nsteps // run.every)
+            if st != "stable":
+                other[kind] = st
+                continue
+            eps = -(k[run.inner + 1] - k[run.inner - 1]) / (2.0 * run.dt)
+            other[kind] = float(np.mean(((eps - run.eps_ref) / run.scale) ** 2))
+        out["samples"][key] = {"untrained": l0, "trained": l1, "fixed_rate": other["mrt"], "bgk": other["bgk"]}
+        run.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--tgv-dissipation", default="",
@@ -307,6 +373,13 @@ def main():
     ap.add_argument("--precision-horizon", type=float, default=0.0,
                     help="instead of the benchmark: the reduced-precision study over this many convective times")
     ap.add_argument("--f64-steps", type=int, default=20)
+    ap.add_argument("--tgv-training", default="",
+                    help="instead of the benchmark: dissipation training on reduced cubes of these sizes")
+    ap.add_argument("--re", default="400,800,1600")
+    ap.add_argument("--ma", default="0.1")
+    ap.add_argument("--ref-cube", type=int, default=128)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--lr", type=float, default=1e-2)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
@@ -316,7 +389,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the lattice path runs on a single MI355X; "
-              "multi-GPU domain decomposition is not part of this build", file=sys.stderr)
+              "multi-GPU domain decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.tgv_dissipation:
         sizes = [int(x) for x in args.tgv_dissipation.split(",")]
@@ -324,6 +397,10 @@ def main():
         return
     if args.convergence:
         convergence([int(x) for x in args.convergence.split(",")])
+        return
+    if args.tgv_training:
+        tgv_training([int(x) for x in args.tgv_training.split(",")], [float(x) for x in args.re.split(",")],
+                     [float(x) for x in args.ma.split(",")], args.ref_cube, args.epochs, args.lr)
         return
     if args.precision_horizon > 0:
         precision_horizon(args.n, args.precision_horizon, 100, args.f64_steps)
@@ -353,11 +430,17 @@ def main():
                 results[op]["forward_ms_per_step"], results[op]["reverse_ms_per_step"]), file=sys.stderr, flush=True)
             continue
         kind, storage, mlp, act = VARIANTS[op]
-        n_op = GRID.get(op, n)
-        if n_op not in fields:
-            fields[n_op] = (inputs.viscosity(n_op, u0, 1600.0)[1],) + inputs.tgv3d(n_op, u0)
-        tau_op, rho_op, u_op = fields[n_op]
+        domain = DOMAIN.get(op, "periodic")
+        if domain == "tgv_octant":
+            n_op = n // 4
+            tau_op, (rho_op, u_op) = tau, inputs.tgv3d_octant(n_op, u0)
+        else:
+            n_op = GRID.get(op, n)
+            if n_op not in fields:
+                fields[n_op] = (inputs.viscosity(n_op, u0, 1600.0)[1],) + inputs.tgv3d(n_op, u0)
+            tau_op, rho_op, u_op = fields[n_op]
         lat = Lattice((n_op, n_op, n_op), storage, kind, tau_op, stream=stream)
+        lat.set_domain(domain)
         if kind == "nco":
             w_op = NET_WIDTH.get(op, width)
             lat.set_net_weights(params if w_op == width else inputs.mlp_params(w_op, seed=0), w_op, act, mlp)
@@ -372,7 +455,7 @@ def main():
         s = lat.global_sums()
         if not np.all(np.isfinite(s)):
             raise RuntimeError("non-finite state after the %s run" % op)
-        if n_op == n:
+        if n_op == n and domain == "periodic":
             spectra[op] = (steps, lat.energy_spectrum(), s[4])
         lat.close()
         glups = n_op ** 3 / (ms * 1e-3) / 1e9
@@ -382,6 +465,10 @@ def main():
                        "network": mlp if kind == "nco" else None,
                        "width": NET_WIDTH.get(op, width) if kind == "nco" else None,
                        "activation": act if kind == "nco" else None}
+        if domain == "tgv_octant":
+            results[op]["domain"] = domain
+            results[op]["box"] = 4 * n_op
+            results[op]["box_equivalent_glups"] = (4 * n_op) ** 3 / (ms * 1e-3) / 1e9
         print("# %s: %.4f ms/step, %.3f GLUPS, %.0f GB/s" % (op, ms, glups, gbs), file=sys.stderr,
               flush=True)
 

@@ -130,6 +130,8 @@ struct nco_lattice {
     long rec_force_t0 = 0;
     long steps_since_record = 0;
     std::vector<void*> ckpt, seg;
+    double* d_k = nullptr;        // energy samples of a recorded run (5 sums each)
+    int d_k_cap = 0;
     float* lam[2] = {nullptr, nullptr};
     float* adj_partial = nullptr;
     double* d_grad = nullptr;
@@ -369,6 +371,7 @@ int nco_lattice_destroy(nco_lattice* lat) {
     if (lat->d_fhat) hipFree(lat->d_fhat);
     for (void* p : lat->ckpt) hipFree(p);
     for (void* p : lat->seg) hipFree(p);
+    if (lat->d_k) hipFree(lat->d_k);
     for (int b = 0; b < 2; ++b)
         if (lat->lam[b]) hipFree(lat->lam[b]);
     if (lat->adj_partial) hipFree(lat->adj_partial);
@@ -741,8 +744,16 @@ int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, doub
         lat->ckpt.push_back(p);
     }
     const int nk = every > 0 ? nsteps / every + 1 : 0;
-    double* d_k = nullptr;
-    if (nk > 0) HIP_TRY(hipMalloc(&d_k, sizeof(double) * 5 * nk));
+    if (nk > lat->d_k_cap) {
+        // Kept between calls: a free would wait for the whole device.
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        if (lat->d_k) HIP_TRY(hipFree(lat->d_k));
+        lat->d_k = nullptr;
+        lat->d_k_cap = 0;
+        HIP_TRY(hipMalloc(&lat->d_k, sizeof(double) * 5 * nk));
+        lat->d_k_cap = nk;
+    }
+    double* d_k = lat->d_k;
     auto sample = [&](int m) -> int {
         HIP_TRY(launch_global_sums(lat->storage, lat->f[lat->cur], lat->partial, d_k + 5 * m, lat->n, lat->stream));
         return NCO_OK;
@@ -770,10 +781,6 @@ int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, doub
             hipStreamSynchronize(lat->stream) != hipSuccess)
             rc = fail(NCO_E_HIP, "reading the energy samples failed");
         for (int m = 0; m < nk && rc == NCO_OK; ++m) k[m] = sums[5 * m + 4] / lat->n;
-    }
-    if (d_k) {
-        hipStreamSynchronize(lat->stream);
-        hipFree(d_k);
     }
     if (rc != NCO_OK) return rc;
     lat->rec_steps = nsteps;

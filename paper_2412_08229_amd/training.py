@@ -123,6 +123,48 @@ class DissipationUnroll:
         self.lat.close()
 
 
+def tgv_cube_energy(kind, n, re, u0, t_end, samples, params=None, tau=None, every=None, nsamp=None,
+                    width=32, act="tanh", mlp="f32_mfma", stream=None):
+    """Mean kinetic energy k(t) / u0^2 of the Taylor-Green vortex on the
+    reduced n^3 cube of Appendix A (the box of 4n nodes per edge), sampled
+    at t = 0, every, 2 every, ... steps; t in convective units.
+
+    Either (re, t_end, samples): tau from the Reynolds number of the 4n box
+    and ``samples`` intervals over [0, t_end]; or (tau, every, nsamp)
+    directly.  kind: 'bgk', 'mrt' (orders 3..6 relaxed at 4/3, the network's
+    rates at a zero output) or 'nco' with ``params``.  A run whose global
+    sums stop being finite ends there.  Returns (t, k, status)."""
+    from . import inputs
+    from . import _lib as L
+    N = 4 * n
+    tc = N / (2.0 * np.pi) / u0                      # steps per convective time
+    if tau is None:
+        tau = inputs.viscosity(N, u0, re)[1]
+    if every is None:
+        every = max(1, int(round(t_end * tc / samples)))
+        nsamp = int(round(t_end * tc / every))
+    rho, u = inputs.tgv3d_octant(n, u0)
+    ts, ks, status = [0.0], [], "stable"
+    with Lattice((n, n, n), "f32", kind, tau, stream=stream) as lat:
+        lat.set_domain("tgv_octant")
+        if kind == "nco":
+            lat.set_net_weights(params, width, act, mlp)
+        if kind == "mrt":
+            lat.set_rates([4.0 / 3.0] * 4)
+        lat.init_equilibrium(rho, u)
+        ks.append(lat.global_sums()[4] / lat.n / u0 ** 2)
+        for i in range(nsamp):
+            lat.step(every)
+            try:
+                s = lat.global_sums()
+            except L.NCOError:
+                status = "unstable at t = %.2f" % ((i + 1) * every / tc)
+                break
+            ts.append((i + 1) * every / tc)
+            ks.append(s[4] / lat.n / u0 ** 2)
+    return np.array(ts), np.array(ks), status
+
+
 def make_autograd(unroll):
     """torch.autograd.Function computing the loss of ``unroll`` from a flat
     float64 parameter tensor, with the hand-written adjoint as backward."""
@@ -166,4 +208,33 @@ def train(unrolls, params0, epochs, lr=1e-3, log=None):
     return p.detach().numpy().copy(), history
 
 
-__all__ = ["log_spectrum_loss", "Unroll", "DissipationUnroll", "make_autograd", "train", "n_bins"]
+def train_batched(unrolls, params0, epochs, lr=1e-3, log=None):
+    """Adam with one step per epoch on the mean loss of all samples.  The
+    samples' recorded runs and reverse sweeps go concurrently, one host
+    thread per sample, each lattice on its own stream (the library's calls
+    on different lattices are independent and release the interpreter
+    lock), so that small lattices share the device instead of queueing.
+    Returns (params, mean loss per epoch)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    p = torch.nn.Parameter(torch.tensor(np.asarray(params0, np.float64)))
+    opt = torch.optim.Adam([p], lr=lr)
+    history = []
+    with ThreadPoolExecutor(max_workers=len(unrolls)) as pool:
+        for ep in range(epochs):
+            x = p.detach().numpy().copy()
+            res = list(pool.map(lambda u: u.loss_and_grad(x), unrolls))
+            opt.zero_grad()
+            p.grad = torch.from_numpy(np.mean([r[1] for r in res], axis=0))
+            opt.step()
+            with torch.no_grad():
+                p.copy_(p.float().double())          # parameters live as float32 values
+            history.append(float(np.mean([r[0] for r in res])))
+            if log:
+                log("epoch %d: loss %.6f" % (ep, history[-1]))
+    return p.detach().numpy().copy(), history
+
+
+__all__ = ["log_spectrum_loss", "Unroll", "DissipationUnroll", "tgv_cube_energy", "make_autograd", "train",
+           "train_batched", "n_bins"]
