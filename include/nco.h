@@ -134,6 +134,18 @@ int nco_set_rates(nco_lattice* lat, const double omega_high[4]);
 int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec,
                         const float* params, size_t n_params);
 
+/* The same with depth = 2 or 3 hidden layers.  Depth 3 is the network of
+ * Sec. "Training based on dissipation rates", which adds a hidden layer:
+ * 27 -> width -> width -> width -> 4, params in the order W1[27][width],
+ * b1, W2[width][width], b2, W2b[width][width], b2b, W3[width][4], b3
+ * (n_params = width*(27 + 2 width + 4) + 3 width + 4).  Depth 3 runs on the
+ * vector-unit network only (NCO_MLP_F32; NCO_E_UNSUPPORTED otherwise), with
+ * narrower networks zero-padded to width 32, and has the reverse mode:
+ * nco_backward returns the gradient in this parameter order.  Setting the
+ * weights drops a recorded run. */
+int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, int mlp_prec,
+                              const float* params, size_t n_params);
+
 /* f = f^eq(rho, u) (Eq. EquilibriumDistribution).  rho: N values or NULL
  * for rho = 1; u: 3N values. */
 int nco_init_equilibrium(nco_lattice* lat, const double* rho, const double* u);

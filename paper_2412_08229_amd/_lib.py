@@ -42,6 +42,7 @@ SIGNATURES = {
     "nco_set_rates": (_I, [_P, _D]),
     "nco_set_domain": (_I, [_P, _I]),
     "nco_set_net_weights": (_I, [_P, _I, _I, _I, _F, _SZ]),
+    "nco_set_net_weights_depth": (_I, [_P, _I, _I, _I, _I, _F, _SZ]),
     "nco_init_equilibrium": (_I, [_P, _D, _D]),
     "nco_init_populations": (_I, [_P, _D]),
     "nco_step": (_I, [_P, _I]),
@@ -147,9 +148,12 @@ def nco_set_rates(h, omega_high):
     check(lib().nco_set_rates(h, dptr(w)))
 
 
-def nco_set_net_weights(h, width, act, mlp_prec, params):
+def nco_set_net_weights(h, width, act, mlp_prec, params, depth=2):
     p = np.ascontiguousarray(params, dtype=np.float32)
-    check(lib().nco_set_net_weights(h, width, act, mlp_prec, fptr(p), p.size))
+    if depth == 2:
+        check(lib().nco_set_net_weights(h, width, act, mlp_prec, fptr(p), p.size))
+    else:
+        check(lib().nco_set_net_weights_depth(h, depth, width, act, mlp_prec, fptr(p), p.size))
 
 
 def nco_init_equilibrium(h, n, rho, u):

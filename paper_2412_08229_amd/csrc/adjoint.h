@@ -14,6 +14,8 @@ inline constexpr int AW = 32;                    // network width of the adjoint
 inline constexpr int NPAR = AW * (27 + AW + 4) + 2 * AW + 4;
 inline constexpr int OFF_W1 = 0, OFF_B1 = 27 * AW, OFF_W2 = OFF_B1 + AW, OFF_B2 = OFF_W2 + AW * AW;
 inline constexpr int OFF_W3 = OFF_B2 + AW, OFF_B3 = OFF_W3 + 4 * AW;
+// Depth 3 (vector-unit adjoint): the third hidden layer's gradient follows.
+inline constexpr int OFF_W2B = NPAR, OFF_B2B = OFF_W2B + AW * AW, NPAR3 = OFF_B2B + AW;
 
 // One-dimensional pieces of M^T (transpose of fwd3) and M^{-T} (transpose
 // of inv3), applied along each axis like the transforms themselves.

@@ -22,15 +22,23 @@ namespace nco {
 
 namespace {
 
-template <int S, int ACT>
+// DEPTH = 3: a third hidden layer (W2b, b2b) between the second and the
+// output layer; its gradient goes to the tail OFF_W2B, OFF_B2B of a partial
+// row of NPAR3 values.
+template <int S, int ACT, int DEPTH>
 __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t* __restrict__ xin,
                                                 const float* __restrict__ lam_in, float* __restrict__ lam_out,
                                                 StepArgs a, const int* __restrict__ gsrc,
                                                 float* __restrict__ partial) {
     constexpr int W = AW;
+    constexpr int W3X = DEPTH == 3 ? W : 1;     // extent of the third layer's arrays
+    constexpr int ROW = DEPTH == 3 ? NPAR3 : NPAR;
     // Network (unstacked W1 [27][W], b1, W2 [W][W], b2, W3 [W][4], b3), read
     // by every lane with the same address (LDS broadcast).
     __shared__ float s_w1[27 * W], s_b1[W], s_w2[W * W], s_b2[W], s_w3[W * 4], s_b3[4];
+    __shared__ float s_w2b[W3X * W3X], s_b2b[W3X];
+    __shared__ float s_h2[64][W3X];
+    __shared__ float s_d3[64][W3X];
     // Per-node rows: moments (paper order, [27] = 1), dL/dm, and the vectors
     // of the current group element for the parameter-gradient reduction.
     __shared__ float s_m[64][28];
@@ -52,6 +60,10 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
             s_b2[lane] = net[net_off_b2(W) + lane];
         }
         if (lane < 4) s_b3[lane] = net[net_off_b3(W) + lane];
+        if constexpr (DEPTH == 3) {
+            for (int e = lane; e < W * W; e += 64) s_w2b[e] = net[net_off_w2b(W) + e];
+            if (lane < W) s_b2b[lane] = net[net_off_b2b(W) + lane];
+        }
     }
 
     // Forward quantities of the node: pulled populations and moments.
@@ -101,8 +113,22 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
             for (int o = 0; o < W; ++o) z[o] = fmaf(s_w2[j * W + o], hj, z[o]);
         }
+        if constexpr (DEPTH == 2) {
 #pragma unroll
-        for (int o = 0; o < W; ++o) S2[o] += act_f<ACT>(z[o]);
+            for (int o = 0; o < W; ++o) S2[o] += act_f<ACT>(z[o]);
+        } else {
+            float z3[W];
+#pragma unroll
+            for (int o = 0; o < W; ++o) z3[o] = s_b2b[o];
+#pragma unroll 4
+            for (int j = 0; j < W; ++j) {
+                const float hj = act_f<ACT>(z[j]);
+#pragma unroll
+                for (int o = 0; o < W; ++o) z3[o] = fmaf(s_w2b[j * W + o], hj, z3[o]);
+            }
+#pragma unroll
+            for (int o = 0; o < W; ++o) S2[o] += act_f<ACT>(z3[o]);
+        }
     }
     float tt[4], omega[4], tau[4];
 #pragma unroll
@@ -152,12 +178,14 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
     const int r1 = 7 * (lane >> 4), c1 = 2 * (lane & 15);        // W1 rows r1..r1+6 (27 = b1), cols c1, c1+1
     const int r2 = 4 * (lane >> 3), c2 = 4 * (lane & 7);         // W2 rows r2..r2+3, cols c2..c2+3
     float acc1[7][2], acc2[4][4], accb2 = 0.0f;
+    // Depth 3: W2b rows r2..r2+3, cols c2..c2+3 in acc3; lanes 32..63 own b2b.
+    float acc3[4][4], accb2b = 0.0f;
 #pragma unroll
     for (int i = 0; i < 7; ++i) acc1[i][0] = acc1[i][1] = 0.0f;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc2[i][j] = 0.0f;
+        for (int j = 0; j < 4; ++j) acc2[i][j] = acc3[i][j] = 0.0f;
 
     // Pass 2: per group element, recompute, back-propagate, reduce.
 #pragma unroll 1
@@ -185,10 +213,40 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
         for (int j = 0; j < W; ++j)
 #pragma unroll
             for (int o = 0; o < W; ++o) dz2[o] = fmaf(s_w2[j * W + o], h1[j], dz2[o]);
+        if constexpr (DEPTH == 2) {
 #pragma unroll
-        for (int o = 0; o < W; ++o) {
-            dz2[o] = dh2[o] * act_d<ACT>(act_f<ACT>(dz2[o]));
-            s_d2[lane][o] = dz2[o];
+            for (int o = 0; o < W; ++o) {
+                dz2[o] = dh2[o] * act_d<ACT>(act_f<ACT>(dz2[o]));
+                s_d2[lane][o] = dz2[o];
+            }
+        } else {
+            // h2 = act(z2); z3 = W2b^T h2 + b2b; dz3 = dh3 act'(z3) with dh3
+            // the output layer's adjoint (dh2 above); dz2 = (W2b dz3) act'(z2).
+#pragma unroll
+            for (int o = 0; o < W; ++o) {
+                dz2[o] = act_f<ACT>(dz2[o]);
+                s_h2[lane][o] = dz2[o];
+            }
+            float dz3[W];
+#pragma unroll
+            for (int o = 0; o < W; ++o) dz3[o] = s_b2b[o];
+#pragma unroll 4
+            for (int j = 0; j < W; ++j)
+#pragma unroll
+                for (int o = 0; o < W; ++o) dz3[o] = fmaf(s_w2b[j * W + o], dz2[j], dz3[o]);
+#pragma unroll
+            for (int o = 0; o < W; ++o) {
+                dz3[o] = dh2[o] * act_d<ACT>(act_f<ACT>(dz3[o]));
+                s_d3[lane][o] = dz3[o];
+            }
+#pragma unroll 4
+            for (int j = 0; j < W; ++j) {
+                float t = 0.0f;
+#pragma unroll
+                for (int o = 0; o < W; ++o) t = fmaf(s_w2b[j * W + o], dz3[o], t);
+                dz2[j] = t * act_d<ACT>(s_h2[lane][j]);
+                s_d2[lane][j] = dz2[j];
+            }
         }
         float dz1[W];
 #pragma unroll 4
@@ -236,6 +294,18 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc2[i][c] = fmaf(hv[i], d2v[c], acc2[i][c]);
             if (lane < W) accb2 += s_d2[nd][lane];
+            if constexpr (DEPTH == 3) {
+                float h2v[4], d3v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) h2v[i] = s_h2[nd][r2 + i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) d3v[c] = s_d3[nd][c2 + c];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc3[i][c] = fmaf(h2v[i], d3v[c], acc3[i][c]);
+                if (lane >= 64 - W) accb2b += s_d3[nd][lane - (64 - W)];
+            }
         }
         __syncthreads();
     }
@@ -259,7 +329,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
     for (int n = 0; n < 4; ++n) s_d2[lane][n] = dtt[n];
     __syncthreads();
-    float* __restrict__ out = partial + (size_t)blockIdx.x * NPAR;
+    float* __restrict__ out = partial + (size_t)blockIdx.x * ROW;
     {
         float w3a = 0.0f, w3b = 0.0f, b3a = 0.0f;
         const int e0 = 2 * lane, e1 = 2 * lane + 1;              // W3 entries [o][n] = e / 4, e % 4
@@ -288,16 +358,24 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
         for (int c = 0; c < 4; ++c) out[OFF_W2 + (r2 + i) * W + c2 + c] = acc2[i][c];
     if (lane < W) out[OFF_B2 + lane] = accb2;
+    if constexpr (DEPTH == 3) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) out[OFF_W2B + (r2 + i) * W + c2 + c] = acc3[i][c];
+        if (lane >= 64 - W) out[OFF_B2B + lane - (64 - W)] = accb2b;
+    }
 }
 
 
-// grad[p] += sum over blocks of partial[b][p], in block order, in float64.
-__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial, int nblocks,
+// grad[p] += sum over blocks of partial[b][p] (rows of npar), in block
+// order, in float64.
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial, int nblocks, int npar,
                                                      double* __restrict__ grad) {
     const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pidx >= NPAR) return;
+    if (pidx >= npar) return;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += (double)partial[(size_t)b * NPAR + pidx];
+    for (int b = 0; b < nblocks; ++b) s += (double)partial[(size_t)b * npar + pidx];
     grad[pidx] += s;
 }
 
@@ -370,6 +448,7 @@ __global__ __launch_bounds__(256) void k_f32_to_f64(const float* __restrict__ sr
 }  // namespace
 
 int adjoint_param_count() { return NPAR; }
+int adjoint_param_count_depth(int depth) { return depth == 3 ? NPAR3 : NPAR; }
 int adjoint_blocks(int n) { return (n + 63) / 64; }
 
 hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
@@ -378,12 +457,21 @@ hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, flo
 #define ADJ_CASE(SS)                                                                                         \
     case SS: {                                                                                               \
         using T = typename Codec<SS>::store_t;                                                               \
-        if (a.act == ACT_TANH)                                                                               \
-            hipLaunchKernelGGL((k_adjoint<SS, ACT_TANH>), grid, block, 0, st, static_cast<const T*>(xin),    \
-                               lam_in, lam_out, a, gsrc, partial);                                           \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_adjoint<SS, ACT_RELU>), grid, block, 0, st, static_cast<const T*>(xin),    \
-                               lam_in, lam_out, a, gsrc, partial);                                           \
+        const T* x = static_cast<const T*>(xin);                                                            \
+        if (a.depth == 3) {                                                                                  \
+            if (a.act == ACT_TANH)                                                                           \
+                hipLaunchKernelGGL((k_adjoint<SS, ACT_TANH, 3>), grid, block, 0, st, x, lam_in, lam_out, a, gsrc, \
+                                   partial);                                                                 \
+            else                                                                                             \
+                hipLaunchKernelGGL((k_adjoint<SS, ACT_RELU, 3>), grid, block, 0, st, x, lam_in, lam_out, a, gsrc, \
+                                   partial);                                                                 \
+        } else if (a.act == ACT_TANH) {                                                                      \
+            hipLaunchKernelGGL((k_adjoint<SS, ACT_TANH, 2>), grid, block, 0, st, x, lam_in, lam_out, a, gsrc,   \
+                               partial);                                                                     \
+        } else {                                                                                             \
+            hipLaunchKernelGGL((k_adjoint<SS, ACT_RELU, 2>), grid, block, 0, st, x, lam_in, lam_out, a, gsrc,   \
+                               partial);                                                                     \
+        }                                                                                                    \
         return hipGetLastError();                                                                            \
     }
     switch (storage) {
@@ -395,8 +483,8 @@ hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, flo
 #undef ADJ_CASE
 }
 
-hipError_t launch_grad_reduce(const float* partial, int nblocks, double* grad, hipStream_t st) {
-    hipLaunchKernelGGL(k_grad_reduce, dim3((NPAR + 255) / 256), dim3(256), 0, st, partial, nblocks, grad);
+hipError_t launch_grad_reduce(const float* partial, int nblocks, int npar, double* grad, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_reduce, dim3((npar + 255) / 256), dim3(256), 0, st, partial, nblocks, npar, grad);
     return hipGetLastError();
 }
 

@@ -55,6 +55,67 @@ size_t store_bytes(int storage) {
 bool width_ok(int w) { return w == 8 || w == 16 || w == 20 || w == 32; }
 
 size_t n_params_for(int width) { return (size_t)width * (27 + width + 4) + 2 * (size_t)width + 4; }
+size_t n_params_depth(int width, int depth) {
+    return n_params_for(width) + (depth == 3 ? (size_t)width * width + width : 0);
+}
+
+// Parameters of a width-W network (order W1, b1, W2, b2, [W2b, b2b,] W3, b3,
+// each W [in][out]) zero-padded to width P: a padded hidden unit has zero
+// weights in and out and a zero bias, so it adds exactly nothing.
+std::vector<float> pad_params(const float* p, int W, int depth, int P) {
+    std::vector<float> out(n_params_depth(P, depth), 0.0f);
+    const float* s = p;
+    float* d = out.data();
+    for (int k = 0; k < 27; ++k)
+        for (int h = 0; h < W; ++h) d[k * P + h] = s[k * W + h];
+    s += 27 * W;
+    d += 27 * P;
+    for (int h = 0; h < W; ++h) d[h] = s[h];
+    s += W;
+    d += P;
+    for (int layer = 1; layer < depth; ++layer) {
+        for (int i = 0; i < W; ++i)
+            for (int o = 0; o < W; ++o) d[i * P + o] = s[i * W + o];
+        s += W * W;
+        d += P * P;
+        for (int o = 0; o < W; ++o) d[o] = s[o];
+        s += W;
+        d += P;
+    }
+    for (int i = 0; i < W; ++i)
+        for (int n = 0; n < 4; ++n) d[i * 4 + n] = s[i * 4 + n];
+    s += 4 * W;
+    d += 4 * P;
+    for (int n = 0; n < 4; ++n) d[n] = s[n];
+    return out;
+}
+
+// Depth-3 gradient from the vector-unit adjoint's row layout at width P
+// (W1, b1, W2, b2, W3, b3, then W2b, b2b) to the parameter order at width W
+// (W1, b1, W2, b2, W2b, b2b, W3, b3), dropping the padded units.
+void unpad_grad3(const double* g, int P, int W, double* out) {
+    const double* gW1 = g;
+    const double* gb1 = gW1 + 27 * P;
+    const double* gW2 = gb1 + P;
+    const double* gb2 = gW2 + P * P;
+    const double* gW3 = gb2 + P;
+    const double* gb3 = gW3 + 4 * P;
+    const double* gW2b = gb3 + 4;
+    const double* gb2b = gW2b + P * P;
+    double* d = out;
+    for (int k = 0; k < 27; ++k)
+        for (int h = 0; h < W; ++h) *d++ = gW1[k * P + h];
+    for (int h = 0; h < W; ++h) *d++ = gb1[h];
+    for (int i = 0; i < W; ++i)
+        for (int o = 0; o < W; ++o) *d++ = gW2[i * P + o];
+    for (int o = 0; o < W; ++o) *d++ = gb2[o];
+    for (int i = 0; i < W; ++i)
+        for (int o = 0; o < W; ++o) *d++ = gW2b[i * P + o];
+    for (int o = 0; o < W; ++o) *d++ = gb2b[o];
+    for (int i = 0; i < W; ++i)
+        for (int n = 0; n < 4; ++n) *d++ = gW3[i * 4 + n];
+    for (int n = 0; n < 4; ++n) *d++ = gb3[n];
+}
 
 // Paper row of a Hermite multi-index (inverse of row_tensor).
 int row_of_tensor(int t) {
@@ -114,6 +175,8 @@ struct nco_lattice {
     float* net = nullptr;
     void* mfma_tab = nullptr;     // per-lane operand table + group gather table
     int width = 0, act = 0, mlp_prec = 0;
+    int depth = 2;                // hidden layers
+    int user_width = 0;           // width as given (a depth-3 network runs padded to 32)
     double* staging = nullptr;    // host-transfer staging, allocated on first use
     int staging_per_node = 0;     // its size in doubles per node
     double* partial = nullptr;    // global-sum partials
@@ -134,6 +197,7 @@ struct nco_lattice {
     int d_k_cap = 0;
     float* lam[2] = {nullptr, nullptr};
     float* adj_partial = nullptr;
+    size_t adj_partial_floats = 0;
     double* d_grad = nullptr;
     double* d_dE = nullptr;
     int* d_gsrc = nullptr;        // [48][27] group source row | sign bit
@@ -248,6 +312,7 @@ StepArgs step_args(const nco_lattice* lat) {
     a.op = lat->op;
     a.domain = lat->domain;
     a.width = lat->width;
+    a.depth = lat->depth;
     a.act = lat->act;
     a.omega_nu = 1.0 / lat->tau;
     a.omega_nu_f = (float)a.omega_nu;
@@ -420,26 +485,46 @@ int nco_set_rates(nco_lattice* lat, const double omega_high[4]) {
 
 int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, const float* params,
                         size_t n_params) {
+    return nco_set_net_weights_depth(lat, 2, width, act, mlp_prec, params, n_params);
+}
+
+int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, int mlp_prec, const float* params,
+                              size_t n_params) {
     if (int rc = check_lat(lat)) return rc;
+    if (depth != 2 && depth != 3) return fail(NCO_E_INVALID, "depth %d not supported (2, 3)", depth);
     if (!width_ok(width)) return fail(NCO_E_INVALID, "width %d not supported (8, 16, 20, 32)", width);
     if (act != NCO_ACT_TANH && act != NCO_ACT_RELU) return fail(NCO_E_INVALID, "unknown activation %d", act);
     if (mlp_prec != NCO_MLP_F32 && mlp_prec != NCO_MLP_F32_MFMA && mlp_prec != NCO_MLP_BF16)
         return fail(NCO_E_INVALID, "unknown network precision %d", mlp_prec);
     if (mlp_prec != NCO_MLP_F32 && lat->storage == NCO_F64)
         return fail(NCO_E_UNSUPPORTED, "the matrix-core network needs float32 or 16-bit storage");
+    if (depth == 3 && mlp_prec != NCO_MLP_F32)
+        return fail(NCO_E_UNSUPPORTED, "a third hidden layer runs on the vector-unit network (NCO_MLP_F32)");
     if (!params) return fail(NCO_E_INVALID, "null parameters");
-    if (n_params != n_params_for(width))
-        return fail(NCO_E_INVALID, "expected %zu parameters for width %d, got %zu", n_params_for(width),
-                    width, n_params);
-    const int W = width;
+    if (n_params != n_params_depth(width, depth))
+        return fail(NCO_E_INVALID, "expected %zu parameters for width %d and depth %d, got %zu",
+                    n_params_depth(width, depth), width, depth, n_params);
+    // Depth 3 runs at width 32, narrower networks zero-padded.
+    std::vector<float> padded3;
+    if (depth == 3 && width < 32) {
+        padded3 = pad_params(params, width, 3, 32);
+        params = padded3.data();
+    }
+    const int W = depth == 3 ? 32 : width;
     static const GroupAction G = build_group_action();
-    std::vector<float> buf(net_floats(W), 0.0f);
+    std::vector<float> buf(net_floats_depth(W, depth), 0.0f);
     const float* W1 = params;
     const float* b1 = W1 + 27 * W;
     const float* W2 = b1 + W;
     const float* b2 = W2 + W * W;
-    const float* W3 = b2 + W;
+    const float* W2b = b2 + W;                      // depth 3 only
+    const float* b2b = W2b + W * W;
+    const float* W3 = depth == 3 ? b2b + W : b2 + W;
     const float* b3 = W3 + 4 * W;
+    if (depth == 3) {
+        std::memcpy(&buf[net_off_w2b(W)], W2b, sizeof(float) * W * W);
+        std::memcpy(&buf[net_off_b2b(W)], b2b, sizeof(float) * W);
+    }
     for (int g = 0; g < NGROUP; ++g)
         for (int k = 0; k < 27; ++k)
             for (int h = 0; h < W; ++h)
@@ -450,18 +535,21 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec, cons
     std::memcpy(&buf[net_off_w3(W)], W3, sizeof(float) * W * 4);
     std::memcpy(&buf[net_off_b3(W)], b3, sizeof(float) * 4);
     if (int rc = set_device(lat)) return rc;
-    if (lat->net && lat->width != W) {
+    if (lat->net && (lat->width != W || lat->depth != depth)) {
         HIP_TRY(hipStreamSynchronize(lat->stream));
         HIP_TRY(hipFree(lat->net));
         lat->net = nullptr;
     }
-    if (!lat->net) HIP_TRY(hipMalloc(&lat->net, sizeof(float) * net_floats(W)));
+    if (!lat->net) HIP_TRY(hipMalloc(&lat->net, sizeof(float) * buf.size()));
     HIP_TRY(hipMemcpyAsync(lat->net, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice,
                            lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
     lat->width = W;
+    lat->user_width = width;
+    lat->depth = depth;
     lat->act = act;
     lat->mlp_prec = mlp_prec;
+    lat->rec_steps = -1;  // a recorded run used the previous network
     {
         // Group table of the adjoint: source row | sign bit per element and row.
         int gs[48 * 27];
@@ -806,8 +894,8 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
     if (int rc = check_lat(lat)) return rc;
     if (lat->rec_steps < 1 || lat->steps_since_record != 0)
         return fail(NCO_E_STATE, "backward needs nco_forward_record immediately before it");
-    if (!grad || n_params != (size_t)adjoint_param_count())
-        return fail(NCO_E_INVALID, "grad must hold %d values", adjoint_param_count());
+    const size_t want = lat->depth == 3 ? n_params_depth(lat->user_width, 3) : (size_t)adjoint_param_count();
+    if (!grad || n_params != want) return fail(NCO_E_INVALID, "grad must hold %zu values", want);
     if (!dL_dE && !dL_df && !dL_dk) return fail(NCO_E_INVALID, "give dL_dE, dL_df or dL_dk");
     if (dL_dE && lat->domain != NCO_DOMAIN_PERIODIC)
         return fail(NCO_E_UNSUPPORTED, "a spectrum loss needs the periodic domain");
@@ -830,17 +918,22 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
     // Matrix-core adjoint for matrix-core networks, vector-unit adjoint for
     // the vector-unit network.
     const bool mfma = lat->mlp_prec != NCO_MLP_F32 && lat->adj_tab;
-    const int npar = adjoint_param_count();
+    const int npar = mfma ? adjoint_param_count() : adjoint_param_count_depth(lat->depth);
     const int nblk = mfma ? adjoint_mfma_blocks(lat->n) : adjoint_blocks(lat->n);
     const int ngrp = (nblk + 63) / 64;
     if (mfma) {
         if (!lat->adj_partial64)
             HIP_TRY(hipMalloc(&lat->adj_partial64, sizeof(double) * (size_t)(nblk + ngrp) * npar));
         HIP_TRY(launch_fill_f64(lat->adj_partial64, (size_t)nblk * npar, 0.0, lat->stream));
-    } else if (!lat->adj_partial) {
+    } else if (lat->adj_partial_floats < (size_t)nblk * npar) {
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        if (lat->adj_partial) HIP_TRY(hipFree(lat->adj_partial));
+        lat->adj_partial = nullptr;
+        lat->adj_partial_floats = 0;
         HIP_TRY(hipMalloc(&lat->adj_partial, sizeof(float) * (size_t)nblk * npar));
+        lat->adj_partial_floats = (size_t)nblk * npar;
     }
-    if (!lat->d_grad) HIP_TRY(hipMalloc(&lat->d_grad, sizeof(double) * adjoint_param_count()));
+    if (!lat->d_grad) HIP_TRY(hipMalloc(&lat->d_grad, sizeof(double) * adjoint_param_count_depth(3)));
     while ((int)lat->seg.size() < lat->rec_every) {
         void* p = nullptr;
         HIP_TRY(hipMalloc(&p, lat->pop_bytes));
@@ -865,7 +958,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
         HIP_TRY(launch_add_f64_to_f32(lin, lat->staging, nf, lat->stream));
     }
     if (int rc = inject(lat->rec_steps, lat->f[lat->cur], lin)) return rc;
-    HIP_TRY(launch_fill_f64(lat->d_grad, adjoint_param_count(), 0.0, lat->stream));
+    HIP_TRY(launch_fill_f64(lat->d_grad, npar, 0.0, lat->stream));
     const int T = lat->rec_steps, K = lat->rec_every;
     const int ncp = (T + K - 1) / K;
     for (int sgi = ncp - 1; sgi >= 0; --sgi) {
@@ -887,7 +980,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
             } else {
                 HIP_TRY(launch_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_gsrc, lat->adj_partial,
                                        lat->stream));
-                HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, lat->d_grad, lat->stream));
+                HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, npar, lat->d_grad, lat->stream));
             }
             if (int rc = inject(t, lat->seg[t - t0], lout)) return rc;
             std::swap(lin, lout);
@@ -896,14 +989,17 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
     if (mfma)
         HIP_TRY(launch_grad_reduce_f64(lat->adj_partial64, nblk, lat->adj_partial64 + (size_t)nblk * npar,
                                        lat->d_grad, lat->stream));
-    HIP_TRY(hipMemcpyAsync(grad, lat->d_grad, sizeof(double) * adjoint_param_count(), hipMemcpyDeviceToHost,
-                           lat->stream));
     if (dL_df0) {
         if (int rc = ensure_staging(lat, 27)) return rc;
         HIP_TRY(launch_f32_to_f64(lin, lat->staging, nf, lat->stream));
         HIP_TRY(hipMemcpyAsync(dL_df0, lat->staging, sizeof(double) * nf, hipMemcpyDeviceToHost, lat->stream));
     }
+    // Last before the wait, so that no early return leaves a copy into g3 in flight.
+    std::vector<double> g3(lat->depth == 3 ? npar : 0);
+    HIP_TRY(hipMemcpyAsync(lat->depth == 3 ? g3.data() : grad, lat->d_grad, sizeof(double) * npar,
+                           hipMemcpyDeviceToHost, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
+    if (lat->depth == 3) unpad_grad3(g3.data(), lat->width, lat->user_width, grad);
     return NCO_OK;
 }
 

@@ -36,6 +36,12 @@ __host__ __device__ constexpr int net_off_b2(int W) { return net_off_w2(W) + W *
 __host__ __device__ constexpr int net_off_w3(int W) { return net_off_b2(W) + W; }
 __host__ __device__ constexpr int net_off_b3(int W) { return net_off_w3(W) + 4 * W; }
 __host__ __device__ constexpr int net_floats(int W) { return net_off_b3(W) + 4; }
+// A third hidden layer (depth 3) follows: W2b[W][W], b2b[W].
+__host__ __device__ constexpr int net_off_w2b(int W) { return net_floats(W); }
+__host__ __device__ constexpr int net_off_b2b(int W) { return net_off_w2b(W) + W * W; }
+__host__ __device__ constexpr int net_floats_depth(int W, int depth) {
+    return depth == 3 ? net_off_b2b(W) + W : net_floats(W);
+}
 
 template <int ACT, typename R>
 __device__ __forceinline__ R activate(R x) {
@@ -53,8 +59,9 @@ __device__ __forceinline__ R squash_rate(R t) {
     return R(1) / tau;
 }
 
-// omega_3..omega_6 of one node from its moments (tensor order).
-template <typename R, int W, int ACT>
+// omega_3..omega_6 of one node from its moments (tensor order), with
+// DEPTH = 2 or 3 hidden layers.
+template <typename R, int W, int ACT, int DEPTH = 2>
 __device__ __forceinline__ void net_rates(const R (&m)[Q], const float* __restrict__ net,
                                           R (&omega)[4]) {
     R x[Q];
@@ -80,12 +87,32 @@ __device__ __forceinline__ void net_rates(const R (&m)[Q], const float* __restri
             for (int j = 0; j < W; ++j) h[j] = fma((R)wg[k * W + j], x[k], h[j]);
 #pragma unroll
         for (int j = 0; j < W; ++j) h[j] = activate<ACT>(h[j]);
+        if constexpr (DEPTH == 2) {
 #pragma unroll
-        for (int o = 0; o < W; ++o) {
-            R s = (R)b2[o];
+            for (int o = 0; o < W; ++o) {
+                R s = (R)b2[o];
 #pragma unroll
-            for (int j = 0; j < W; ++j) s = fma((R)w2[j * W + o], h[j], s);
-            acc[o] += activate<ACT>(s);
+                for (int j = 0; j < W; ++j) s = fma((R)w2[j * W + o], h[j], s);
+                acc[o] += activate<ACT>(s);
+            }
+        } else {
+            const float* __restrict__ w2b = net + net_off_w2b(W);
+            const float* __restrict__ b2b = net + net_off_b2b(W);
+            R h2[W];
+#pragma unroll
+            for (int o = 0; o < W; ++o) {
+                R s = (R)b2[o];
+#pragma unroll
+                for (int j = 0; j < W; ++j) s = fma((R)w2[j * W + o], h[j], s);
+                h2[o] = activate<ACT>(s);
+            }
+#pragma unroll
+            for (int o = 0; o < W; ++o) {
+                R s = (R)b2b[o];
+#pragma unroll
+                for (int j = 0; j < W; ++j) s = fma((R)w2b[j * W + o], h2[j], s);
+                acc[o] += activate<ACT>(s);
+            }
         }
     }
 #pragma unroll

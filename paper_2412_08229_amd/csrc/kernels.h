@@ -18,6 +18,7 @@ struct StepArgs {
     int op;                  // OP_BGK / OP_MRT / OP_NCO
     int domain;              // DOMAIN_PERIODIC / DOMAIN_TGV_OCTANT (nx = ny = nz)
     int width, act;          // network shape (OP_NCO)
+    int depth;               // hidden layers: 2, or 3 (vector-unit network, width 32)
     double omega_nu;         // 1 / tau
     float omega_nu_f;
     double omega_high[4];    // fixed rates of orders 3..6 (OP_MRT)
@@ -104,7 +105,8 @@ int adjoint_param_count();
 int adjoint_blocks(int n);
 hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
                           const int* gsrc, float* partial, hipStream_t st);
-hipError_t launch_grad_reduce(const float* partial, int nblocks, double* grad, hipStream_t st);
+hipError_t launch_grad_reduce(const float* partial, int nblocks, int npar, double* grad, hipStream_t st);
+int adjoint_param_count_depth(int depth);
 // lam += coef d(sum over nodes of |u|^2 / 2) / df for the state f (float64 arithmetic).
 hipError_t launch_add_energy_grad(int storage, const void* f, float* lam, double coef, int n, hipStream_t st);
 // grad = sum over rows of partial[nblocks][NPAR] (float64) in row order, in

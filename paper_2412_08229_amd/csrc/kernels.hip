@@ -15,7 +15,7 @@ template <> __device__ __forceinline__ double pick<double>(float, double d) { re
 
 // Collision of one node in place (plus the Kupershtokh source of force F when
 // FORCED); OP and W/ACT select the operator.
-template <typename R, int OP, int W, int ACT, bool FORCED>
+template <typename R, int OP, int W, int ACT, bool FORCED, int DEPTH = 2>
 __device__ __forceinline__ void collide_node(R (&f)[Q], const StepArgs& a, R Fx, R Fy, R Fz) {
     const R omega_nu = pick<R>(a.omega_nu_f, a.omega_nu);
     if constexpr (OP == OP_BGK) {
@@ -25,7 +25,7 @@ __device__ __forceinline__ void collide_node(R (&f)[Q], const StepArgs& a, R Fx,
         to_moments(f, m);
         R omega[4];
         if constexpr (OP == OP_NCO) {
-            net_rates<R, W, ACT>(m, a.net, omega);
+            net_rates<R, W, ACT, DEPTH>(m, a.net, omega);
         } else {
 #pragma unroll
             for (int n = 0; n < 4; ++n) omega[n] = pick<R>(a.omega_high_f[n], a.omega_high[n]);
@@ -38,16 +38,16 @@ __device__ __forceinline__ void collide_node(R (&f)[Q], const StepArgs& a, R Fx,
     }
 }
 
-template <int S, int OP, int W, int ACT>
+template <int S, int OP, int W, int ACT, int DEPTH = 2>
 __device__ __forceinline__ void stream_collide_node(const typename Codec<S>::store_t* __restrict__ fin,
                                                     typename Codec<S>::store_t* __restrict__ fout,
                                                     const StepArgs& a, int idx);
 
-template <int S, int OP, int W, int ACT>
+template <int S, int OP, int W, int ACT, int DEPTH = 2>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename Codec<S>::store_t* __restrict__ fin,
                                                         typename Codec<S>::store_t* __restrict__ fout,
                                                         StepArgs a) {
-    stream_collide_node<S, OP, W, ACT>(fin, fout, a, blockIdx.x * blockDim.x + threadIdx.x);
+    stream_collide_node<S, OP, W, ACT, DEPTH>(fin, fout, a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // One step of several lattices of the same kind in one dispatch.
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_grouped(LaunchGroup g) {
                                             (blockIdx.x - g.prefix[i]) * blockDim.x + threadIdx.x);
 }
 
-template <int S, int OP, int W, int ACT>
+template <int S, int OP, int W, int ACT, int DEPTH>
 __device__ __forceinline__ void stream_collide_node(const typename Codec<S>::store_t* __restrict__ fin,
                                                     typename Codec<S>::store_t* __restrict__ fout,
                                                     const StepArgs& a, int idx) {
@@ -72,9 +72,9 @@ __device__ __forceinline__ void stream_collide_node(const typename Codec<S>::sto
     if (a.n_modes > 0) {
         double Fx, Fy, Fz;
         force_at(a, p.x, p.y, p.z, Fx, Fy, Fz);
-        collide_node<R, OP, W, ACT, true>(f, a, (R)Fx, (R)Fy, (R)Fz);
+        collide_node<R, OP, W, ACT, true, DEPTH>(f, a, (R)Fx, (R)Fy, (R)Fz);
     } else {
-        collide_node<R, OP, W, ACT, false>(f, a, R(0), R(0), R(0));
+        collide_node<R, OP, W, ACT, false, DEPTH>(f, a, R(0), R(0), R(0));
     }
     store_local<S>(fout, a.n, idx, f);
 }
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_stream_only(const typename Codec<S>::st
     }
 }
 
-template <int S, int W, int ACT>
+template <int S, int W, int ACT, int DEPTH = 2>
 __global__ __launch_bounds__(256) void k_rates(const typename Codec<S>::store_t* __restrict__ fin,
                                                double* __restrict__ omega_out, StepArgs a) {
     using R = typename Codec<S>::real;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_rates(const typename Codec<S>::store_t*
     R f[Q], m[Q], omega[4];
     load_local<S>(fin, a.n, idx, f);
     to_moments(f, m);
-    net_rates<R, W, ACT>(m, a.net, omega);
+    net_rates<R, W, ACT, DEPTH>(m, a.net, omega);
 #pragma unroll
     for (int k = 0; k < 4; ++k) omega_out[(size_t)k * a.n + idx] = (double)omega[k];
 }
@@ -290,11 +290,21 @@ hipError_t launch_step_op(const void* fin, void* fout, const StepArgs& a, hipStr
         hipLaunchKernelGGL((k_stream_collide<S, OP, 8, ACT_TANH>), dim3(nblocks(a.n)), dim3(256), 0, st, in, out, a);
     } else {
 #define NCO_CASE(WW, AA)                                                                               \
-    if (a.width == WW && a.act == AA) {                                                                \
+    if (a.depth == 2 && a.width == WW && a.act == AA) {                                                \
         hipLaunchKernelGGL((k_stream_collide<S, OP, WW, AA>), dim3(nblocks(a.n)), dim3(256), 0, st, in, \
                            out, a);                                                                    \
         return hipGetLastError();                                                                      \
     }
+        // Depth 3 runs at width 32 (narrower networks are zero-padded).
+        if (a.depth == 3 && a.width == 32) {
+            if (a.act == ACT_TANH)
+                hipLaunchKernelGGL((k_stream_collide<S, OP, 32, ACT_TANH, 3>), dim3(nblocks(a.n)), dim3(256), 0, st,
+                                   in, out, a);
+            else
+                hipLaunchKernelGGL((k_stream_collide<S, OP, 32, ACT_RELU, 3>), dim3(nblocks(a.n)), dim3(256), 0, st,
+                                   in, out, a);
+            return hipGetLastError();
+        }
         NCO_CASE(8, ACT_TANH) NCO_CASE(16, ACT_TANH) NCO_CASE(20, ACT_TANH) NCO_CASE(32, ACT_TANH)
         NCO_CASE(8, ACT_RELU) NCO_CASE(16, ACT_RELU) NCO_CASE(20, ACT_RELU) NCO_CASE(32, ACT_RELU)
 #undef NCO_CASE
@@ -307,8 +317,15 @@ template <int S>
 hipError_t launch_rates_s(const void* fin, double* out, const StepArgs& a, hipStream_t st) {
     using T = typename Codec<S>::store_t;
     const T* in = static_cast<const T*>(fin);
+    if (a.depth == 3 && a.width == 32) {
+        if (a.act == ACT_TANH)
+            hipLaunchKernelGGL((k_rates<S, 32, ACT_TANH, 3>), dim3(nblocks(a.n)), dim3(256), 0, st, in, out, a);
+        else
+            hipLaunchKernelGGL((k_rates<S, 32, ACT_RELU, 3>), dim3(nblocks(a.n)), dim3(256), 0, st, in, out, a);
+        return hipGetLastError();
+    }
 #define RATE_CASE(WW, AA)                                                                            \
-    if (a.width == WW && a.act == AA) {                                                              \
+    if (a.depth == 2 && a.width == WW && a.act == AA) {                                                              \
         hipLaunchKernelGGL((k_rates<S, WW, AA>), dim3(nblocks(a.n)), dim3(256), 0, st, in, out, a); \
         return hipGetLastError();                                                                    \
     }

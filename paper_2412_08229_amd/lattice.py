@@ -33,6 +33,7 @@ class Lattice:
         self.storage = storage
         self.op = op
         self.tau = float(tau)
+        self.n_params = 2084          # width-32, depth-2 network until set_net_weights
         self._h = L.nco_lattice_create(self.nx, self.ny, self.nz, L.STORAGE[storage], L.OPS[op],
                                        self.tau, stream)
 
@@ -71,8 +72,11 @@ class Lattice:
     def set_rates(self, omega_high):
         L.nco_set_rates(self._h, omega_high)
 
-    def set_net_weights(self, params, width, act="tanh", mlp_prec="f32"):
-        L.nco_set_net_weights(self._h, width, L.ACTS[act], L.MLP_PREC[mlp_prec], params)
+    def set_net_weights(self, params, width, act="tanh", mlp_prec="f32", depth=2):
+        """Network weights (order W1, b1, W2, b2, [W2b, b2b,] W3, b3); depth
+        3 adds the third hidden layer (vector-unit network only)."""
+        L.nco_set_net_weights(self._h, width, L.ACTS[act], L.MLP_PREC[mlp_prec], params, depth)
+        self.n_params = int(np.asarray(params).size)
 
     def init_equilibrium(self, rho, u):
         L.nco_init_equilibrium(self._h, self.n, None if rho is None else np.asarray(rho).ravel(),
@@ -129,9 +133,11 @@ class Lattice:
         L.nco_forward_record(self._h, int(nsteps), int(ckpt_every))
         return None
 
-    def backward(self, dL_dE=None, dL_df=None, n_params=2084, want_df0=False, dL_dk=None, energy_every=0):
-        """Gradient of the recorded run: (dL/dtheta, dL/df0 or None).  dL_dk:
+    def backward(self, dL_dE=None, dL_df=None, n_params=None, want_df0=False, dL_dk=None, energy_every=0):
+        """Gradient of the recorded run: (dL/dtheta, dL/df0 or None), dL/dtheta
+        in the order of the parameters given to set_net_weights.  dL_dk:
         loss gradient on the kinetic-energy samples of forward_record."""
+        n_params = self.n_params if n_params is None else n_params
         df = None if dL_df is None else np.asarray(dL_df).ravel()
         if dL_dk is not None:
             g, df0 = L.nco_backward_energy(self._h, self.n, n_params, dL_dk, int(energy_every), dL_dE, df, want_df0)

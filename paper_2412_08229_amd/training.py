@@ -72,11 +72,14 @@ class DissipationUnroll:
 
     domain: 'periodic' (the box itself) or 'tgv_octant', the reduced cube of
     Appendix A, whose n nodes per edge stand for the N = 4n box (fields from
-    ``inputs.tgv3d_octant``)."""
+    ``inputs.tgv3d_octant``).  depth: hidden layers of the network (3 adds
+    the paper's extra layer for this training; vector-unit network, mlp
+    'f32')."""
 
     def __init__(self, shape, tau, rho, u, u0, nsteps, ckpt_every, every, eps_ref, t_min=1.0,
-                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, domain="periodic"):
+                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, domain="periodic", depth=2):
         self.lat = Lattice(shape, storage, "nco", tau, stream=stream)
+        self.depth = int(depth)
         if domain != "periodic":
             self.lat.set_domain(domain)
         self.rho, self.u, self.u0 = rho, u, float(u0)
@@ -93,7 +96,7 @@ class DissipationUnroll:
 
     def _run(self, params):
         lat = self.lat
-        lat.set_net_weights(params, self.width, self.act, self.mlp)
+        lat.set_net_weights(params, self.width, self.act, self.mlp, depth=self.depth)
         lat.init_equilibrium(self.rho, self.u)
         k = lat.forward_record(self.nsteps, self.ckpt_every, energy_every=self.every) / self.u0 ** 2
         eps = -(k[self.inner + 1] - k[self.inner - 1]) / (2.0 * self.dt)
@@ -124,7 +127,7 @@ class DissipationUnroll:
 
 
 def tgv_cube_energy(kind, n, re, u0, t_end, samples, params=None, tau=None, every=None, nsamp=None,
-                    width=32, act="tanh", mlp="f32_mfma", stream=None):
+                    width=32, act="tanh", mlp="f32_mfma", stream=None, depth=2):
     """Mean kinetic energy k(t) / u0^2 of the Taylor-Green vortex on the
     reduced n^3 cube of Appendix A (the box of 4n nodes per edge), sampled
     at t = 0, every, 2 every, ... steps; t in convective units.
@@ -148,7 +151,7 @@ def tgv_cube_energy(kind, n, re, u0, t_end, samples, params=None, tau=None, ever
     with Lattice((n, n, n), "f32", kind, tau, stream=stream) as lat:
         lat.set_domain("tgv_octant")
         if kind == "nco":
-            lat.set_net_weights(params, width, act, mlp)
+            lat.set_net_weights(params, width, act, mlp, depth=depth)
         if kind == "mrt":
             lat.set_rates([4.0 / 3.0] * 4)
         lat.init_equilibrium(rho, u)

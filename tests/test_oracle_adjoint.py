@@ -180,3 +180,22 @@ def test_trajectory_loss_gradient_matches_finite_differences():
     fd = (loss(layers, f0 + h * d) - loss(layers, f0 - h * d)) / (2 * h)
     an = (gf0 * d).sum()
     assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12), (fd, an)
+
+
+def test_collision_vjp_depth3_matches_finite_differences():
+    """The reverse mode through a network with a third hidden layer (the
+    network of Sec. "Training based on dissipation rates")."""
+    rng = _rng(31)
+    f = inputs.random_populations((6,), seed=32, lo=0.8, hi=1.2)
+    lam = rng.standard_normal((27, 6))
+    layers = collision.unpack_params(inputs.mlp_params(8, 33, depth=3), 8, depth=3)
+    assert len(layers) == 4
+    tau, h = 0.56, 1e-6
+    g_f, g_p = adjoint.nco_collide_vjp(f, lam, tau, layers, "tanh")
+    d = rng.standard_normal((27, 6))
+    fd = ((collision.nco(f + h * d, tau, layers) - collision.nco(f - h * d, tau, layers)) / (2 * h) * lam).sum()
+    assert abs(fd - (g_f * d).sum()) < 1e-7 * max(1.0, abs(fd))
+    v = rng.standard_normal(collision.n_params(8, depth=3))
+    fd = ((collision.nco(f, tau, _perturb(layers, v, h)) - collision.nco(f, tau, _perturb(layers, v, -h)))
+          / (2 * h) * lam).sum()
+    assert abs(fd - adjoint.flatten(g_p) @ v) < 1e-7 * max(1.0, abs(fd))
