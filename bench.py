@@ -302,7 +302,8 @@ def tgv_dissipation(sizes, ref_n, t_end=20.0, dt=0.1, re=1600.0):
     print(json.dumps(out), flush=True)
 
 
-def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100):
+def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100, width=32, act="tanh", depth=2,
+                 mlp="f32_mfma"):
     """Dissipation-rate training of Sec. "Training based on dissipation
     rates" on the reduced Taylor-Green cube of Appendix A: every (Re, Ma,
     cube) of the grid is one sample, its loss the mean squared gap of -dk/dt
@@ -310,7 +311,10 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100)
     0 <= t <= t_end; one Adam step per epoch on the mean loss, the samples
     run concurrently on their own streams.  Reports the loss per sample
     before and after training, for the fixed-rate operator and BGK (or the
-    time they became unstable), and the time per epoch.  Prints one JSON line."""
+    time they became unstable), and the time per epoch.  The network is
+    27-width-...-4 with ``depth`` hidden layers (depth 3 with width 20 and
+    ReLU is the paper's network for this training; it runs on the vector
+    units, mlp 'f32').  Prints one JSON line."""
     from paper_2412_08229_amd import inputs
     from paper_2412_08229_amd.training import DissipationUnroll, tgv_cube_energy, train_batched
 
@@ -322,7 +326,7 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100)
             t, k, st = tgv_cube_energy("bgk", ref_cube, re, u0, t_end, 3 * samples)
             refs[(re, ma)] = (t, -np.gradient(k, t), st)
             print("# reference Re %g Ma %g: %s, %.1f s" % (re, ma, st, time.time() - t0), file=sys.stderr, flush=True)
-    p0 = inputs.mlp_params(32, seed=1)
+    p0 = inputs.mlp_params(width, seed=1, depth=depth)
     runs, keys = [], []
     for re in res:
         for ma in mas:
@@ -336,7 +340,7 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100)
                 rho, u = inputs.tgv3d_octant(n, u0)
                 runs.append(DissipationUnroll((n, n, n), tau, rho, u, u0, nsteps, 50, every,
                                               lambda t, tr=tr, er=er: float(np.interp(t, tr, er)), t_min=0.0,
-                                              domain="tgv_octant"))
+                                              domain="tgv_octant", width=width, act=act, mlp=mlp, depth=depth))
                 keys.append("Re%g_Ma%g_n%d" % (re, ma, n))
     L0 = [r.loss(p0) for r in runs]
     t1 = time.time()
@@ -347,6 +351,7 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100)
     out = {"workload": "Taylor-Green dissipation training on the reduced cube, t <= %g, %d points" % (t_end, samples),
            "reference": {"operator": "bgk", "cube": ref_cube, "box": 4 * ref_cube,
                          "status": {"Re%g_Ma%g" % k: v[2] for k, v in refs.items()}},
+           "network": {"width": width, "depth": depth, "activation": act, "arithmetic": mlp},
            "epochs": epochs, "lr": lr, "seconds_per_epoch": t_epoch, "history": hist, "samples": {}}
     for key, run, l0, l1 in zip(keys, runs, L0, L1):
         other = {}
@@ -380,6 +385,7 @@ def main():
     ap.add_argument("--ref-cube", type=int, default=128)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--net", default="32,2,tanh,f32_mfma", help="width,depth,activation,arithmetic of --tgv-training")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
@@ -399,8 +405,10 @@ def main():
         convergence([int(x) for x in args.convergence.split(",")])
         return
     if args.tgv_training:
+        w, d, a, m = args.net.split(",")
         tgv_training([int(x) for x in args.tgv_training.split(",")], [float(x) for x in args.re.split(",")],
-                     [float(x) for x in args.ma.split(",")], args.ref_cube, args.epochs, args.lr)
+                     [float(x) for x in args.ma.split(",")], args.ref_cube, args.epochs, args.lr,
+                     width=int(w), depth=int(d), act=a, mlp=m)
         return
     if args.precision_horizon > 0:
         precision_horizon(args.n, args.precision_horizon, 100, args.f64_steps)
