@@ -26,6 +26,8 @@ paper defines, in float64, with the passage it follows named in its docstring:
 * ``reduced``     - the reduced Taylor-Green domain of Appendix A: the cube
                     [0, pi/2]^3 stepped by unfolding it to the periodic box
                     through the vortex's symmetry group.
+* ``restrict``    - fine-to-coarse restriction by acoustic scaling (Sec.
+                    "Learning Task").
 * ``adjoint``     - reverse-mode derivative of an unrolled run with respect to
                     the network parameters (what Adam consumes in Sec.
                     "Learning Task").

@@ -20,17 +20,49 @@ def log_spectrum_loss(E, E_target, kmin, kmax):
     return float(np.mean(r * r)), dE
 
 
+def paper_spectrum_loss(E, E_target, kmin=4, kmax=10, omega=20.0, kappa_max=None):
+    """The loss of Eq. (loss) in Sec. "Learning Task": the mean squared gap
+    of the spectrum to the target over kmin <= k <= kmax plus omega E(kappa_max),
+    which presses down the energy piling up at the grid cutoff; kappa_max is
+    the shell N/2 of an N^3 box (without it, the smallest N whose spectrum
+    has len(E) shells is taken).  Returns (L, dL/dE)."""
+    E = np.asarray(E, np.float64)
+    ks = np.arange(kmin, kmax + 1)
+    kc = int(kappa_max) if kappa_max is not None else _cutoff_shell(len(E))
+    r = E[ks] - E_target[ks]
+    dE = np.zeros_like(E)
+    dE[ks] = 2.0 * r / len(ks)
+    dE[kc] += omega
+    return float(np.mean(r * r) + omega * E[kc]), dE
+
+
+def _cutoff_shell(nbins):
+    """N/2 for a spectrum of n_bins(N) shells."""
+    for n in range(2, 4 * nbins):
+        if n_bins(n) == nbins:
+            return n // 2
+    raise ValueError("no lattice size has %d shells" % nbins)
+
+
 class Unroll:
     """One training sample: initial populations (or fields), forcing and the
     unroll length; evaluates the loss and its gradient for given parameters
     on a lattice that stays resident on the device."""
 
     def __init__(self, shape, tau, init, nsteps, ckpt_every, target, kmin, kmax, forcing=None,
-                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None):
+                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, loss="log", omega=20.0):
         self.lat = Lattice(shape, storage, "nco", tau, stream=stream)
         self.init, self.nsteps, self.ckpt_every = init, int(nsteps), int(ckpt_every)
         self.target, self.kmin, self.kmax = np.asarray(target, np.float64), int(kmin), int(kmax)
         self.forcing, self.act, self.mlp, self.width = forcing, act, mlp, width
+        # 'log': mean squared log gap over kmin..kmax; 'paper': Eq. (loss),
+        # the squared gap over kmin..kmax plus omega E(N/2).
+        self.loss_kind, self.omega = loss, float(omega)
+
+    def _loss(self, E):
+        if self.loss_kind == "paper":
+            return paper_spectrum_loss(E, self.target, self.kmin, self.kmax, self.omega, self.lat.nx // 2)
+        return log_spectrum_loss(E, self.target, self.kmin, self.kmax)
 
     def _reset(self, params):
         lat = self.lat
@@ -47,13 +79,13 @@ class Unroll:
     def loss(self, params):
         self._reset(params)
         self.lat.step(self.nsteps)
-        return log_spectrum_loss(self.lat.energy_spectrum(), self.target, self.kmin, self.kmax)[0]
+        return self._loss(self.lat.energy_spectrum())[0]
 
     def loss_and_grad(self, params):
         self._reset(params)
         self.lat.forward_record(self.nsteps, self.ckpt_every)
         E = self.lat.energy_spectrum()
-        L, dE = log_spectrum_loss(E, self.target, self.kmin, self.kmax)
+        L, dE = self._loss(E)
         g, _ = self.lat.backward(dL_dE=dE)
         return L, g, E
 
@@ -188,14 +220,25 @@ def make_autograd(unroll):
     return NCOUnrollLoss.apply
 
 
-def train(unrolls, params0, epochs, lr=1e-3, log=None):
-    """Adam (torch.optim) over the given samples; returns (params, losses)."""
+def curriculum_steps(epoch, start=200, grow=200, every=10):
+    """Unroll length of the curriculum of Sec. "Learning Task": the loss is
+    first taken after 200 steps, and 200 more every ten epochs."""
+    return start + grow * (epoch // every)
+
+
+def train(unrolls, params0, epochs, lr=1e-3, log=None, schedule=None):
+    """Adam (torch.optim) over the given samples; returns (params, losses).
+    schedule: None, or a function epoch -> unroll length (e.g.
+    ``curriculum_steps``) applied to every sample at the start of an epoch."""
     import torch
     p = torch.nn.Parameter(torch.tensor(np.asarray(params0, np.float64)))
     opt = torch.optim.Adam([p], lr=lr)
     fns = [make_autograd(u) for u in unrolls]
     history = []
     for ep in range(epochs):
+        if schedule is not None:
+            for u in unrolls:
+                u.nsteps = int(schedule(ep))
         total = 0.0
         for fn in fns:
             opt.zero_grad()
@@ -239,5 +282,5 @@ def train_batched(unrolls, params0, epochs, lr=1e-3, log=None):
     return p.detach().numpy().copy(), history
 
 
-__all__ = ["log_spectrum_loss", "Unroll", "DissipationUnroll", "tgv_cube_energy", "make_autograd", "train",
+__all__ = ["log_spectrum_loss", "paper_spectrum_loss", "curriculum_steps", "Unroll", "DissipationUnroll", "tgv_cube_energy", "make_autograd", "train",
            "train_batched", "n_bins"]
