@@ -150,6 +150,24 @@ int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, i
  * for rho = 1; u: 3N values. */
 int nco_init_equilibrium(nco_lattice* lat, const double* rho, const double* u);
 
+/* Fine-to-coarse restriction by acoustic scaling (Sec. "Learning Task",
+ * the equation for f_{i,c}): set the state of `coarse` from that of `fine`,
+ * whose extent is r times the coarse one on every axis (integer r >= 1;
+ * coarse node X sits on fine node r X).  At each coarse node the fine
+ * node's density and velocity give f^eq, and the fine non-equilibrium part
+ * f - f^eq is scaled by r tau_c / tau_f (the taus of the two lattices; the
+ * paper prints 2 tau_c / tau_f, the r = 2 case).  The formula is applied to
+ * the distribution entering the collision: the fine state is streamed
+ * first, and the result is stored un-streamed, so that the coarse lattice's
+ * next step streams it back and collides exactly the restricted
+ * distribution.  float64 arithmetic, any storages.  Waits for the fine
+ * lattice's stream, runs on the coarse one's and returns when done; the
+ * coarse lattice counts as freshly initialised (stability check mass,
+ * recorded run dropped).  NCO_E_INVALID for extents that are not an integer
+ * multiple or lattices on different devices; NCO_E_UNSUPPORTED for the
+ * reduced domain. */
+int nco_restrict(const nco_lattice* fine, nco_lattice* coarse);
+
 /* Set the populations directly: f holds 27N values. */
 int nco_init_populations(nco_lattice* lat, const double* f);
 

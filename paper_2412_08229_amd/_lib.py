@@ -41,6 +41,7 @@ SIGNATURES = {
     "nco_set_op": (_I, [_P, _I, ctypes.c_double]),
     "nco_set_rates": (_I, [_P, _D]),
     "nco_set_domain": (_I, [_P, _I]),
+    "nco_restrict": (_I, [_P, _P]),
     "nco_set_net_weights": (_I, [_P, _I, _I, _I, _F, _SZ]),
     "nco_set_net_weights_depth": (_I, [_P, _I, _I, _I, _I, _F, _SZ]),
     "nco_init_equilibrium": (_I, [_P, _D, _D]),
@@ -176,6 +177,10 @@ def nco_step(h, nsteps):
 
 def nco_sync(h):
     check(lib().nco_sync(h))
+
+
+def nco_restrict(fine, coarse):
+    check(lib().nco_restrict(fine, coarse))
 
 
 DOMAINS = {"periodic": 0, "tgv_octant": 1}

@@ -627,6 +627,26 @@ int nco_init_equilibrium(nco_lattice* lat, const double* rho, const double* u) {
     return record_mass(lat);
 }
 
+int nco_restrict(const nco_lattice* fine, nco_lattice* coarse) {
+    if (int rc = check_lat(coarse)) return rc;
+    if (int rc = check_lat(const_cast<nco_lattice*>(fine))) return rc;
+    if (fine == coarse) return fail(NCO_E_INVALID, "restriction needs two lattices");
+    const int r = fine->nx / coarse->nx;
+    if (r < 1 || fine->nx != r * coarse->nx || fine->ny != r * coarse->ny || fine->nz != r * coarse->nz)
+        return fail(NCO_E_INVALID, "the fine extent must be the same integer multiple of the coarse one on every axis");
+    if (fine->domain != NCO_DOMAIN_PERIODIC || coarse->domain != NCO_DOMAIN_PERIODIC)
+        return fail(NCO_E_UNSUPPORTED, "restriction needs periodic lattices");
+    if (fine->device != coarse->device) return fail(NCO_E_INVALID, "the lattices live on different devices");
+    if (int rc = set_device(coarse)) return rc;
+    HIP_TRY(hipStreamSynchronize(fine->stream));
+    const double factor = r * coarse->tau / fine->tau;
+    HIP_TRY(launch_restrict(fine->storage, fine->f[fine->cur], fine->nx, fine->ny, fine->nz, coarse->storage,
+                            coarse->f[coarse->cur], coarse->nx, coarse->ny, coarse->nz, r, factor, coarse->stream));
+    HIP_TRY(hipStreamSynchronize(coarse->stream));
+    coarse->rec_steps = -1;
+    return record_mass(coarse);
+}
+
 int nco_init_populations(nco_lattice* lat, const double* f) {
     if (int rc = check_lat(lat)) return rc;
     if (!f) return fail(NCO_E_INVALID, "null populations");

@@ -74,6 +74,9 @@ __device__ __forceinline__ int group_member(const LaunchGroup& g, int b) {
 }
 
 hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs& a, hipStream_t st);
+// Fine-to-coarse restriction (coarse extent x r = fine extent on every axis).
+hipError_t launch_restrict(int fine_storage, const void* fine, int fnx, int fny, int fnz, int coarse_storage,
+                           void* coarse, int cnx, int cny, int cnz, int r, double factor, hipStream_t st);
 // BGK and fixed-rate lattices (op in a.op of every member, same storage).
 hipError_t launch_step_grouped(int storage, int op, const LaunchGroup& g, hipStream_t st);
 hipError_t launch_rates(int storage, const void* fin, double* omega, const StepArgs& a, hipStream_t st);

@@ -124,6 +124,46 @@ __global__ __launch_bounds__(256) void k_rates(const typename Codec<S>::store_t*
     for (int k = 0; k < 4; ++k) omega_out[(size_t)k * a.n + idx] = (double)omega[k];
 }
 
+// Fine-to-coarse restriction by acoustic scaling (Sec. "Learning Task"):
+// for coarse node X on fine node r X, the pre-collision populations of the
+// fine node, f_i = fine_i(r X - c_i) (pull on the periodic fine lattice),
+// give rho, u and f^eq, and f^eq_i + factor (f_i - f^eq_i) is stored
+// un-streamed on the coarse lattice, at slot (i, X - c_i), where the coarse
+// step's pull reads it back at X.  float64 arithmetic; every coarse slot is
+// written once (un-streaming is a permutation).
+template <int SF, int SC>
+__global__ __launch_bounds__(256) void k_restrict(const typename Codec<SF>::store_t* __restrict__ fine,
+                                                  typename Codec<SC>::store_t* __restrict__ coarse, int fnx,
+                                                  int fny, int fnz, int cnx, int cny, int cnz, int r, double factor) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cn = cnx * cny * cnz;
+    if (idx >= cn) return;
+    const int X = idx % cnx, Y = (idx / cnx) % cny, Z = idx / (cnx * cny);
+    const size_t fn = (size_t)fnx * fny * fnz;
+    double f[Q];
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int sx = (r * X - cx_of(i) + fnx) % fnx, sy = (r * Y - cy_of(i) + fny) % fny;
+        const int sz = (r * Z - cz_of(i) + fnz) % fnz;
+        f[i] = Codec<SF>::to_double(fine[(size_t)i * fn + ((size_t)sz * fny + sy) * fnx + sx], i);
+        rho += f[i];
+        jx += cx_of(i) * f[i];
+        jy += cy_of(i) * f[i];
+        jz += cz_of(i) * f[i];
+    }
+    const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cu = cx_of(i) * ux + cy_of(i) * uy + cz_of(i) * uz;
+        const double feq = weight_of(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const int dx = (X - cx_of(i) + cnx) % cnx, dy = (Y - cy_of(i) + cny) % cny, dz = (Z - cz_of(i) + cnz) % cnz;
+        coarse[(size_t)i * cn + ((size_t)dz * cny + dy) * cnx + dx] =
+            Codec<SC>::from_double(feq + factor * (f[i] - feq), i);
+    }
+}
+
 template <int S>
 __global__ __launch_bounds__(256) void k_init_equilibrium(typename Codec<S>::store_t* __restrict__ f,
                                                           const double* __restrict__ rho,
@@ -408,6 +448,27 @@ hipError_t launch_macroscopic(int storage, const void* f, double* rho, double* u
                            static_cast<const typename Codec<SS>::store_t*>(f), rho, u, n);
         return hipGetLastError();
     })
+}
+
+hipError_t launch_restrict(int fine_storage, const void* fine, int fnx, int fny, int fnz, int coarse_storage,
+                           void* coarse, int cnx, int cny, int cnz, int r, double factor, hipStream_t st) {
+    const int cn = cnx * cny * cnz;
+#define RESTRICT_TO(SF)                                                                                       \
+    DISPATCH_STORAGE(coarse_storage, {                                                                        \
+        hipLaunchKernelGGL((k_restrict<SF, SS>), dim3(nblocks(cn)), dim3(256), 0, st,                        \
+                           static_cast<const typename Codec<SF>::store_t*>(fine),                            \
+                           static_cast<typename Codec<SS>::store_t*>(coarse), fnx, fny, fnz, cnx, cny, cnz, r, \
+                           factor);                                                                           \
+        return hipGetLastError();                                                                             \
+    })
+    switch (fine_storage) {
+        case ST_F32: RESTRICT_TO(ST_F32)
+        case ST_F16: RESTRICT_TO(ST_F16)
+        case ST_BF16: RESTRICT_TO(ST_BF16)
+        case ST_F64: RESTRICT_TO(ST_F64)
+        default: return hipErrorInvalidValue;
+    }
+#undef RESTRICT_TO
 }
 
 int sums_partial_count(int n) { return nblocks(n); }

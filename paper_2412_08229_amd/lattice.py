@@ -91,6 +91,11 @@ class Lattice:
     def sync(self):
         L.nco_sync(self._h)
 
+    def restrict_from(self, fine):
+        """Set this (coarse) lattice's state from the finer lattice ``fine``
+        by acoustic scaling (Sec. "Learning Task"); see nco_restrict."""
+        L.nco_restrict(fine._h, self._h)
+
     def set_domain(self, domain):
         """'periodic' (default) or 'tgv_octant': the cube [0, pi/2]^3 of the
         Taylor-Green vortex standing for the symmetric 4n box (Appendix A);
