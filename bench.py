@@ -57,6 +57,11 @@ GRID = {"bgk_256": 256, "mrt_256": 256}
 VARIANTS["nco_w20_relu"] = ("nco", "f32", "f32_mfma", "relu")
 VARIANTS["nco_w20_relu_bf16net"] = ("nco", "f32", "bf16", "relu")
 NET_WIDTH = {"nco_w20_relu": 20, "nco_w20_relu_bf16net": 20}
+# The paper's network for the dissipation training, 27-20-20-20-4 ReLU (third
+# hidden layer on the vector units, zero-padded to width 32).
+VARIANTS["nco_d3_w20_relu_valu"] = ("nco", "f32", "f32", "relu")
+NET_WIDTH["nco_d3_w20_relu_valu"] = 20
+NET_DEPTH = {"nco_d3_w20_relu_valu": 3}
 # The same Taylor-Green vortex on the reduced cube of Appendix A: an n/4
 # cube standing for the n box (the node grid is offset by half a spacing).
 VARIANTS["nco_octant"] = ("nco", "f32", "f32_mfma", "tanh")
@@ -450,8 +455,9 @@ def main():
         lat = Lattice((n_op, n_op, n_op), storage, kind, tau_op, stream=stream)
         lat.set_domain(domain)
         if kind == "nco":
-            w_op = NET_WIDTH.get(op, width)
-            lat.set_net_weights(params if w_op == width else inputs.mlp_params(w_op, seed=0), w_op, act, mlp)
+            w_op, d_op = NET_WIDTH.get(op, width), NET_DEPTH.get(op, 2)
+            p_op = params if (w_op, d_op) == (width, 2) else inputs.mlp_params(w_op, seed=0, depth=d_op)
+            lat.set_net_weights(p_op, w_op, act, mlp, depth=d_op)
         if kind == "mrt":
             lat.set_rates([4.0 / 3.0] * 4)
         lat.init_equilibrium(rho_op, u_op)
@@ -472,6 +478,7 @@ def main():
                        "hbm_frac": gbs / HBM_PEAK_GBS, "steps": steps, "storage": storage,
                        "network": mlp if kind == "nco" else None,
                        "width": NET_WIDTH.get(op, width) if kind == "nco" else None,
+                       "depth": NET_DEPTH.get(op, 2) if kind == "nco" else None,
                        "activation": act if kind == "nco" else None}
         if domain == "tgv_octant":
             results[op]["domain"] = domain
