@@ -51,7 +51,7 @@ typedef enum {
     NCO_E_HIP = -3,         /* a HIP runtime call failed */
     NCO_E_UNSTABLE = -4,    /* non-finite state or failed stability check */
     NCO_E_STATE = -5,       /* call not valid in the lattice's current state */
-    NCO_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+    NCO_E_UNSUPPORTED = -6  /* valid request this library does not implement */
 } nco_status;
 
 /* Storage of the populations in HBM.  *_DEV stores the deviation from the
