@@ -246,6 +246,23 @@ int nco_device_populations(nco_lattice* lat, void** dev_ptr, size_t* bytes);
 int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
                     double amplitude, double kf, double c);
 
+/* nco_set_forcing, and with phase_rule = 1 Alvelius' velocity-dependent
+ * phase (Sec. "Training Data - Forced Isotropic Turbulence", the tangent
+ * equation) instead of the drawn theta1.  Before each step, on the device,
+ * the library computes:
+ *   - u_hat(k) = N^-1 sum_x u(x) exp(-i k.x) of the state the step starts
+ *     from (u = j / rho, float64, fixed-order sums);
+ *   - xi_i = u_hat . e_i and Z = g_A conj(xi1) + g_B exp(i psi) conj(xi2);
+ *   - theta1 = atan2(Re Z, Im Z), the solution of the printed
+ *     tan theta1 = Re Z / Im Z that keeps the force continuous in u_hat.
+ * The force then does no work on the velocity at every forced mode.  The
+ * draws' third column is not used.  Forward only: nco_forward_record
+ * returns NCO_E_UNSUPPORTED while the rule is on, because the reverse mode
+ * takes the phases as given, and nco_batch_step refuses such lattices.
+ * NCO_E_INVALID for phase_rule outside {0, 1} or more than 1024 modes. */
+int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
+                       double amplitude, double kf, double c, int phase_rule);
+
 /* Run nsteps steps (NCO operator, width 32, float storage) keeping a
  * checkpoint of the state every ckpt_every steps in device memory, for a
  * following nco_backward (the gradient of Adam in Sec. "Learning Task"). */

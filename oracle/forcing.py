@@ -15,8 +15,9 @@ Readings: the printed e1 = (k_x k_y, -k_x k_y, 0)/sqrt(k_x^2 + k_y^2) is not
 normal to k; the unit vector normal to k in the x-y plane,
 e1 = (k_y, -k_x, 0)/sqrt(k_x^2 + k_y^2), is used, with e2 as printed; for
 k_x = k_y = 0, e1 = (1, 0, 0) and e2 = (0, 1, 0).  theta1 is drawn from the
-random numbers like phi and psi instead of the velocity-dependent rule, so
-the force is a known function of time.  The amplitude A of F(kk) is given
+random numbers like phi and psi, so that the force is a known function of
+time (what the reverse mode needs); ``coefficients_state`` is the
+velocity-dependent rule itself, forward only.  The amplitude A of F(kk) is given
 directly (lattice units) instead of through the power input.  The force
 field is real: one wavevector of each +-k pair carries F_hat and
 F(x) = sum 2 Re(F_hat(k) exp(i k.x)), x in [0, 2 pi)^3.
@@ -54,6 +55,52 @@ def coefficients(ks, draws, amplitude, kf, c):
         A = mag * np.exp(1j * th1) * np.sin(2.0 * phi)
         B = mag * np.exp(1j * (th1 + psi)) * np.cos(2.0 * phi)
         out[:, mi, :] = A[:, None] * e1[None, :] + B[:, None] * e2[None, :]
+    return out
+
+
+def velocity_modes(ks, u):
+    """u_hat(k) = N^-1 sum_x u(x) exp(-i k.x) at the given integer
+    wavevectors, for a velocity field u (3, nz, ny, nx) on [0, 2 pi)^3
+    (the coefficient of exp(i k.x) in u).  Returns complex (n_modes, 3)."""
+    _, nz, ny, nx = u.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.zeros((len(ks), 3), dtype=np.complex128)
+    for mi, k in enumerate(np.asarray(ks)):
+        e = np.exp(-2j * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz))
+        for a in range(3):
+            out[mi, a] = (u[a] * e).sum() / u[a].size
+    return out
+
+
+def phase_rule(g_a, g_b, psi, xi1, xi2):
+    """theta1 of Alvelius' rule (Sec. "Training Data - Forced Isotropic
+    Turbulence", the tangent equation): the phase that makes the force of a
+    mode uncorrelated with the velocity there, Re(F_hat . conj(u_hat)) = 0.
+    With Z = g_A conj(xi1) + g_B exp(i psi) conj(xi2) that correlation is
+    |A| Re(exp(i theta1) Z), zero for tan theta1 = Re Z / Im Z, which is the
+    printed ratio (the stray factor e in front of tan is dropped).  Of the
+    two solutions theta1 and theta1 + pi, atan2(Re Z, Im Z) is taken: it
+    keeps F_hat continuous in u_hat (the other choice of branch flips the
+    force's sign where Im Z changes sign)."""
+    Z = g_a * np.conj(xi1) + g_b * np.exp(1j * psi) * np.conj(xi2)
+    return np.arctan2(Z.real, Z.imag)
+
+
+def coefficients_state(ks, draw, amplitude, kf, c, u):
+    """F_hat of one step with the velocity-dependent theta1: draw (n_modes,
+    3) as in ``coefficients`` (the theta1 column unused), u the velocity field
+    the force acts on.  Returns complex (n_modes, 3)."""
+    ks = np.asarray(ks)
+    uh = velocity_modes(ks, u)
+    out = np.zeros((len(ks), 3), dtype=np.complex128)
+    for mi, k in enumerate(ks):
+        kk = np.sqrt(float((k * k).sum()))
+        e1, e2 = basis(k)
+        mag = np.sqrt(amplitude * np.exp(-(kk - kf) ** 2 / c) / (2.0 * np.pi * kk * kk))
+        phi, psi = np.pi * draw[mi, 0], 2.0 * np.pi * draw[mi, 1]
+        ga, gb = np.sin(2.0 * phi), np.cos(2.0 * phi)
+        th1 = phase_rule(ga, gb, psi, uh[mi] @ e1, uh[mi] @ e2)
+        out[mi] = mag * (ga * np.exp(1j * th1) * e1 + gb * np.exp(1j * (th1 + psi)) * e2)
     return out
 
 

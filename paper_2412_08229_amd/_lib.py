@@ -57,6 +57,8 @@ SIGNATURES = {
     "nco_device_populations": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
     "nco_set_forcing": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), _D, _I, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double]),
+    "nco_set_forcing_ex": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), _D, _I, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, _I]),
     "nco_forward_record": (_I, [_P, _I, _I]),
     "nco_forward_record_energy": (_I, [_P, _I, _I, _I, _D]),
     "nco_backward_energy": (_I, [_P, _D, _I, _D, _I, _D, _D, _SZ, _D]),
@@ -225,7 +227,7 @@ def nco_energy_spectrum(h, nbins):
     return out
 
 
-def nco_set_forcing(h, k, draws, amplitude, kf, c):
+def nco_set_forcing(h, k, draws, amplitude, kf, c, phase_rule=False):
     if k is None or len(k) == 0:
         check(lib().nco_set_forcing(h, 0, None, None, 0, 0.0, 0.0, 1.0))
         return
@@ -234,8 +236,8 @@ def nco_set_forcing(h, k, draws, amplitude, kf, c):
     n_modes = kk.shape[0]
     if d.ndim != 3 or d.shape[1] != n_modes or d.shape[2] != 3:
         raise ValueError("draws must have shape (n_steps, n_modes, 3)")
-    check(lib().nco_set_forcing(h, n_modes, kk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dptr(d),
-                                d.shape[0], amplitude, kf, c))
+    check(lib().nco_set_forcing_ex(h, n_modes, kk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dptr(d),
+                                   d.shape[0], amplitude, kf, c, int(bool(phase_rule))))
 
 
 def nco_batch_step(handles, nsteps):

@@ -188,6 +188,14 @@ struct nco_lattice {
     long force_t = 0;             // forcing step of the next lattice step
     int* d_fk = nullptr;
     double* d_fhat = nullptr;
+    // Velocity-dependent phase (Alvelius' rule): per-mode basis and |A|
+    // [8 per mode], per-step draws phi, psi [steps][modes][2], mode-sum work
+    // space and the coefficients of the current step.
+    bool phase_rule = false;
+    double* d_fbasis = nullptr;
+    double* d_fdraw = nullptr;
+    double* d_fpart = nullptr;
+    double* d_fhat_cur = nullptr;
     // Recorded forward run (checkpoints) for the adjoint.
     int rec_steps = -1, rec_every = 0;
     long rec_force_t0 = 0;
@@ -340,7 +348,15 @@ StepArgs step_args_at(const nco_lattice* lat, long t) {
 
 // One forward step from buffer fin to fout with the given forcing step.
 int launch_one(nco_lattice* lat, const void* fin, void* fout, long t) {
-    const StepArgs a = step_args_at(lat, t);
+    StepArgs a = step_args_at(lat, t);
+    if (lat->phase_rule && lat->n_modes > 0) {
+        // This step's coefficients from the velocity of the state it starts from.
+        HIP_TRY(launch_force_phase(lat->storage, fin, lat->n, lat->nx, lat->ny, lat->nz, lat->d_fk, lat->n_modes,
+                                   lat->d_fpart, lat->d_fbasis,
+                                   lat->d_fdraw + (size_t)(t % lat->force_steps) * lat->n_modes * 2,
+                                   lat->d_fhat_cur, lat->stream));
+        a.fhat = lat->d_fhat_cur;
+    }
     if (use_mfma(lat))
         HIP_TRY(launch_nco_mfma(lat->storage, lat->mlp_prec, fin, fout, a, mfma_lane_tab(lat), mfma_group_tab(lat),
                                 nullptr, lat->stream));
@@ -434,6 +450,10 @@ int nco_lattice_destroy(nco_lattice* lat) {
     if (lat->spec_work) hipFree(lat->spec_work);
     if (lat->d_fk) hipFree(lat->d_fk);
     if (lat->d_fhat) hipFree(lat->d_fhat);
+    if (lat->d_fbasis) hipFree(lat->d_fbasis);
+    if (lat->d_fdraw) hipFree(lat->d_fdraw);
+    if (lat->d_fpart) hipFree(lat->d_fpart);
+    if (lat->d_fhat_cur) hipFree(lat->d_fhat_cur);
     for (void* p : lat->ckpt) hipFree(p);
     for (void* p : lat->seg) hipFree(p);
     if (lat->d_k) hipFree(lat->d_k);
@@ -700,6 +720,7 @@ int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
         if (lat->op == NCO_OP_NCO && !use_mfma(lat))
             return fail(NCO_E_UNSUPPORTED, "batched NCO lattices need the matrix-core network (width 32)");
         if (lat->op == NCO_OP_STREAM) return fail(NCO_E_UNSUPPORTED, "batched streaming-only lattices");
+        if (lat->phase_rule) return fail(NCO_E_UNSUPPORTED, "batched lattices with the velocity-dependent forcing phase");
         max_steps = std::max(max_steps, nsteps[i]);
     }
     if (int rc = set_device(first)) return rc;
@@ -776,9 +797,16 @@ int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
 
 int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
                     double amplitude, double kf, double c) {
+    return nco_set_forcing_ex(lat, n_modes, k, draws, n_steps, amplitude, kf, c, 0);
+}
+
+int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
+                       double amplitude, double kf, double c, int phase_rule) {
     if (int rc = check_lat(lat)) return rc;
     if (n_modes < 0 || (n_modes > 0 && (!k || !draws || n_steps < 1 || !(c > 0.0))))
         return fail(NCO_E_INVALID, "bad forcing arguments");
+    if (phase_rule != 0 && phase_rule != 1) return fail(NCO_E_INVALID, "phase_rule must be 0 or 1");
+    if (phase_rule && n_modes > 1024) return fail(NCO_E_INVALID, "at most 1024 modes with the phase rule");
     if (n_modes > 0 && lat->domain != NCO_DOMAIN_PERIODIC)
         return fail(NCO_E_UNSUPPORTED, "spectral forcing needs the periodic domain");
     if (int rc = set_device(lat)) return rc;
@@ -787,6 +815,12 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
     if (lat->d_fhat) HIP_TRY(hipFree(lat->d_fhat));
     lat->d_fk = nullptr;
     lat->d_fhat = nullptr;
+    for (double** b : {&lat->d_fbasis, &lat->d_fdraw, &lat->d_fpart, &lat->d_fhat_cur}) {
+        if (*b) HIP_TRY(hipFree(*b));
+        *b = nullptr;
+    }
+    lat->phase_rule = false;
+    lat->rec_steps = -1;
     lat->n_modes = 0;
     lat->force_t = 0;
     if (n_modes == 0) return NCO_OK;
@@ -796,6 +830,7 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
     // theta2 = theta1 + psi, F(k) = amplitude exp(-(k - kf)^2 / c); e1 the
     // unit normal of k in the x-y plane, e2 = k x e1 / |k| as printed.
     std::vector<double> fh((size_t)n_steps * n_modes * 6);
+    std::vector<double> basis((size_t)n_modes * 8, 0.0);
     for (int m = 0; m < n_modes; ++m) {
         const double kx = k[3 * m], ky = k[3 * m + 1], kz = k[3 * m + 2];
         const double kk = std::sqrt(kx * kx + ky * ky + kz * kz), kp = std::sqrt(kx * kx + ky * ky);
@@ -810,6 +845,11 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
         }
         const double Fk = amplitude * std::exp(-(kk - kf) * (kk - kf) / c);
         const double mag = std::sqrt(Fk / (2.0 * M_PI * kk * kk));
+        for (int a3 = 0; a3 < 3; ++a3) {
+            basis[8 * m + a3] = e1[a3];
+            basis[8 * m + 3 + a3] = e2[a3];
+        }
+        basis[8 * m + 6] = mag;
         for (int t = 0; t < n_steps; ++t) {
             const double* d = draws + ((size_t)t * n_modes + m) * 3;
             const double phi = M_PI * d[0], psi = 2.0 * M_PI * d[1], th1 = 2.0 * M_PI * d[2];
@@ -827,6 +867,23 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
     HIP_TRY(hipMalloc(&lat->d_fhat, sizeof(double) * fh.size()));
     HIP_TRY(hipMemcpyAsync(lat->d_fk, k, sizeof(int) * 3 * n_modes, hipMemcpyHostToDevice, lat->stream));
     HIP_TRY(hipMemcpyAsync(lat->d_fhat, fh.data(), sizeof(double) * fh.size(), hipMemcpyHostToDevice, lat->stream));
+    if (phase_rule) {
+        // phi, psi of every step and mode (the theta1 draws are not used).
+        std::vector<double> dr((size_t)n_steps * n_modes * 2);
+        for (size_t e = 0; e < (size_t)n_steps * n_modes; ++e) {
+            dr[2 * e] = M_PI * draws[3 * e];
+            dr[2 * e + 1] = 2.0 * M_PI * draws[3 * e + 1];
+        }
+        HIP_TRY(hipMalloc(&lat->d_fbasis, sizeof(double) * basis.size()));
+        HIP_TRY(hipMalloc(&lat->d_fdraw, sizeof(double) * dr.size()));
+        HIP_TRY(hipMalloc(&lat->d_fpart, sizeof(double) * 6 * (size_t)n_modes * sums_partial_count(lat->n)));
+        HIP_TRY(hipMalloc(&lat->d_fhat_cur, sizeof(double) * 6 * (size_t)n_modes));
+        HIP_TRY(hipMemcpyAsync(lat->d_fbasis, basis.data(), sizeof(double) * basis.size(), hipMemcpyHostToDevice,
+                               lat->stream));
+        HIP_TRY(hipMemcpyAsync(lat->d_fdraw, dr.data(), sizeof(double) * dr.size(), hipMemcpyHostToDevice,
+                               lat->stream));
+        lat->phase_rule = true;
+    }
     HIP_TRY(hipStreamSynchronize(lat->stream));
     lat->n_modes = n_modes;
     lat->force_steps = n_steps;
@@ -844,6 +901,8 @@ int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, doub
     if (lat->op != NCO_OP_NCO || !lat->net) return fail(NCO_E_STATE, "recording needs the NCO operator with weights");
     if (lat->width != 32 || lat->storage == NCO_F64)
         return fail(NCO_E_UNSUPPORTED, "the adjoint needs width 32 and float storage");
+    if (lat->phase_rule)
+        return fail(NCO_E_UNSUPPORTED, "the reverse mode needs the forcing phases given, not the velocity-dependent rule");
     if (int rc = set_device(lat)) return rc;
     const int ncp = (nsteps + ckpt_every - 1) / ckpt_every;
     while ((int)lat->ckpt.size() < ncp) {

@@ -74,6 +74,11 @@ __device__ __forceinline__ int group_member(const LaunchGroup& g, int b) {
 }
 
 hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs& a, hipStream_t st);
+// Velocity-dependent Alvelius phase: F_hat of this step's forced modes from
+// the state f (partial: nblocks(n) x n_modes x 6 doubles of work space).
+hipError_t launch_force_phase(int storage, const void* f, int n, int nx, int ny, int nz, const int* fk,
+                              int n_modes, double* partial, const double* basis, const double* draw, double* fhat,
+                              hipStream_t st);
 // Fine-to-coarse restriction (coarse extent x r = fine extent on every axis).
 hipError_t launch_restrict(int fine_storage, const void* fine, int fnx, int fny, int fnz, int coarse_storage,
                            void* coarse, int cnx, int cny, int cnz, int r, double factor, hipStream_t st);

@@ -283,6 +283,104 @@ __global__ __launch_bounds__(256) void k_sums_partial(const typename Codec<S>::s
     block_sum<5>(v, partial);
 }
 
+// Velocity-dependent forcing phase (Alvelius' rule, Sec. "Training Data -
+// Forced Isotropic Turbulence").  Stage 1: per block and forced mode m, the
+// partial sums of u(x) exp(-i k_m.x) over the block's nodes, six doubles
+// (Re, Im of u_x, u_y, u_z), at partial[(6 m + s) nblocks + block].
+template <int S>
+__global__ __launch_bounds__(256) void k_mode_partials(const typename Codec<S>::store_t* __restrict__ f, int n,
+                                                       int nx, int ny, int nz, const int* __restrict__ fk,
+                                                       int n_modes, double* __restrict__ partial) {
+    __shared__ double part[6][4];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    int x = 0, y = 0, z = 0;
+    if (idx < n) {
+        double r;
+        macro_double<S>(f, n, idx, r, ux, uy, uz);
+        x = idx % nx;
+        y = (idx / nx) % ny;
+        z = idx / (nx * ny);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int m = 0; m < n_modes; ++m) {
+        const int* k = fk + 3 * m;
+        // Phase as a fraction of a turn, reduced exactly in integers.
+        const long px = ((long)k[0] * x) % nx, py = ((long)k[1] * y) % ny, pz = ((long)k[2] * z) % nz;
+        double sn, cs;
+        sincospi(2.0 * ((double)px / nx + (double)py / ny + (double)pz / nz), &sn, &cs);
+        double v[6] = {ux * cs, -ux * sn, uy * cs, -uy * sn, uz * cs, -uz * sn};
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) part[q][wave] = v[q];
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            const int q = threadIdx.x;
+            partial[(size_t)(6 * m + q) * gridDim.x + blockIdx.x] = part[q][0] + part[q][1] + part[q][2] + part[q][3];
+        }
+        __syncthreads();
+    }
+}
+
+// Stage 2, one block per mode: u_hat = sum of the partials (fixed order) / N,
+// xi_i = u_hat . e_i, Z = g_A conj(xi1) + g_B exp(i psi) conj(xi2),
+// theta1 = atan2(Re Z, Im Z) (the force then does no work on the mode), and
+// F_hat = |A| (g_A exp(i theta1) e1 + g_B exp(i (theta1 + psi)) e2) into
+// fhat[6 m ..] as (Re, Im) of x, y, z.  basis[8 m ..] = e1, e2, |A|;
+// draw[2 m ..] = phi, psi of this step.
+__global__ __launch_bounds__(256) void k_force_phase(const double* __restrict__ partial, int nblocks, double inv_n,
+                                                     const double* __restrict__ basis,
+                                                     const double* __restrict__ draw, double* __restrict__ fhat) {
+    __shared__ double part[6][4];
+    const int m = blockIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] += partial[(size_t)(6 * m + q) * nblocks + b];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) part[q][wave] = v[q];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double ur[3], ui[3];
+    for (int a = 0; a < 3; ++a) {
+        ur[a] = (part[2 * a][0] + part[2 * a][1] + part[2 * a][2] + part[2 * a][3]) * inv_n;
+        ui[a] = (part[2 * a + 1][0] + part[2 * a + 1][1] + part[2 * a + 1][2] + part[2 * a + 1][3]) * inv_n;
+    }
+    const double* e1 = basis + 8 * m;
+    const double* e2 = e1 + 3;
+    const double mag = e1[6];
+    const double x1r = ur[0] * e1[0] + ur[1] * e1[1] + ur[2] * e1[2];
+    const double x1i = ui[0] * e1[0] + ui[1] * e1[1] + ui[2] * e1[2];
+    const double x2r = ur[0] * e2[0] + ur[1] * e2[1] + ur[2] * e2[2];
+    const double x2i = ui[0] * e2[0] + ui[1] * e2[1] + ui[2] * e2[2];
+    const double phi = draw[2 * m], psi = draw[2 * m + 1];
+    double sp, cp, s2, c2;
+    sincos(psi, &sp, &cp);
+    sincos(2.0 * phi, &s2, &c2);
+    const double ga = s2, gb = c2;
+    // Z = ga conj(xi1) + gb (cos psi + i sin psi)(x2r - i x2i).
+    const double zr = ga * x1r + gb * (cp * x2r + sp * x2i);
+    const double zi = -ga * x1i + gb * (sp * x2r - cp * x2i);
+    const double th1 = atan2(zr, zi);
+    double s1, c1, s12, c12;
+    sincos(th1, &s1, &c1);
+    sincos(th1 + psi, &s12, &c12);
+    for (int a = 0; a < 3; ++a) {
+        fhat[6 * m + 2 * a] = mag * (ga * c1 * e1[a] + gb * c12 * e2[a]);
+        fhat[6 * m + 2 * a + 1] = mag * (ga * s1 * e1[a] + gb * s12 * e2[a]);
+    }
+}
+
 // Stage 2: a single block adds the partials in a fixed order.
 __global__ __launch_bounds__(256) void k_sums_final(const double* __restrict__ partial, int nblocks,
                                                     double* __restrict__ out) {
@@ -480,6 +578,20 @@ hipError_t launch_global_sums(int storage, const void* f, double* partial, doubl
         hipLaunchKernelGGL(k_sums_partial<SS>, dim3(nb), dim3(256), 0, st,
                            static_cast<const typename Codec<SS>::store_t*>(f), partial, n);
         hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, st, partial, nb, out);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_force_phase(int storage, const void* f, int n, int nx, int ny, int nz, const int* fk,
+                              int n_modes, double* partial, const double* basis, const double* draw, double* fhat,
+                              hipStream_t st) {
+    const int nb = nblocks(n);
+    DISPATCH_STORAGE(storage, {
+        hipLaunchKernelGGL(k_mode_partials<SS>, dim3(nb), dim3(256), 0, st,
+                           static_cast<const typename Codec<SS>::store_t*>(f), n, nx, ny, nz, fk, n_modes, partial);
+        if (hipError_t e = hipGetLastError()) return e;
+        hipLaunchKernelGGL(k_force_phase, dim3(n_modes), dim3(256), 0, st, partial, nb, 1.0 / n, basis, draw,
+                           fhat);
         return hipGetLastError();
     })
 }

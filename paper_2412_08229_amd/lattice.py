@@ -126,9 +126,10 @@ class Lattice:
     def device_populations(self):
         return L.nco_device_populations(self._h)
 
-    def set_forcing(self, k, draws, amplitude, kf, c):
-        """Spectral forcing for the following steps; k=None switches it off."""
-        L.nco_set_forcing(self._h, k, draws, amplitude, kf, c)
+    def set_forcing(self, k, draws, amplitude, kf, c, phase_rule=False):
+        """Spectral forcing for the following steps; k=None switches it off.
+        phase_rule: Alvelius' velocity-dependent theta1 (forward only)."""
+        L.nco_set_forcing(self._h, k, draws, amplitude, kf, c, phase_rule)
 
     def forward_record(self, nsteps, ckpt_every, energy_every=0):
         """Recorded run for backward(); with energy_every > 0 it returns the

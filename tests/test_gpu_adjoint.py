@@ -181,3 +181,60 @@ def test_energy_trajectory_gradient_matches_oracle(mlp):
     relf = np.linalg.norm(df0 - gfo) / np.linalg.norm(gfo)
     print("energy trajectory %s: grad rel err %.2e, dL/df0 rel err %.2e" % (mlp, rel, relf))
     assert rel < 2e-3 and relf < 2e-3
+
+
+@pytest.mark.parametrize("storage,kind,mlp,tol", [("f64", "bgk", "f32", 1e-13), ("f64", "nco", "f32", 1e-13),
+                                                  ("f32", "nco", "f32_mfma", 2e-6)])
+def test_velocity_dependent_phase_matches_oracle(storage, kind, mlp, tol):
+    """Alvelius' velocity-dependent theta1 (nco_set_forcing_ex): each step's
+    coefficients come from the velocity of the state it starts from; the
+    GPU run equals the oracle's (coefficients_state, then the forced step)
+    on a 12^3 lattice (ragged against the 256-node blocks), and differs from
+    the run with the drawn theta1."""
+    n, T, amp = 12, 5, 1e-4
+    ks, draws = _forcing(4, seed=61)
+    _, u = inputs.turbulence(n, seed=62, k0=2.0, urms=0.05)
+    rho = np.ones((n, n, n))
+    params = inputs.mlp_params(32, 63)
+    layers = collision.unpack_params(params, 32)
+    runs = {}
+    for rule in (True, False):
+        with Lattice((n, n, n), storage, kind, 0.6) as lat:
+            if kind == "nco":
+                lat.set_net_weights(params, 32, "tanh", mlp)
+            lat.set_forcing(ks, draws, amp, KF, CW, phase_rule=rule)
+            lat.init_equilibrium(rho, u)
+            f0 = lat.populations()
+            lat.step(T)
+            runs[rule] = lat.populations()
+    op = step.Operator(kind, 0.6, layers=layers, act="tanh")
+    f = f0
+    for t in range(T):
+        _, ut = collision.macroscopic(f)
+        fh = forcing.coefficients_state(ks, draws[t % len(draws)], amp, KF, CW, ut)
+        f = step.step(f, op, force=forcing.field(ks, fh, (n, n, n)))
+    err = np.abs(runs[True] - f).max()
+    print("phase rule %s/%s/%s: max err %.3e, vs drawn phase %.3e"
+          % (storage, kind, mlp, err, np.abs(runs[True] - runs[False]).max()))
+    assert err < tol
+    assert np.abs(runs[True] - runs[False]).max() > 100 * tol
+
+
+def test_velocity_dependent_phase_is_forward_only():
+    n = 8
+    ks, draws = _forcing(2, seed=64)
+    _, u = inputs.turbulence(n, seed=65, k0=2.0, urms=0.05)
+    with Lattice((n, n, n), "f32", "nco", 0.6) as lat:
+        lat.set_net_weights(inputs.mlp_params(32, 66), 32, "tanh", "f32_mfma")
+        lat.set_forcing(ks, draws, 1e-4, KF, CW, phase_rule=True)
+        lat.init_equilibrium(None, u)
+        with pytest.raises(L.NCOError) as e:
+            lat.forward_record(4, 2)
+        assert e.value.status == L.NCO_E_UNSUPPORTED
+        from paper_2412_08229_amd.lattice import batch_step
+        with pytest.raises(L.NCOError) as e:
+            batch_step([lat], [2])
+        assert e.value.status == L.NCO_E_UNSUPPORTED
+        # Switching to the drawn phase re-enables the reverse mode.
+        lat.set_forcing(ks, draws, 1e-4, KF, CW)
+        lat.forward_record(4, 2)

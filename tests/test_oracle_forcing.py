@@ -43,3 +43,40 @@ def test_field_has_the_prescribed_fourier_coefficients():
     for k, c in zip(ks, fh):
         np.testing.assert_allclose(Fh[:, k[2] % n, k[1] % n, k[0] % n], c, rtol=1e-12, atol=1e-18)
     assert abs(F.mean()) < 1e-20
+
+
+def test_phase_rule_matches_the_printed_tangent_and_decorrelates():
+    """The velocity-dependent theta1: tan theta1 equals the printed ratio,
+    and every forced mode's force is uncorrelated with the velocity there,
+    so the force does no work on the field: sum_x F . u = 0."""
+    rng = np.random.Generator(np.random.PCG64(71))
+    n = 8
+    u = 0.05 * rng.standard_normal((3, n, n, n))
+    ks = inputs.forcing_half_modes(2.0)
+    draw = rng.random((len(ks), 3))
+    fh = forcing.coefficients_state(ks, draw, 1e-3, 1.5, 1.0, u)
+    uh = forcing.velocity_modes(ks, u)
+    for mi, k in enumerate(ks):
+        assert abs(np.real(fh[mi] @ np.conj(uh[mi]))) < 1e-17
+        e1, e2 = forcing.basis(k)
+        xi1, xi2 = uh[mi] @ e1, uh[mi] @ e2
+        phi, psi = np.pi * draw[mi, 0], 2 * np.pi * draw[mi, 1]
+        ga, gb = np.sin(2 * phi), np.cos(2 * phi)
+        num = ga * xi1.real + gb * (np.sin(psi) * xi2.imag + np.cos(psi) * xi2.real)
+        den = -ga * xi1.imag + gb * (np.sin(psi) * xi2.real - np.cos(psi) * xi2.imag)
+        assert np.isclose(np.tan(forcing.phase_rule(ga, gb, psi, xi1, xi2)), num / den, rtol=1e-10)
+    F = forcing.field(ks, fh, (n, n, n))
+    assert abs((F * u).sum()) < 1e-14 * np.abs(F).sum() * np.abs(u).max()
+    # A random theta1 (the training forcing) does work on the same field.
+    F0 = forcing.field(ks, forcing.coefficients(ks, draw[None], 1e-3, 1.5, 1.0)[0], (n, n, n))
+    assert abs((F0 * u).sum()) > 1e-6 * np.abs(F0).sum() * np.abs(u).max()
+
+
+def test_velocity_modes_match_the_fft():
+    rng = np.random.Generator(np.random.PCG64(72))
+    u = rng.standard_normal((3, 6, 5, 4))
+    ks = np.array([[1, 0, 0], [0, 2, 1], [1, -1, 2]])
+    uh = forcing.velocity_modes(ks, u)
+    U = np.fft.fftn(u, axes=(1, 2, 3)) / (6 * 5 * 4)
+    for mi, (kx, ky, kz) in enumerate(ks):
+        assert np.allclose(uh[mi], U[:, kz % 6, ky % 5, kx % 4], atol=1e-15)
