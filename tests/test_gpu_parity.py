@@ -388,3 +388,63 @@ def test_precision_forms_tgv16_100_steps(storage, mlp):
     print("storage %s, network %s: max |f - f_oracle| = %.3e, kinetic energy rel. err %.3e"
           % (storage, mlp, err, abs(ke - ke_ref) / ke_ref))
     assert err < PRECISION_BOUNDS[(storage, mlp)]
+
+
+def _pulled(state, pts, n):
+    C = np.array([(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)])
+    out = np.empty((27, len(pts)))
+    for i, (cx, cy, cz) in enumerate(C):
+        out[i] = state[i, (pts[:, 0] - cz) % n, (pts[:, 1] - cy) % n, (pts[:, 2] - cx) % n]
+    return out
+
+
+@pytest.mark.parametrize("kind", ["bgk", "mrt"])
+def test_bench_256_datapath_sampled_against_oracle(kind):
+    """The 256^3 stream-collide datapath in the benchmark's configuration
+    (float32, Taylor-Green at Re 1600, fixed rates 4/3): one step checked
+    node by node on 512 sampled nodes."""
+    n = 256
+    _, tau = inputs.viscosity(n, 0.1 / np.sqrt(3.0), 1600.0)
+    rho, u = inputs.tgv3d(n, 0.1 / np.sqrt(3.0))
+    with Lattice((n, n, n), "f32", kind, tau) as lat:
+        if kind == "mrt":
+            lat.set_rates([4.0 / 3.0] * 4)
+        lat.init_equilibrium(rho, u)
+        del rho, u
+        lat.step(2)
+        before = lat.populations()
+        lat.step(1)
+        after = lat.populations()
+    pts = np.random.Generator(np.random.PCG64(13)).integers(0, n, size=(512, 3))
+    pulled = _pulled(before, pts, n)
+    del before
+    op = step.Operator(kind, tau, omega_high=np.array([4.0 / 3.0] * 4))
+    want = op.collide(pulled)
+    got = after[:, pts[:, 0], pts[:, 1], pts[:, 2]]
+    err = np.abs(got - want).max()
+    print("256^3 %s, sampled: max err %.3e" % (kind, err))
+    # float32 arithmetic: rho is a 27-term float32 sum (~3e-7 relative) and at
+    # tau = 0.5044 the update is ~2 f^eq - f, which doubles f^eq's rounding
+    # on the 0.3 rest population; the 128^3 NCO check uses the same bound.
+    assert err < 1e-6
+
+
+def test_bench_size_bf16_network_sampled_against_oracle():
+    """128^3 NCO with the bf16 matrix-core network (the benchmark's
+    nco_bf16net variant): one step on 256 sampled nodes, within the bf16
+    network's rounding (its rates carry ~1e-3 relative error)."""
+    n = 128
+    _, tau = inputs.viscosity(n, 0.1 / np.sqrt(3.0), 1600.0)
+    rho, u = inputs.tgv3d(n, 0.1 / np.sqrt(3.0))
+    with _lattice((n, n, n), "f32", "nco", tau, mlp="bf16") as lat:
+        lat.init_equilibrium(rho, u)
+        lat.step(3)
+        before = lat.populations()
+        lat.step(1)
+        after = lat.populations()
+    pts = np.random.Generator(np.random.PCG64(14)).integers(0, n, size=(256, 3))
+    want = _oracle_op("nco", tau).collide(_pulled(before, pts, n))
+    got = after[:, pts[:, 0], pts[:, 1], pts[:, 2]]
+    err = np.abs(got - want).max()
+    print("128^3 bf16 network, sampled: max err %.3e" % err)
+    assert err < 1e-5
