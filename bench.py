@@ -58,10 +58,11 @@ VARIANTS["nco_w20_relu"] = ("nco", "f32", "f32_mfma", "relu")
 VARIANTS["nco_w20_relu_bf16net"] = ("nco", "f32", "bf16", "relu")
 NET_WIDTH = {"nco_w20_relu": 20, "nco_w20_relu_bf16net": 20}
 # The paper's network for the dissipation training, 27-20-20-20-4 ReLU (third
-# hidden layer on the vector units, zero-padded to width 32).
+# hidden layer; float32 matrix cores or vector units, zero-padded to width 32).
+VARIANTS["nco_d3_w20_relu"] = ("nco", "f32", "f32_mfma", "relu")
 VARIANTS["nco_d3_w20_relu_valu"] = ("nco", "f32", "f32", "relu")
-NET_WIDTH["nco_d3_w20_relu_valu"] = 20
-NET_DEPTH = {"nco_d3_w20_relu_valu": 3}
+NET_WIDTH["nco_d3_w20_relu"] = NET_WIDTH["nco_d3_w20_relu_valu"] = 20
+NET_DEPTH = {"nco_d3_w20_relu": 3, "nco_d3_w20_relu_valu": 3}
 # The same Taylor-Green vortex on the reduced cube of Appendix A: an n/4
 # cube standing for the n box (the node grid is offset by half a spacing).
 VARIANTS["nco_octant"] = ("nco", "f32", "f32_mfma", "tanh")
@@ -307,8 +308,13 @@ def tgv_dissipation(sizes, ref_n, t_end=20.0, dt=0.1, re=1600.0):
     print(json.dumps(out), flush=True)
 
 
+# The case table of Sec. "Training based on dissipation rates": cube sizes per
+# Mach number, at every Reynolds number.
+PAPER_TGV_GRID = {0.05: (16,), 0.1: (10, 16, 25), 0.15: (10, 16, 25, 32), 0.2: (10, 16, 25, 32)}
+
+
 def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100, width=32, act="tanh", depth=2,
-                 mlp="f32_mfma"):
+                 mlp="f32_mfma", grid=None):
     """Dissipation-rate training of Sec. "Training based on dissipation
     rates" on the reduced Taylor-Green cube of Appendix A: every (Re, Ma,
     cube) of the grid is one sample, its loss the mean squared gap of -dk/dt
@@ -337,7 +343,7 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100,
         for ma in mas:
             u0 = ma / math.sqrt(3.0)
             tr, er, _ = refs[(re, ma)]
-            for n in cubes:
+            for n in (grid[ma] if grid else cubes):
                 _, tau = inputs.viscosity(4 * n, u0, re)
                 tc = 4 * n / (2.0 * math.pi) / u0
                 every = max(1, int(round(t_end * tc / samples)))
@@ -357,7 +363,8 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100,
            "reference": {"operator": "bgk", "cube": ref_cube, "box": 4 * ref_cube,
                          "status": {"Re%g_Ma%g" % k: v[2] for k, v in refs.items()}},
            "network": {"width": width, "depth": depth, "activation": act, "arithmetic": mlp},
-           "epochs": epochs, "lr": lr, "seconds_per_epoch": t_epoch, "history": hist, "samples": {}}
+           "epochs": epochs, "lr": lr, "seconds_per_epoch": t_epoch,
+           "history": [h if np.isfinite(h) else None for h in hist], "samples": {}}
     for key, run, l0, l1 in zip(keys, runs, L0, L1):
         other = {}
         for kind in ("mrt", "bgk"):
@@ -369,7 +376,10 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100,
                 continue
             eps = -(k[run.inner + 1] - k[run.inner - 1]) / (2.0 * run.dt)
             other[kind] = float(np.mean(((eps - run.eps_ref) / run.scale) ** 2))
-        out["samples"][key] = {"untrained": l0, "trained": l1, "fixed_rate": other["mrt"], "bgk": other["bgk"]}
+        def fin(v):
+            return v if isinstance(v, str) or np.isfinite(v) else "non-finite"
+        out["samples"][key] = {"untrained": fin(l0), "trained": fin(l1), "fixed_rate": fin(other["mrt"]),
+                               "bgk": fin(other["bgk"])}
         run.close()
     print(json.dumps(out), flush=True)
 
@@ -391,6 +401,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-2)
     ap.add_argument("--net", default="32,2,tanh,f32_mfma", help="width,depth,activation,arithmetic of --tgv-training")
+    ap.add_argument("--paper-grid", action="store_true",
+                    help="--tgv-training over the paper's case table (cube sizes per Mach number, every Re)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
@@ -411,9 +423,10 @@ def main():
         return
     if args.tgv_training:
         w, d, a, m = args.net.split(",")
+        mas = sorted(PAPER_TGV_GRID) if args.paper_grid else [float(x) for x in args.ma.split(",")]
         tgv_training([int(x) for x in args.tgv_training.split(",")], [float(x) for x in args.re.split(",")],
-                     [float(x) for x in args.ma.split(",")], args.ref_cube, args.epochs, args.lr,
-                     width=int(w), depth=int(d), act=a, mlp=m)
+                     mas, args.ref_cube, args.epochs, args.lr, width=int(w), depth=int(d), act=a, mlp=m,
+                     grid=PAPER_TGV_GRID if args.paper_grid else None)
         return
     if args.precision_horizon > 0:
         precision_horizon(args.n, args.precision_horizon, 100, args.f64_steps)

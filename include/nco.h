@@ -139,10 +139,11 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec,
  * 27 -> width -> width -> width -> 4, params in the order W1[27][width],
  * b1, W2[width][width], b2, W2b[width][width], b2b, W3[width][4], b3
  * (n_params = width*(27 + 2 width + 4) + 3 width + 4).  Depth 3 runs on the
- * vector-unit network only (NCO_MLP_F32; NCO_E_UNSUPPORTED otherwise), with
- * narrower networks zero-padded to width 32, and has the reverse mode:
- * nco_backward returns the gradient in this parameter order.  Setting the
- * weights drops a recorded run. */
+ * vector units (NCO_MLP_F32) or the float32 matrix cores (NCO_MLP_F32_MFMA),
+ * not the bf16 ones (NCO_E_UNSUPPORTED), with narrower networks zero-padded
+ * to width 32, and has the reverse mode (vector-unit adjoint): nco_backward
+ * returns the gradient in this parameter order.  nco_batch_step refuses
+ * depth-3 lattices.  Setting the weights drops a recorded run. */
 int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, int mlp_prec,
                               const float* params, size_t n_params);
 

@@ -518,8 +518,8 @@ int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, i
         return fail(NCO_E_INVALID, "unknown network precision %d", mlp_prec);
     if (mlp_prec != NCO_MLP_F32 && lat->storage == NCO_F64)
         return fail(NCO_E_UNSUPPORTED, "the matrix-core network needs float32 or 16-bit storage");
-    if (depth == 3 && mlp_prec != NCO_MLP_F32)
-        return fail(NCO_E_UNSUPPORTED, "a third hidden layer runs on the vector-unit network (NCO_MLP_F32)");
+    if (depth == 3 && mlp_prec == NCO_MLP_BF16)
+        return fail(NCO_E_UNSUPPORTED, "a third hidden layer runs on the vector units or the float32 matrix cores");
     if (!params) return fail(NCO_E_INVALID, "null parameters");
     if (n_params != n_params_depth(width, depth))
         return fail(NCO_E_INVALID, "expected %zu parameters for width %d and depth %d, got %zu",
@@ -609,11 +609,11 @@ int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, i
             p32 = padded.data();
         }
         mfma_prepare_tables(p32, act, mlp_prec, G.src, reinterpret_cast<float*>(tab.data()),
-                            reinterpret_cast<int*>(tab.data() + sizeof(float) * nf));
+                            reinterpret_cast<int*>(tab.data() + sizeof(float) * nf), depth);
         if (!lat->mfma_tab) HIP_TRY(hipMalloc(&lat->mfma_tab, tab.size()));
         HIP_TRY(hipMemcpyAsync(lat->mfma_tab, tab.data(), tab.size(), hipMemcpyHostToDevice, lat->stream));
         HIP_TRY(hipStreamSynchronize(lat->stream));
-        if (W == 32) {
+        if (W == 32 && depth == 2) {
             // Reverse mode on the matrix cores: the float32 forward tables
             // (also for a bf16 network) and the adjoint's own table.
             const size_t na = mfma_adjoint_table_floats();
@@ -721,6 +721,7 @@ int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
             return fail(NCO_E_UNSUPPORTED, "batched NCO lattices need the matrix-core network (width 32)");
         if (lat->op == NCO_OP_STREAM) return fail(NCO_E_UNSUPPORTED, "batched streaming-only lattices");
         if (lat->phase_rule) return fail(NCO_E_UNSUPPORTED, "batched lattices with the velocity-dependent forcing phase");
+        if (lat->depth != 2) return fail(NCO_E_UNSUPPORTED, "batched lattices with a third hidden layer");
         max_steps = std::max(max_steps, nsteps[i]);
     }
     if (int rc = set_device(first)) return rc;
@@ -996,7 +997,8 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
         if (!lat->lam[b]) HIP_TRY(hipMalloc(&lat->lam[b], sizeof(float) * nf));
     // Matrix-core adjoint for matrix-core networks, vector-unit adjoint for
     // the vector-unit network.
-    const bool mfma = lat->mlp_prec != NCO_MLP_F32 && lat->adj_tab;
+    // (a depth-3 network takes the vector-unit adjoint)
+    const bool mfma = lat->mlp_prec != NCO_MLP_F32 && lat->adj_tab && lat->depth == 2;
     const int npar = mfma ? adjoint_param_count() : adjoint_param_count_depth(lat->depth);
     const int nblk = mfma ? adjoint_mfma_blocks(lat->n) : adjoint_blocks(lat->n);
     const int ngrp = (nblk + 63) / 64;

@@ -103,7 +103,7 @@ hipError_t launch_check_state(int storage, const void* f, double* partial, doubl
 size_t mfma_lane_table_floats();
 size_t mfma_group_table_ints();
 void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsrc)[27], float* lane_tab,
-                         int* gtab);
+                         int* gtab, int depth = 2);
 hipError_t launch_nco_mfma(int storage, int prec, const void* fin, void* fout, const StepArgs& a,
                            const float* lane_tab, const int* gtab, double* omega_out, hipStream_t st);
 hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchGroup& g, hipStream_t st);

@@ -74,6 +74,8 @@ constexpr int LT_A2 = 20;           // [u 2][t 2][r 4] W2 as A operand
 constexpr int LT_B2 = 36;           // [u 2][r 4]      b2 as accumulator init
 constexpr int LT_W3 = 44;           // [u 2][r 4][n 4] W3 / 48
 constexpr int LT_B3 = 76;           // [n 4]
+constexpr int LT_A2B = 80;          // [v 2][t 2][r 4] W2b as A operand (depth 3)
+constexpr int LT_B2B = 96;          // [v 2][r 4]      b2b as accumulator init (depth 3)
 // bf16 path (A operands as packed bf16 pairs, two per word):
 constexpr int LB_A1 = 0;            // [t 2][4 words]  W1 rows 8q..8q+7 / b1
 constexpr int LB_A2 = 8;            // [u 2][4 words]  W2
@@ -81,7 +83,7 @@ constexpr int LB_B2 = 16;           // [u 2][r 4]
 constexpr int LB_W3 = 24;           // [u 2][r 4][n 4]
 constexpr int LB_B3 = 56;           // [n 4]
 constexpr int LB_SM = 60;           // [bit 3][4 words] sign masks of classes with that bit
-constexpr int LANE_WORDS = 80;
+constexpr int LANE_WORDS = 104;
 
 // Activation as evaluated on this path.  For tanh the pre-activation arrives
 // scaled by kappa = 2 log2(e) and the function returns r = 1 / (1 + 2^(kappa z)),
@@ -142,7 +144,11 @@ __device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float*
 // s2 != nullptr (adjoint): sw receives tilde tau instead of the rates and
 // s2[node][32] the group sum of the folded second-layer activations (row
 // 16 u + 4 q + r in lane (q, c)).
-template <int ACT>
+//
+// DEPTH = 3: a third hidden layer (W2b, b2b) between the second layer and
+// the group sum, one more product per group element whose B operand is the
+// second layer's accumulator, like the second layer's is the first's.
+template <int ACT, int DEPTH = 2>
 __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const int* __restrict__ sg,
                                             float* __restrict__ sw, const float* __restrict__ lt, int wave,
                                             int q, int c, float* __restrict__ s2 = nullptr) {
@@ -198,6 +204,48 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
                             Y[ci][t] = u0 + u1;
                             Y[ci | bit][t] = u0 - u1;
                         }
+            if constexpr (DEPTH == 3) {
+                // Unrolled: Y[s] must stay in registers.
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    float h1v[2][4];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h1v[t][r] = act_scaled<ACT>(Y[s][t][r]);
+                    f32x4 c2[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int u = 0; u < 2; ++u) c2[u] = mfma4(A2[u][t][r], h1v[t][r], c2[u]);
+                    float h2v[2][4];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h2v[u][r] = act_scaled<ACT>(c2[u][r]);
+                    f32x4 c3[2];
+#pragma unroll
+                    for (int v = 0; v < 2; ++v)
+                        c3[v] = f32x4{lt[LT_B2B + v * 4], lt[LT_B2B + v * 4 + 1], lt[LT_B2B + v * 4 + 2],
+                                      lt[LT_B2B + v * 4 + 3]};
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int v = 0; v < 2; ++v)
+                                c3[v] = mfma4(lt[LT_A2B + v * 8 + t * 4 + r], h2v[t][r], c3[v]);
+#pragma unroll
+                    for (int v = 0; v < 2; ++v)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[v][r] += act_scaled<ACT>(c3[v][r]);
+                }
+                continue;
+            }
             // Layer 2 and the two activations, software-pipelined over the
             // reflections: while the 16 products of reflection s run on the
             // matrix cores, the vector units activate layer 1 of reflection
@@ -325,7 +373,7 @@ struct BlockLds {
     float* sw;      // [NODES][4] rates
 };
 
-template <int S, int ACT, bool RATES, int PREC, int NODES>
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH = 2>
 __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t* __restrict__ fin,
                                                typename Codec<S>::store_t* __restrict__ fout, const StepArgs& a,
                                                const float* __restrict__ lane_tab, const int* __restrict__ gtab,
@@ -337,13 +385,13 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
     __shared__ float lds_sw[(NODES) * 4];            \
     const BlockLds lds{lds_sm, lds_sg, lds_sw};
 
-template <int S, int ACT, bool RATES, int PREC, int NODES>
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH>
 __global__ __launch_bounds__(NODES) void k_nco_mfma(const typename Codec<S>::store_t* __restrict__ fin,
                                                     typename Codec<S>::store_t* __restrict__ fout, StepArgs a,
                                                     const float* __restrict__ lane_tab,
                                                     const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
-    nco_mfma_block<S, ACT, RATES, PREC, NODES>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x, lds);
+    nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x, lds);
 }
 
 template <int S, int ACT, int PREC>
@@ -362,7 +410,7 @@ __global__ __launch_bounds__(256) void k_nco_mfma_grouped(LaunchGroup g) {
     grouped_block<S, ACT, PREC>(g.d[i], blockIdx.x - g.prefix[i], lds);
 }
 
-template <int S, int ACT, bool RATES, int PREC, int NODES>
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH>
 __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t* __restrict__ fin,
                                                typename Codec<S>::store_t* __restrict__ fout, const StepArgs& a,
                                                const float* __restrict__ lane_tab, const int* __restrict__ gtab,
@@ -405,7 +453,7 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
         if constexpr (PREC == MLP_PREC_BF16)
             network_bf16<ACT>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
         else
-            network_f32<ACT>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
+            network_f32<ACT, DEPTH>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
     }
     __syncthreads();
 
@@ -917,13 +965,15 @@ size_t mfma_group_table_ints() { return GT_ENTRIES; }
 // that m^(g) places at k.  gsrc is indexed by group element g = 8 p +
 // reflection mask; the reflection-free elements g = 8 p give Q_p.
 void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsrc)[27], float* lane_tab,
-                         int* gtab) {
+                         int* gtab, int depth) {
     const int W = MW;
     const float* W1 = params;
     const float* b1 = W1 + 27 * W;
     const float* W2 = b1 + W;
     const float* b2 = W2 + W * W;
-    const float* W3 = b2 + W;
+    const float* W2b = b2 + W;                      // depth 3 only
+    const float* b2b = W2b + W * W;
+    const float* W3 = depth == 3 ? b2b + W : b2 + W;
     const float* b3 = W3 + 4 * W;
     const bool th = act == ACT_TANH;
     const float kappa = th ? (float)(2.0 / 0.69314718055994530942) : 1.0f;
@@ -969,6 +1019,21 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
                     for (int n = 0; n < 4; ++n)
                         lt[LT_W3 + (u * 4 + r) * 4 + n] = fold * W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
             for (int n = 0; n < 4; ++n) lt[LT_B3 + n] = b3f[n];
+            if (depth == 3) {
+                // Third layer: tanh of the second folded in as for W2 above.
+                for (int v = 0; v < 2; ++v)
+                    for (int t = 0; t < 2; ++t)
+                        for (int r = 0; r < 4; ++r)
+                            lt[LT_A2B + v * 8 + t * 4 + r] = kappa * fold * W2b[(16 * t + 4 * q + r) * W + 16 * v + c];
+                for (int v = 0; v < 2; ++v)
+                    for (int r = 0; r < 4; ++r) {
+                        const int o = 16 * v + 4 * q + r;
+                        double sb = b2b[o];
+                        if (th)
+                            for (int h = 0; h < W; ++h) sb += W2b[h * W + o];
+                        lt[LT_B2B + v * 4 + r] = kappa * (float)sb;
+                    }
+            }
         } else {
             // K slot j of lane group q is row k = 8 q + j (layer 1) and hidden
             // unit 16 (j / 4) + 4 q + j % 4 (layer 2).
@@ -1105,45 +1170,49 @@ hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchG
 // for a 32^3 lattice, equal from 64^3 up; the results are bit-identical).
 int mfma_block_nodes(int n) { return n < 2 * 256 * 256 ? 64 : 256; }
 
+template <int S, int ACT, bool RR, int PP, int DD>
+hipError_t launch_mfma_kind(int nodes, const void* fin, void* fout, const StepArgs& a, const float* lane_tab,
+                            const int* gtab, double* omega_out, hipStream_t st) {
+    using T = typename Codec<S>::store_t;
+    const dim3 grid((a.n + nodes - 1) / nodes), block(nodes);
+    if (nodes == 64)
+        hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD>), grid, block, 0, st, static_cast<const T*>(fin),
+                           static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+    else
+        hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 256, DD>), grid, block, 0, st, static_cast<const T*>(fin),
+                           static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+    return hipGetLastError();
+}
+
+template <int S, int ACT, bool RR>
+hipError_t launch_mfma_prec(int prec, const void* fin, void* fout, const StepArgs& a, const float* lane_tab,
+                            const int* gtab, double* omega_out, hipStream_t st) {
+    const int nodes = mfma_block_nodes(a.n);
+    if (prec == MLP_PREC_BF16)
+        return launch_mfma_kind<S, ACT, RR, MLP_PREC_BF16, 2>(nodes, fin, fout, a, lane_tab, gtab, omega_out, st);
+    if (a.depth == 3)
+        return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 3>(nodes, fin, fout, a, lane_tab, gtab, omega_out, st);
+    return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 2>(nodes, fin, fout, a, lane_tab, gtab, omega_out, st);
+}
+
+template <int S>
+hipError_t launch_mfma_storage(int prec, const void* fin, void* fout, const StepArgs& a, const float* lane_tab,
+                               const int* gtab, double* omega_out, hipStream_t st) {
+    if (omega_out)
+        return a.act == ACT_TANH ? launch_mfma_prec<S, ACT_TANH, true>(prec, fin, fout, a, lane_tab, gtab, omega_out, st)
+                                 : launch_mfma_prec<S, ACT_RELU, true>(prec, fin, fout, a, lane_tab, gtab, omega_out, st);
+    return a.act == ACT_TANH ? launch_mfma_prec<S, ACT_TANH, false>(prec, fin, fout, a, lane_tab, gtab, omega_out, st)
+                             : launch_mfma_prec<S, ACT_RELU, false>(prec, fin, fout, a, lane_tab, gtab, omega_out, st);
+}
+
 hipError_t launch_nco_mfma(int storage, int prec, const void* fin, void* fout, const StepArgs& a,
                            const float* lane_tab, const int* gtab, double* omega_out, hipStream_t st) {
-    const int nodes = mfma_block_nodes(a.n);
-    const dim3 grid((a.n + nodes - 1) / nodes), block(nodes);
-#define MFMA_LAUNCH(SS, AA, RR, PP)                                                                      \
-    do {                                                                                                 \
-        if (nodes == 64)                                                                                 \
-            hipLaunchKernelGGL((k_nco_mfma<SS, AA, RR, PP, 64>), grid, block, 0, st,                     \
-                               static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab,     \
-                               omega_out);                                                               \
-        else                                                                                             \
-            hipLaunchKernelGGL((k_nco_mfma<SS, AA, RR, PP, 256>), grid, block, 0, st,                    \
-                               static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab,     \
-                               omega_out);                                                               \
-    } while (0)
-#define MFMA_PREC(SS, AA, RR)                                             \
-    if (prec == MLP_PREC_BF16) MFMA_LAUNCH(SS, AA, RR, MLP_PREC_BF16);    \
-    else MFMA_LAUNCH(SS, AA, RR, MLP_PREC_F32);
-#define MFMA_CASE(SS)                                                    \
-    case SS: {                                                           \
-        using T = typename Codec<SS>::store_t;                           \
-        if (omega_out) {                                                 \
-            if (a.act == ACT_TANH) { MFMA_PREC(SS, ACT_TANH, true) }     \
-            else { MFMA_PREC(SS, ACT_RELU, true) }                       \
-        } else {                                                         \
-            if (a.act == ACT_TANH) { MFMA_PREC(SS, ACT_TANH, false) }    \
-            else { MFMA_PREC(SS, ACT_RELU, false) }                      \
-        }                                                                \
-        return hipGetLastError();                                        \
-    }
     switch (storage) {
-        MFMA_CASE(ST_F32)
-        MFMA_CASE(ST_F16)
-        MFMA_CASE(ST_BF16)
+        case ST_F32: return launch_mfma_storage<ST_F32>(prec, fin, fout, a, lane_tab, gtab, omega_out, st);
+        case ST_F16: return launch_mfma_storage<ST_F16>(prec, fin, fout, a, lane_tab, gtab, omega_out, st);
+        case ST_BF16: return launch_mfma_storage<ST_BF16>(prec, fin, fout, a, lane_tab, gtab, omega_out, st);
         default: return hipErrorInvalidValue;
     }
-#undef MFMA_CASE
-#undef MFMA_PREC
-#undef MFMA_LAUNCH
 }
 
 }  // namespace nco

@@ -270,16 +270,32 @@ def train_batched(unrolls, params0, epochs, lr=1e-3, log=None):
     with ThreadPoolExecutor(max_workers=len(unrolls)) as pool:
         for ep in range(epochs):
             x = p.detach().numpy().copy()
-            res = list(pool.map(lambda u: u.loss_and_grad(x), unrolls))
+            res = list(pool.map(lambda u: _loss_and_grad_or_none(u, x), unrolls))
+            # A sample whose run has blown up (non-finite loss or gradient)
+            # sits this epoch out instead of poisoning the step.
+            ok = [r for r in res if r is not None]
+            history.append(float(np.mean([r[0] for r in ok])) if ok else float("nan"))
+            if log:
+                log("epoch %d: loss %.6f (%d of %d samples finite)" % (ep, history[-1], len(ok), len(res)))
+            if not ok:
+                break
             opt.zero_grad()
-            p.grad = torch.from_numpy(np.mean([r[1] for r in res], axis=0))
+            p.grad = torch.from_numpy(np.mean([r[1] for r in ok], axis=0))
             opt.step()
             with torch.no_grad():
                 p.copy_(p.float().double())          # parameters live as float32 values
-            history.append(float(np.mean([r[0] for r in res])))
-            if log:
-                log("epoch %d: loss %.6f" % (ep, history[-1]))
     return p.detach().numpy().copy(), history
+
+
+def _loss_and_grad_or_none(unroll, params):
+    from ._lib import NCOError
+    try:
+        L, g, _ = unroll.loss_and_grad(params)
+    except NCOError:
+        return None
+    if not (np.isfinite(L) and np.all(np.isfinite(g))):
+        return None
+    return L, g
 
 
 __all__ = ["log_spectrum_loss", "paper_spectrum_loss", "curriculum_steps", "Unroll", "DissipationUnroll", "tgv_cube_energy", "make_autograd", "train",

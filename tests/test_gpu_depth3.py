@@ -1,7 +1,8 @@
 """Networks with a third hidden layer (the network of Sec. "Training based
-on dissipation rates") on the vector-unit path, through the C ABI, against
-the oracle.  Depth 3 runs at width 32; narrower networks are zero-padded, so
-float64 storage must match the oracle to rounding at every width."""
+on dissipation rates") on the vector units and the float32 matrix cores,
+through the C ABI, against the oracle.  Depth 3 runs at width 32; narrower
+networks are zero-padded, so float64 storage must match the oracle to
+rounding at every width."""
 import numpy as np
 import pytest
 
@@ -36,6 +37,28 @@ def test_depth3_steps_match_oracle(storage, tol, width, act):
     assert err < tol
 
 
+@pytest.mark.parametrize("width,act", [(20, "relu"), (32, "tanh")])
+def test_depth3_matrix_cores_match_oracle(width, act):
+    """The third layer on the float32 matrix cores (one more product per
+    group element, chained on the second layer's accumulator): 10 steps and
+    the rates readout against the oracle, in float32 storage; on a 9^3
+    lattice (ragged against the 64-node blocks)."""
+    params, layers, rho, u = _setup(width, act, 48, n=9)
+    tau, n = 0.56, 9
+    with Lattice((n, n, n), "f32", "nco", tau) as lat:
+        lat.set_net_weights(params, width, act, "f32_mfma", depth=3)
+        lat.init_equilibrium(rho, u)
+        f0 = lat.populations()
+        om = lat.rates()
+        lat.step(10)
+        got = lat.populations()
+    want = step.run(f0, step.Operator("nco", tau, layers=layers, act=act), 10)
+    err = np.abs(got - want).max()
+    rerr = np.abs(om - collision.nco_rates(f0, layers, act)).max()
+    print("depth 3 on matrix cores, width %d %s: max err %.3e, rates %.3e" % (width, act, err, rerr))
+    assert err < 1e-5 and rerr < 1e-5
+
+
 def test_depth3_rates_match_oracle():
     params, layers, _, _ = _setup(20, "relu", 41)
     f = inputs.random_populations((6, 5, 7), seed=42, lo=0.8, hi=1.2)
@@ -47,8 +70,8 @@ def test_depth3_rates_match_oracle():
     assert np.abs(got - want).max() < 1e-13
 
 
-@pytest.mark.parametrize("width,act", [(20, "relu"), (32, "tanh")])
-def test_depth3_energy_gradient_matches_oracle(width, act):
+@pytest.mark.parametrize("width,act,mlp", [(20, "relu", "f32"), (32, "tanh", "f32"), (20, "relu", "f32_mfma")])
+def test_depth3_energy_gradient_matches_oracle(width, act, mlp):
     """Gradient of sum_m a_m k(t_m) over a 6-step run (checkpoints every 4)
     against the oracle's reverse mode, in the caller's parameter order
     (the padded units dropped)."""
@@ -56,7 +79,7 @@ def test_depth3_energy_gradient_matches_oracle(width, act):
     params, layers, rho, u = _setup(width, act, 43, n=n, amp=0.08)
     a = np.random.Generator(np.random.PCG64(44)).standard_normal(T // every + 1)
     with Lattice((n, n, n), "f32", "nco", tau) as lat:
-        lat.set_net_weights(params, width, act, "f32", depth=3)
+        lat.set_net_weights(params, width, act, mlp, depth=3)
         lat.init_equilibrium(rho, u)
         fs = lat.populations()
         k = lat.forward_record(T, K, energy_every=every)
@@ -77,7 +100,7 @@ def test_depth3_energy_gradient_matches_oracle(width, act):
     go = adjoint.flatten(go)
     rel = np.linalg.norm(g - go) / np.linalg.norm(go)
     relf = np.linalg.norm(df0 - gfo) / np.linalg.norm(gfo)
-    print("depth 3 width %d %s energy gradient: rel err %.2e, dL/df0 rel err %.2e" % (width, act, rel, relf))
+    print("depth 3 width %d %s %s energy gradient: rel err %.2e, dL/df0 rel err %.2e" % (width, act, mlp, rel, relf))
     assert rel < 2e-3 and relf < 2e-3
 
 
@@ -86,10 +109,15 @@ def test_depth3_arguments_and_switching_back():
     params2 = inputs.mlp_params(32, 46)
     rho, u = inputs.random_velocity((4, 4, 4), seed=47, amp=0.05)
     with Lattice((4, 4, 4), "f32", "nco", 0.6) as lat:
-        for mlp in ("f32_mfma", "bf16"):
-            with pytest.raises(L.NCOError) as e:
-                lat.set_net_weights(params3, 20, "relu", mlp, depth=3)
-            assert e.value.status == L.NCO_E_UNSUPPORTED
+        with pytest.raises(L.NCOError) as e:
+            lat.set_net_weights(params3, 20, "relu", "bf16", depth=3)
+        assert e.value.status == L.NCO_E_UNSUPPORTED
+        # Batched stepping takes depth-2 networks only.
+        lat.set_net_weights(params3, 20, "relu", "f32_mfma", depth=3)
+        from paper_2412_08229_amd.lattice import batch_step
+        with pytest.raises(L.NCOError) as e:
+            batch_step([lat], [1])
+        assert e.value.status == L.NCO_E_UNSUPPORTED
         with pytest.raises(L.NCOError) as e:
             lat.set_net_weights(params3[:-1], 20, "relu", "f32", depth=3)
         assert e.value.status == L.NCO_E_INVALID
