@@ -257,10 +257,13 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
  *   - theta1 = atan2(Re Z, Im Z), the solution of the printed
  *     tan theta1 = Re Z / Im Z that keeps the force continuous in u_hat.
  * The force then does no work on the velocity at every forced mode.  The
- * draws' third column is not used.  Forward only: nco_forward_record
- * returns NCO_E_UNSUPPORTED while the rule is on, because the reverse mode
- * takes the phases as given, and nco_batch_step refuses such lattices.
- * NCO_E_INVALID for phase_rule outside {0, 1} or more than 1024 modes. */
+ * draws' third column is not used.  nco_forward_record keeps F_hat and
+ * u_hat of every recorded step (12 doubles per mode and step of device
+ * memory), and nco_backward follows the force back to the state through
+ * them: dL/dF per node, dL/dF_hat per mode, then theta1 -> Z -> u_hat -> u
+ * (zero where Z = 0, where theta1 has no derivative).  nco_batch_step
+ * refuses such lattices (NCO_E_UNSUPPORTED).  NCO_E_INVALID for phase_rule
+ * outside {0, 1} or more than 1024 modes. */
 int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
                        double amplitude, double kf, double c, int phase_rule);
 

@@ -20,7 +20,7 @@ can be flattened with ``flatten``.
 """
 import numpy as np
 
-from . import collision, lattice, observables, step
+from . import collision, forcing, lattice, observables, step
 
 _C = lattice.velocities().astype(np.float64)
 _W = lattice.weights()
@@ -129,6 +129,17 @@ def nco_collide_vjp(f, lam, tau, layers, act, force=None):
     return g, pgrads
 
 
+def force_vjp(rho, j, force, lam):
+    """(d S / d F)^T lam for the exact-difference source S = f^eq(rho, j + F)
+    - f^eq(rho, j) of one collision: dS_i/dF_a is d f^eq_i / d j_a taken at
+    j + F, w_i (3 c_ia + 9 (c_i . (j + F)) c_ia / rho - 3 (j + F)_a / rho).
+    rho (N,), j and force (3, N), lam (27, N); returns dL/dF (3, N)."""
+    jf = j + force
+    w = _W[:, None]
+    cj = _C @ jf
+    return _C.T @ (lam * w * (3.0 + 9.0 * cj / rho)) - 3.0 * jf / rho * (lam * w).sum(axis=0)
+
+
 def spectrum_vjp(f, dL_dE):
     """(dE / d f)^T dL_dE for the shell spectrum of ``observables``."""
     n = f.shape[1]
@@ -166,7 +177,7 @@ def kinetic_energy_vjp(f):
     return (uc - uu) / rho / rho.size
 
 
-def run_and_grad(f0, tau, layers, act, nsteps, loss_grad, forces=None, traj_grad=None):
+def run_and_grad(f0, tau, layers, act, nsteps, loss_grad, forces=None, traj_grad=None, state_forcing=None):
     """Forward nsteps NCO steps from f0, then the exact gradient of
     L = loss(x_T) (+ terms on the intermediate states) with respect to the
     network parameters and to f0.
@@ -174,11 +185,26 @@ def run_and_grad(f0, tau, layers, act, nsteps, loss_grad, forces=None, traj_grad
     loss_grad(x_T) -> (L, dL/dx_T).  forces: None or callable t -> (3, ...).
     traj_grad: None or callable (t, x_t) -> dL/dx_t (or None) for the loss
     terms on the state after t steps, t = 0 .. nsteps, whose values the
-    caller adds to L.  Returns (L, parameter gradients, dL/df0)."""
+    caller adds to L.  state_forcing: None or (ks, draws, amplitude, kf, c),
+    the spectral forcing with Alvelius' velocity-dependent theta1: step t
+    takes the coefficients ``forcing.coefficients_state`` of draws[t mod
+    len(draws)] and of the velocity of x_t, and the reverse mode follows the
+    force back to x_t through them.  Returns (L, parameter gradients,
+    dL/df0)."""
+    if forces is not None and state_forcing is not None:
+        raise ValueError("give forces or state_forcing, not both")
     op = step.Operator("nco", tau, layers=layers, act=act)
-    xs = [f0]
+    shape = f0.shape
+    xs, us, Fs = [f0], [], []
     for t in range(nsteps):
-        xs.append(step.step(xs[-1], op, None if forces is None else forces(t)))
+        F = None if forces is None else forces(t)
+        if state_forcing is not None:
+            ks, draws, amp, kf, c = state_forcing
+            _, u = collision.macroscopic(xs[-1])
+            F = forcing.field(ks, forcing.coefficients_state(ks, draws[t % len(draws)], amp, kf, c, u), shape[1:])
+            us.append(u)
+        Fs.append(F)
+        xs.append(step.step(xs[-1], op, F))
     L, lam = loss_grad(xs[-1])
 
     def add_traj(t, lam):
@@ -186,12 +212,21 @@ def run_and_grad(f0, tau, layers, act, nsteps, loss_grad, forces=None, traj_grad
         return lam if extra is None else lam + extra
 
     lam = add_traj(nsteps, lam)
-    shape = f0.shape
     total = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
     for t in range(nsteps - 1, -1, -1):
         y = step.stream(xs[t]).reshape(27, -1)
-        F = None if forces is None else forces(t).reshape(3, -1)
-        g, pg = nco_collide_vjp(y, lam.reshape(27, -1), tau, layers, act, F)
+        F = None if Fs[t] is None else Fs[t].reshape(3, -1)
+        lam_next = lam.reshape(27, -1)
+        g, pg = nco_collide_vjp(y, lam_next, tau, layers, act, F)
         total = [(a + c, b + d) for (a, b), (c, d) in zip(total, pg)]
-        lam = add_traj(t, step.unstream(g.reshape(shape)))
+        lam = step.unstream(g.reshape(shape))
+        if state_forcing is not None:
+            # The force of step t depends on x_t through u = j / rho.
+            ks, draws, amp, kf, c = state_forcing
+            gF = force_vjp(y.sum(axis=0), _C.T @ y, F, lam_next).reshape((3,) + shape[1:])
+            du = forcing.coefficients_state_vjp(ks, draws[t % len(draws)], amp, kf, c, us[t],
+                                                forcing.field_vjp(ks, gF))
+            rho, u = collision.macroscopic(xs[t])
+            lam = lam + (np.einsum("ia,a...->i...", _C, du) - (u * du).sum(axis=0)) / rho
+        lam = add_traj(t, lam)
     return L, total, lam

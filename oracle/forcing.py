@@ -16,8 +16,8 @@ normal to k; the unit vector normal to k in the x-y plane,
 e1 = (k_y, -k_x, 0)/sqrt(k_x^2 + k_y^2), is used, with e2 as printed; for
 k_x = k_y = 0, e1 = (1, 0, 0) and e2 = (0, 1, 0).  theta1 is drawn from the
 random numbers like phi and psi, so that the force is a known function of
-time (what the reverse mode needs); ``coefficients_state`` is the
-velocity-dependent rule itself, forward only.  The amplitude A of F(kk) is given
+time; ``coefficients_state`` is the velocity-dependent rule itself, and
+``coefficients_state_vjp`` its reverse mode.  The amplitude A of F(kk) is given
 directly (lattice units) instead of through the power input.  The force
 field is real: one wavevector of each +-k pair carries F_hat and
 F(x) = sum 2 Re(F_hat(k) exp(i k.x)), x in [0, 2 pi)^3.
@@ -101,6 +101,66 @@ def coefficients_state(ks, draw, amplitude, kf, c, u):
         ga, gb = np.sin(2.0 * phi), np.cos(2.0 * phi)
         th1 = phase_rule(ga, gb, psi, uh[mi] @ e1, uh[mi] @ e2)
         out[mi] = mag * (ga * np.exp(1j * th1) * e1 + gb * np.exp(1j * (th1 + psi)) * e2)
+    return out
+
+
+def coefficients_state_vjp(ks, draw, amplitude, kf, c, u, dfhat):
+    """Reverse mode of ``coefficients_state``: dL/du (3, nz, ny, nx) for
+    dfhat = dL/d Re F_hat + i dL/d Im F_hat (complex (n_modes, 3)).
+
+    Per mode, backwards through the definitions above: F_hat is |A| e^{i
+    theta1} (g_A e1 + g_B e^{i psi} e2), so dF_hat/d theta1 = i F_hat;
+    theta1 = atan2(Re Z, Im Z) has gradient (Im Z, -Re Z) / |Z|^2 in (Re Z,
+    Im Z) (taken as zero where Z = 0, where theta1 is not differentiable);
+    Z = g_A conj(xi1) + g_B e^{i psi} conj(xi2) and xi_i = u_hat . e_i are
+    real-linear, and u_hat = N^-1 sum_x u(x) e^{-i k.x}."""
+    ks = np.asarray(ks)
+    _, nz, ny, nx = u.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    uh = velocity_modes(ks, u)
+    du = np.zeros(u.shape)
+    for mi, k in enumerate(ks):
+        kk = np.sqrt(float((k * k).sum()))
+        e1, e2 = basis(k)
+        mag = np.sqrt(amplitude * np.exp(-(kk - kf) ** 2 / c) / (2.0 * np.pi * kk * kk))
+        phi, psi = np.pi * draw[mi, 0], 2.0 * np.pi * draw[mi, 1]
+        ga, gb = np.sin(2.0 * phi), np.cos(2.0 * phi)
+        xi1, xi2 = uh[mi] @ e1, uh[mi] @ e2
+        Z = ga * np.conj(xi1) + gb * np.exp(1j * psi) * np.conj(xi2)
+        th1 = np.arctan2(Z.real, Z.imag)
+        fh = mag * (ga * np.exp(1j * th1) * e1 + gb * np.exp(1j * (th1 + psi)) * e2)
+        d_th1 = float(np.sum(dfhat[mi].real * (1j * fh).real + dfhat[mi].imag * (1j * fh).imag))
+        z2 = Z.real ** 2 + Z.imag ** 2
+        if z2 == 0.0:
+            continue
+        dzr, dzi = d_th1 * Z.imag / z2, -d_th1 * Z.real / z2
+        # Z.real = ga xi1.re + gb (cos psi xi2.re + sin psi xi2.im)
+        # Z.imag = -ga xi1.im + gb (sin psi xi2.re - cos psi xi2.im)
+        cp, sp = np.cos(psi), np.sin(psi)
+        d1r, d1i = ga * dzr, -ga * dzi
+        d2r, d2i = gb * (cp * dzr + sp * dzi), gb * (sp * dzr - cp * dzi)
+        dur, dui = d1r * e1 + d2r * e2, d1i * e1 + d2i * e2
+        # u_hat.re = N^-1 sum u cos(k.x), u_hat.im = -N^-1 sum u sin(k.x)
+        th = 2.0 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz)
+        cs, sn = np.cos(th), np.sin(th)
+        for a in range(3):
+            du[a] += (dur[a] * cs - dui[a] * sn) / cs.size
+    return du
+
+
+def field_vjp(ks, gF):
+    """Transpose of ``field``: for gF = dL/dF (3, nz, ny, nx), the complex
+    (n_modes, 3) array dL/d Re F_hat + i dL/d Im F_hat.  With F_a(x) =
+    2 (Re F_hat_a cos(k.x) - Im F_hat_a sin(k.x)) that is
+    2 sum_x gF_a(x) (cos(k.x) - i sin(k.x))."""
+    _, nz, ny, nx = gF.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.zeros((len(ks), 3), dtype=np.complex128)
+    for mi, k in enumerate(np.asarray(ks)):
+        th = 2.0 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz)
+        cs, sn = np.cos(th), np.sin(th)
+        for a in range(3):
+            out[mi, a] = 2.0 * (gF[a] * cs).sum() - 2.0j * (gF[a] * sn).sum()
     return out
 
 

@@ -423,6 +423,184 @@ __global__ __launch_bounds__(256) void k_add_energy_grad(const typename Codec<S>
     }
 }
 
+// Reverse mode of the velocity-dependent forcing phase (Alvelius' rule,
+// Sec. "Training Data - Forced Isotropic Turbulence").  The force of a step is
+// F(x) = sum_m 2 Re(F_hat_m e^{i k_m.x}) with F_hat_m a function of the
+// velocity modes u_hat_m of the state x_t the step starts from.  Given
+// lambda = dL/dx_t+1, the extra term of dL/dx_t runs in three kernels.
+//
+// Stage 1, per collision node: g = dL/dF = (dS/dF)^T lambda for the exact-
+// difference source S = f^eq(rho, j + F) - f^eq(rho, j) of the pulled
+// populations (the forward adds the same source in moment form):
+//     g_a = sum_i lambda_i w_i (3 c_ia + 9 (c_i . v) c_ia / rho) - 3 v_a / rho sum_i lambda_i w_i,
+// v = j + F; then per block and forced mode the partial sums of
+// (g cos(k.x), -g sin(k.x)), six doubles at partial[(6 m + q) nblocks + block].
+template <int S>
+__global__ __launch_bounds__(256) void k_force_adj_partials(const typename Codec<S>::store_t* __restrict__ xin,
+                                                            const float* __restrict__ lam, StepArgs a,
+                                                            double* __restrict__ partial) {
+    __shared__ double part[6][4];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    double g[3] = {0.0, 0.0, 0.0};
+    NodeIdx p = {0, 0, 0};
+    if (idx < a.n) {
+        p = node_of(idx, a.nx, a.ny);
+        typename Codec<S>::real f[Q];
+        pull<S>(xin, a, p, f);
+        double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double v = (double)f[i];
+            rho += v;
+            j[0] += cx_of(i) * v;
+            j[1] += cy_of(i) * v;
+            j[2] += cz_of(i) * v;
+        }
+        double F[3];
+        force_at(a, p.x, p.y, p.z, F[0], F[1], F[2]);
+        const double v[3] = {j[0] + F[0], j[1] + F[1], j[2] + F[2]};
+        const double inv_rho = 1.0 / rho;
+        double s0 = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double lw = (double)lam[(size_t)i * a.n + idx] * weight_of(i);
+            const double cv = cx_of(i) * v[0] + cy_of(i) * v[1] + cz_of(i) * v[2];
+            const double t = lw * (3.0 + 9.0 * cv * inv_rho);
+            g[0] += cx_of(i) * t;
+            g[1] += cy_of(i) * t;
+            g[2] += cz_of(i) * t;
+            s0 += lw;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[c] -= 3.0 * v[c] * inv_rho * s0;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int m = 0; m < a.n_modes; ++m) {
+        const int* k = a.fk + 3 * m;
+        // Phase as a fraction of a turn, reduced exactly in integers.
+        const long px = ((long)k[0] * p.x) % a.nx, py = ((long)k[1] * p.y) % a.ny, pz = ((long)k[2] * p.z) % a.nz;
+        double sn, cs;
+        sincospi(2.0 * ((double)px / a.nx + (double)py / a.ny + (double)pz / a.nz), &sn, &cs);
+        double q6[6] = {g[0] * cs, -g[0] * sn, g[1] * cs, -g[1] * sn, g[2] * cs, -g[2] * sn};
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) q6[q] += __shfl_down(q6[q], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) part[q][wave] = q6[q];
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            const int q = threadIdx.x;
+            partial[(size_t)(6 * m + q) * gridDim.x + blockIdx.x] = part[q][0] + part[q][1] + part[q][2] + part[q][3];
+        }
+        __syncthreads();
+    }
+}
+
+// Stage 2, one block per mode: dL/dF_hat = 2 x (sum of the partials, fixed
+// order), then backwards through the phase rule with this step's F_hat and
+// u_hat: dF_hat/d theta1 = i F_hat; theta1 = atan2(Re Z, Im Z) has gradient
+// (Im Z, -Re Z) / |Z|^2 (zero where Z = 0); Z = g_A conj(xi1) + g_B e^{i psi}
+// conj(xi2) and xi_i = u_hat . e_i are real-linear in u_hat.  Writes
+// dL/du_hat / N as (Re, Im) of x, y, z to duhat[6 m ..].
+__global__ __launch_bounds__(256) void k_force_phase_adj(const double* __restrict__ partial, int nblocks, double inv_n,
+                                                         const double* __restrict__ basis,
+                                                         const double* __restrict__ draw,
+                                                         const double* __restrict__ fhat,
+                                                         const double* __restrict__ uhat, double* __restrict__ duhat) {
+    __shared__ double part[6][4];
+    const int m = blockIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] += partial[(size_t)(6 * m + q) * nblocks + b];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) part[q][wave] = v[q];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    // dL/d Re F_hat_a and dL/d Im F_hat_a.
+    double gr[3], gi[3];
+    for (int c = 0; c < 3; ++c) {
+        gr[c] = 2.0 * (part[2 * c][0] + part[2 * c][1] + part[2 * c][2] + part[2 * c][3]);
+        gi[c] = 2.0 * (part[2 * c + 1][0] + part[2 * c + 1][1] + part[2 * c + 1][2] + part[2 * c + 1][3]);
+    }
+    const double* fh = fhat + 6 * m;
+    const double* uh = uhat + 6 * m;
+    double d_th1 = 0.0;
+    for (int c = 0; c < 3; ++c) d_th1 += -gr[c] * fh[2 * c + 1] + gi[c] * fh[2 * c];
+    const double* e1 = basis + 8 * m;
+    const double* e2 = e1 + 3;
+    const double x1r = uh[0] * e1[0] + uh[2] * e1[1] + uh[4] * e1[2];
+    const double x1i = uh[1] * e1[0] + uh[3] * e1[1] + uh[5] * e1[2];
+    const double x2r = uh[0] * e2[0] + uh[2] * e2[1] + uh[4] * e2[2];
+    const double x2i = uh[1] * e2[0] + uh[3] * e2[1] + uh[5] * e2[2];
+    const double phi = draw[2 * m], psi = draw[2 * m + 1];
+    double sp, cp, s2, c2;
+    sincos(psi, &sp, &cp);
+    sincos(2.0 * phi, &s2, &c2);
+    const double ga = s2, gb = c2;
+    const double zr = ga * x1r + gb * (cp * x2r + sp * x2i);
+    const double zi = -ga * x1i + gb * (sp * x2r - cp * x2i);
+    const double z2 = zr * zr + zi * zi;
+    double dzr = 0.0, dzi = 0.0;
+    if (z2 > 0.0) {
+        dzr = d_th1 * zi / z2;
+        dzi = -d_th1 * zr / z2;
+    }
+    const double d1r = ga * dzr, d1i = -ga * dzi;
+    const double d2r = gb * (cp * dzr + sp * dzi), d2i = gb * (sp * dzr - cp * dzi);
+    for (int c = 0; c < 3; ++c) {
+        duhat[6 * m + 2 * c] = (d1r * e1[c] + d2r * e2[c]) * inv_n;
+        duhat[6 * m + 2 * c + 1] = (d1i * e1[c] + d2i * e2[c]) * inv_n;
+    }
+}
+
+// Stage 3, per node of x_t: dL/du = sum_m (duhat_re cos(k.x) - duhat_im
+// sin(k.x)), and through u = j / rho of the stored populations,
+// lam_i += (c_i . dL/du - u . dL/du) / rho.
+template <int S>
+__global__ __launch_bounds__(256) void k_add_velocity_grad(const typename Codec<S>::store_t* __restrict__ x,
+                                                           float* __restrict__ lam, StepArgs a,
+                                                           const double* __restrict__ duhat) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n) return;
+    const NodeIdx p = node_of(idx, a.nx, a.ny);
+    double du[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < a.n_modes; ++m) {
+        const int* k = a.fk + 3 * m;
+        const long px = ((long)k[0] * p.x) % a.nx, py = ((long)k[1] * p.y) % a.ny, pz = ((long)k[2] * p.z) % a.nz;
+        double sn, cs;
+        sincospi(2.0 * ((double)px / a.nx + (double)py / a.ny + (double)pz / a.nz), &sn, &cs);
+        const double* d = duhat + 6 * m;
+        du[0] += d[0] * cs - d[1] * sn;
+        du[1] += d[2] * cs - d[3] * sn;
+        du[2] += d[4] * cs - d[5] * sn;
+    }
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double v = Codec<S>::to_double(x[(size_t)i * a.n + idx], i);
+        rho += v;
+        j[0] += cx_of(i) * v;
+        j[1] += cy_of(i) * v;
+        j[2] += cz_of(i) * v;
+    }
+    const double inv_rho = 1.0 / rho;
+    const double udu = (j[0] * du[0] + j[1] * du[1] + j[2] * du[2]) * inv_rho;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cdu = cx_of(i) * du[0] + cy_of(i) * du[1] + cz_of(i) * du[2];
+        lam[(size_t)i * a.n + idx] += (float)((cdu - udu) * inv_rho);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, size_t count, float v) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = v;
@@ -510,6 +688,32 @@ hipError_t launch_add_energy_grad(int storage, const void* f, float* lam, double
         default: return hipErrorInvalidValue;
     }
 #undef AEG_CASE
+}
+
+hipError_t launch_force_phase_adjoint(int storage, const void* x, const float* lam_next, float* lam_out,
+                                      const StepArgs& a, double* partial, const double* basis, const double* draw,
+                                      const double* uhat, double* duhat, hipStream_t st) {
+    if (a.n_modes < 1 || !a.fk || !a.fhat) return hipErrorInvalidValue;
+    const dim3 grid((a.n + 255) / 256), block(256);
+#define FPA_CASE(SS)                                                                                           \
+    case SS: {                                                                                                 \
+        const auto* xs = static_cast<const typename Codec<SS>::store_t*>(x);                                   \
+        hipLaunchKernelGGL(k_force_adj_partials<SS>, grid, block, 0, st, xs, lam_next, a, partial);            \
+        if (hipError_t e = hipGetLastError()) return e;                                                        \
+        hipLaunchKernelGGL(k_force_phase_adj, dim3(a.n_modes), block, 0, st, partial, (int)grid.x, 1.0 / a.n,  \
+                           basis, draw, a.fhat, uhat, duhat);                                                  \
+        if (hipError_t e = hipGetLastError()) return e;                                                        \
+        hipLaunchKernelGGL(k_add_velocity_grad<SS>, grid, block, 0, st, xs, lam_out, a,                        \
+                           static_cast<const double*>(duhat));                                                 \
+        return hipGetLastError();                                                                              \
+    }
+    switch (storage) {
+        FPA_CASE(ST_F32)
+        FPA_CASE(ST_F16)
+        FPA_CASE(ST_BF16)
+        default: return hipErrorInvalidValue;
+    }
+#undef FPA_CASE
 }
 
 hipError_t launch_fill_f32(float* p, size_t count, float v, hipStream_t st) {

@@ -196,6 +196,11 @@ struct nco_lattice {
     double* d_fdraw = nullptr;
     double* d_fpart = nullptr;
     double* d_fhat_cur = nullptr;
+    // For the reverse mode: F_hat and u_hat of every recorded step
+    // [steps][12 per mode] (capacity in doubles), and dL/du_hat [6 per mode].
+    double* d_phist = nullptr;
+    size_t phist_cap = 0;
+    double* d_fduhat = nullptr;
     // Recorded forward run (checkpoints) for the adjoint.
     int rec_steps = -1, rec_every = 0;
     long rec_force_t0 = 0;
@@ -346,16 +351,26 @@ StepArgs step_args_at(const nco_lattice* lat, long t) {
     return a;
 }
 
+// F_hat (then u_hat) of recorded step `slot` under the velocity-dependent phase.
+double* phase_slot(const nco_lattice* lat, int slot) {
+    return lat->d_phist + (size_t)slot * 12 * lat->n_modes;
+}
+
 // One forward step from buffer fin to fout with the given forcing step.
-int launch_one(nco_lattice* lat, const void* fin, void* fout, long t) {
+// Under the velocity-dependent phase, slot >= 0 keeps the step's F_hat and
+// u_hat in recorded slot `slot`, and replay takes F_hat from that slot
+// instead of computing it again.
+int launch_one(nco_lattice* lat, const void* fin, void* fout, long t, int slot = -1, bool replay = false) {
     StepArgs a = step_args_at(lat, t);
     if (lat->phase_rule && lat->n_modes > 0) {
+        double* fh = slot >= 0 ? phase_slot(lat, slot) : lat->d_fhat_cur;
         // This step's coefficients from the velocity of the state it starts from.
-        HIP_TRY(launch_force_phase(lat->storage, fin, lat->n, lat->nx, lat->ny, lat->nz, lat->d_fk, lat->n_modes,
-                                   lat->d_fpart, lat->d_fbasis,
-                                   lat->d_fdraw + (size_t)(t % lat->force_steps) * lat->n_modes * 2,
-                                   lat->d_fhat_cur, lat->stream));
-        a.fhat = lat->d_fhat_cur;
+        if (!replay)
+            HIP_TRY(launch_force_phase(lat->storage, fin, lat->n, lat->nx, lat->ny, lat->nz, lat->d_fk,
+                                       lat->n_modes, lat->d_fpart, lat->d_fbasis,
+                                       lat->d_fdraw + (size_t)(t % lat->force_steps) * lat->n_modes * 2, fh,
+                                       slot >= 0 ? fh + 6 * lat->n_modes : nullptr, lat->stream));
+        a.fhat = fh;
     }
     if (use_mfma(lat))
         HIP_TRY(launch_nco_mfma(lat->storage, lat->mlp_prec, fin, fout, a, mfma_lane_tab(lat), mfma_group_tab(lat),
@@ -454,6 +469,8 @@ int nco_lattice_destroy(nco_lattice* lat) {
     if (lat->d_fdraw) hipFree(lat->d_fdraw);
     if (lat->d_fpart) hipFree(lat->d_fpart);
     if (lat->d_fhat_cur) hipFree(lat->d_fhat_cur);
+    if (lat->d_phist) hipFree(lat->d_phist);
+    if (lat->d_fduhat) hipFree(lat->d_fduhat);
     for (void* p : lat->ckpt) hipFree(p);
     for (void* p : lat->seg) hipFree(p);
     if (lat->d_k) hipFree(lat->d_k);
@@ -816,10 +833,12 @@ int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double
     if (lat->d_fhat) HIP_TRY(hipFree(lat->d_fhat));
     lat->d_fk = nullptr;
     lat->d_fhat = nullptr;
-    for (double** b : {&lat->d_fbasis, &lat->d_fdraw, &lat->d_fpart, &lat->d_fhat_cur}) {
+    for (double** b : {&lat->d_fbasis, &lat->d_fdraw, &lat->d_fpart, &lat->d_fhat_cur, &lat->d_phist,
+                       &lat->d_fduhat}) {
         if (*b) HIP_TRY(hipFree(*b));
         *b = nullptr;
     }
+    lat->phist_cap = 0;
     lat->phase_rule = false;
     lat->rec_steps = -1;
     lat->n_modes = 0;
@@ -879,6 +898,7 @@ int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double
         HIP_TRY(hipMalloc(&lat->d_fdraw, sizeof(double) * dr.size()));
         HIP_TRY(hipMalloc(&lat->d_fpart, sizeof(double) * 6 * (size_t)n_modes * sums_partial_count(lat->n)));
         HIP_TRY(hipMalloc(&lat->d_fhat_cur, sizeof(double) * 6 * (size_t)n_modes));
+        HIP_TRY(hipMalloc(&lat->d_fduhat, sizeof(double) * 6 * (size_t)n_modes));
         HIP_TRY(hipMemcpyAsync(lat->d_fbasis, basis.data(), sizeof(double) * basis.size(), hipMemcpyHostToDevice,
                                lat->stream));
         HIP_TRY(hipMemcpyAsync(lat->d_fdraw, dr.data(), sizeof(double) * dr.size(), hipMemcpyHostToDevice,
@@ -902,9 +922,18 @@ int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, doub
     if (lat->op != NCO_OP_NCO || !lat->net) return fail(NCO_E_STATE, "recording needs the NCO operator with weights");
     if (lat->width != 32 || lat->storage == NCO_F64)
         return fail(NCO_E_UNSUPPORTED, "the adjoint needs width 32 and float storage");
-    if (lat->phase_rule)
-        return fail(NCO_E_UNSUPPORTED, "the reverse mode needs the forcing phases given, not the velocity-dependent rule");
     if (int rc = set_device(lat)) return rc;
+    if (lat->phase_rule && lat->n_modes > 0) {
+        const size_t need = (size_t)nsteps * 12 * lat->n_modes;
+        if (need > lat->phist_cap) {
+            HIP_TRY(hipStreamSynchronize(lat->stream));
+            if (lat->d_phist) HIP_TRY(hipFree(lat->d_phist));
+            lat->d_phist = nullptr;
+            lat->phist_cap = 0;
+            HIP_TRY(hipMalloc(&lat->d_phist, sizeof(double) * need));
+            lat->phist_cap = need;
+        }
+    }
     const int ncp = (nsteps + ckpt_every - 1) / ckpt_every;
     while ((int)lat->ckpt.size() < ncp) {
         void* p = nullptr;
@@ -937,7 +966,7 @@ int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, doub
                 break;
             }
         }
-        if ((rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t))) break;
+        if ((rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t, s))) break;
         lat->cur = 1 - lat->cur;
         ++lat->force_t;
         if (nk > 0 && (s + 1) % every == 0) rc = sample((s + 1) / every);
@@ -1047,9 +1076,13 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
         // Recompute the states of this segment from its checkpoint.
         HIP_TRY(hipMemcpyAsync(lat->seg[0], lat->ckpt[sgi], lat->pop_bytes, hipMemcpyDeviceToDevice, lat->stream));
         for (int i = 1; i < len; ++i)
-            if (int rc = launch_one(lat, lat->seg[i - 1], lat->seg[i], lat->rec_force_t0 + t0 + i - 1)) return rc;
+            if (int rc = launch_one(lat, lat->seg[i - 1], lat->seg[i], lat->rec_force_t0 + t0 + i - 1, t0 + i - 1,
+                                    true))
+                return rc;
         for (int t = t0 + len - 1; t >= t0; --t) {
-            const StepArgs a = step_args_at(lat, lat->rec_force_t0 + t);
+            StepArgs a = step_args_at(lat, lat->rec_force_t0 + t);
+            const bool phase = lat->phase_rule && lat->n_modes > 0;
+            if (phase) a.fhat = phase_slot(lat, t);
             if (mfma) {
                 const char* tab = static_cast<const char*>(lat->adj_tab);
                 const float* lt32 = reinterpret_cast<const float*>(tab);
@@ -1062,6 +1095,14 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
                 HIP_TRY(launch_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_gsrc, lat->adj_partial,
                                        lat->stream));
                 HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, npar, lat->d_grad, lat->stream));
+            }
+            if (phase) {
+                // The force of step t also depends on x_t through its velocity modes.
+                const long ft = (lat->rec_force_t0 + t) % lat->force_steps;
+                HIP_TRY(launch_force_phase_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_fpart,
+                                                   lat->d_fbasis, lat->d_fdraw + (size_t)ft * lat->n_modes * 2,
+                                                   phase_slot(lat, t) + 6 * lat->n_modes, lat->d_fduhat,
+                                                   lat->stream));
             }
             if (int rc = inject(t, lat->seg[t - t0], lout)) return rc;
             std::swap(lin, lout);

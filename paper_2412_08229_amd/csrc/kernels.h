@@ -75,10 +75,11 @@ __device__ __forceinline__ int group_member(const LaunchGroup& g, int b) {
 
 hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs& a, hipStream_t st);
 // Velocity-dependent Alvelius phase: F_hat of this step's forced modes from
-// the state f (partial: nblocks(n) x n_modes x 6 doubles of work space).
+// the state f (partial: nblocks(n) x n_modes x 6 doubles of work space), and
+// u_hat into uhat (6 doubles per mode) unless it is null.
 hipError_t launch_force_phase(int storage, const void* f, int n, int nx, int ny, int nz, const int* fk,
                               int n_modes, double* partial, const double* basis, const double* draw, double* fhat,
-                              hipStream_t st);
+                              double* uhat, hipStream_t st);
 // Fine-to-coarse restriction (coarse extent x r = fine extent on every axis).
 hipError_t launch_restrict(int fine_storage, const void* fine, int fnx, int fny, int fnz, int coarse_storage,
                            void* coarse, int cnx, int cny, int cnz, int r, double factor, hipStream_t st);
@@ -120,6 +121,15 @@ hipError_t launch_add_energy_grad(int storage, const void* f, float* lam, double
 // grad = sum over rows of partial[nblocks][NPAR] (float64) in row order, in
 // two passes over groups of 64 rows; stage holds ceil(nblocks / 64) rows.
 hipError_t launch_grad_reduce_f64(const double* partial, int nblocks, double* stage, double* grad, hipStream_t st);
+// Reverse mode of the velocity-dependent forcing phase of one step: x the
+// state the step started from, lam_next = dL/d(state after it), a.fhat the
+// step's coefficients, uhat its u_hat, draw its (phi, psi) per mode;
+// lam_out (already holding the rest of dL/dx) gets the path x -> u_hat ->
+// theta1 -> F_hat -> source added.  partial: nblocks(n) x n_modes x 6
+// doubles of work space, duhat: 6 doubles per mode.  Float storages only.
+hipError_t launch_force_phase_adjoint(int storage, const void* x, const float* lam_next, float* lam_out,
+                                      const StepArgs& a, double* partial, const double* basis, const double* draw,
+                                      const double* uhat, double* duhat, hipStream_t st);
 
 // The same adjoint on the matrix cores (nco_mfma.hip): 256 nodes per block;
 // lane_tab and gtab are the float32 forward tables of mfma_prepare_tables,

@@ -331,10 +331,12 @@ __global__ __launch_bounds__(256) void k_mode_partials(const typename Codec<S>::
 // theta1 = atan2(Re Z, Im Z) (the force then does no work on the mode), and
 // F_hat = |A| (g_A exp(i theta1) e1 + g_B exp(i (theta1 + psi)) e2) into
 // fhat[6 m ..] as (Re, Im) of x, y, z.  basis[8 m ..] = e1, e2, |A|;
-// draw[2 m ..] = phi, psi of this step.
+// draw[2 m ..] = phi, psi of this step.  u_hat goes to uhat[6 m ..] in the
+// same layout when uhat is not null (kept for the reverse mode).
 __global__ __launch_bounds__(256) void k_force_phase(const double* __restrict__ partial, int nblocks, double inv_n,
                                                      const double* __restrict__ basis,
-                                                     const double* __restrict__ draw, double* __restrict__ fhat) {
+                                                     const double* __restrict__ draw, double* __restrict__ fhat,
+                                                     double* __restrict__ uhat) {
     __shared__ double part[6][4];
     const int m = blockIdx.x;
     double v[6] = {0, 0, 0, 0, 0, 0};
@@ -379,6 +381,11 @@ __global__ __launch_bounds__(256) void k_force_phase(const double* __restrict__ 
         fhat[6 * m + 2 * a] = mag * (ga * c1 * e1[a] + gb * c12 * e2[a]);
         fhat[6 * m + 2 * a + 1] = mag * (ga * s1 * e1[a] + gb * s12 * e2[a]);
     }
+    if (uhat)
+        for (int a = 0; a < 3; ++a) {
+            uhat[6 * m + 2 * a] = ur[a];
+            uhat[6 * m + 2 * a + 1] = ui[a];
+        }
 }
 
 // Stage 2: a single block adds the partials in a fixed order.
@@ -584,14 +591,14 @@ hipError_t launch_global_sums(int storage, const void* f, double* partial, doubl
 
 hipError_t launch_force_phase(int storage, const void* f, int n, int nx, int ny, int nz, const int* fk,
                               int n_modes, double* partial, const double* basis, const double* draw, double* fhat,
-                              hipStream_t st) {
+                              double* uhat, hipStream_t st) {
     const int nb = nblocks(n);
     DISPATCH_STORAGE(storage, {
         hipLaunchKernelGGL(k_mode_partials<SS>, dim3(nb), dim3(256), 0, st,
                            static_cast<const typename Codec<SS>::store_t*>(f), n, nx, ny, nz, fk, n_modes, partial);
         if (hipError_t e = hipGetLastError()) return e;
         hipLaunchKernelGGL(k_force_phase, dim3(n_modes), dim3(256), 0, st, partial, nb, 1.0 / n, basis, draw,
-                           fhat);
+                           fhat, uhat);
         return hipGetLastError();
     })
 }

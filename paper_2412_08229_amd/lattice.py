@@ -128,7 +128,8 @@ class Lattice:
 
     def set_forcing(self, k, draws, amplitude, kf, c, phase_rule=False):
         """Spectral forcing for the following steps; k=None switches it off.
-        phase_rule: Alvelius' velocity-dependent theta1 (forward only)."""
+        phase_rule: Alvelius' velocity-dependent theta1 (the reverse mode
+        follows the force back to the state through it)."""
         L.nco_set_forcing(self._h, k, draws, amplitude, kf, c, phase_rule)
 
     def forward_record(self, nsteps, ckpt_every, energy_every=0):

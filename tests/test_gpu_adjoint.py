@@ -220,7 +220,81 @@ def test_velocity_dependent_phase_matches_oracle(storage, kind, mlp, tol):
     assert np.abs(runs[True] - runs[False]).max() > 100 * tol
 
 
-def test_velocity_dependent_phase_is_forward_only():
+@pytest.mark.parametrize("shape,mlp,loss", [((8, 8, 8), "f32_mfma", "population"), ((7, 6, 9), "f32", "population"),
+                                             ((8, 8, 8), "f32_mfma", "spectrum"), ((9, 9, 9), "f32", "spectrum")])
+def test_velocity_dependent_phase_gradient_matches_oracle(shape, mlp, loss):
+    """Reverse mode through Alvelius' velocity-dependent theta1: the force of
+    each step depends on the state it starts from, and the GPU gradient
+    (parameters and dL/df0) follows that path like the oracle's.  The
+    recording starts 2 steps into a forcing period of 3 draws and spans 5
+    steps in checkpoint segments of 2 (the recomputed segments replay the
+    kept coefficients); the lattices of 378 and 729 nodes end in a partial
+    block.  Two backward passes agree bitwise, and the gradient with the same
+    forces held fixed is far from both."""
+    width, tau, T, K, amp, t0 = 32, 0.58, 5, 2, 1e-4, 2
+    n_nodes = int(np.prod(shape))
+    ks, draws = _forcing(3, seed=67)
+    params = inputs.mlp_params(width, 68)
+    if len(set(shape)) == 1:
+        _, u = inputs.turbulence(shape[0], seed=69, k0=2.0, urms=0.05)
+    else:
+        _, u = inputs.random_velocity(shape, seed=69, amp=0.05)
+    rho = np.ones(shape)
+    f_init = collision.equilibrium(rho, u)
+    w = np.random.Generator(np.random.PCG64(70)).standard_normal((27,) + shape)
+    Et = None
+    if loss == "spectrum":
+        Et = observables.spectrum(f_init) * np.linspace(0.7, 1.3, observables.n_bins(shape[0])) + 1e-12
+    grads = []
+    with Lattice(shape, "f32", "nco", tau) as lat:
+        lat.set_net_weights(params, width, "tanh", mlp)
+        lat.set_forcing(ks, draws, amp, KF, CW, phase_rule=True)
+        lat.init_equilibrium(rho, u)
+        lat.step(t0)                                   # forcing step t0 next
+        for _ in range(2):
+            lat.init_populations(f_init)
+            fs = lat.populations()
+            lat.forward_record(T, K)
+            if loss == "spectrum":
+                _, dE = log_spectrum_loss(lat.energy_spectrum(), Et, 1, 3)
+                grads.append(lat.backward(dL_dE=dE, want_df0=True))
+            else:
+                grads.append(lat.backward(dL_df=w, want_df0=True))
+            lat.step(3 - T % 3)                         # back to forcing step t0
+    assert np.array_equal(grads[0][0], grads[1][0]) and np.array_equal(grads[0][1], grads[1][1])
+    g, df0 = grads[0]
+    layers = collision.unpack_params(params, width)
+    rolled = np.roll(draws, -t0, axis=0)
+    sf = (ks, rolled, amp, KF, CW)
+
+    if loss == "spectrum":
+        def loss_grad(x):
+            Lx, d = adjoint.log_spectrum_loss(observables.spectrum(x), Et, 1, 3)
+            return Lx, adjoint.spectrum_vjp(x, d)
+    else:
+        def loss_grad(x):
+            return float((w * x).sum()), w
+    _, go, gfo = adjoint.run_and_grad(fs, tau, layers, "tanh", T, loss_grad, state_forcing=sf)
+    go = adjoint.flatten(go)
+    # The same run with its forces held fixed: the reverse mode without the phase path.
+    op = step.Operator("nco", tau, layers=layers, act="tanh")
+    x, fields = fs, []
+    for t in range(T):
+        _, ut = collision.macroscopic(x)
+        fields.append(forcing.field(ks, forcing.coefficients_state(ks, rolled[t % 3], amp, KF, CW, ut), shape))
+        x = step.step(x, op, fields[-1])
+    _, gz, gfz = adjoint.run_and_grad(fs, tau, layers, "tanh", T, loss_grad, forces=lambda t: fields[t])
+    gz = adjoint.flatten(gz)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    relf = np.linalg.norm(df0 - gfo) / np.linalg.norm(gfo)
+    relz = np.linalg.norm(gfz - gfo) / np.linalg.norm(gfo)
+    print("phase-rule gradient %s %s %s (%d nodes): grad rel err %.2e, dL/df0 rel err %.2e; frozen-force "
+          "dL/df0 differs by %.2e" % (shape, mlp, loss, n_nodes, rel, relf, relz))
+    assert rel < 2e-3 and relf < 2e-3
+    assert relz > 20 * relf
+
+
+def test_velocity_dependent_phase_refused_by_batched_steps():
     n = 8
     ks, draws = _forcing(2, seed=64)
     _, u = inputs.turbulence(n, seed=65, k0=2.0, urms=0.05)
@@ -228,13 +302,10 @@ def test_velocity_dependent_phase_is_forward_only():
         lat.set_net_weights(inputs.mlp_params(32, 66), 32, "tanh", "f32_mfma")
         lat.set_forcing(ks, draws, 1e-4, KF, CW, phase_rule=True)
         lat.init_equilibrium(None, u)
-        with pytest.raises(L.NCOError) as e:
-            lat.forward_record(4, 2)
-        assert e.value.status == L.NCO_E_UNSUPPORTED
         from paper_2412_08229_amd.lattice import batch_step
         with pytest.raises(L.NCOError) as e:
             batch_step([lat], [2])
         assert e.value.status == L.NCO_E_UNSUPPORTED
-        # Switching to the drawn phase re-enables the reverse mode.
-        lat.set_forcing(ks, draws, 1e-4, KF, CW)
         lat.forward_record(4, 2)
+
+

@@ -3,7 +3,7 @@ differences of the (separately pinned) forward oracle, in float64."""
 import numpy as np
 import pytest
 
-from oracle import adjoint, collision, observables, step
+from oracle import adjoint, collision, forcing, observables, step
 from paper_2412_08229_amd import inputs
 
 
@@ -199,3 +199,66 @@ def test_collision_vjp_depth3_matches_finite_differences():
     fd = ((collision.nco(f, tau, _perturb(layers, v, h)) - collision.nco(f, tau, _perturb(layers, v, -h)))
           / (2 * h) * lam).sum()
     assert abs(fd - adjoint.flatten(g_p) @ v) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_force_vjp_matches_finite_differences():
+    """dL/dF of one forced collision, L = <w, x_next>, against central
+    differences in the force."""
+    rng = _rng(90)
+    n, tau = 4, 0.56
+    layers = _layers(8, 91)
+    f = inputs.random_populations((n, n, n), seed=92, lo=0.9, hi=1.1)
+    F = 1e-3 * rng.standard_normal((3, n, n, n))
+    w = rng.standard_normal(f.shape)
+    op = step.Operator("nco", tau, layers=layers, act="tanh")
+    y = step.stream(f).reshape(27, -1)
+    g = adjoint.force_vjp(y.sum(0), adjoint._C.T @ y, F.reshape(3, -1), w.reshape(27, -1))
+    h = 1e-6
+    for _ in range(2):
+        d = rng.standard_normal(F.shape)
+        fd = ((w * step.step(f, op, F + h * d)).sum() - (w * step.step(f, op, F - h * d)).sum()) / (2 * h)
+        an = (g * d.reshape(3, -1)).sum()
+        assert abs(fd - an) < 1e-7 * abs(an), (fd, an)
+
+
+def test_unrolled_gradient_with_velocity_dependent_phase():
+    """Alvelius' rule makes each step's force a function of the state it
+    starts from; the reverse mode through it matches central differences of
+    the forward run (parameters and initial populations), and dropping that
+    path (the same forces held fixed) gives a visibly different gradient."""
+    n, width, tau, T = 6, 8, 0.55, 3
+    rng = _rng(93)
+    layers = _layers(width, 94)
+    _, u = inputs.turbulence(n, seed=95, k0=2.0, urms=0.05)
+    f0 = collision.equilibrium(np.ones((n, n, n)), u)
+    ks = inputs.forcing_half_modes(2.0)
+    draws = inputs.uniform_draws(T, len(ks), 96)
+    sf = (ks, draws, 1e-4, 1.5, 1.0)
+    w = rng.standard_normal(f0.shape)
+
+    def loss_grad(x):
+        return float((w * x).sum()), w
+
+    def forward(lay, g0):
+        op = step.Operator("nco", tau, layers=lay, act="tanh")
+        x, fields = g0, []
+        for t in range(T):
+            _, ut = collision.macroscopic(x)
+            fields.append(forcing.field(ks, forcing.coefficients_state(ks, draws[t], 1e-4, 1.5, 1.0, ut), (n, n, n)))
+            x = step.step(x, op, fields[-1])
+        return float((w * x).sum()), fields
+    L, gp, gf0 = adjoint.run_and_grad(f0, tau, layers, "tanh", T, loss_grad, state_forcing=sf)
+    L0, fields = forward(layers, f0)
+    assert abs(L - L0) < 1e-12 * abs(L0)
+    h = 1e-6
+    v = rng.standard_normal(collision.n_params(width))
+    fd = (forward(_perturb(layers, v, h), f0)[0] - forward(_perturb(layers, v, -h), f0)[0]) / (2 * h)
+    an = adjoint.flatten(gp) @ v
+    assert abs(fd - an) < 1e-6 * abs(an), (fd, an)
+    d = 1e-3 * rng.standard_normal(f0.shape)
+    fd = (forward(layers, f0 + h * d)[0] - forward(layers, f0 - h * d)[0]) / (2 * h)
+    an = (gf0 * d).sum()
+    assert abs(fd - an) < 1e-6 * abs(an), (fd, an)
+    # Negative control: the forces of this run held fixed.
+    _, _, frozen = adjoint.run_and_grad(f0, tau, layers, "tanh", T, loss_grad, forces=lambda t: fields[t])
+    assert abs((frozen * d).sum() - an) > 1e3 * abs(fd - an)

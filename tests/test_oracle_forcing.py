@@ -80,3 +80,38 @@ def test_velocity_modes_match_the_fft():
     U = np.fft.fftn(u, axes=(1, 2, 3)) / (6 * 5 * 4)
     for mi, (kx, ky, kz) in enumerate(ks):
         assert np.allclose(uh[mi], U[:, kz % 6, ky % 5, kx % 4], atol=1e-15)
+
+
+def test_field_vjp_is_the_transpose_of_field():
+    """<field(d), g> = Re d . Re field_vjp(g) + Im d . Im field_vjp(g) for any
+    coefficients d and weights g on a non-cubic grid."""
+    ks = inputs.forcing_half_modes(2.0)[:6]
+    rng = np.random.Generator(np.random.PCG64(81))
+    shape = (5, 6, 7)
+    d = rng.standard_normal((len(ks), 3)) + 1j * rng.standard_normal((len(ks), 3))
+    g = rng.standard_normal((3,) + shape)
+    lhs = (forcing.field(ks, d, shape) * g).sum()
+    v = forcing.field_vjp(ks, g)
+    rhs = (d.real * v.real).sum() + (d.imag * v.imag).sum()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_phase_rule_vjp_matches_finite_differences():
+    """Reverse mode of the velocity-dependent coefficients against central
+    differences of ``coefficients_state`` along random velocity directions."""
+    n = 6
+    ks, draws = _forcing(1, seed=82)
+    _, u = inputs.turbulence(n, seed=83, k0=2.0, urms=0.05)
+    rng = np.random.Generator(np.random.PCG64(84))
+    w = rng.standard_normal((len(ks), 3)) + 1j * rng.standard_normal((len(ks), 3))
+
+    def loss(v):
+        fh = forcing.coefficients_state(ks, draws[0], 1e-4, KF, CW, v)
+        return (fh.real * w.real).sum() + (fh.imag * w.imag).sum()
+    du = forcing.coefficients_state_vjp(ks, draws[0], 1e-4, KF, CW, u, w)
+    h = 1e-7
+    for _ in range(3):
+        d = rng.standard_normal(u.shape) * 0.01
+        fd = (loss(u + h * d) - loss(u - h * d)) / (2 * h)
+        an = (du * d).sum()
+        assert abs(fd - an) < 1e-6 * abs(an), (fd, an)
