@@ -47,7 +47,9 @@ def _cutoff_shell(nbins):
 class Unroll:
     """One training sample: initial populations (or fields), forcing and the
     unroll length; evaluates the loss and its gradient for given parameters
-    on a lattice that stays resident on the device."""
+    on a lattice that stays resident on the device.  forcing: None or the
+    arguments of ``Lattice.set_forcing``, (k, draws, amplitude, kf, c) with
+    an optional sixth, phase_rule."""
 
     def __init__(self, shape, tau, init, nsteps, ckpt_every, target, kmin, kmax, forcing=None,
                  storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, loss="log", omega=20.0):

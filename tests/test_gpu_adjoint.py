@@ -290,8 +290,10 @@ def test_velocity_dependent_phase_gradient_matches_oracle(shape, mlp, loss):
     relz = np.linalg.norm(gfz - gfo) / np.linalg.norm(gfo)
     print("phase-rule gradient %s %s %s (%d nodes): grad rel err %.2e, dL/df0 rel err %.2e; frozen-force "
           "dL/df0 differs by %.2e" % (shape, mlp, loss, n_nodes, rel, relf, relz))
-    assert rel < 2e-3 and relf < 2e-3
-    assert relz > 20 * relf
+    # float32 adjoint arithmetic over 5 steps and < 1000 nodes: measured
+    # errors stay below 1e-5.
+    assert rel < 1e-4 and relf < 1e-4
+    assert relz > 100 * relf
 
 
 def test_velocity_dependent_phase_refused_by_batched_steps():

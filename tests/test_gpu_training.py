@@ -25,13 +25,15 @@ def forced_turbulence(n, nsteps, seed, tau, urms=0.05, k0=4.0, amp=2e-6):
     return rho, u, (ks, draws, amp, 1.5, 1.0), target
 
 
-def test_c4_gradient_matches_finite_differences():
+@pytest.mark.parametrize("phase_rule", [False, True])
+def test_c4_gradient_matches_finite_differences(phase_rule):
     """64^3, 200-step unroll, checkpoints every 20: the adjoint's directional
-    derivative against a central difference of the loss."""
+    derivative against a central difference of the loss, with drawn forcing
+    phases or Alvelius' velocity-dependent phase."""
     n, T, K, tau = 64, 200, 20, 0.52
     rho, u, frc, target = forced_turbulence(n, T, seed=11, tau=tau)
     params = inputs.mlp_params(32, 0)
-    run = Unroll((n, n, n), tau, ("eq", rho, u), T, K, target, 2, 16, forcing=frc)
+    run = Unroll((n, n, n), tau, ("eq", rho, u), T, K, target, 2, 16, forcing=frc + (phase_rule,))
     L0, g, _ = run.loss_and_grad(params)
     v = np.random.Generator(np.random.PCG64(12)).standard_normal(params.size)
     v /= np.linalg.norm(v)
@@ -41,8 +43,8 @@ def test_c4_gradient_matches_finite_differences():
     run.close()
     fd = (Lp - Lm) / (2 * h)
     an = float(g @ v)
-    print("C4 64^3 x200: loss %.6f, directional derivative adjoint %.6e, finite difference %.6e"
-          % (L0, an, fd))
+    print("C4 64^3 x200 (phase rule %s): loss %.6f, directional derivative adjoint %.6e, finite difference %.6e"
+          % (phase_rule, L0, an, fd))
     assert np.isfinite(L0) and abs(fd - an) < 3e-2 * abs(an)
 
 
@@ -213,19 +215,23 @@ def test_dissipation_training_reduced_cubes():
 
 
 def test_paper_spectrum_training_pipeline():
-    """The data side of Sec. "Learning Task" at a small scale: a forced 32^3
-    BGK run (fine) restricted by acoustic scaling to 16^3 (coarse, tau_c =
-    1/2 + (tau_f - 1/2) / 2); the coarse NCO runs from the restricted state
-    under the paper's loss (squared spectrum gap over 2 <= k <= 6 plus
-    20 E(8); target: the fine spectrum at the restriction time) with the
-    unroll curriculum (20 steps, 20 more every 3 epochs).  Training lowers
+    """The data side of Sec. "Learning Task" at a small scale: a 32^3 BGK
+    run (fine) forced with Alvelius' velocity-dependent phase, restricted by
+    acoustic scaling to 16^3 (coarse, tau_c = 1/2 + (tau_f - 1/2) / 2); the
+    coarse NCO runs from the restricted state, forced by the same rule (the
+    force per step doubles when the time step does, so the amplitude of
+    F(k), which enters squared, grows 4x), under the paper's loss (squared
+    spectrum gap over 2 <= k <= 6 plus 20 E(8); target: the fine spectrum at
+    the restriction time) with the unroll curriculum (20 steps, 20 more every
+    3 epochs).  The gradient runs through the phase rule.  Training lowers
     the loss at the final unroll length below the untrained network's."""
     nf, nc = 32, 16
     tau_f = 0.52
     tau_c = 0.5 + (tau_f - 0.5) / 2
     rho, u, frc, _ = forced_turbulence(nf, 200, seed=41, tau=tau_f, urms=0.06)
+    ks, draws, amp, kf, cw = frc
     with Lattice((nf,) * 3, "f32", "bgk", tau_f) as fine, Lattice((nc,) * 3, "f32", "nco", tau_c) as coarse:
-        fine.set_forcing(*frc)
+        fine.set_forcing(*frc, phase_rule=True)
         fine.init_equilibrium(rho, u)
         fine.step(200)
         target = fine.energy_spectrum()[:n_bins(nc)]
@@ -236,7 +242,8 @@ def test_paper_spectrum_training_pipeline():
     def sched(ep):
         return curriculum_steps(ep, start=20, grow=20, every=3)
     epochs = 9
-    run = Unroll((nc,) * 3, tau_c, ("pop", f0), sched(0), 10, target, 2, 6, loss="paper", omega=20.0)
+    run = Unroll((nc,) * 3, tau_c, ("pop", f0), sched(0), 10, target, 2, 6, loss="paper", omega=20.0,
+                 forcing=(ks, draws, 4.0 * amp, kf, cw, True))
     p0 = inputs.mlp_params(32, 1)
     run.nsteps = sched(epochs - 1)
     L_untrained = run.loss(p0)
