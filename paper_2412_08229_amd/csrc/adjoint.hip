@@ -25,51 +25,64 @@ namespace {
 // DEPTH = 3: a third hidden layer (W2b, b2b) between the second and the
 // output layer; its gradient goes to the tail OFF_W2B, OFF_B2B of a partial
 // row of NPAR3 values.
-template <int S, int ACT, int DEPTH>
-__global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t* __restrict__ xin,
+//
+// A block holds 64 nodes (one per lane) and SPLIT wavefronts.  Wavefront w
+// takes the group elements w G .. w G + G - 1, G = 48 / SPLIT, of every
+// node in both passes, with its own LDS rows, so the serial chain of one
+// lane is G group elements instead of 48.  The per-node parts (the group
+// sum of pass 1, the collision adjoint) are formed from the wavefronts'
+// partial sums in a fixed order; every wavefront writes its own partial
+// gradient row, blockIdx.x * SPLIT + w, and wavefront 0 scatters dL/dx.
+template <int S, int ACT, int DEPTH, int SPLIT>
+__global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>::store_t* __restrict__ xin,
                                                 const float* __restrict__ lam_in, float* __restrict__ lam_out,
                                                 StepArgs a, const int* __restrict__ gsrc,
                                                 float* __restrict__ partial) {
     constexpr int W = AW;
     constexpr int W3X = DEPTH == 3 ? W : 1;     // extent of the third layer's arrays
     constexpr int ROW = DEPTH == 3 ? NPAR3 : NPAR;
+    static_assert(NGROUP % SPLIT == 0, "the group elements split evenly over the wavefronts");
+    constexpr int G = NGROUP / SPLIT;
     // Network (unstacked W1 [27][W], b1, W2 [W][W], b2, W3 [W][4], b3), read
     // by every lane with the same address (LDS broadcast).
     __shared__ float s_w1[27 * W], s_b1[W], s_w2[W * W], s_b2[W], s_w3[W * 4], s_b3[4];
     __shared__ float s_w2b[W3X * W3X], s_b2b[W3X];
-    __shared__ float s_h2[64][W3X];
-    __shared__ float s_d3[64][W3X];
-    // Per-node rows: moments (paper order, [27] = 1), dL/dm, and the vectors
-    // of the current group element for the parameter-gradient reduction.
+    __shared__ float s_h2[SPLIT][64][W3X];
+    __shared__ float s_d3[SPLIT][64][W3X];
+    // Per-node rows: moments (paper order, [27] = 1); per wavefront dL/dm
+    // and the vectors of the current group element for the parameter-
+    // gradient reduction.
     __shared__ float s_m[64][28];
-    __shared__ float s_dm[64][28];
-    __shared__ float s_h1[64][W];
-    __shared__ float s_d1[64][W];
-    __shared__ float s_d2[64][W];
-    const int lane = threadIdx.x;
+    __shared__ float s_dm[SPLIT][64][27];
+    __shared__ float s_h1[SPLIT][64][W];
+    __shared__ float s_d1[SPLIT][64][W];
+    __shared__ float s_d2[SPLIT][64][W];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int idx = blockIdx.x * 64 + lane;
     const bool live = idx < a.n;
     {
         // Unstacked W1 is the identity element's slice (g = 0, no permutation).
         const float* __restrict__ net = a.net;
-        for (int e = lane; e < 27 * W; e += 64) s_w1[e] = net[e];
-        for (int e = lane; e < W * W; e += 64) s_w2[e] = net[net_off_w2(W) + e];
-        for (int e = lane; e < W * 4; e += 64) s_w3[e] = net[net_off_w3(W) + e];
-        if (lane < W) {
-            s_b1[lane] = net[net_off_b1(W) + lane];
-            s_b2[lane] = net[net_off_b2(W) + lane];
+        for (int e = tid; e < 27 * W; e += 64 * SPLIT) s_w1[e] = net[e];
+        for (int e = tid; e < W * W; e += 64 * SPLIT) s_w2[e] = net[net_off_w2(W) + e];
+        for (int e = tid; e < W * 4; e += 64 * SPLIT) s_w3[e] = net[net_off_w3(W) + e];
+        if (tid < W) {
+            s_b1[tid] = net[net_off_b1(W) + tid];
+            s_b2[tid] = net[net_off_b2(W) + tid];
         }
-        if (lane < 4) s_b3[lane] = net[net_off_b3(W) + lane];
+        if (tid < 4) s_b3[tid] = net[net_off_b3(W) + tid];
         if constexpr (DEPTH == 3) {
-            for (int e = lane; e < W * W; e += 64) s_w2b[e] = net[net_off_w2b(W) + e];
-            if (lane < W) s_b2b[lane] = net[net_off_b2b(W) + lane];
+            for (int e = tid; e < W * W; e += 64 * SPLIT) s_w2b[e] = net[net_off_w2b(W) + e];
+            if (tid < W) s_b2b[tid] = net[net_off_b2b(W) + tid];
         }
     }
 
-    // Forward quantities of the node: pulled populations and moments.
+    // Forward quantities of the node: pulled populations and moments (one
+    // wavefront pulls; the others read the moments back).
     float m[Q];
     const NodeIdx p = node_of(live ? idx : 0, a.nx, a.ny);
-    {
+    if (wave == 0) {
         float f[Q];
         if (live) {
             pull<S>(xin, a, p, f);
@@ -78,21 +91,25 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
             for (int i = 0; i < Q; ++i) f[i] = (float)weight_of(i);
         }
         to_moments(f, m);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) s_m[lane][k] = m[row_tensor(k)];
+        s_m[lane][27] = 1.0f;
     }
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        s_m[lane][k] = m[row_tensor(k)];
-        s_dm[lane][k] = 0.0f;
-    }
-    s_m[lane][27] = 1.0f;
+    for (int k = 0; k < Q; ++k) s_dm[wave][lane][k] = 0.0f;
     __syncthreads();
+    if (wave != 0) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) m[row_tensor(k)] = s_m[lane][k];
+    }
 
-    // Pass 1: network forward for the rates; sum over g of act(z2).
+    // Pass 1: network forward for the rates; sum over g of act(z2), this
+    // wavefront's share first.
     float S2[W];
 #pragma unroll
     for (int o = 0; o < W; ++o) S2[o] = 0.0f;
 #pragma unroll 1
-    for (int g = 0; g < NGROUP; ++g) {
+    for (int g = wave * G; g < wave * G + G; ++g) {
         const int* __restrict__ gs = gsrc + g * 27;
         float h[W];
 #pragma unroll
@@ -129,6 +146,20 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
             for (int o = 0; o < W; ++o) S2[o] += act_f<ACT>(z3[o]);
         }
+    }
+    if constexpr (SPLIT > 1) {
+        // The full group sum, in wavefront order (every wavefront the same).
+#pragma unroll
+        for (int o = 0; o < W; ++o) s_h1[wave][lane][o] = S2[o];
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < W; ++o) {
+            float t = s_h1[0][lane][o];
+#pragma unroll
+            for (int w = 1; w < SPLIT; ++w) t += s_h1[w][lane][o];
+            S2[o] = t;
+        }
+        __syncthreads();
     }
     float tt[4], omega[4], tau[4];
 #pragma unroll
@@ -189,7 +220,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 
     // Pass 2: per group element, recompute, back-propagate, reduce.
 #pragma unroll 1
-    for (int g = 0; g < NGROUP; ++g) {
+    for (int g = wave * G; g < wave * G + G; ++g) {
         const int* __restrict__ gs = gsrc + g * 27;
         float h1[W];
 #pragma unroll
@@ -204,7 +235,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             h1[j] = act_f<ACT>(h1[j]);
-            s_h1[lane][j] = h1[j];
+            s_h1[wave][lane][j] = h1[j];
         }
         float dz2[W];
 #pragma unroll
@@ -217,7 +248,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
             for (int o = 0; o < W; ++o) {
                 dz2[o] = dh2[o] * act_d<ACT>(act_f<ACT>(dz2[o]));
-                s_d2[lane][o] = dz2[o];
+                s_d2[wave][lane][o] = dz2[o];
             }
         } else {
             // h2 = act(z2); z3 = W2b^T h2 + b2b; dz3 = dh3 act'(z3) with dh3
@@ -225,7 +256,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
             for (int o = 0; o < W; ++o) {
                 dz2[o] = act_f<ACT>(dz2[o]);
-                s_h2[lane][o] = dz2[o];
+                s_h2[wave][lane][o] = dz2[o];
             }
             float dz3[W];
 #pragma unroll
@@ -237,15 +268,15 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
             for (int o = 0; o < W; ++o) {
                 dz3[o] = dh2[o] * act_d<ACT>(act_f<ACT>(dz3[o]));
-                s_d3[lane][o] = dz3[o];
+                s_d3[wave][lane][o] = dz3[o];
             }
 #pragma unroll 4
             for (int j = 0; j < W; ++j) {
                 float t = 0.0f;
 #pragma unroll
                 for (int o = 0; o < W; ++o) t = fmaf(s_w2b[j * W + o], dz3[o], t);
-                dz2[j] = t * act_d<ACT>(s_h2[lane][j]);
-                s_d2[lane][j] = dz2[j];
+                dz2[j] = t * act_d<ACT>(s_h2[wave][lane][j]);
+                s_d2[wave][lane][j] = dz2[j];
             }
         }
         float dz1[W];
@@ -254,8 +285,8 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
             float s = 0.0f;
 #pragma unroll
             for (int o = 0; o < W; ++o) s = fmaf(s_w2[j * W + o], dz2[o], s);
-            dz1[j] = s * act_d<ACT>(s_h1[lane][j]);
-            s_d1[lane][j] = dz1[j];
+            dz1[j] = s * act_d<ACT>(s_h1[wave][lane][j]);
+            s_d1[wave][lane][j] = dz1[j];
         }
         // dL/dm^(g) = W1 dz1, scattered back through the signed permutation.
 #pragma unroll 3
@@ -264,9 +295,12 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
 #pragma unroll
             for (int j = 0; j < W; ++j) s = fmaf(s_w1[k * W + j], dz1[j], s);
             const int e = gs[k];
-            s_dm[lane][e & 31] += __int_as_float(__float_as_int(s) ^ (e & (int)0x80000000));
+            s_dm[wave][lane][e & 31] += __int_as_float(__float_as_int(s) ^ (e & (int)0x80000000));
         }
-        __syncthreads();
+        // Only this wavefront's rows are exchanged: a wavefront barrier.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // Block reduction of this group element's parameter gradients.
         int er[7];
 #pragma unroll
@@ -280,11 +314,11 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
                             ? __int_as_float(__float_as_int(s_m[nd][er[i] & 31]) ^ (er[i] & (int)0x80000000))
                             : 0.0f;
 #pragma unroll
-            for (int c = 0; c < 2; ++c) d1v[c] = s_d1[nd][c1 + c];
+            for (int c = 0; c < 2; ++c) d1v[c] = s_d1[wave][nd][c1 + c];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) hv[i] = s_h1[nd][r2 + i];
+            for (int i = 0; i < 4; ++i) hv[i] = s_h1[wave][nd][r2 + i];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) d2v[c] = s_d2[nd][c2 + c];
+            for (int c = 0; c < 4; ++c) d2v[c] = s_d2[wave][nd][c2 + c];
 #pragma unroll
             for (int i = 0; i < 7; ++i)
 #pragma unroll
@@ -293,54 +327,71 @@ __global__ __launch_bounds__(64) void k_adjoint(const typename Codec<S>::store_t
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc2[i][c] = fmaf(hv[i], d2v[c], acc2[i][c]);
-            if (lane < W) accb2 += s_d2[nd][lane];
+            if (lane < W) accb2 += s_d2[wave][nd][lane];
             if constexpr (DEPTH == 3) {
                 float h2v[4], d3v[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) h2v[i] = s_h2[nd][r2 + i];
+                for (int i = 0; i < 4; ++i) h2v[i] = s_h2[wave][nd][r2 + i];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) d3v[c] = s_d3[nd][c2 + c];
+                for (int c = 0; c < 4; ++c) d3v[c] = s_d3[wave][nd][c2 + c];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) acc3[i][c] = fmaf(h2v[i], d3v[c], acc3[i][c]);
-                if (lane >= 64 - W) accb2b += s_d3[nd][lane - (64 - W)];
+                if (lane >= 64 - W) accb2b += s_d3[wave][nd][lane - (64 - W)];
             }
         }
-        __syncthreads();
+        // Only this wavefront's rows are exchanged: a wavefront barrier.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
-    // dL/dy = lambda + M^T g_m, with the network's share of g_m from s_dm.
-#pragma unroll
-    for (int k = 0; k < Q; ++k) gm[row_tensor(k)] += s_dm[lane][k];
-    float gf[Q];
-    moments_T(gm, gf);
-    // Scatter back along the streaming: the slot the pull read.
-    if (live) {
-        float v[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) v[i] = lam[i] + gf[i];
-        scatter_to_sources(lam_out, a, p, v);
-    }
-
-    // Output-layer gradients: dW3 = sum (S2/48) dtt^T, db3 = sum dtt.
-#pragma unroll
-    for (int o = 0; o < W; ++o) s_h1[lane][o] = S2[o] * (1.0f / NGROUP);
-#pragma unroll
-    for (int n = 0; n < 4; ++n) s_d2[lane][n] = dtt[n];
+    // dL/dy = lambda + M^T g_m, with the network's share of g_m from the
+    // wavefronts' s_dm rows (in wavefront order); wavefront 0 scatters.
     __syncthreads();
-    float* __restrict__ out = partial + (size_t)blockIdx.x * ROW;
-    {
+    float* __restrict__ out = partial + ((size_t)blockIdx.x * SPLIT + wave) * ROW;
+    if (wave == 0) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            float t = s_dm[0][lane][k];
+#pragma unroll
+            for (int w = 1; w < SPLIT; ++w) t += s_dm[w][lane][k];
+            gm[row_tensor(k)] += t;
+        }
+        float gf[Q];
+        moments_T(gm, gf);
+        // Scatter back along the streaming: the slot the pull read.
+        if (live) {
+            float v[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) v[i] = lam[i] + gf[i];
+            scatter_to_sources(lam_out, a, p, v);
+        }
+
+        // Output-layer gradients: dW3 = sum (S2/48) dtt^T, db3 = sum dtt.
+#pragma unroll
+        for (int o = 0; o < W; ++o) s_h1[0][lane][o] = S2[o] * (1.0f / NGROUP);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) s_d2[0][lane][n] = dtt[n];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float w3a = 0.0f, w3b = 0.0f, b3a = 0.0f;
         const int e0 = 2 * lane, e1 = 2 * lane + 1;              // W3 entries [o][n] = e / 4, e % 4
         for (int nd = 0; nd < 64; ++nd) {
-            w3a = fmaf(s_h1[nd][e0 >> 2], s_d2[nd][e0 & 3], w3a);
-            w3b = fmaf(s_h1[nd][e1 >> 2], s_d2[nd][e1 & 3], w3b);
-            if (lane < 4) b3a += s_d2[nd][lane];
+            w3a = fmaf(s_h1[0][nd][e0 >> 2], s_d2[0][nd][e0 & 3], w3a);
+            w3b = fmaf(s_h1[0][nd][e1 >> 2], s_d2[0][nd][e1 & 3], w3b);
+            if (lane < 4) b3a += s_d2[0][nd][lane];
         }
         out[OFF_W3 + e0] = w3a;
         out[OFF_W3 + e1] = w3b;
         if (lane < 4) out[OFF_B3 + lane] = b3a;
+    } else {
+        // The output layer's gradient is wavefront 0's.
+        out[OFF_W3 + 2 * lane] = 0.0f;
+        out[OFF_W3 + 2 * lane + 1] = 0.0f;
+        if (lane < 4) out[OFF_B3 + lane] = 0.0f;
     }
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
@@ -627,31 +678,47 @@ __global__ __launch_bounds__(256) void k_f32_to_f64(const float* __restrict__ sr
 
 int adjoint_param_count() { return NPAR; }
 int adjoint_param_count_depth(int depth) { return depth == 3 ? NPAR3 : NPAR; }
-int adjoint_blocks(int n) { return (n + 63) / 64; }
+// Wavefronts per 64-node block of the vector-unit adjoint: as many as the
+// 160 KiB of LDS holds (each keeps five [64][32] rows at depth 3, three at
+// depth 2), which shortens the serial chain of every lane.  Measured on the
+// reduced Taylor-Green cubes and periodic boxes from 16^3 to 96^3, the split
+// wins at every size at depth 3 (2.4x at 16^3, 1.1x at 96^3); at depth 2 it
+// wins up to ~2000 blocks, breaks even at 4096 and loses at 13824, where one
+// wavefront per block leaves room for more blocks per CU.
+constexpr int ADJ_SPLIT_D3 = 3, ADJ_SPLIT_D2 = 4, ADJ_SPLIT_D2_MAX_BLOCKS = 2048;
+int adjoint_split(int n, int depth) {
+    if (depth == 3) return ADJ_SPLIT_D3;
+    return (n + 63) / 64 <= ADJ_SPLIT_D2_MAX_BLOCKS ? ADJ_SPLIT_D2 : 1;
+}
+
+int adjoint_blocks(int n, int depth) { return (n + 63) / 64 * adjoint_split(n, depth); }
 
 hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
                           const int* gsrc, float* partial, hipStream_t st) {
-    const dim3 grid((a.n + 63) / 64), block(64);
+    const int split = adjoint_split(a.n, a.depth);
+    const dim3 grid((a.n + 63) / 64), block(64 * split);
+#define ADJ_LAUNCH(SS, ACT, DEPTH, SPLIT)                                                                    \
+    hipLaunchKernelGGL((k_adjoint<SS, ACT, DEPTH, SPLIT>), grid, block, 0, st,                                \
+                       static_cast<const typename Codec<SS>::store_t*>(xin), lam_in, lam_out, a, gsrc, partial)
 #define ADJ_CASE(SS)                                                                                         \
-    case SS: {                                                                                               \
-        using T = typename Codec<SS>::store_t;                                                               \
-        const T* x = static_cast<const T*>(xin);                                                            \
+    case SS:                                                                                                 \
         if (a.depth == 3) {                                                                                  \
             if (a.act == ACT_TANH)                                                                           \
-                hipLaunchKernelGGL((k_adjoint<SS, ACT_TANH, 3>), grid, block, 0, st, x, lam_in, lam_out, a, gsrc, \
-                                   partial);                                                                 \
+                ADJ_LAUNCH(SS, ACT_TANH, 3, ADJ_SPLIT_D3);                                                   \
             else                                                                                             \
-                hipLaunchKernelGGL((k_adjoint<SS, ACT_RELU, 3>), grid, block, 0, st, x, lam_in, lam_out, a, gsrc, \
-                                   partial);                                                                 \
-        } else if (a.act == ACT_TANH) {                                                                      \
-            hipLaunchKernelGGL((k_adjoint<SS, ACT_TANH, 2>), grid, block, 0, st, x, lam_in, lam_out, a, gsrc,   \
-                               partial);                                                                     \
+                ADJ_LAUNCH(SS, ACT_RELU, 3, ADJ_SPLIT_D3);                                                   \
+        } else if (split > 1) {                                                                              \
+            if (a.act == ACT_TANH)                                                                           \
+                ADJ_LAUNCH(SS, ACT_TANH, 2, ADJ_SPLIT_D2);                                                   \
+            else                                                                                             \
+                ADJ_LAUNCH(SS, ACT_RELU, 2, ADJ_SPLIT_D2);                                                   \
         } else {                                                                                             \
-            hipLaunchKernelGGL((k_adjoint<SS, ACT_RELU, 2>), grid, block, 0, st, x, lam_in, lam_out, a, gsrc,   \
-                               partial);                                                                     \
+            if (a.act == ACT_TANH)                                                                           \
+                ADJ_LAUNCH(SS, ACT_TANH, 2, 1);                                                              \
+            else                                                                                             \
+                ADJ_LAUNCH(SS, ACT_RELU, 2, 1);                                                              \
         }                                                                                                    \
-        return hipGetLastError();                                                                            \
-    }
+        return hipGetLastError();
     switch (storage) {
         ADJ_CASE(ST_F32)
         ADJ_CASE(ST_F16)
@@ -659,6 +726,7 @@ hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, flo
         default: return hipErrorInvalidValue;
     }
 #undef ADJ_CASE
+#undef ADJ_LAUNCH
 }
 
 hipError_t launch_grad_reduce(const float* partial, int nblocks, int npar, double* grad, hipStream_t st) {

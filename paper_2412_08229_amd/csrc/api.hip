@@ -1029,7 +1029,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
     // (a depth-3 network takes the vector-unit adjoint)
     const bool mfma = lat->mlp_prec != NCO_MLP_F32 && lat->adj_tab && lat->depth == 2;
     const int npar = mfma ? adjoint_param_count() : adjoint_param_count_depth(lat->depth);
-    const int nblk = mfma ? adjoint_mfma_blocks(lat->n) : adjoint_blocks(lat->n);
+    const int nblk = mfma ? adjoint_mfma_blocks(lat->n) : adjoint_blocks(lat->n, lat->depth);
     const int ngrp = (nblk + 63) / 64;
     if (mfma) {
         if (!lat->adj_partial64)

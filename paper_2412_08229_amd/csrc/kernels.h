@@ -111,7 +111,8 @@ hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchG
 
 // Adjoint of a step (adjoint.hip), network width 32, float arithmetic.
 int adjoint_param_count();
-int adjoint_blocks(int n);
+// Partial gradient rows of one launch_adjoint (several per 64-node block).
+int adjoint_blocks(int n, int depth);
 hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
                           const int* gsrc, float* partial, hipStream_t st);
 hipError_t launch_grad_reduce(const float* partial, int nblocks, int npar, double* grad, hipStream_t st);

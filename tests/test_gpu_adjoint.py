@@ -311,3 +311,31 @@ def test_velocity_dependent_phase_refused_by_batched_steps():
         lat.forward_record(4, 2)
 
 
+
+
+@pytest.mark.parametrize("n", [48, 64])
+def test_vector_adjoint_matches_matrix_core_adjoint_at_size(n):
+    """The vector-unit adjoint splits each 64-node block's group elements
+    over four wavefronts up to 2048 blocks and keeps one wavefront above; on
+    both sides of that switch (48^3: 1728 blocks, 64^3: 4096) its gradient
+    equals the matrix-core adjoint's (oracle-pinned at small sizes) on the
+    same recorded 12-step run to float32 accumulation error.  The loss
+    weights have random signs, so the parameter gradient is a sum with heavy
+    cancellation: both paths differ from each other by ~1e-6 absolute at
+    16^3 .. 64^3, a few 1e-4 of the gradient's norm where that norm is small
+    (2.6e-3 at 48^3, 1.1e-2 at 64^3)."""
+    width, tau, T, K = 32, 0.56, 12, 4
+    params = inputs.mlp_params(width, 71)
+    _, u = inputs.turbulence(n, seed=72, k0=4.0, urms=0.05)
+    w = np.random.Generator(np.random.PCG64(73)).standard_normal((27, n, n, n))
+    out = {}
+    for mlp in ("f32", "f32_mfma"):
+        with Lattice((n, n, n), "f32", "nco", tau) as lat:
+            lat.set_net_weights(params, width, "tanh", mlp)
+            lat.init_equilibrium(None, u)
+            lat.forward_record(T, K)
+            out[mlp] = lat.backward(dL_df=w, want_df0=True)
+    rel = np.linalg.norm(out["f32"][0] - out["f32_mfma"][0]) / np.linalg.norm(out["f32_mfma"][0])
+    relf = np.linalg.norm(out["f32"][1] - out["f32_mfma"][1]) / np.linalg.norm(out["f32_mfma"][1])
+    print("%d^3: vector vs matrix-core adjoint, grad rel diff %.2e, dL/df0 rel diff %.2e" % (n, rel, relf))
+    assert rel < 1e-3 and relf < 1e-5
