@@ -148,7 +148,9 @@ __device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float*
 // DEPTH = 3: a third hidden layer (W2b, b2b) between the second layer and
 // the group sum, one more product per group element whose B operand is the
 // second layer's accumulator, like the second layer's is the first's.
-template <int ACT, int DEPTH = 2>
+// TPW: 16-node tiles per wavefront; wavefront w serves nodes
+// [16 TPW w, 16 TPW (w + 1)) of the block.
+template <int ACT, int DEPTH = 2, int TPW = 4>
 __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const int* __restrict__ sg,
                                             float* __restrict__ sw, const float* __restrict__ lt, int wave,
                                             int q, int c, float* __restrict__ s2 = nullptr) {
@@ -169,8 +171,8 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
         for (int r = 0; r < 4; ++r) B2[u][r] = lt[LT_B2 + u * 4 + r];
 
 #pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-        const int node = wave * 64 + j * 16 + c;
+    for (int j = 0; j < TPW; ++j) {
+        const int node = wave * 16 * TPW + j * 16 + c;
         const float* __restrict__ mrow = sm + node * NODE_STRIDE;
         f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll 1
@@ -298,7 +300,7 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
     }
 }
 
-template <int ACT>
+template <int ACT, int TPW = 4>
 __device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const int* __restrict__ sg,
                                              float* __restrict__ sw, const float* __restrict__ lt, int wave,
                                              int q, int c) {
@@ -320,8 +322,8 @@ __device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const
         for (int r = 0; r < 4; ++r) B2[u][r] = lt[LB_B2 + u * 4 + r];
 
 #pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-        const int node = wave * 64 + j * 16 + c;
+    for (int j = 0; j < TPW; ++j) {
+        const int node = wave * 16 * TPW + j * 16 + c;
         const float* __restrict__ mrow = sm + node * NODE_STRIDE;
         f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll 1
@@ -363,17 +365,20 @@ __device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const
 
 // RATES = true: no streaming, the rates of the stored state are written to
 // omega_out [4][n] instead of a step (readout and tests of the network alone).
-// Work space of one block in LDS, declared by each kernel.  A block of
-// NODES = 256 or 64 threads serves as many nodes; the wavefronts of a block
-// share only the gather table (each runs the network on its own 64 nodes),
-// so the one-wavefront block is the same computation with 4x more blocks.
+// Work space of one block in LDS, declared by each kernel.  A block serves
+// NODES = 256 or 64 nodes with TPW 16-node tiles per wavefront, so
+// 64 NODES / (16 TPW) threads: 256 nodes on 4 wavefronts (TPW 4), 64 nodes on
+// one wavefront (TPW 4) or on 4 wavefronts of one tile each (TPW 1, the
+// shortest serial chain per wavefront, for small lattices).  The wavefronts
+// of a block share only the gather table; every variant does the same
+// arithmetic per node.
 struct BlockLds {
     float* sm;      // [NODES][NODE_STRIDE] moments, then hidden activations
     int* sg;        // [GT_ENTRIES] gather table
     float* sw;      // [NODES][4] rates
 };
 
-template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH = 2>
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH = 2, int TPW = 4>
 __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t* __restrict__ fin,
                                                typename Codec<S>::store_t* __restrict__ fout, const StepArgs& a,
                                                const float* __restrict__ lane_tab, const int* __restrict__ gtab,
@@ -385,13 +390,15 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
     __shared__ float lds_sw[(NODES) * 4];            \
     const BlockLds lds{lds_sm, lds_sg, lds_sw};
 
-template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH>
-__global__ __launch_bounds__(NODES) void k_nco_mfma(const typename Codec<S>::store_t* __restrict__ fin,
-                                                    typename Codec<S>::store_t* __restrict__ fout, StepArgs a,
-                                                    const float* __restrict__ lane_tab,
-                                                    const int* __restrict__ gtab, double* __restrict__ omega_out) {
+constexpr int mfma_block_threads(int nodes, int tpw) { return nodes / (16 * tpw) * 64; }
+
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW>
+__global__ __launch_bounds__(mfma_block_threads(NODES, TPW)) void k_nco_mfma(
+    const typename Codec<S>::store_t* __restrict__ fin, typename Codec<S>::store_t* __restrict__ fout,
+    StepArgs a, const float* __restrict__ lane_tab, const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
-    nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x, lds);
+    nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x,
+                                                           lds);
 }
 
 template <int S, int ACT, int PREC>
@@ -410,22 +417,23 @@ __global__ __launch_bounds__(256) void k_nco_mfma_grouped(LaunchGroup g) {
     grouped_block<S, ACT, PREC>(g.d[i], blockIdx.x - g.prefix[i], lds);
 }
 
-template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH>
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW>
 __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t* __restrict__ fin,
                                                typename Codec<S>::store_t* __restrict__ fout, const StepArgs& a,
                                                const float* __restrict__ lane_tab, const int* __restrict__ gtab,
                                                double* __restrict__ omega_out, int blk, BlockLds lds) {
+    constexpr int THREADS = mfma_block_threads(NODES, TPW);
     float* __restrict__ sm = lds.sm;
     int* __restrict__ sg = lds.sg;
     float* __restrict__ sw = lds.sw;
     const int tid = threadIdx.x;
     const int idx = blk * NODES + tid;
-    const bool live = idx < a.n;
+    const bool live = (THREADS == NODES || tid < NODES) && idx < a.n;
 
-    for (int e = tid; e < GT_ENTRIES; e += NODES) sg[e] = gtab[e];
+    for (int e = tid; e < GT_ENTRIES; e += THREADS) sg[e] = gtab[e];
 
     // Phase A: pull and transform to moments.
-    {
+    if (THREADS == NODES || tid < NODES) {
         float f[Q];
         if (live) {
             if constexpr (RATES)
@@ -451,9 +459,9 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
         const int lane = tid & 63;
         const float* __restrict__ lt = lane_tab + lane * LANE_WORDS;
         if constexpr (PREC == MLP_PREC_BF16)
-            network_bf16<ACT>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
+            network_bf16<ACT, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
         else
-            network_f32<ACT, DEPTH>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
+            network_f32<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
     }
     __syncthreads();
 
@@ -543,7 +551,10 @@ __device__ __forceinline__ float act_value(float r) {
         return 1.0f - 2.0f * r;
 }
 
-template <int S, int ACT>
+// TPW = 4: 256 nodes per block, 4 tiles per wavefront; TPW = 1: 64 nodes
+// per block, one tile per wavefront (a 4x shorter serial chain for lattices
+// too small to fill the device with 256-node blocks).
+template <int S, int ACT, int TPW>
 __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::store_t* __restrict__ xin,
                                                       const float* __restrict__ lam_in, float* __restrict__ lam_out,
                                                       StepArgs a, const float* __restrict__ lane_tab,
@@ -558,8 +569,9 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
     __shared__ float sdm[256 * 32];             // group sums of the second layer, then dL/dm (network part)
     __shared__ float sbuf[4][3][16 * TB];       // per-wave transposes
     const int tid = threadIdx.x;
-    const int idx = blockIdx.x * 256 + tid;
-    const bool live = idx < a.n;
+    constexpr int NB = 64 * TPW;                // nodes of the block
+    const int idx = blockIdx.x * NB + tid;
+    const bool live = (NB == 256 || tid < NB) && idx < a.n;
     const NodeIdx p = node_of(live ? idx : 0, a.nx, a.ny);
 
     for (int e = tid; e < GT_ENTRIES; e += 256) sg[e] = gtab[e];
@@ -588,7 +600,7 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
 
     const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
     // Phase B1: the network forward for tilde tau and the group sums.
-    network_f32<ACT>(sm, sg, sw, lane_tab + lane * LANE_WORDS, wave, q, c, sdm);
+    network_f32<ACT, 2, TPW>(sm, sg, sw, lane_tab + lane * LANE_WORDS, wave, q, c, sdm);
     __syncthreads();
 
     // Phase B2: per node, dL/d tilde tau from the node-local collision adjoint.
@@ -623,7 +635,7 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
         if (tid < 128) {
             const int o = tid >> 2, n = tid & 3;
             float v = 0.0f;
-            for (int nd = 0; nd < 256; ++nd) {
+            for (int nd = 0; nd < NB; ++nd) {
                 const float acc = sdm[nd * 32 + o];
                 const float h2 = ACT == ACT_RELU ? acc : (float)NGROUP - 2.0f * acc;
                 v = fmaf(h2 * (1.0f / NGROUP), sw[nd * 4 + n], v);
@@ -633,7 +645,7 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
         } else {
             const int n = tid - 128;
             float v = 0.0f;
-            for (int nd = 0; nd < 256; ++nd) v += sw[nd * 4 + n];
+            for (int nd = 0; nd < NB; ++nd) v += sw[nd * 4 + n];
             out[OFF_B3 + n] += (double)v;
         }
     }
@@ -690,8 +702,8 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
         float* __restrict__ bz1 = sbuf[wave][2];
 
 #pragma unroll 1
-        for (int j = 0; j < 4; ++j) {
-            const int base = wave * 64 + j * 16;
+        for (int j = 0; j < TPW; ++j) {
+            const int base = wave * 16 * TPW + j * 16;
             const int node = base + c;
             const float* __restrict__ mrow = sm + node * NODE_STRIDE;
             // dh2 = W3 dtt / 48 for this lane's rows.
@@ -1114,23 +1126,36 @@ void mfma_prepare_adjoint_table(const float* params, float* tab) {
     }
 }
 
-int adjoint_mfma_blocks(int n) { return (n + 255) / 256; }
+// One 4-wavefront block per CU (the kernel's registers): with 256-node
+// blocks each wavefront runs 4 tiles per round, with 64-node blocks one tile
+// and 4x the blocks, so below 256 CUs x 256 nodes the small blocks finish in
+// fewer tile-rounds (4x fewer up to 16384 nodes) and above it they tie.
+constexpr int ADJM_SMALL_NODES = 65536;
+int adjoint_mfma_blocks(int n) { return n < ADJM_SMALL_NODES ? (n + 63) / 64 : (n + 255) / 256; }
 
 hipError_t launch_adjoint_mfma(int storage, int act, const void* xin, const float* lam_in, float* lam_out,
                                const StepArgs& a, const float* lane_tab, const int* gtab, const float* adj_tab,
                                const int* gsrc, double* partial, hipStream_t st) {
+    const bool small = a.n < ADJM_SMALL_NODES;
     const dim3 grid(adjoint_mfma_blocks(a.n)), block(256);
+#define ADJM_LAUNCH(SS, ACT, TPW)                                                                                \
+    hipLaunchKernelGGL((k_adjoint_mfma<SS, ACT, TPW>), grid, block, 0, st,                                      \
+                       static_cast<const typename Codec<SS>::store_t*>(xin), lam_in, lam_out, a, lane_tab, gtab,  \
+                       adj_tab, gsrc, partial)
 #define ADJM_CASE(SS)                                                                                            \
-    case SS: {                                                                                                   \
-        using T = typename Codec<SS>::store_t;                                                                   \
-        if (act == ACT_TANH)                                                                                     \
-            hipLaunchKernelGGL((k_adjoint_mfma<SS, ACT_TANH>), grid, block, 0, st, static_cast<const T*>(xin),   \
-                               lam_in, lam_out, a, lane_tab, gtab, adj_tab, gsrc, partial);                     \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_adjoint_mfma<SS, ACT_RELU>), grid, block, 0, st, static_cast<const T*>(xin),   \
-                               lam_in, lam_out, a, lane_tab, gtab, adj_tab, gsrc, partial);                     \
-        return hipGetLastError();                                                                                \
-    }
+    case SS:                                                                                                     \
+        if (act == ACT_TANH) {                                                                                   \
+            if (small)                                                                                           \
+                ADJM_LAUNCH(SS, ACT_TANH, 1);                                                                    \
+            else                                                                                                 \
+                ADJM_LAUNCH(SS, ACT_TANH, 4);                                                                    \
+        } else {                                                                                                 \
+            if (small)                                                                                           \
+                ADJM_LAUNCH(SS, ACT_RELU, 1);                                                                    \
+            else                                                                                                 \
+                ADJM_LAUNCH(SS, ACT_RELU, 4);                                                                    \
+        }                                                                                                        \
+        return hipGetLastError();
     switch (storage) {
         ADJM_CASE(ST_F32)
         ADJM_CASE(ST_F16)
@@ -1138,6 +1163,7 @@ hipError_t launch_adjoint_mfma(int storage, int act, const void* xin, const floa
         default: return hipErrorInvalidValue;
     }
 #undef ADJM_CASE
+#undef ADJM_LAUNCH
 }
 
 // omega_out == nullptr: one stream-collide step fin -> fout.  Otherwise the
@@ -1165,34 +1191,45 @@ hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchG
 #undef GRP_LAUNCH
 }
 
-// Nodes per block of the single-lattice kernel: one-wavefront blocks when
-// 256-node blocks would not give two per compute unit (measured: 10 % faster
-// for a 32^3 lattice, equal from 64^3 up; the results are bit-identical).
-int mfma_block_nodes(int n) { return n < 2 * 256 * 256 ? 64 : 256; }
+// Block shape of the single-lattice kernel (the results are bit-identical
+// for all three).  About 2 wavefronts per SIMD are resident (8 per CU).
+// Below 65536 nodes, 64-node blocks with one tile per wavefront finish in
+// fewer rounds of tiles (4x fewer up to 32768 nodes).  Up to 131072 nodes,
+// one-wavefront 64-node blocks (measured 10 % faster than 256-node blocks at
+// 32^3 before the one-tile blocks existed, equal from 64^3 up).  Above, the
+// 256-node blocks.
+enum MfmaBlock { MFMA_BLOCK_256 = 0, MFMA_BLOCK_64 = 1, MFMA_BLOCK_64_TILE = 2 };
+int mfma_block_kind(int n) {
+    return n < 65536 ? MFMA_BLOCK_64_TILE : n < 2 * 256 * 256 ? MFMA_BLOCK_64 : MFMA_BLOCK_256;
+}
 
 template <int S, int ACT, bool RR, int PP, int DD>
-hipError_t launch_mfma_kind(int nodes, const void* fin, void* fout, const StepArgs& a, const float* lane_tab,
+hipError_t launch_mfma_kind(int kind, const void* fin, void* fout, const StepArgs& a, const float* lane_tab,
                             const int* gtab, double* omega_out, hipStream_t st) {
     using T = typename Codec<S>::store_t;
-    const dim3 grid((a.n + nodes - 1) / nodes), block(nodes);
-    if (nodes == 64)
-        hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD>), grid, block, 0, st, static_cast<const T*>(fin),
-                           static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+    const int nodes = kind == MFMA_BLOCK_256 ? 256 : 64;
+    const dim3 grid((a.n + nodes - 1) / nodes);
+    if (kind == MFMA_BLOCK_64_TILE)
+        hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 1>), dim3(grid), dim3(mfma_block_threads(64, 1)), 0,
+                           st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+    else if (kind == MFMA_BLOCK_64)
+        hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 4>), dim3(grid), dim3(mfma_block_threads(64, 4)), 0,
+                           st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
     else
-        hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 256, DD>), grid, block, 0, st, static_cast<const T*>(fin),
-                           static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+        hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 256, DD, 4>), dim3(grid), dim3(mfma_block_threads(256, 4)),
+                           0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
     return hipGetLastError();
 }
 
 template <int S, int ACT, bool RR>
 hipError_t launch_mfma_prec(int prec, const void* fin, void* fout, const StepArgs& a, const float* lane_tab,
                             const int* gtab, double* omega_out, hipStream_t st) {
-    const int nodes = mfma_block_nodes(a.n);
+    const int kind = mfma_block_kind(a.n);
     if (prec == MLP_PREC_BF16)
-        return launch_mfma_kind<S, ACT, RR, MLP_PREC_BF16, 2>(nodes, fin, fout, a, lane_tab, gtab, omega_out, st);
+        return launch_mfma_kind<S, ACT, RR, MLP_PREC_BF16, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
     if (a.depth == 3)
-        return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 3>(nodes, fin, fout, a, lane_tab, gtab, omega_out, st);
-    return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 2>(nodes, fin, fout, a, lane_tab, gtab, omega_out, st);
+        return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 3>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
+    return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
 }
 
 template <int S>

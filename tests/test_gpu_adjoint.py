@@ -313,13 +313,15 @@ def test_velocity_dependent_phase_refused_by_batched_steps():
 
 
 
-@pytest.mark.parametrize("n", [48, 64])
+@pytest.mark.parametrize("n", [32, 48, 64])
 def test_vector_adjoint_matches_matrix_core_adjoint_at_size(n):
     """The vector-unit adjoint splits each 64-node block's group elements
-    over four wavefronts up to 2048 blocks and keeps one wavefront above; on
-    both sides of that switch (48^3: 1728 blocks, 64^3: 4096) its gradient
-    equals the matrix-core adjoint's (oracle-pinned at small sizes) on the
-    same recorded 12-step run to float32 accumulation error.  The loss
+    over four wavefronts up to 2048 blocks and keeps one wavefront above; the
+    matrix-core adjoint runs 64-node blocks (one tile per wavefront) below
+    65536 nodes and 256-node blocks above.  Across these switches (32^3: 512
+    and 512 blocks, 48^3: 1728 and 432, 64^3: 4096 and 1024) the two
+    gradients agree on the same recorded 12-step run to float32 accumulation
+    error; both are pinned to the oracle at small sizes.  The loss
     weights have random signs, so the parameter gradient is a sum with heavy
     cancellation: both paths differ from each other by ~1e-6 absolute at
     16^3 .. 64^3, a few 1e-4 of the gradient's norm where that norm is small
