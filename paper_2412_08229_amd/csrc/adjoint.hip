@@ -686,7 +686,7 @@ int adjoint_param_count_depth(int depth) { return depth == 3 ? NPAR3 : NPAR; }
 // wins up to ~2000 blocks, breaks even at 4096 and loses at 13824, where one
 // wavefront per block leaves room for more blocks per CU.
 constexpr int ADJ_SPLIT_D3 = 3, ADJ_SPLIT_D2 = 4, ADJ_SPLIT_D2_MAX_BLOCKS = 2048;
-int adjoint_split(int n, int depth) {
+static int adjoint_split(int n, int depth) {
     if (depth == 3) return ADJ_SPLIT_D3;
     return (n + 63) / 64 <= ADJ_SPLIT_D2_MAX_BLOCKS ? ADJ_SPLIT_D2 : 1;
 }
