@@ -384,6 +384,114 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100,
     print(json.dumps(out), flush=True)
 
 
+def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-6, urms=0.05, spinup=5.0,
+                      start=200, grow=200, every=10, kmin=4, kmax=10, omega=20.0):
+    """The spectrum training of Sec. "Learning Task" at the paper's grid
+    sizes.  A forced n_fine^3 BGK run stands in for the DNS: Alvelius
+    forcing on |k| <= 2 with the velocity-dependent phase, from a seeded
+    random-phase field of rms velocity ``urms``, tau_f = 0.6 (nu = 1/30),
+    forcing amplitude amp_f (the kinetic energy is printed every large-eddy
+    time of the spin-up, which must stay finite).  After
+    ``spinup`` large-eddy times, n_snap snapshots half a large-eddy time
+    apart are restricted by acoustic scaling to n_coarse^3 (tau_c = 1/2 +
+    (tau_f - 1/2) / r); each is a sample whose coarse NCO run is forced by
+    the same rule (amplitude x r^2: the force per step grows with the time
+    step and F(k) enters squared) and scored by the paper's loss (squared
+    spectrum gap over kmin <= k <= kmax plus omega E(N/2)) against the fine
+    run's spectrum averaged over the snapshots.  Adam over the samples with
+    the unroll curriculum (start steps, grow more every ``every`` epochs).
+    Reports the loss per sample at the final unroll length for the untrained
+    and trained network, the fixed-rate operator and BGK, and the times.
+    Prints one JSON line."""
+    from paper_2412_08229_amd import Lattice, inputs
+    from paper_2412_08229_amd._lib import NCOError
+    from paper_2412_08229_amd.training import (Unroll, curriculum_steps, n_bins, paper_spectrum_loss,
+                                               train_batched)
+
+    r = n_fine // n_coarse
+    if r * n_coarse != n_fine:
+        raise ValueError("the fine extent must be a multiple of the coarse one")
+    tau_c = 0.5 + (tau_f - 0.5) / r
+    amp_c = amp_f * r * r
+    ks = inputs.forcing_half_modes(2.0)
+    t_large = int(round(n_fine / (2.0 * math.pi * 1.5) / urms))     # large-eddy time in fine steps
+    t0 = time.time()
+    rho, u = inputs.turbulence(n_fine, seed=101, k0=4.0, urms=urms)
+    snaps, spectra = [], []
+    with Lattice((n_fine,) * 3, "f32", "bgk", tau_f) as fine:
+        fine.set_forcing(ks, inputs.uniform_draws(4096, len(ks), 102), amp_f, 1.5, 1.0, phase_rule=True)
+        fine.init_equilibrium(rho, u)
+        del rho, u
+        for i in range(int(math.ceil(spinup))):
+            fine.step(t_large)
+            k = fine.global_sums()[4] / fine.n
+            print("# fine spin-up: %d large-eddy times, mean kinetic energy %.4e (u_rms %.4f)"
+                  % (i + 1, k, math.sqrt(2.0 * k / 3.0)), file=sys.stderr, flush=True)
+        t_spin = time.time() - t0
+        print("# fine %d^3 spun up over %d steps in %.1f s" % (n_fine, int(math.ceil(spinup)) * t_large, t_spin),
+              file=sys.stderr, flush=True)
+        with Lattice((n_coarse,) * 3, "f32", "bgk", tau_c) as coarse:
+            for i in range(n_snap):
+                fine.step(t_large // 2)
+                spectra.append(fine.energy_spectrum()[:n_bins(n_coarse)])
+                coarse.restrict_from(fine)
+                snaps.append(coarse.populations())
+        kin = fine.global_sums()[4] / fine.n
+    t_data = time.time() - t0
+    target = np.mean(spectra, axis=0)
+
+    def sched(ep):
+        return curriculum_steps(ep, start=start, grow=grow, every=every)
+    final = sched(epochs - 1)
+    forcing = (ks, inputs.uniform_draws(4096, len(ks), 103), amp_c, 1.5, 1.0, True)
+    runs = [Unroll((n_coarse,) * 3, tau_c, ("pop", f0), final, 20, target, kmin, kmax, forcing=forcing,
+                   loss="paper", omega=omega) for f0 in snaps]
+    p0 = inputs.mlp_params(32, seed=1)
+
+    def safe_loss(run, params):
+        try:
+            v = run.loss(params)
+        except NCOError:
+            return "unstable"
+        return v if np.isfinite(v) else "non-finite"
+    L0 = [safe_loss(run, p0) for run in runs]
+    t1 = time.time()
+    params, hist = train_batched(runs, p0, epochs, lr=lr, schedule=sched,
+                                 log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    t_epoch = (time.time() - t1) / max(1, epochs)
+    for run in runs:
+        run.nsteps = final
+    L1 = [safe_loss(run, params) for run in runs]
+    out = {"workload": "forced isotropic turbulence spectrum training, %d^3 BGK -> %d^3 NCO" % (n_fine, n_coarse),
+           "fine": {"n": n_fine, "tau": tau_f, "forcing_amplitude": amp_f, "large_eddy_steps": t_large,
+                    "spinup_large_eddy_times": spinup, "mean_kinetic_energy": float(kin),
+                    "seconds": t_data},
+           "coarse": {"n": n_coarse, "ratio": r, "tau": tau_c, "forcing_amplitude": amp_c},
+           "loss": {"kmin": kmin, "kmax": kmax, "omega": omega, "target": "fine spectrum averaged over the snapshots"},
+           "curriculum": {"start": start, "grow": grow, "every": every, "final": final},
+           "epochs": epochs, "lr": lr, "seconds_per_epoch": t_epoch,
+           "history": [h if np.isfinite(h) else None for h in hist], "samples": {}}
+    for i, (run, f0, l0, l1) in enumerate(zip(runs, snaps, L0, L1)):
+        other = {}
+        for kind in ("mrt", "bgk"):
+            with Lattice((n_coarse,) * 3, "f32", kind, tau_c) as lat:
+                if kind == "mrt":
+                    lat.set_rates([4.0 / 3.0] * 4)
+                lat.set_forcing(*forcing)
+                lat.init_populations(f0)
+                try:
+                    lat.step(final)
+                    E = lat.energy_spectrum()
+                    v = paper_spectrum_loss(E, target, kmin, kmax, omega, n_coarse // 2)[0]
+                    other[kind] = v if np.isfinite(v) else "non-finite"
+                except NCOError:
+                    other[kind] = "unstable"
+        out["samples"]["snapshot%d" % i] = {"untrained": l0, "trained": l1, "fixed_rate": other["mrt"],
+                                            "bgk": other["bgk"]}
+        run.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--tgv-dissipation", default="",
@@ -403,6 +511,13 @@ def main():
     ap.add_argument("--net", default="32,2,tanh,f32_mfma", help="width,depth,activation,arithmetic of --tgv-training")
     ap.add_argument("--paper-grid", action="store_true",
                     help="--tgv-training over the paper's case table (cube sizes per Mach number, every Re)")
+    ap.add_argument("--spectrum-training", default="",
+                    help="instead of the benchmark: FINE,COARSE[,TAU_FINE[,AMPLITUDE]] (e.g. 256,32,0.6), the "
+                         "forced-turbulence spectrum training at those grid sizes; with --snapshots, --epochs, "
+                         "--lr, --curriculum")
+    ap.add_argument("--snapshots", type=int, default=8)
+    ap.add_argument("--curriculum", default="200,200,10",
+                    help="START,GROW,EVERY of the --spectrum-training unroll curriculum (coarse steps)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
@@ -427,6 +542,17 @@ def main():
         tgv_training([int(x) for x in args.tgv_training.split(",")], [float(x) for x in args.re.split(",")],
                      mas, args.ref_cube, args.epochs, args.lr, width=int(w), depth=int(d), act=a, mlp=m,
                      grid=PAPER_TGV_GRID if args.paper_grid else None)
+        return
+    if args.spectrum_training:
+        f = args.spectrum_training.split(",")
+        start, grow, every = (int(x) for x in args.curriculum.split(","))
+        extra = {}
+        if len(f) > 2:
+            extra["tau_f"] = float(f[2])
+        if len(f) > 3:
+            extra["amp_f"] = float(f[3])
+        spectrum_training(int(f[0]), int(f[1]), args.snapshots, args.epochs, args.lr, start=start, grow=grow,
+                          every=every, **extra)
         return
     if args.precision_horizon > 0:
         precision_horizon(args.n, args.precision_horizon, 100, args.f64_steps)

@@ -256,12 +256,14 @@ def train(unrolls, params0, epochs, lr=1e-3, log=None, schedule=None):
     return p.detach().numpy().copy(), history
 
 
-def train_batched(unrolls, params0, epochs, lr=1e-3, log=None):
+def train_batched(unrolls, params0, epochs, lr=1e-3, log=None, schedule=None):
     """Adam with one step per epoch on the mean loss of all samples.  The
     samples' recorded runs and reverse sweeps go concurrently, one host
     thread per sample, each lattice on its own stream (the library's calls
     on different lattices are independent and release the interpreter
     lock), so that small lattices share the device instead of queueing.
+    schedule: None, or a function epoch -> unroll length set on every sample
+    before that epoch (the curriculum of Sec. "Learning Task").
     Returns (params, mean loss per epoch)."""
     from concurrent.futures import ThreadPoolExecutor
 
@@ -271,6 +273,9 @@ def train_batched(unrolls, params0, epochs, lr=1e-3, log=None):
     history = []
     with ThreadPoolExecutor(max_workers=len(unrolls)) as pool:
         for ep in range(epochs):
+            if schedule is not None:
+                for u in unrolls:
+                    u.nsteps = int(schedule(ep))
             x = p.detach().numpy().copy()
             res = list(pool.map(lambda u: _loss_and_grad_or_none(u, x), unrolls))
             # A sample whose run has blown up (non-finite loss or gradient)

@@ -30,3 +30,30 @@ def test_paper_loss_value_and_gradient():
 
 def test_curriculum_schedule():
     assert [curriculum_steps(e) for e in (0, 9, 10, 19, 20, 89)] == [200, 200, 400, 400, 600, 1800]
+
+
+def test_train_batched_applies_the_schedule_and_skips_failed_samples():
+    """train_batched sets every sample's unroll length from the schedule
+    before each epoch, averages the gradients of the samples that returned a
+    finite loss, and steps Adam on them (CPU, stand-in samples whose loss is
+    a quadratic in the parameters)."""
+    from paper_2412_08229_amd.training import train_batched
+
+    class Quadratic:
+        def __init__(self, centre, fail_at=None):
+            self.centre, self.fail_at, self.nsteps, self.seen = np.asarray(centre, float), fail_at, 0, []
+
+        def loss_and_grad(self, p):
+            self.seen.append(self.nsteps)
+            if self.fail_at is not None and self.nsteps == self.fail_at:
+                return float("nan"), np.zeros_like(p), None
+            d = p - self.centre
+            return float(d @ d), 2.0 * d, None
+
+    runs = [Quadratic([1.0, -1.0]), Quadratic([3.0, 1.0], fail_at=40)]
+    p, hist = train_batched(runs, np.zeros(2), 6, lr=0.5,
+                            schedule=lambda ep: curriculum_steps(ep, start=20, grow=20, every=2))
+    assert runs[0].seen == [20, 20, 40, 40, 60, 60] and runs[1].seen == runs[0].seen
+    assert len(hist) == 6 and all(np.isfinite(hist))
+    # Adam moves towards the mean of the centres, (2, 0).
+    assert np.linalg.norm(p - np.array([2.0, 0.0])) < np.linalg.norm(np.array([2.0, 0.0]))
