@@ -395,8 +395,10 @@ def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-
     ``spinup`` large-eddy times, n_snap snapshots half a large-eddy time
     apart are restricted by acoustic scaling to n_coarse^3 (tau_c = 1/2 +
     (tau_f - 1/2) / r); each is a sample whose coarse NCO run is forced by
-    the same rule (amplitude x r^2: the force per step grows with the time
-    step and F(k) enters squared) and scored by the paper's loss (squared
+    the same rule, amplitude x r: the phases are redrawn every step and the
+    rule leaves no correlation with u, so a step injects |F|^2 / 2, in
+    proportion to the amplitude, and one coarse step must inject what r fine
+    steps do.  The loss is the paper's (squared
     spectrum gap over kmin <= k <= kmax plus omega E(N/2)) against the fine
     run's spectrum averaged over the snapshots.  Adam over the samples with
     the unroll curriculum (start steps, grow more every ``every`` epochs).
@@ -412,7 +414,7 @@ def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-
     if r * n_coarse != n_fine:
         raise ValueError("the fine extent must be a multiple of the coarse one")
     tau_c = 0.5 + (tau_f - 0.5) / r
-    amp_c = amp_f * r * r
+    amp_c = amp_f * r
     ks = inputs.forcing_half_modes(2.0)
     t_large = int(round(n_fine / (2.0 * math.pi * 1.5) / urms))     # large-eddy time in fine steps
     t0 = time.time()

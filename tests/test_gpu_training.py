@@ -219,8 +219,10 @@ def test_paper_spectrum_training_pipeline():
     run (fine) forced with Alvelius' velocity-dependent phase, restricted by
     acoustic scaling to 16^3 (coarse, tau_c = 1/2 + (tau_f - 1/2) / 2); the
     coarse NCO runs from the restricted state, forced by the same rule (the
-    force per step doubles when the time step does, so the amplitude of
-    F(k), which enters squared, grows 4x), under the paper's loss (squared
+    phases are redrawn every step and the rule leaves no correlation with u,
+    so a step injects |F|^2 / 2, in proportion to the amplitude of F(k): one
+    coarse step must inject what two fine steps do, amplitude x2), under the
+    paper's loss (squared
     spectrum gap over 2 <= k <= 6 plus 20 E(8); target: the fine spectrum at
     the restriction time) with the unroll curriculum (20 steps, 20 more every
     3 epochs).  The gradient runs through the phase rule.  Training lowers
@@ -243,7 +245,7 @@ def test_paper_spectrum_training_pipeline():
         return curriculum_steps(ep, start=20, grow=20, every=3)
     epochs = 9
     run = Unroll((nc,) * 3, tau_c, ("pop", f0), sched(0), 10, target, 2, 6, loss="paper", omega=20.0,
-                 forcing=(ks, draws, 4.0 * amp, kf, cw, True))
+                 forcing=(ks, draws, 2.0 * amp, kf, cw, True))
     p0 = inputs.mlp_params(32, 1)
     run.nsteps = sched(epochs - 1)
     L_untrained = run.loss(p0)
