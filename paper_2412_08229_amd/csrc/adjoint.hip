@@ -486,64 +486,93 @@ __global__ __launch_bounds__(256) void k_add_energy_grad(const typename Codec<S>
 //     g_a = sum_i lambda_i w_i (3 c_ia + 9 (c_i . v) c_ia / rho) - 3 v_a / rho sum_i lambda_i w_i,
 // v = j + F; then per block and forced mode the partial sums of
 // (g cos(k.x), -g sin(k.x)), six doubles at partial[(6 m + q) nblocks + block].
+// A thread takes FA_NPT nodes (256 apart) and the modes go in chunks of
+// FA_CHUNK, one block reduction per chunk.
+constexpr int FA_NPT = 4, FA_CHUNK = 8, FA_BLOCK_NODES = 256 * FA_NPT;
+
 template <int S>
 __global__ __launch_bounds__(256) void k_force_adj_partials(const typename Codec<S>::store_t* __restrict__ xin,
                                                             const float* __restrict__ lam, StepArgs a,
                                                             double* __restrict__ partial) {
-    __shared__ double part[6][4];
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    double g[3] = {0.0, 0.0, 0.0};
-    NodeIdx p = {0, 0, 0};
-    if (idx < a.n) {
-        p = node_of(idx, a.nx, a.ny);
-        typename Codec<S>::real f[Q];
-        pull<S>(xin, a, p, f);
-        double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    __shared__ double part[6 * FA_CHUNK][4];
+    double g[FA_NPT][3];
+    NodePhasors ph[FA_NPT];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double v = (double)f[i];
-            rho += v;
-            j[0] += cx_of(i) * v;
-            j[1] += cy_of(i) * v;
-            j[2] += cz_of(i) * v;
+    for (int j = 0; j < FA_NPT; ++j) {
+        const int idx = blockIdx.x * FA_BLOCK_NODES + j * 256 + threadIdx.x;
+        g[j][0] = g[j][1] = g[j][2] = 0.0;
+        ph[j] = node_phasors(0, 0, 0, a.nx, a.ny, a.nz);
+        if (idx < a.n) {
+            const NodeIdx p = node_of(idx, a.nx, a.ny);
+            ph[j] = node_phasors(p.x, p.y, p.z, a.nx, a.ny, a.nz);
+            typename Codec<S>::real f[Q];
+            pull<S>(xin, a, p, f);
+            double rho = 0.0, jm[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double v = (double)f[i];
+                rho += v;
+                jm[0] += cx_of(i) * v;
+                jm[1] += cy_of(i) * v;
+                jm[2] += cz_of(i) * v;
+            }
+            double F[3];
+            force_at(a, p.x, p.y, p.z, F[0], F[1], F[2]);
+            const double v[3] = {jm[0] + F[0], jm[1] + F[1], jm[2] + F[2]};
+            const double inv_rho = 1.0 / rho;
+            double s0 = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double lw = (double)lam[(size_t)i * a.n + idx] * weight_of(i);
+                const double cv = cx_of(i) * v[0] + cy_of(i) * v[1] + cz_of(i) * v[2];
+                const double t = lw * (3.0 + 9.0 * cv * inv_rho);
+                g[j][0] += cx_of(i) * t;
+                g[j][1] += cy_of(i) * t;
+                g[j][2] += cz_of(i) * t;
+                s0 += lw;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g[j][c] -= 3.0 * v[c] * inv_rho * s0;
         }
-        double F[3];
-        force_at(a, p.x, p.y, p.z, F[0], F[1], F[2]);
-        const double v[3] = {j[0] + F[0], j[1] + F[1], j[2] + F[2]};
-        const double inv_rho = 1.0 / rho;
-        double s0 = 0.0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double lw = (double)lam[(size_t)i * a.n + idx] * weight_of(i);
-            const double cv = cx_of(i) * v[0] + cy_of(i) * v[1] + cz_of(i) * v[2];
-            const double t = lw * (3.0 + 9.0 * cv * inv_rho);
-            g[0] += cx_of(i) * t;
-            g[1] += cy_of(i) * t;
-            g[2] += cz_of(i) * t;
-            s0 += lw;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g[c] -= 3.0 * v[c] * inv_rho * s0;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int m = 0; m < a.n_modes; ++m) {
-        const int* k = a.fk + 3 * m;
-        // Phase as a fraction of a turn, reduced exactly in integers.
-        const long px = ((long)k[0] * p.x) % a.nx, py = ((long)k[1] * p.y) % a.ny, pz = ((long)k[2] * p.z) % a.nz;
-        double sn, cs;
-        sincospi(2.0 * ((double)px / a.nx + (double)py / a.ny + (double)pz / a.nz), &sn, &cs);
-        double q6[6] = {g[0] * cs, -g[0] * sn, g[1] * cs, -g[1] * sn, g[2] * cs, -g[2] * sn};
+    for (int m0 = 0; m0 < a.n_modes; m0 += FA_CHUNK) {
+        double q6[FA_CHUNK][6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q)
+        for (int c = 0; c < FA_CHUNK; ++c) {
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) q6[q] += __shfl_down(q6[q], off, 64);
+            for (int q = 0; q < 6; ++q) q6[c][q] = 0.0;
+            const int m = m0 + c;
+            if (m < a.n_modes) {
+                const int* k = a.fk + 3 * m;
+#pragma unroll
+                for (int j = 0; j < FA_NPT; ++j) {
+                    const Phasor e = mode_phase(k, ph[j]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        q6[c][2 * d] += g[j][d] * e.c;
+                        q6[c][2 * d + 1] -= g[j][d] * e.s;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < FA_CHUNK; ++c)
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) q6[c][q] += __shfl_down(q6[c][q], off, 64);
         if (lane == 0)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) part[q][wave] = q6[q];
+            for (int c = 0; c < FA_CHUNK; ++c)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) part[6 * c + q][wave] = q6[c][q];
         __syncthreads();
-        if (threadIdx.x < 6) {
-            const int q = threadIdx.x;
-            partial[(size_t)(6 * m + q) * gridDim.x + blockIdx.x] = part[q][0] + part[q][1] + part[q][2] + part[q][3];
+        if (threadIdx.x < 6 * FA_CHUNK) {
+            const int e = threadIdx.x, m = m0 + e / 6;
+            if (m < a.n_modes)
+                partial[(size_t)(6 * m0 + e) * gridDim.x + blockIdx.x] =
+                    part[e][0] + part[e][1] + part[e][2] + part[e][3];
         }
         __syncthreads();
     }
@@ -623,16 +652,14 @@ __global__ __launch_bounds__(256) void k_add_velocity_grad(const typename Codec<
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.n) return;
     const NodeIdx p = node_of(idx, a.nx, a.ny);
+    const NodePhasors ph = node_phasors(p.x, p.y, p.z, a.nx, a.ny, a.nz);
     double du[3] = {0.0, 0.0, 0.0};
     for (int m = 0; m < a.n_modes; ++m) {
-        const int* k = a.fk + 3 * m;
-        const long px = ((long)k[0] * p.x) % a.nx, py = ((long)k[1] * p.y) % a.ny, pz = ((long)k[2] * p.z) % a.nz;
-        double sn, cs;
-        sincospi(2.0 * ((double)px / a.nx + (double)py / a.ny + (double)pz / a.nz), &sn, &cs);
+        const Phasor e = mode_phase(a.fk + 3 * m, ph);
         const double* d = duhat + 6 * m;
-        du[0] += d[0] * cs - d[1] * sn;
-        du[1] += d[2] * cs - d[3] * sn;
-        du[2] += d[4] * cs - d[5] * sn;
+        du[0] += d[0] * e.c - d[1] * e.s;
+        du[1] += d[2] * e.c - d[3] * e.s;
+        du[2] += d[4] * e.c - d[5] * e.s;
     }
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -762,13 +789,13 @@ hipError_t launch_force_phase_adjoint(int storage, const void* x, const float* l
                                       const StepArgs& a, double* partial, const double* basis, const double* draw,
                                       const double* uhat, double* duhat, hipStream_t st) {
     if (a.n_modes < 1 || !a.fk || !a.fhat) return hipErrorInvalidValue;
-    const dim3 grid((a.n + 255) / 256), block(256);
+    const dim3 grid((a.n + 255) / 256), pgrid((a.n + FA_BLOCK_NODES - 1) / FA_BLOCK_NODES), block(256);
 #define FPA_CASE(SS)                                                                                           \
     case SS: {                                                                                                 \
         const auto* xs = static_cast<const typename Codec<SS>::store_t*>(x);                                   \
-        hipLaunchKernelGGL(k_force_adj_partials<SS>, grid, block, 0, st, xs, lam_next, a, partial);            \
+        hipLaunchKernelGGL(k_force_adj_partials<SS>, pgrid, block, 0, st, xs, lam_next, a, partial);           \
         if (hipError_t e = hipGetLastError()) return e;                                                        \
-        hipLaunchKernelGGL(k_force_phase_adj, dim3(a.n_modes), block, 0, st, partial, (int)grid.x, 1.0 / a.n,  \
+        hipLaunchKernelGGL(k_force_phase_adj, dim3(a.n_modes), block, 0, st, partial, (int)pgrid.x, 1.0 / a.n, \
                            basis, draw, a.fhat, uhat, duhat);                                                  \
         if (hipError_t e = hipGetLastError()) return e;                                                        \
         hipLaunchKernelGGL(k_add_velocity_grad<SS>, grid, block, 0, st, xs, lam_out, a,                        \

@@ -31,21 +31,59 @@ struct StepArgs {
     const double* fhat;      // [n_modes][6] Re/Im of Fhat_x, Fhat_y, Fhat_z for this step
 };
 
+// Phases of the spectral modes at a node, e^{i 2 pi (k_x x / nx + k_y y / ny
+// + k_z z / nz)}, as the product over the axes of integer powers of the
+// node's axis phasors e^{i 2 pi x / nx} (one sincospi of an exact fraction
+// per axis; binary powering, so a wavevector component k costs about
+// log2 |k| complex products).
+struct Phasor {
+    double c, s;
+};
+
+__device__ __forceinline__ Phasor phasor_mul(Phasor a, Phasor b) {
+    return Phasor{a.c * b.c - a.s * b.s, a.c * b.s + a.s * b.c};
+}
+
+__device__ __forceinline__ Phasor axis_phasor(int x, int n) {
+    Phasor p;
+    sincospi(2.0 * (double)x / (double)n, &p.s, &p.c);
+    return p;
+}
+
+__device__ __forceinline__ Phasor phasor_pow(Phasor b, int k) {
+    Phasor r{1.0, 0.0};
+    Phasor p = k < 0 ? Phasor{b.c, -b.s} : b;
+    for (int e = k < 0 ? -k : k; e; e >>= 1) {
+        if (e & 1) r = phasor_mul(r, p);
+        if (e > 1) p = phasor_mul(p, p);
+    }
+    return r;
+}
+
+struct NodePhasors {
+    Phasor x, y, z;
+};
+
+__device__ __forceinline__ NodePhasors node_phasors(int x, int y, int z, int nx, int ny, int nz) {
+    return NodePhasors{axis_phasor(x, nx), axis_phasor(y, ny), axis_phasor(z, nz)};
+}
+
+// e^{i k.x} for wavevector k (3 ints) at the node of `b`.
+__device__ __forceinline__ Phasor mode_phase(const int* k, const NodePhasors& b) {
+    return phasor_mul(phasor_mul(phasor_pow(b.x, k[0]), phasor_pow(b.y, k[1])), phasor_pow(b.z, k[2]));
+}
+
 // Force density at node (x, y, z) for the current step (float64 synthesis).
 __device__ __forceinline__ void force_at(const StepArgs& a, int x, int y, int z, double& Fx, double& Fy,
                                          double& Fz) {
     Fx = Fy = Fz = 0.0;
+    const NodePhasors b = node_phasors(x, y, z, a.nx, a.ny, a.nz);
     for (int m = 0; m < a.n_modes; ++m) {
-        const int* k = a.fk + 3 * m;
-        // Phase as a fraction of a turn, reduced exactly in integers.
-        const long px = ((long)k[0] * x) % a.nx, py = ((long)k[1] * y) % a.ny, pz = ((long)k[2] * z) % a.nz;
-        const double turn = (double)px / a.nx + (double)py / a.ny + (double)pz / a.nz;
-        double s, c;
-        sincospi(2.0 * turn, &s, &c);
+        const Phasor e = mode_phase(a.fk + 3 * m, b);
         const double* fh = a.fhat + 6 * m;
-        Fx += 2.0 * (fh[0] * c - fh[1] * s);
-        Fy += 2.0 * (fh[2] * c - fh[3] * s);
-        Fz += 2.0 * (fh[4] * c - fh[5] * s);
+        Fx += 2.0 * (fh[0] * e.c - fh[1] * e.s);
+        Fy += 2.0 * (fh[2] * e.c - fh[3] * e.s);
+        Fz += 2.0 * (fh[4] * e.c - fh[5] * e.s);
     }
 }
 

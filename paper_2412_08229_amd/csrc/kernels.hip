@@ -286,41 +286,72 @@ __global__ __launch_bounds__(256) void k_sums_partial(const typename Codec<S>::s
 // Velocity-dependent forcing phase (Alvelius' rule, Sec. "Training Data -
 // Forced Isotropic Turbulence").  Stage 1: per block and forced mode m, the
 // partial sums of u(x) exp(-i k_m.x) over the block's nodes, six doubles
-// (Re, Im of u_x, u_y, u_z), at partial[(6 m + s) nblocks + block].
+// (Re, Im of u_x, u_y, u_z), at partial[(6 m + s) nblocks + block].  A
+// thread takes MODE_NPT nodes (coalesced, 256 apart) and keeps their
+// velocities in registers; the modes go in chunks of MODE_CHUNK, one block
+// reduction per chunk.
+constexpr int MODE_NPT = 8, MODE_CHUNK = 8, MODE_BLOCK_NODES = 256 * MODE_NPT;
+inline int mode_partial_blocks(int n) { return (n + MODE_BLOCK_NODES - 1) / MODE_BLOCK_NODES; }
+
 template <int S>
 __global__ __launch_bounds__(256) void k_mode_partials(const typename Codec<S>::store_t* __restrict__ f, int n,
                                                        int nx, int ny, int nz, const int* __restrict__ fk,
                                                        int n_modes, double* __restrict__ partial) {
-    __shared__ double part[6][4];
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    double ux = 0.0, uy = 0.0, uz = 0.0;
-    int x = 0, y = 0, z = 0;
-    if (idx < n) {
-        double r;
-        macro_double<S>(f, n, idx, r, ux, uy, uz);
-        x = idx % nx;
-        y = (idx / nx) % ny;
-        z = idx / (nx * ny);
-    }
+    __shared__ double part[6 * MODE_CHUNK][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int m = 0; m < n_modes; ++m) {
-        const int* k = fk + 3 * m;
-        // Phase as a fraction of a turn, reduced exactly in integers.
-        const long px = ((long)k[0] * x) % nx, py = ((long)k[1] * y) % ny, pz = ((long)k[2] * z) % nz;
-        double sn, cs;
-        sincospi(2.0 * ((double)px / nx + (double)py / ny + (double)pz / nz), &sn, &cs);
-        double v[6] = {ux * cs, -ux * sn, uy * cs, -uy * sn, uz * cs, -uz * sn};
+    double u[MODE_NPT][3];
+    NodePhasors ph[MODE_NPT];
 #pragma unroll
-        for (int q = 0; q < 6; ++q)
+    for (int j = 0; j < MODE_NPT; ++j) {
+        const int idx = blockIdx.x * MODE_BLOCK_NODES + j * 256 + threadIdx.x;
+        u[j][0] = u[j][1] = u[j][2] = 0.0;
+        int x = 0, y = 0, z = 0;
+        if (idx < n) {
+            double r;
+            macro_double<S>(f, n, idx, r, u[j][0], u[j][1], u[j][2]);
+            x = idx % nx;
+            y = (idx / nx) % ny;
+            z = idx / (nx * ny);
+        }
+        ph[j] = node_phasors(x, y, z, nx, ny, nz);
+    }
+    for (int m0 = 0; m0 < n_modes; m0 += MODE_CHUNK) {
+        double v[MODE_CHUNK][6];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+        for (int c = 0; c < MODE_CHUNK; ++c) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[c][q] = 0.0;
+            const int m = m0 + c;
+            if (m < n_modes) {
+                const int* k = fk + 3 * m;
+#pragma unroll
+                for (int j = 0; j < MODE_NPT; ++j) {
+                    const Phasor e = mode_phase(k, ph[j]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        v[c][2 * d] += u[j][d] * e.c;
+                        v[c][2 * d + 1] -= u[j][d] * e.s;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < MODE_CHUNK; ++c)
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v[c][q] += __shfl_down(v[c][q], off, 64);
         if (lane == 0)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) part[q][wave] = v[q];
+            for (int c = 0; c < MODE_CHUNK; ++c)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) part[6 * c + q][wave] = v[c][q];
         __syncthreads();
-        if (threadIdx.x < 6) {
-            const int q = threadIdx.x;
-            partial[(size_t)(6 * m + q) * gridDim.x + blockIdx.x] = part[q][0] + part[q][1] + part[q][2] + part[q][3];
+        if (threadIdx.x < 6 * MODE_CHUNK) {
+            const int e = threadIdx.x, m = m0 + e / 6;
+            if (m < n_modes)
+                partial[(size_t)(6 * m0 + e) * gridDim.x + blockIdx.x] =
+                    part[e][0] + part[e][1] + part[e][2] + part[e][3];
         }
         __syncthreads();
     }
@@ -592,7 +623,7 @@ hipError_t launch_global_sums(int storage, const void* f, double* partial, doubl
 hipError_t launch_force_phase(int storage, const void* f, int n, int nx, int ny, int nz, const int* fk,
                               int n_modes, double* partial, const double* basis, const double* draw, double* fhat,
                               double* uhat, hipStream_t st) {
-    const int nb = nblocks(n);
+    const int nb = mode_partial_blocks(n);
     DISPATCH_STORAGE(storage, {
         hipLaunchKernelGGL(k_mode_partials<SS>, dim3(nb), dim3(256), 0, st,
                            static_cast<const typename Codec<SS>::store_t*>(f), n, nx, ny, nz, fk, n_modes, partial);

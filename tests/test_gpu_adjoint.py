@@ -183,23 +183,29 @@ def test_energy_trajectory_gradient_matches_oracle(mlp):
     assert rel < 2e-3 and relf < 2e-3
 
 
-@pytest.mark.parametrize("storage,kind,mlp,tol", [("f64", "bgk", "f32", 1e-13), ("f64", "nco", "f32", 1e-13),
-                                                  ("f32", "nco", "f32_mfma", 2e-6)])
-def test_velocity_dependent_phase_matches_oracle(storage, kind, mlp, tol):
+@pytest.mark.parametrize("shape,storage,kind,mlp,tol", [((12, 12, 12), "f64", "bgk", "f32", 1e-13),
+                                                        ((12, 12, 12), "f64", "nco", "f32", 1e-13),
+                                                        ((12, 12, 12), "f32", "nco", "f32_mfma", 2e-6),
+                                                        ((17, 13, 11), "f64", "bgk", "f32", 1e-13)])
+def test_velocity_dependent_phase_matches_oracle(shape, storage, kind, mlp, tol):
     """Alvelius' velocity-dependent theta1 (nco_set_forcing_ex): each step's
     coefficients come from the velocity of the state it starts from; the
     GPU run equals the oracle's (coefficients_state, then the forced step)
-    on a 12^3 lattice (ragged against the 256-node blocks), and differs from
-    the run with the drawn theta1."""
-    n, T, amp = 12, 5, 1e-4
+    on a 12^3 lattice (ragged against the 256-node blocks) and a 17x13x11
+    one (2431 nodes: two blocks of the 2048-node mode sums, the second
+    partial), and differs from the run with the drawn theta1."""
+    T, amp = 5, 1e-4
     ks, draws = _forcing(4, seed=61)
-    _, u = inputs.turbulence(n, seed=62, k0=2.0, urms=0.05)
-    rho = np.ones((n, n, n))
+    if len(set(shape)) == 1:
+        _, u = inputs.turbulence(shape[0], seed=62, k0=2.0, urms=0.05)
+    else:
+        _, u = inputs.random_velocity(shape, seed=62, amp=0.05)
+    rho = np.ones(shape)
     params = inputs.mlp_params(32, 63)
     layers = collision.unpack_params(params, 32)
     runs = {}
     for rule in (True, False):
-        with Lattice((n, n, n), storage, kind, 0.6) as lat:
+        with Lattice(shape, storage, kind, 0.6) as lat:
             if kind == "nco":
                 lat.set_net_weights(params, 32, "tanh", mlp)
             lat.set_forcing(ks, draws, amp, KF, CW, phase_rule=rule)
@@ -212,7 +218,7 @@ def test_velocity_dependent_phase_matches_oracle(storage, kind, mlp, tol):
     for t in range(T):
         _, ut = collision.macroscopic(f)
         fh = forcing.coefficients_state(ks, draws[t % len(draws)], amp, KF, CW, ut)
-        f = step.step(f, op, force=forcing.field(ks, fh, (n, n, n)))
+        f = step.step(f, op, force=forcing.field(ks, fh, shape))
     err = np.abs(runs[True] - f).max()
     print("phase rule %s/%s/%s: max err %.3e, vs drawn phase %.3e"
           % (storage, kind, mlp, err, np.abs(runs[True] - runs[False]).max()))
@@ -221,7 +227,8 @@ def test_velocity_dependent_phase_matches_oracle(storage, kind, mlp, tol):
 
 
 @pytest.mark.parametrize("shape,mlp,loss", [((8, 8, 8), "f32_mfma", "population"), ((7, 6, 9), "f32", "population"),
-                                             ((8, 8, 8), "f32_mfma", "spectrum"), ((9, 9, 9), "f32", "spectrum")])
+                                             ((8, 8, 8), "f32_mfma", "spectrum"), ((9, 9, 9), "f32", "spectrum"),
+                                             ((13, 14, 15), "f32_mfma", "population")])
 def test_velocity_dependent_phase_gradient_matches_oracle(shape, mlp, loss):
     """Reverse mode through Alvelius' velocity-dependent theta1: the force of
     each step depends on the state it starts from, and the GPU gradient
@@ -229,7 +236,8 @@ def test_velocity_dependent_phase_gradient_matches_oracle(shape, mlp, loss):
     recording starts 2 steps into a forcing period of 3 draws and spans 5
     steps in checkpoint segments of 2 (the recomputed segments replay the
     kept coefficients); the lattices of 378 and 729 nodes end in a partial
-    block.  Two backward passes agree bitwise, and the gradient with the same
+    block, and the one of 2730 nodes spans two blocks of the 1024-node mode
+    sums of the reverse pass, the second partial.  Two backward passes agree bitwise, and the gradient with the same
     forces held fixed is far from both."""
     width, tau, T, K, amp, t0 = 32, 0.58, 5, 2, 1e-4, 2
     n_nodes = int(np.prod(shape))
