@@ -74,16 +74,24 @@ __device__ __forceinline__ Phasor mode_phase(const int* k, const NodePhasors& b)
 }
 
 // Force density at node (x, y, z) for the current step (float64 synthesis).
+// Inlined into every stream-collide kernel, so it keeps to per-mode
+// arithmetic without loops (the axis-phasor form above, with its powering
+// loops, raised the scalar-register pressure of the vector-unit network
+// kernels into spills).
 __device__ __forceinline__ void force_at(const StepArgs& a, int x, int y, int z, double& Fx, double& Fy,
                                          double& Fz) {
     Fx = Fy = Fz = 0.0;
-    const NodePhasors b = node_phasors(x, y, z, a.nx, a.ny, a.nz);
     for (int m = 0; m < a.n_modes; ++m) {
-        const Phasor e = mode_phase(a.fk + 3 * m, b);
+        const int* k = a.fk + 3 * m;
+        // Phase as a fraction of a turn, reduced exactly in integers.
+        const long px = ((long)k[0] * x) % a.nx, py = ((long)k[1] * y) % a.ny, pz = ((long)k[2] * z) % a.nz;
+        const double turn = (double)px / a.nx + (double)py / a.ny + (double)pz / a.nz;
+        double s, c;
+        sincospi(2.0 * turn, &s, &c);
         const double* fh = a.fhat + 6 * m;
-        Fx += 2.0 * (fh[0] * e.c - fh[1] * e.s);
-        Fy += 2.0 * (fh[2] * e.c - fh[3] * e.s);
-        Fz += 2.0 * (fh[4] * e.c - fh[5] * e.s);
+        Fx += 2.0 * (fh[0] * c - fh[1] * s);
+        Fy += 2.0 * (fh[2] * c - fh[3] * s);
+        Fz += 2.0 * (fh[4] * c - fh[5] * s);
     }
 }
 
