@@ -450,20 +450,25 @@ def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-
                    loss="paper", omega=omega) for f0 in snaps]
     p0 = inputs.mlp_params(32, seed=1)
 
-    def safe_loss(run, params):
+    spec = {"untrained": [], "trained": [], "fixed_rate": [], "bgk": []}
+
+    def safe_loss(run, params, key):
         try:
             v = run.loss(params)
         except NCOError:
             return "unstable"
-        return v if np.isfinite(v) else "non-finite"
-    L0 = [safe_loss(run, p0) for run in runs]
+        if not np.isfinite(v):
+            return "non-finite"
+        spec[key].append(run.lat.energy_spectrum())
+        return v
+    L0 = [safe_loss(run, p0, "untrained") for run in runs]
     t1 = time.time()
     params, hist = train_batched(runs, p0, epochs, lr=lr, schedule=sched,
                                  log=lambda m: print("# " + m, file=sys.stderr, flush=True))
     t_epoch = (time.time() - t1) / max(1, epochs)
     for run in runs:
         run.nsteps = final
-    L1 = [safe_loss(run, params) for run in runs]
+    L1 = [safe_loss(run, params, "trained") for run in runs]
     out = {"workload": "forced isotropic turbulence spectrum training, %d^3 BGK -> %d^3 NCO" % (n_fine, n_coarse),
            "fine": {"n": n_fine, "tau": tau_f, "forcing_amplitude": amp_f, "large_eddy_steps": t_large,
                     "spinup_large_eddy_times": spinup, "mean_kinetic_energy": float(kin),
@@ -486,11 +491,18 @@ def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-
                     E = lat.energy_spectrum()
                     v = paper_spectrum_loss(E, target, kmin, kmax, omega, n_coarse // 2)[0]
                     other[kind] = v if np.isfinite(v) else "non-finite"
+                    if np.isfinite(v):
+                        spec["fixed_rate" if kind == "mrt" else kind].append(E)
                 except NCOError:
                     other[kind] = "unstable"
         out["samples"]["snapshot%d" % i] = {"untrained": l0, "trained": l1, "fixed_rate": other["mrt"],
                                             "bgk": other["bgk"]}
         run.close()
+    # Energy spectra at the final unroll length, averaged over the snapshots
+    # each operator kept finite, next to the target (k = 0 .. N/2).
+    out["spectra"] = {"k": list(range(n_coarse // 2 + 1)), "target": [float(x) for x in target[:n_coarse // 2 + 1]]}
+    for key, es in spec.items():
+        out["spectra"][key] = [float(x) for x in np.mean(es, axis=0)[:n_coarse // 2 + 1]] if es else None
     print(json.dumps(out), flush=True)
 
 
