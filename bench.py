@@ -384,7 +384,7 @@ def tgv_training(cubes, res, mas, ref_cube, epochs, lr, t_end=15.0, samples=100,
     print(json.dumps(out), flush=True)
 
 
-def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-6, urms=0.05, spinup=5.0,
+def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-6, urms=0.05, spinup=20.0,
                       start=200, grow=200, every=10, kmin=4, kmax=10, omega=20.0):
     """The spectrum training of Sec. "Learning Task" at the paper's grid
     sizes.  A forced n_fine^3 BGK run stands in for the DNS: Alvelius
@@ -526,7 +526,8 @@ def main():
     ap.add_argument("--paper-grid", action="store_true",
                     help="--tgv-training over the paper's case table (cube sizes per Mach number, every Re)")
     ap.add_argument("--spectrum-training", default="",
-                    help="instead of the benchmark: FINE,COARSE[,TAU_FINE[,AMPLITUDE]] (e.g. 256,32,0.6), the "
+                    help="instead of the benchmark: FINE,COARSE[,TAU_FINE[,AMPLITUDE[,SPINUP]]] (e.g. 256,32,0.6; "
+                         "SPINUP in large-eddy times, default 20), the "
                          "forced-turbulence spectrum training at those grid sizes; with --snapshots, --epochs, "
                          "--lr, --curriculum")
     ap.add_argument("--snapshots", type=int, default=8)
@@ -565,6 +566,8 @@ def main():
             extra["tau_f"] = float(f[2])
         if len(f) > 3:
             extra["amp_f"] = float(f[3])
+        if len(f) > 4:
+            extra["spinup"] = float(f[4])
         spectrum_training(int(f[0]), int(f[1]), args.snapshots, args.epochs, args.lr, start=start, grow=grow,
                           every=every, **extra)
         return
