@@ -1,0 +1,37 @@
+"""The spectrum-training workflow of bench.py end to end at a small size:
+a forced 32^3 BGK run with the velocity-dependent phase, restricted to
+16^3, trained for a few epochs under the paper's loss with a curriculum;
+the JSON line carries every operator's loss per snapshot and the spectra."""
+import contextlib
+import io
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+
+def test_spectrum_training_workflow_small():
+    import bench
+    buf = io.StringIO()
+    with contextlib.redirect_stdout(buf):
+        bench.spectrum_training(32, 16, 2, 4, 1e-2, amp_f=2e-6, spinup=2.0, start=20, grow=20, every=2,
+                                kmin=2, kmax=6)
+    out = json.loads(buf.getvalue().strip().splitlines()[-1])
+    assert out["coarse"]["ratio"] == 2 and out["coarse"]["tau"] == pytest.approx(0.55)
+    assert out["curriculum"]["final"] == 40 and len(out["history"]) == 4
+    assert len(out["samples"]) == 2
+    for s in out["samples"].values():
+        for key in ("untrained", "trained", "fixed_rate", "bgk"):
+            assert isinstance(s[key], float) and np.isfinite(s[key]) and s[key] > 0.0
+    sp = out["spectra"]
+    assert sp["k"] == list(range(9)) and len(sp["target"]) == 9
+    assert all(sp[key] is not None and len(sp[key]) == 9 for key in ("untrained", "trained", "fixed_rate", "bgk"))
+    # Training does not make the loss worse on average at the final length.
+    assert np.mean([s["trained"] for s in out["samples"].values()]) <= \
+        1.05 * np.mean([s["untrained"] for s in out["samples"].values()])
