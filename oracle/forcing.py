@@ -8,8 +8,12 @@ For a wavevector k with |k| = kk the force coefficient is
     A_ran = (F(kk) / (2 pi kk^2))^(1/2) exp(i theta1) g_A(phi),
     B_ran = (F(kk) / (2 pi kk^2))^(1/2) exp(i theta2) g_B(phi),
     g_A = sin 2 phi, g_B = cos 2 phi, theta2 = theta1 + psi,
-    F(kk) = amplitude exp(-(kk - k_f)^2 / c),
-with phi uniform in [0, pi), psi and theta1 uniform in [0, 2 pi).
+    F(kk) = A exp(-(kk - k_f)^2 / c),
+with phi uniform in [0, pi), psi and theta1 uniform in [0, 2 pi).  The
+amplitude A follows from the power input P over the time step dt (the
+equation for A in the same section):
+    A = (P / dt) / int_{k_a}^{k_b} exp(-(k - k_f)^2 / c) dk
+(``amplitude_from_power``); the functions below also take A directly.
 
 Readings: the printed e1 = (k_x k_y, -k_x k_y, 0)/sqrt(k_x^2 + k_y^2) is not
 normal to k; the unit vector normal to k in the x-y plane,
@@ -17,11 +21,15 @@ e1 = (k_y, -k_x, 0)/sqrt(k_x^2 + k_y^2), is used, with e2 as printed; for
 k_x = k_y = 0, e1 = (1, 0, 0) and e2 = (0, 1, 0).  theta1 is drawn from the
 random numbers like phi and psi, so that the force is a known function of
 time; ``coefficients_state`` is the velocity-dependent rule itself, and
-``coefficients_state_vjp`` its reverse mode.  The amplitude A of F(kk) is given
-directly (lattice units) instead of through the power input.  The force
-field is real: one wavevector of each +-k pair carries F_hat and
-F(x) = sum 2 Re(F_hat(k) exp(i k.x)), x in [0, 2 pi)^3.
+``coefficients_state_vjp`` its reverse mode.  The force field is real: one
+wavevector of each +-k pair carries F_hat and
+F(x) = sum 2 Re(F_hat(k) exp(i k.x)), x in [0, 2 pi)^3.  F is the force per
+unit mass: a step of length dt changes the velocity by F dt (the lattice's
+own step has dt = 1).  k_a and k_b are the edges of the forced band of
+wavenumbers, the integral's limits.
 """
+import math
+
 import numpy as np
 
 
@@ -37,6 +45,33 @@ def basis(k):
     return e1, e2
 
 
+def spectrum(kk, amplitude, kf, c):
+    """Force density F(k) = A exp(-(k - k_f)^2 / c), the Gaussian of the
+    section's equation for F(k), at wavenumber magnitude kk."""
+    return amplitude * np.exp(-(np.asarray(kk, dtype=np.float64) - kf) ** 2 / c)
+
+
+def amplitude_from_power(power, dt, ka, kb, kf, c):
+    """Amplitude A of F(k) for a power input P over a time step dt: the
+    section's equation A = (P / dt) / int_{k_a}^{k_b} exp(-(k - k_f)^2 / c) dk,
+    with the Gaussian's integral in closed form,
+    sqrt(pi c) / 2 (erf((k_b - k_f) / sqrt c) - erf((k_a - k_f) / sqrt c))."""
+    sc = math.sqrt(c)
+    integral = 0.5 * math.sqrt(math.pi * c) * (math.erf((kb - kf) / sc) - math.erf((ka - kf) / sc))
+    return (power / dt) / integral
+
+
+def random_amplitudes(k, amplitude, kf, c, phi, psi, theta1):
+    """(A_ran, B_ran) of the wavevector k for arrays of the angles phi, psi
+    and theta1: (F(|k|) / (2 pi |k|^2))^(1/2) exp(i theta1) g_A(phi) and the
+    same with theta2 = theta1 + psi and g_B(phi)."""
+    kk = np.sqrt(float((np.asarray(k) ** 2).sum()))
+    mag = np.sqrt(spectrum(kk, amplitude, kf, c) / (2.0 * np.pi * kk * kk))
+    a = mag * np.exp(1j * theta1) * np.sin(2.0 * phi)
+    b = mag * np.exp(1j * (theta1 + psi)) * np.cos(2.0 * phi)
+    return a, b
+
+
 def coefficients(ks, draws, amplitude, kf, c):
     """F_hat for every step and mode: ks (n_modes, 3) integers, draws
     (n_steps, n_modes, 3) uniform in [0, 1) as (phi, psi, theta1) / range.
@@ -45,15 +80,9 @@ def coefficients(ks, draws, amplitude, kf, c):
     draws = np.asarray(draws, dtype=np.float64)
     out = np.zeros(draws.shape[:2] + (3,), dtype=np.complex128)
     for mi, k in enumerate(ks):
-        kk = np.sqrt(float((k * k).sum()))
         e1, e2 = basis(k)
-        Fk = amplitude * np.exp(-(kk - kf) ** 2 / c)
-        mag = np.sqrt(Fk / (2.0 * np.pi * kk * kk))
-        phi = np.pi * draws[:, mi, 0]
-        psi = 2.0 * np.pi * draws[:, mi, 1]
-        th1 = 2.0 * np.pi * draws[:, mi, 2]
-        A = mag * np.exp(1j * th1) * np.sin(2.0 * phi)
-        B = mag * np.exp(1j * (th1 + psi)) * np.cos(2.0 * phi)
+        A, B = random_amplitudes(k, amplitude, kf, c, np.pi * draws[:, mi, 0], 2.0 * np.pi * draws[:, mi, 1],
+                                 2.0 * np.pi * draws[:, mi, 2])
         out[:, mi, :] = A[:, None] * e1[None, :] + B[:, None] * e2[None, :]
     return out
 
@@ -94,13 +123,12 @@ def coefficients_state(ks, draw, amplitude, kf, c, u):
     uh = velocity_modes(ks, u)
     out = np.zeros((len(ks), 3), dtype=np.complex128)
     for mi, k in enumerate(ks):
-        kk = np.sqrt(float((k * k).sum()))
         e1, e2 = basis(k)
-        mag = np.sqrt(amplitude * np.exp(-(kk - kf) ** 2 / c) / (2.0 * np.pi * kk * kk))
         phi, psi = np.pi * draw[mi, 0], 2.0 * np.pi * draw[mi, 1]
         ga, gb = np.sin(2.0 * phi), np.cos(2.0 * phi)
         th1 = phase_rule(ga, gb, psi, uh[mi] @ e1, uh[mi] @ e2)
-        out[mi] = mag * (ga * np.exp(1j * th1) * e1 + gb * np.exp(1j * (th1 + psi)) * e2)
+        A, B = random_amplitudes(k, amplitude, kf, c, phi, psi, th1)
+        out[mi] = A * e1 + B * e2
     return out
 
 
@@ -120,15 +148,14 @@ def coefficients_state_vjp(ks, draw, amplitude, kf, c, u, dfhat):
     uh = velocity_modes(ks, u)
     du = np.zeros(u.shape)
     for mi, k in enumerate(ks):
-        kk = np.sqrt(float((k * k).sum()))
         e1, e2 = basis(k)
-        mag = np.sqrt(amplitude * np.exp(-(kk - kf) ** 2 / c) / (2.0 * np.pi * kk * kk))
         phi, psi = np.pi * draw[mi, 0], 2.0 * np.pi * draw[mi, 1]
         ga, gb = np.sin(2.0 * phi), np.cos(2.0 * phi)
         xi1, xi2 = uh[mi] @ e1, uh[mi] @ e2
         Z = ga * np.conj(xi1) + gb * np.exp(1j * psi) * np.conj(xi2)
         th1 = np.arctan2(Z.real, Z.imag)
-        fh = mag * (ga * np.exp(1j * th1) * e1 + gb * np.exp(1j * (th1 + psi)) * e2)
+        A, B = random_amplitudes(k, amplitude, kf, c, phi, psi, th1)
+        fh = A * e1 + B * e2
         d_th1 = float(np.sum(dfhat[mi].real * (1j * fh).real + dfhat[mi].imag * (1j * fh).imag))
         z2 = Z.real ** 2 + Z.imag ** 2
         if z2 == 0.0:

@@ -143,18 +143,19 @@ def n_params(width, depth=2, n_in=27, n_out=4):
     return sum(a * b + b for a, b in zip(sizes[:-1], sizes[1:]))
 
 
-def alvelius_modes(kmax=2.0):
-    """Integer wavevectors with 0 < |k| <= kmax, shape (n, 3) as (kx, ky, kz)."""
+def alvelius_modes(kmax=2.0, kmin=0.0):
+    """Integer wavevectors with kmin <= |k| <= kmax and k != 0, shape (n, 3) as
+    (kx, ky, kz)."""
     r = int(math.floor(kmax))
     ks = [(kx, ky, kz) for kz in range(-r, r + 1) for ky in range(-r, r + 1) for kx in range(-r, r + 1)
-          if 0 < kx * kx + ky * ky + kz * kz <= kmax * kmax]
+          if 0 < kx * kx + ky * ky + kz * kz <= kmax * kmax and kx * kx + ky * ky + kz * kz >= kmin * kmin]
     return np.array(ks, dtype=np.int64)
 
 
-def forcing_half_modes(kmax=2.0):
+def forcing_half_modes(kmax=2.0, kmin=0.0):
     """One wavevector of each +-k pair of ``alvelius_modes`` (the one whose
     first nonzero component, in the order z, y, x, is positive)."""
-    ks = alvelius_modes(kmax)
+    ks = alvelius_modes(kmax, kmin)
     keep = [(kz > 0) or (kz == 0 and ky > 0) or (kz == 0 and ky == 0 and kx > 0) for kx, ky, kz in ks]
     return ks[np.array(keep)]
 

@@ -1,7 +1,15 @@
 """Oracle pins of the spectral forcing (Sec. "Training Data - Forced
 Isotropic Turbulence"): the force is solenoidal, its basis orthonormal, the
-synthesised field real with the prescribed Fourier content."""
+synthesised field real with the prescribed Fourier content; every mode
+carries the force density F(|k|) / (2 pi |k|^2) of the section's equations
+for A_ran and B_ran, split between e1 and e2 as tan 2 phi with the phase
+offset psi; the amplitude A of F(k) follows from the power input, and the
+force injects that power."""
+import math
+
 import numpy as np
+import pytest
+from scipy import integrate
 
 from oracle import forcing
 from paper_2412_08229_amd import inputs
@@ -115,3 +123,189 @@ def test_phase_rule_vjp_matches_finite_differences():
         fd = (loss(u + h * d) - loss(u - h * d)) / (2 * h)
         an = (du * d).sum()
         assert abs(fd - an) < 1e-6 * abs(an), (fd, an)
+
+
+# ---------------------------------------------------------------------------
+# Amplitude, force density and power input.
+
+def _split(ks, fh):
+    """(A_ran, B_ran): the components of coefficients F_hat (..., n_modes, 3)
+    along e1 and e2 of each mode."""
+    a = np.zeros(fh.shape[:-1], dtype=np.complex128)
+    b = np.zeros(fh.shape[:-1], dtype=np.complex128)
+    for mi, k in enumerate(ks):
+        e1, e2 = forcing.basis(k)
+        a[..., mi] = fh[..., mi, :] @ e1
+        b[..., mi] = fh[..., mi, :] @ e2
+    return a, b
+
+
+def _magnitude_error(ks, fh, amp, kf, c):
+    """max |(|F_hat|^2 (2 pi |k|^2) / F(|k|)) - 1| over steps and modes: every
+    mode carries the density F(|k|) / (2 pi |k|^2) whatever the angles (the
+    basis is orthonormal and g_A^2 + g_B^2 = 1)."""
+    kk = np.sqrt((np.asarray(ks, dtype=np.float64) ** 2).sum(axis=1))
+    want = forcing.spectrum(kk, amp, kf, c) / (2.0 * np.pi * kk * kk)
+    got = (np.abs(fh) ** 2).sum(axis=-1)
+    return float(np.abs(got / want - 1.0).max())
+
+
+def _ratio_phase_errors(ks, fh, phi, psi):
+    """Largest deviations of |A_ran| / |B_ran| from |tan 2 phi| (relative)
+    and of arg B_ran - arg A_ran from psi (mod 2 pi), over the modes where
+    both are well away from zero."""
+    a, b = _split(ks, fh)
+    ok = (np.abs(np.sin(2 * phi)) > 0.05) & (np.abs(np.cos(2 * phi)) > 0.05)
+    ratio = np.abs(np.abs(a[ok]) / np.abs(b[ok]) / np.abs(np.tan(2 * phi[ok])) - 1.0).max()
+    # B_ran / A_ran = exp(i psi) cot 2 phi: its phase is psi, or psi + pi
+    # where cot 2 phi < 0.
+    q = b[ok] / a[ok] * np.sign(np.tan(2 * phi[ok]))
+    dphase = np.angle(q * np.exp(-1j * psi[ok]))
+    return float(ratio), float(np.abs(dphase).max())
+
+
+def test_force_density_is_the_gaussian():
+    """F(k_f) = A and F(k_f +- sqrt c) = A / e, F(k_f +- 2 sqrt c) = A e^-4."""
+    amp, kf, c = 3e-4, 1.5, 0.7
+    assert forcing.spectrum(kf, amp, kf, c) == amp
+    for d, f in [(1.0, math.exp(-1.0)), (2.0, math.exp(-4.0))]:
+        for sgn in (-1.0, 1.0):
+            assert math.isclose(forcing.spectrum(kf + sgn * d * math.sqrt(c), amp, kf, c), amp * f, rel_tol=1e-14)
+
+
+def test_unit_modes_carry_the_printed_density():
+    """Worked values: with F(|k|) = 2 pi |k|^2 at the mode, |F_hat| = 1 for
+    any angles (k = (1,0,0) at k_f = 1 with A = 2 pi; k = (0,2,0) at k_f = 2
+    with A = 8 pi)."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    for k, kf, amp in [((1, 0, 0), 1.0, 2 * np.pi), ((0, 2, 0), 2.0, 8 * np.pi), ((0, 0, 3), 3.0, 18 * np.pi)]:
+        draws = rng.random((6, 1, 3))
+        fh = forcing.coefficients(np.array([k]), draws, amp, kf, 1.0)
+        np.testing.assert_allclose(np.abs(fh[:, 0, :]) ** 2 @ np.ones(3), 1.0, rtol=1e-14)
+
+
+def test_every_mode_carries_the_force_density():
+    """|F_hat(k)|^2 = F(|k|) / (2 pi |k|^2) for every mode and step, drawn
+    phases and the velocity-dependent rule alike."""
+    amp, kf, c = 2e-5, 1.5, 1.0
+    ks = inputs.forcing_half_modes(2.5, 0.5)
+    draws = inputs.uniform_draws(5, len(ks), seed=91)
+    assert _magnitude_error(ks, forcing.coefficients(ks, draws, amp, kf, c), amp, kf, c) < 1e-13
+    _, u = inputs.turbulence(8, seed=92, k0=2.0, urms=0.05)
+    fh = forcing.coefficients_state(ks, draws[0], amp, kf, c, u)
+    assert _magnitude_error(ks, fh, amp, kf, c) < 1e-13
+
+
+def test_random_amplitudes_split_as_tan_two_phi_with_phase_offset_psi():
+    """|A_ran| / |B_ran| = |tan 2 phi| and arg B_ran - arg A_ran = psi: the
+    ratio of g_A = sin 2 phi to g_B = cos 2 phi and theta2 = theta1 + psi.
+    With drawn phases arg A_ran is theta1 itself (up to the sign of g_A)."""
+    amp, kf, c = 2e-5, 1.5, 1.0
+    ks = inputs.forcing_half_modes(2.5, 0.5)
+    draws = inputs.uniform_draws(6, len(ks), seed=93)
+    phi, psi, th1 = np.pi * draws[..., 0], 2 * np.pi * draws[..., 1], 2 * np.pi * draws[..., 2]
+    fh = forcing.coefficients(ks, draws, amp, kf, c)
+    ratio, dphase = _ratio_phase_errors(ks, fh, phi, psi)
+    assert ratio < 1e-12 and dphase < 1e-12
+    a, _ = _split(ks, fh)
+    assert np.abs(np.angle(a * np.sign(np.sin(2 * phi)) * np.exp(-1j * th1))).max() < 1e-12
+    # The velocity-dependent rule keeps the split and the offset.
+    _, u = inputs.turbulence(8, seed=94, k0=2.0, urms=0.05)
+    fh = forcing.coefficients_state(ks, draws[0], amp, kf, c, u)
+    ratio, dphase = _ratio_phase_errors(ks, fh, phi[0], psi[0])
+    assert ratio < 1e-12 and dphase < 1e-12
+
+
+def test_amplitude_from_power_matches_quadrature():
+    """A = (P / dt) / int_{k_a}^{k_b} exp(-(k - k_f)^2 / c) dk: the closed
+    form against numerical quadrature, and the whole-line limit sqrt(pi c)."""
+    for p, dt, ka, kb, kf, c in [(0.1, 1.0, 0.5, 2.5, 1.5, 1.0), (2e-6, 0.5, 1.0, 2.0, 1.5, 0.3),
+                                 (1e-3, 2.0, 3.0, 9.0, 4.0, 5.0)]:
+        integral, _ = integrate.quad(lambda k: math.exp(-(k - kf) ** 2 / c), ka, kb, epsabs=0, epsrel=1e-13)
+        assert math.isclose(forcing.amplitude_from_power(p, dt, ka, kb, kf, c), p / dt / integral, rel_tol=1e-12)
+    assert math.isclose(forcing.amplitude_from_power(1.0, 1.0, -60.0, 60.0, 3.0, 2.0), 1.0 / math.sqrt(2.0 * math.pi),
+                        rel_tol=1e-14)
+
+
+POWER, DT, KA, KB, KFP, CP = 2e-6, 0.5, 0.5, 2.5, 1.5, 1.0
+
+
+def _injected_power(ks, coef, u):
+    """Mean kinetic-energy gain per unit time of one step of length DT under
+    the force field of coefficients coef: <|u + F dt|^2 - |u|^2> / (2 dt)."""
+    F = forcing.field(ks, coef, u.shape[1:])
+    return float((((u + DT * F) ** 2).sum(axis=0) - (u ** 2).sum(axis=0)).mean() / (2.0 * DT))
+
+
+def test_forcing_injects_the_power_input():
+    """With A from the power input P, the force injects P: exactly per step
+    under the velocity-dependent phase (the force does no work on u, so the
+    gain is dt / 2 <|F|^2>, the same for every draw), and on average over
+    draws with drawn phases, whose work on u has zero mean.  The modes are every integer wavevector of the
+    band k_a <= |k| <= k_b; the only difference to P is that of the shell sum
+    over those wavevectors to the equation's integral, 0.16 % for this band."""
+    ks = inputs.forcing_half_modes(KB, KA)
+    amp = forcing.amplitude_from_power(POWER, DT, KA, KB, KFP, CP)
+    _, u = inputs.turbulence(8, seed=95, k0=2.0, urms=0.05)
+    draws = inputs.uniform_draws(400, len(ks), seed=96)
+    ruled = [_injected_power(ks, forcing.coefficients_state(ks, draws[t], amp, KFP, CP, u), u) for t in range(4)]
+    assert np.ptp(ruled) < 1e-12 * POWER
+    assert abs(ruled[0] / POWER - 1.0) < 3e-3, ruled[0] / POWER
+    # Drawn phases: the work term <u . F> averages out over the draws (its
+    # per-draw spread at this weaker velocity is ~4 % of P, 0.2 % over 400 draws).
+    fh = forcing.coefficients(ks, draws, amp, KFP, CP)
+    _, uw = inputs.turbulence(8, seed=95, k0=2.0, urms=2e-4)
+    drawn = np.mean([_injected_power(ks, fh[t], uw) for t in range(len(draws))])
+    assert abs(drawn / POWER - 1.0) < 0.015, drawn / POWER
+
+
+def _slip_k_not_k2(k, amplitude, kf, c, phi, psi, theta1):
+    kk = np.sqrt(float((np.asarray(k) ** 2).sum()))
+    mag = np.sqrt(forcing.spectrum(kk, amplitude, kf, c) / (2.0 * np.pi * kk))
+    return mag * np.exp(1j * theta1) * np.sin(2 * phi), mag * np.exp(1j * (theta1 + psi)) * np.cos(2 * phi)
+
+
+def _slip_swapped_g(k, amplitude, kf, c, phi, psi, theta1):
+    kk = np.sqrt(float((np.asarray(k) ** 2).sum()))
+    mag = np.sqrt(forcing.spectrum(kk, amplitude, kf, c) / (2.0 * np.pi * kk * kk))
+    return mag * np.exp(1j * theta1) * np.cos(2 * phi), mag * np.exp(1j * (theta1 + psi)) * np.sin(2 * phi)
+
+
+def _slip_theta2(k, amplitude, kf, c, phi, psi, theta1):
+    kk = np.sqrt(float((np.asarray(k) ** 2).sum()))
+    mag = np.sqrt(forcing.spectrum(kk, amplitude, kf, c) / (2.0 * np.pi * kk * kk))
+    return mag * np.exp(1j * theta1) * np.sin(2 * phi), mag * np.exp(1j * (theta1 - psi)) * np.cos(2 * phi)
+
+
+@pytest.mark.parametrize("slip", ["k_not_k2", "swapped_g", "theta2", "power_times_dt", "no_2pi"])
+def test_planted_forcing_mistakes_fail_the_pins(monkeypatch, slip):
+    """Negative controls: a mistake planted in the oracle's forcing is caught
+    by at least one of the pins above."""
+    amp, kf, c = 2e-5, 1.5, 1.0
+    ks = inputs.forcing_half_modes(2.5, 0.5)
+    draws = inputs.uniform_draws(4, len(ks), seed=97)
+    phi, psi = np.pi * draws[..., 0], 2 * np.pi * draws[..., 1]
+    if slip == "k_not_k2":
+        monkeypatch.setattr(forcing, "random_amplitudes", _slip_k_not_k2)
+    elif slip == "swapped_g":
+        monkeypatch.setattr(forcing, "random_amplitudes", _slip_swapped_g)
+    elif slip == "theta2":
+        monkeypatch.setattr(forcing, "random_amplitudes", _slip_theta2)
+    elif slip == "power_times_dt":
+        good = forcing.amplitude_from_power
+        monkeypatch.setattr(forcing, "amplitude_from_power",
+                            lambda p, dt, ka, kb, kf_, c_: good(p, dt, ka, kb, kf_, c_) * dt * dt)
+    elif slip == "no_2pi":
+        good_ra = forcing.random_amplitudes
+        monkeypatch.setattr(forcing, "random_amplitudes",
+                            lambda *a: tuple(v * math.sqrt(2 * math.pi) for v in good_ra(*a)))
+    fh = forcing.coefficients(ks, draws, amp, kf, c)
+    ratio, dphase = _ratio_phase_errors(ks, fh, phi, psi)
+    caught = _magnitude_error(ks, fh, amp, kf, c) > 1e-6 or ratio > 1e-6 or dphase > 1e-6
+    pks = inputs.forcing_half_modes(KB, KA)
+    _, u = inputs.turbulence(8, seed=95, k0=2.0, urms=0.05)
+    pa = forcing.amplitude_from_power(POWER, DT, KA, KB, KFP, CP)
+    pd = inputs.uniform_draws(1, len(pks), seed=98)
+    gain = _injected_power(pks, forcing.coefficients_state(pks, pd[0], pa, KFP, CP, u), u)
+    caught = caught or abs(gain / POWER - 1.0) > 3e-3
+    assert caught, slip
