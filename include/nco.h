@@ -267,6 +267,30 @@ int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* d
 int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
                        double amplitude, double kf, double c, int phase_rule);
 
+/* Amplitude A of the force density F(k) = A exp(-(k - kf)^2 / c) for a power
+ * input P injected over a time step dt (Sec. "Training Data - Forced
+ * Isotropic Turbulence", the equation for A):
+ *   A = (P / dt) / integral_{ka}^{kb} exp(-(k - kf)^2 / c) dk,
+ * with the Gaussian's integral in closed form (error functions).  ka < kb
+ * are the edges of the forced band of wavenumbers (units of the 2 pi box,
+ * like the integer wavevectors of nco_set_forcing).  With every integer
+ * wavevector of the band forced, a step of length dt raises the kinetic
+ * energy per unit mass by P dt (the force does no work on the velocity
+ * under the velocity-dependent phase, and none on average with drawn
+ * phases), up to the difference between the sum over the band's
+ * wavevectors and the integral.  Host arithmetic only: needs no device.
+ * NCO_E_INVALID for P < 0, dt <= 0, c <= 0, ka >= kb, non-finite arguments
+ * or an integral that underflows to zero. */
+int nco_forcing_amplitude(double power, double dt, double ka, double kb, double kf, double c,
+                          double* amplitude);
+
+/* nco_set_forcing_ex with the amplitude from the power input: A =
+ * nco_forcing_amplitude(power, 1, ka, kb, kf, c), power in lattice units
+ * (kinetic energy per unit mass per time step; the lattice's time step is
+ * dt = 1 and its velocity changes by F per step). */
+int nco_set_forcing_power(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
+                          double power, double ka, double kb, double kf, double c, int phase_rule);
+
 /* Run nsteps steps (NCO operator, width 32, float storage) keeping a
  * checkpoint of the state every ckpt_every steps in device memory, for a
  * following nco_backward (the gradient of Adam in Sec. "Learning Task"). */

@@ -59,6 +59,8 @@ SIGNATURES = {
                              ctypes.c_double]),
     "nco_set_forcing_ex": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), _D, _I, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, _I]),
+    "nco_forcing_amplitude": (_I, [ctypes.c_double] * 6 + [_D]),
+    "nco_set_forcing_power": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), _D, _I] + [ctypes.c_double] * 5 + [_I]),
     "nco_forward_record": (_I, [_P, _I, _I]),
     "nco_forward_record_energy": (_I, [_P, _I, _I, _I, _D]),
     "nco_backward_energy": (_I, [_P, _D, _I, _D, _I, _D, _D, _SZ, _D]),
@@ -238,6 +240,22 @@ def nco_set_forcing(h, k, draws, amplitude, kf, c, phase_rule=False):
         raise ValueError("draws must have shape (n_steps, n_modes, 3)")
     check(lib().nco_set_forcing_ex(h, n_modes, kk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dptr(d),
                                    d.shape[0], amplitude, kf, c, int(bool(phase_rule))))
+
+
+def nco_forcing_amplitude(power, dt, ka, kb, kf, c):
+    out = ctypes.c_double(0.0)
+    check(lib().nco_forcing_amplitude(power, dt, ka, kb, kf, c, ctypes.byref(out)))
+    return out.value
+
+
+def nco_set_forcing_power(h, k, draws, power, ka, kb, kf, c, phase_rule=False):
+    kk = np.ascontiguousarray(k, dtype=np.int32)
+    d = np.ascontiguousarray(draws, dtype=np.float64)
+    n_modes = kk.shape[0]
+    if d.ndim != 3 or d.shape[1] != n_modes or d.shape[2] != 3:
+        raise ValueError("draws must have shape (n_steps, n_modes, 3)")
+    check(lib().nco_set_forcing_power(h, n_modes, kk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dptr(d),
+                                      d.shape[0], power, ka, kb, kf, c, int(bool(phase_rule))))
 
 
 def nco_batch_step(handles, nsteps):

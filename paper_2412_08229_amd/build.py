@@ -23,17 +23,30 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose=False, out=None, extra_flags=(), obj_dir=None):
+def _newest_header():
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    heads += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(h) for h in heads)
+
+
+def build(verbose=False, out=None, extra_flags=(), obj_dir=None, incremental=False):
     """Compile and link.  ``out``/``extra_flags``/``obj_dir`` build a variant
-    library elsewhere (tuning experiments); the defaults build libnco.so."""
+    library elsewhere (tuning experiments); the defaults build libnco.so.
+    ``incremental`` skips sources whose object is newer than the source and
+    every header (a development shortcut; the default compiles everything)."""
     out = out or LIB
     obj_dir = obj_dir or OBJ
     os.makedirs(obj_dir, exist_ok=True)
     procs = []
     objs = []
+    newest_header = _newest_header()
     for src in SOURCES:
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
         objs.append(obj)
+        if incremental and os.path.exists(obj):
+            t = os.path.getmtime(obj)
+            if t > os.path.getmtime(os.path.join(CSRC, src)) and t > newest_header:
+                continue
         cmd = [HIPCC] + FLAGS + list(extra_flags) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -57,4 +70,4 @@ def build(verbose=False, out=None, extra_flags=(), obj_dir=None):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -911,6 +911,34 @@ int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double
     return NCO_OK;
 }
 
+int nco_forcing_amplitude(double power, double dt, double ka, double kb, double kf, double c,
+                          double* amplitude) {
+    if (!amplitude) return fail(NCO_E_INVALID, "null output");
+    for (double v : {power, dt, ka, kb, kf, c})
+        if (!std::isfinite(v)) return fail(NCO_E_INVALID, "non-finite forcing argument");
+    if (power < 0.0 || !(dt > 0.0) || !(c > 0.0) || !(ka < kb))
+        return fail(NCO_E_INVALID, "need power >= 0, dt > 0, c > 0 and ka < kb");
+    // integral_{ka}^{kb} exp(-(k - kf)^2 / c) dk = sqrt(pi c) / 2 (erf(b) - erf(a))
+    // with a, b the band edges in units of sqrt(c) from kf; the difference
+    // of complementary error functions keeps its digits in the far tail.
+    const double sc = std::sqrt(c), a = (ka - kf) / sc, b = (kb - kf) / sc;
+    const double diff = a >= 0.0 ? std::erfc(a) - std::erfc(b) : b <= 0.0 ? std::erfc(-b) - std::erfc(-a)
+                                                                       : std::erf(b) - std::erf(a);
+    const double integral = 0.5 * std::sqrt(M_PI * c) * diff;
+    if (!(integral > 0.0)) return fail(NCO_E_INVALID, "the forced band carries no weight (integral %g)", integral);
+    *amplitude = (power / dt) / integral;
+    return NCO_OK;
+}
+
+int nco_set_forcing_power(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
+                          double power, double ka, double kb, double kf, double c, int phase_rule) {
+    if (int rc = check_lat(lat)) return rc;
+    double amplitude = 0.0;
+    if (n_modes > 0)
+        if (int rc = nco_forcing_amplitude(power, 1.0, ka, kb, kf, c, &amplitude)) return rc;
+    return nco_set_forcing_ex(lat, n_modes, k, draws, n_steps, amplitude, kf, c, phase_rule);
+}
+
 namespace {
 
 // Recorded forward run; every > 0: k(t) = <|u|^2> / 2 at t = 0, every, ...

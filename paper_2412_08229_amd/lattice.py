@@ -132,6 +132,12 @@ class Lattice:
         follows the force back to the state through it)."""
         L.nco_set_forcing(self._h, k, draws, amplitude, kf, c, phase_rule)
 
+    def set_forcing_power(self, k, draws, power, ka, kb, kf, c, phase_rule=False):
+        """Spectral forcing with the amplitude from the power input (lattice
+        units: kinetic energy per unit mass per step) over the band
+        ka <= |k| <= kb."""
+        L.nco_set_forcing_power(self._h, k, draws, power, ka, kb, kf, c, phase_rule)
+
     def forward_record(self, nsteps, ckpt_every, energy_every=0):
         """Recorded run for backward(); with energy_every > 0 it returns the
         mean kinetic energy k(t) of the states t = 0, energy_every, ..."""

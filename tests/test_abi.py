@@ -59,3 +59,21 @@ def test_parameter_count_of_the_abi():
     for w in (8, 16, 20, 32):
         assert inputs.n_params(w) == w * (27 + w + 4) + 2 * w + 4
     assert inputs.mlp_params(32, 0).dtype == np.float64
+
+
+def test_forcing_amplitude_from_power_matches_the_oracle():
+    """The host-side amplitude of the power input (the equation for A in
+    Sec. "Training Data - Forced Isotropic Turbulence") against the oracle's,
+    and its argument checks; no device is needed."""
+    from oracle import forcing
+    for args in [(0.1, 1.0, 0.5, 2.5, 1.5, 1.0), (2e-6, 0.5, 1.0, 2.0, 1.5, 0.3), (1e-3, 2.0, 3.0, 9.0, 4.0, 5.0),
+                 (1e-5, 1.0, 0.5, 2.5, -1.0, 0.5), (3e-7, 1.0, 4.0, 6.0, 1.0, 2.0)]:
+        got = L.nco_forcing_amplitude(*args)
+        want = forcing.amplitude_from_power(*args)
+        assert abs(got / want - 1.0) < 1e-12, (args, got, want)
+    for bad in [(-1.0, 1.0, 0.5, 2.5, 1.5, 1.0), (1.0, 0.0, 0.5, 2.5, 1.5, 1.0), (1.0, 1.0, 2.5, 0.5, 1.5, 1.0),
+                (1.0, 1.0, 0.5, 2.5, 1.5, 0.0), (1.0, 1.0, 0.5, float("inf"), 1.5, 1.0),
+                (1.0, 1.0, 500.0, 501.0, 0.0, 1.0)]:
+        with pytest.raises(L.NCOError) as e:
+            L.nco_forcing_amplitude(*bad)
+        assert e.value.status == L.NCO_E_INVALID

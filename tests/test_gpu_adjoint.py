@@ -41,6 +41,97 @@ def test_forced_steps_match_oracle(storage, tol):
     assert np.abs(got - want).max() < tol
 
 
+# Power-input forcing: every integer wavevector of the band 0.5 <= |k| <= 2.5
+# (40 of each +-k pair), Gaussian peak 1.5, width 1, power in lattice units.
+PK_A, PK_B, P_IN = 0.5, 2.5, 1e-6
+
+
+@pytest.mark.parametrize("shape,storage,kind,mlp,tol", [((12, 12, 12), "f64", "bgk", "f32", 1e-13),
+                                                        ((12, 12, 12), "f32", "nco", "f32_mfma", 2e-6),
+                                                        ((11, 13, 10), "f64", "nco", "f32", 1e-13)])
+def test_power_input_forcing_matches_oracle(shape, storage, kind, mlp, tol):
+    """nco_set_forcing_power: the amplitude from the power input (the
+    equation for A, Sec. "Training Data - Forced Isotropic Turbulence") and
+    the forced steps, drawn phases and the velocity-dependent phase, against
+    the oracle's amplitude_from_power and forced steps."""
+    T = 4
+    ks = inputs.forcing_half_modes(PK_B, PK_A)
+    draws = inputs.uniform_draws(3, len(ks), seed=101)
+    amp = forcing.amplitude_from_power(P_IN, 1.0, PK_A, PK_B, KF, CW)
+    assert abs(L.nco_forcing_amplitude(P_IN, 1.0, PK_A, PK_B, KF, CW) / amp - 1) < 1e-12
+    _, u = inputs.random_velocity(shape, seed=102, amp=0.05)
+    rho = np.ones(shape)
+    params = inputs.mlp_params(32, 103)
+    op = step.Operator(kind, 0.6, layers=collision.unpack_params(params, 32), act="tanh")
+    for rule in (False, True):
+        with Lattice(shape, storage, kind, 0.6) as lat:
+            if kind == "nco":
+                lat.set_net_weights(params, 32, "tanh", mlp)
+            lat.set_forcing_power(ks, draws, P_IN, PK_A, PK_B, KF, CW, phase_rule=rule)
+            lat.init_equilibrium(rho, u)
+            f = lat.populations()
+            lat.step(T)
+            got = lat.populations()
+        fh = forcing.coefficients(ks, draws, amp, KF, CW)
+        for t in range(T):
+            if rule:
+                _, ut = collision.macroscopic(f)
+                coef = forcing.coefficients_state(ks, draws[t % 3], amp, KF, CW, ut)
+            else:
+                coef = fh[t % 3]
+            f = step.step(f, op, force=forcing.field(ks, coef, shape))
+        err = np.abs(got - f).max()
+        print("power forcing %s %s/%s rule=%s: max err %.3e" % (shape, storage, mlp, rule, err))
+        assert err < tol
+
+
+@pytest.mark.parametrize("rule", [False, True])
+def test_gradient_matches_oracle_at_the_training_form(rule):
+    """The reverse mode at the form of the forced-turbulence training, scaled
+    to what the oracle finishes in seconds: 16^3, 20 steps in checkpoint
+    segments of 5, forcing from the power input (drawn phases, or the
+    velocity-dependent phase with the gradient through it), the log-spectrum
+    loss over 2 <= k <= 6.  dL/dtheta and dL/df0 of the float32 GPU adjoint
+    (vector-unit and matrix-core networks) within 1e-3 of the oracle's
+    float64 reverse mode."""
+    n, width, tau, T, K, kmin, kmax = 16, 32, 0.52, 20, 5, 2, 6
+    params = inputs.mlp_params(width, 104)
+    _, u = inputs.turbulence(n, seed=105, k0=4.0, urms=0.05)
+    rho = np.ones((n, n, n))
+    f_init = collision.equilibrium(rho, u)
+    Et = observables.spectrum(f_init) * np.linspace(0.8, 1.2, observables.n_bins(n)) + 1e-12
+    ks = inputs.forcing_half_modes(PK_B, PK_A)
+    draws = inputs.uniform_draws(T, len(ks), seed=106)
+    amp = forcing.amplitude_from_power(P_IN, 1.0, PK_A, PK_B, KF, CW)
+    layers = collision.unpack_params(params, width)
+
+    def loss_grad(x):
+        Lx, d = adjoint.log_spectrum_loss(observables.spectrum(x), Et, kmin, kmax)
+        return Lx, adjoint.spectrum_vjp(x, d)
+    if rule:
+        Lo, go, gfo = adjoint.run_and_grad(f_init, tau, layers, "tanh", T, loss_grad,
+                                           state_forcing=(ks, draws, amp, KF, CW))
+    else:
+        fh = forcing.coefficients(ks, draws, amp, KF, CW)
+        Lo, go, gfo = adjoint.run_and_grad(f_init, tau, layers, "tanh", T, loss_grad,
+                                           forces=lambda t: forcing.field(ks, fh[t], (n, n, n)))
+    go = adjoint.flatten(go)
+    for mlp in ("f32_mfma", "f32"):
+        with Lattice((n, n, n), "f32", "nco", tau) as lat:
+            lat.set_net_weights(params, width, "tanh", mlp)
+            lat.set_forcing_power(ks, draws, P_IN, PK_A, PK_B, KF, CW, phase_rule=rule)
+            lat.init_populations(f_init)
+            lat.forward_record(T, K)
+            Lg, dE = log_spectrum_loss(lat.energy_spectrum(), Et, kmin, kmax)
+            g, df0 = lat.backward(dL_dE=dE, want_df0=True)
+        rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+        relf = np.linalg.norm(df0 - gfo) / np.linalg.norm(gfo)
+        print("16^3 x %d (K=%d) rule=%s %s: loss %.8e vs %.8e, dL/dtheta rel err %.2e, dL/df0 rel err %.2e"
+              % (T, K, rule, mlp, Lg, Lo, rel, relf))
+        assert abs(Lg - Lo) < 1e-4 * abs(Lo)
+        assert rel < 1e-3 and relf < 1e-3
+
+
 def _setup(n, width, seed, act):
     params = inputs.mlp_params(width, seed)
     _, u = inputs.turbulence(n, seed=seed + 1, k0=2.0, urms=0.04)
