@@ -227,6 +227,20 @@ int nco_global_sums(nco_lattice* lat, double out[5]);
  * floor(sqrt(3) * (n/2) + 1/2) + 1. */
 int nco_energy_spectrum(nco_lattice* lat, double* E, int nbins);
 
+/* nco_energy_spectrum for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): it calls
+ * no hipMalloc, hipFree or other allocating routine and does not
+ * synchronise.  The spectrum is written to E_dev, nbins doubles of device
+ * memory the caller owns, asynchronously on the lattice's stream; the
+ * values equal those of nco_energy_spectrum bit for bit.  Its work space is
+ * a fixed 36 MiB array per device that the library holds from its first
+ * call on that device until the process ends, enough for cubic lattices
+ * up to 66^3 (NCO_E_INVALID beyond, with the bytes needed in the message).
+ * All calls on one device share that array: calls that overlap in time on
+ * one device (different streams or threads) race and must be serialised by
+ * the caller; the array keeps the last call's contents. */
+int nco_energy_spectrum_noalloc(nco_lattice* lat, double* E_dev, int nbins);
+
 /* Borrowed device pointer to the current population buffer and its size in
  * bytes; valid until the next step or destroy. */
 int nco_device_populations(nco_lattice* lat, void** dev_ptr, size_t* bytes);

@@ -54,6 +54,7 @@ SIGNATURES = {
     "nco_read_rates": (_I, [_P, _D]),
     "nco_global_sums": (_I, [_P, _D]),
     "nco_energy_spectrum": (_I, [_P, _D, _I]),
+    "nco_energy_spectrum_noalloc": (_I, [_P, _P, _I]),
     "nco_device_populations": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
     "nco_set_forcing": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int), _D, _I, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double]),
@@ -227,6 +228,12 @@ def nco_energy_spectrum(h, nbins):
     out = np.empty(nbins)
     check(lib().nco_energy_spectrum(h, dptr(out), nbins))
     return out
+
+
+def nco_energy_spectrum_noalloc(h, E_dev_ptr, nbins):
+    """E(k) into nbins doubles of caller-owned device memory at E_dev_ptr
+    (an integer address), asynchronously on the lattice's stream."""
+    check(lib().nco_energy_spectrum_noalloc(h, ctypes.c_void_p(E_dev_ptr), nbins))
 
 
 def nco_set_forcing(h, k, draws, amplitude, kf, c, phase_rule=False):

@@ -1253,6 +1253,24 @@ int nco_energy_spectrum(nco_lattice* lat, double* E, int nbins) {
     return NCO_OK;
 }
 
+int nco_energy_spectrum_noalloc(nco_lattice* lat, double* E_dev, int nbins) {
+    if (int rc = check_lat(lat)) return rc;
+    if (!E_dev) return fail(NCO_E_INVALID, "null output");
+    if (lat->nx != lat->ny || lat->nx != lat->nz) return fail(NCO_E_INVALID, "spectrum needs a cubic lattice");
+    if (lat->domain != NCO_DOMAIN_PERIODIC) return fail(NCO_E_UNSUPPORTED, "spectrum needs the periodic domain");
+    const int n = lat->nx;
+    if (nbins != spectrum_bins(n)) return fail(NCO_E_INVALID, "nbins must be %d for n = %d", spectrum_bins(n), n);
+    const size_t need = spectrum_forward_bytes(n);
+    if (need > spectrum_scratch_bytes())
+        return fail(NCO_E_INVALID, "a %d^3 spectrum needs %zu bytes of scratch; the allocation-free spectrum has %zu",
+                    n, need, spectrum_scratch_bytes());
+    if (int rc = set_device(lat)) return rc;
+    void* work = nullptr;
+    HIP_TRY(spectrum_scratch(lat->device, &work));
+    HIP_TRY(launch_energy_spectrum(lat->storage, lat->f[lat->cur], n, work, E_dev, nbins, lat->stream));
+    return NCO_OK;
+}
+
 int nco_device_populations(nco_lattice* lat, void** dev_ptr, size_t* bytes) {
     if (int rc = check_lat(lat)) return rc;
     if (!dev_ptr || !bytes) return fail(NCO_E_INVALID, "null output");

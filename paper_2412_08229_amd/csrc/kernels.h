@@ -197,6 +197,9 @@ hipError_t launch_spectrum_adjoint(int storage, const void* f, int n, void* work
 
 // Energy spectrum (spectrum.hip).
 size_t spectrum_workspace_bytes(int n);
+size_t spectrum_forward_bytes(int n);
+size_t spectrum_scratch_bytes();
+hipError_t spectrum_scratch(int device, void** ptr);
 hipError_t launch_energy_spectrum(int storage, const void* f, int n, void* work, double* E_dev,
                                   int nbins, hipStream_t st);
 

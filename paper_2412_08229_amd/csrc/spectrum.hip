@@ -10,6 +10,8 @@
 // are visited in order of |k_x|, so the shell index never decreases and each
 // (shell, row) partial is written exactly once; a second kernel adds the
 // rows of each shell in a fixed order.
+#include <mutex>
+
 #include "kernels.h"
 
 namespace nco {
@@ -204,19 +206,31 @@ SpecLayout spec_layout(int n, int nbins) {
     return L;
 }
 
-// Twiddles exp(-2 pi i m / n), computed on the host in float64.
-hipError_t upload_twiddles(double2* tw, int n, hipStream_t st) {
-    double2* h = static_cast<double2*>(malloc(sizeof(double2) * n));
-    if (!h) return hipErrorOutOfMemory;
-    for (int m = 0; m < n; ++m) {
-        const double ang = 2.0 * M_PI * (double)m / (double)n;
-        h[m] = make_double2(cos(ang), -sin(ang));
-    }
-    hipError_t e = hipMemcpyAsync(tw, h, sizeof(double2) * n, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    free(h);
-    return e;
+// Twiddles exp(-2 pi i m / n), m = 0 .. n-1, in float64 on the device.
+__global__ __launch_bounds__(256) void k_twiddles(double2* __restrict__ tw, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double s, c;
+    sincospi(2.0 * (double)m / (double)n, &s, &c);
+    tw[m] = make_double2(c, -s);
 }
+
+hipError_t upload_twiddles(double2* tw, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, st, tw, n);
+    return hipGetLastError();
+}
+
+// Scratch of the allocation-free spectrum (nco_energy_spectrum_noalloc):
+// one array per device, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it stands for a host-side
+// symbol, not a device address); it uses the device address that
+// hipGetSymbolAddress gives, taken once per device with that device current.
+constexpr size_t SCRATCH_BYTES = (size_t)36 << 20;
+__device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+void* g_scratch_ptr[SCRATCH_DEVICES] = {};
+std::mutex g_scratch_mutex;
 
 }  // namespace
 
@@ -259,6 +273,27 @@ hipError_t launch_spectrum_adjoint(int storage, const void* f, int n, void* work
 }
 
 size_t spectrum_workspace_bytes(int n) { return spec_layout(n, spectrum_bins(n)).total; }
+
+// Bytes of the work space the forward spectrum uses (everything before the
+// density array, which only the adjoint needs).
+size_t spectrum_forward_bytes(int n) { return spec_layout(n, spectrum_bins(n)).rho; }
+
+size_t spectrum_scratch_bytes() { return SCRATCH_BYTES; }
+
+// Device address of the scratch array on `device` (the current device),
+// looked up on the first call per device and kept.
+hipError_t spectrum_scratch(int device, void** ptr) {
+    if (device < 0 || device >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)); e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_energy_spectrum(int storage, const void* f, int n, void* work, double* E_dev,
                                   int nbins, hipStream_t st) {
