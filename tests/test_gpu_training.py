@@ -6,16 +6,16 @@ import numpy as np
 import pytest
 
 from paper_2412_08229_amd import Lattice, inputs
+from paper_2412_08229_amd import _lib as L
 from paper_2412_08229_amd.training import Unroll, curriculum_steps, log_spectrum_loss, n_bins, train
 
 pytestmark = pytest.mark.gpu
 
 
 def forced_turbulence(n, nsteps, seed, tau, urms=0.05, k0=4.0, amp=2e-6):
-    """Seeded forced-turbulence sample: random-phase solenoidal start with
-    E(k) ~ k^4 exp(-2 (k/k0)^2), Alvelius forcing on 0 < |k| <= 2; the
-    target spectrum is the initial one (a statistically steady state keeps
-    its spectrum)."""
+    """Small forced-turbulence sample: random-phase solenoidal start with
+    E(k) ~ k^4 exp(-2 (k/k0)^2), Alvelius forcing on 0 < |k| <= 2 at a given
+    amplitude; the target spectrum is the initial one."""
     rho, u = inputs.turbulence(n, seed=seed, k0=k0, urms=urms)
     ks = inputs.forcing_half_modes(2.0)
     draws = inputs.uniform_draws(nsteps, len(ks), seed + 1)
@@ -25,15 +25,53 @@ def forced_turbulence(n, nsteps, seed, tau, urms=0.05, k0=4.0, amp=2e-6):
     return rho, u, (ks, draws, amp, 1.5, 1.0), target
 
 
+# Forced band of the training workload: every integer wavevector with
+# 0.5 <= |k| <= 2.5, Gaussian force density peaked at k_f = 1.5, width c = 1.
+C4_BAND = (0.5, 2.5, 1.5, 1.0)
+
+
+def c4_sample(seed, n=64, nsteps=200, tau=0.52, phase_rule=False):
+    """The forced-turbulence training sample at its full size.  A random-
+    phase solenoidal field with E(k) ~ k^4 exp(-2 (k/4)^2), u_rms 0.05, is
+    set on a 2n lattice and restricted to the n lattice (the coarse start).
+    The force's power input is the start's dissipation 2 nu sum (2 pi k / n)^2
+    E(k) (lattice units), its amplitude from the power by the equation for A
+    (Sec. "Training Data - Forced Isotropic Turbulence").  The target is the
+    same setup run with BGK on the 2n lattice by acoustic scaling (tau_f =
+    6 nu + 1/2, 2 nsteps steps, each draw held for two fine steps with a
+    quarter of the amplitude: the same force per unit physical time) and
+    restricted to n (Sec. "Learning Task").  Returns the coarse start's
+    populations, the coarse forcing, the target spectrum and the power."""
+    nu = (tau - 0.5) / 3.0
+    nf = 2 * n
+    rho_f, u_f = inputs.turbulence(nf, seed=seed, k0=4.0, urms=0.05)
+    ka, kb, kf, c = C4_BAND
+    ks = inputs.forcing_half_modes(kb, ka)
+    draws = inputs.uniform_draws(nsteps, len(ks), seed + 1)
+    with Lattice((nf,) * 3, "f32", "bgk", 6.0 * nu + 0.5) as fine, Lattice((n,) * 3, "f32", "bgk", tau) as coarse:
+        fine.init_equilibrium(rho_f, u_f)
+        coarse.restrict_from(fine)
+        f0 = coarse.populations()
+        E0 = coarse.energy_spectrum()
+        power = 2.0 * nu * float(np.sum((2.0 * np.pi * np.arange(len(E0)) / n) ** 2 * E0))
+        amp = L.nco_forcing_amplitude(power, 1.0, ka, kb, kf, c)
+        fine.set_forcing(ks, np.repeat(draws, 2, axis=0), amp / 4.0, kf, c, phase_rule)
+        fine.step(2 * nsteps)
+        coarse.restrict_from(fine)
+        target = coarse.energy_spectrum()
+    return f0, (ks, draws, amp, kf, c, phase_rule), target, power
+
+
 @pytest.mark.parametrize("phase_rule", [False, True])
 def test_c4_gradient_matches_finite_differences(phase_rule):
-    """64^3, 200-step unroll, checkpoints every 20: the adjoint's directional
-    derivative against a central difference of the loss, with drawn forcing
-    phases or Alvelius' velocity-dependent phase."""
+    """64^3, 200-step unroll, checkpoints every 20, forcing from the power
+    input, target from the restricted 128^3 BGK run: the adjoint's
+    directional derivative against a central difference of the loss, with
+    drawn forcing phases or Alvelius' velocity-dependent phase."""
     n, T, K, tau = 64, 200, 20, 0.52
-    rho, u, frc, target = forced_turbulence(n, T, seed=11, tau=tau)
+    f0, frc, target, _ = c4_sample(11, n, T, tau, phase_rule)
     params = inputs.mlp_params(32, 0)
-    run = Unroll((n, n, n), tau, ("eq", rho, u), T, K, target, 2, 16, forcing=frc + (phase_rule,))
+    run = Unroll((n, n, n), tau, ("pop", f0), T, K, target, 2, 16, forcing=frc)
     L0, g, _ = run.loss_and_grad(params)
     v = np.random.Generator(np.random.PCG64(12)).standard_normal(params.size)
     v /= np.linalg.norm(v)
@@ -43,7 +81,7 @@ def test_c4_gradient_matches_finite_differences(phase_rule):
     run.close()
     fd = (Lp - Lm) / (2 * h)
     an = float(g @ v)
-    print("C4 64^3 x200 (phase rule %s): loss %.6f, directional derivative adjoint %.6e, finite difference %.6e"
+    print("C4 64^3 x200 (phase rule %s): loss %.6e, directional derivative adjoint %.6e, finite difference %.6e"
           % (phase_rule, L0, an, fd))
     assert np.isfinite(L0) and abs(fd - an) < 3e-2 * abs(an)
 
@@ -74,32 +112,37 @@ def test_training_reduces_loss_below_untrained_fixed_rate_and_bgk():
 
 
 def test_c4_training_gain_64():
-    """The forced-turbulence case at its full size: 64^3, 200-step unrolls,
-    checkpoints every 20, loss on the log-spectrum gap over 2 <= k <= 16.
-    30 Adam epochs on the GPU's own forward and reverse kernels lower the
-    loss below the untrained network's, the fixed-rate operator's (the NCO
-    with tilde tau = 0) and BGK's (measured: 60.48 -> 59.43 against 60.48
-    and 61.21; the higher-order rates move the high shells only a little)."""
+    """The forced-turbulence training at its full size: 64^3, 200-step
+    unrolls, checkpoints every 20, forcing from the power input, target the
+    restricted 128^3 BGK run (``c4_sample``), loss on the log-spectrum gap
+    over 2 <= k <= 16.  30 Adam epochs on the GPU's own forward and reverse
+    kernels (~18 s) cut the loss far below the untrained network's, the
+    fixed-rate operator's and BGK's (measured: 3.73e-3 -> 9.0e-5, against
+    3.73e-3 fixed-rate and 3.7e-4 BGK: the seeded network relaxes the
+    higher orders at ~4/3 and damps the shells above k = 8, which the
+    trained one restores)."""
     n, T, K, tau = 64, 200, 20, 0.52
-    rho, u, frc, target = forced_turbulence(n, T, seed=31, tau=tau)
+    f0, frc, target, power = c4_sample(31, n, T, tau)
     params0 = inputs.mlp_params(32, 1)
-    run = Unroll((n, n, n), tau, ("eq", rho, u), T, K, target, 2, 16, forcing=frc)
+    run = Unroll((n, n, n), tau, ("pop", f0), T, K, target, 2, 16, forcing=frc)
     L_untrained = run.loss(params0)
     params, hist = train([run], params0, epochs=30, lr=1e-2)
     L_trained = run.loss(params)
     run.close()
     others = {}
+    ka, kb, kf, c = C4_BAND
     for kind in ("mrt", "bgk"):
         with Lattice((n, n, n), "f32", kind, tau) as lat:
             lat.set_rates([4.0 / 3.0] * 4)
-            lat.set_forcing(*frc)
-            lat.init_equilibrium(rho, u)
+            lat.set_forcing_power(frc[0], frc[1], power, ka, kb, kf, c)
+            lat.init_populations(f0)
             lat.step(T)
             others[kind] = log_spectrum_loss(lat.energy_spectrum(), target, 2, 16)[0]
-    print("64^3 loss: untrained NCO %.5f, trained NCO %.5f, fixed-rate %.5f, BGK %.5f"
-          % (L_untrained, L_trained, others["mrt"], others["bgk"]))
-    assert L_trained < L_untrained - 0.5
-    assert L_trained < others["mrt"] - 0.5 and L_trained < others["bgk"]
+    print("64^3 loss (power input %.4e): untrained NCO %.4e, trained NCO %.4e, fixed-rate %.4e, BGK %.4e; "
+          "history %s" % (power, L_untrained, L_trained, others["mrt"], others["bgk"],
+                          np.round(hist, 6).tolist()))
+    assert L_trained < 0.1 * L_untrained
+    assert L_trained < 0.1 * others["mrt"] and L_trained < 0.5 * others["bgk"]
 
 
 def _tgv_energy(kind, n, t_end, params=None, u0=0.1 / np.sqrt(3.0), re=1600.0):
