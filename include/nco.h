@@ -257,7 +257,10 @@ int nco_device_populations(nco_lattice* lat, void** dev_ptr, size_t* bytes);
  * ((1,0,0) and (0,1,0) when k_x = k_y = 0).  draws: [n_steps][n_modes][3]
  * uniform numbers in [0, 1) giving phi / pi, psi / 2 pi and theta1 / 2 pi;
  * the t-th step after this call uses draws[t mod n_steps].  n_modes = 0
- * switches forcing off. */
+ * switches forcing off.  Before each step the force is synthesised once on
+ * every node (float64 arithmetic; stored as float32, or float64 for
+ * NCO_F64 storage: 12 or 24 bytes per node of device memory) and the step
+ * reads it; NCO_E_UNSUPPORTED for wavevectors with |k_x| > 16. */
 int nco_set_forcing(nco_lattice* lat, int n_modes, const int* k, const double* draws, int n_steps,
                     double amplitude, double kf, double c);
 

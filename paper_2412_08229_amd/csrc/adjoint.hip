@@ -184,9 +184,8 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
     inverse_T(lam, nu);
     float gm[Q];
     float domega[4];
-    double Fd[3] = {0.0, 0.0, 0.0};
-    if (a.n_modes > 0 && live) force_at(a, p.x, p.y, p.z, Fd[0], Fd[1], Fd[2]);
-    const float F[3] = {(float)Fd[0], (float)Fd[1], (float)Fd[2]};
+    float F[3] = {0.0f, 0.0f, 0.0f};
+    if (a.n_modes > 0 && live) read_force(a, idx, F[0], F[1], F[2]);
     collision_vjp_local(m, nu, a.omega_nu_f, omega, a.n_modes > 0, F, gm, domega);
     // Through the squashing: omega = 1 / tau, tau = 1/2 + 1/(2 (1 + e^t)).
     float dtt[4];
@@ -517,7 +516,7 @@ __global__ __launch_bounds__(256) void k_force_adj_partials(const typename Codec
                 jm[2] += cz_of(i) * v;
             }
             double F[3];
-            force_at(a, p.x, p.y, p.z, F[0], F[1], F[2]);
+            read_force(a, idx, F[0], F[1], F[2]);
             const double v[3] = {jm[0] + F[0], jm[1] + F[1], jm[2] + F[2]};
             const double inv_rho = 1.0 / rho;
             double s0 = 0.0;

@@ -188,6 +188,11 @@ struct nco_lattice {
     long force_t = 0;             // forcing step of the next lattice step
     int* d_fk = nullptr;
     double* d_fhat = nullptr;
+    // The force synthesised on every node for the step about to run
+    // ([3][n]; float64 for float64 storage, float32 otherwise) and the
+    // largest |k_x| of the modes.
+    void* d_force = nullptr;
+    int force_kx = 0;
     // Velocity-dependent phase (Alvelius' rule): per-mode basis and |A|
     // [8 per mode], per-step draws phi, psi [steps][modes][2], mode-sum work
     // space and the coefficients of the current step.
@@ -337,6 +342,8 @@ StepArgs step_args(const nco_lattice* lat) {
     a.n_modes = 0;
     a.fk = nullptr;
     a.fhat = nullptr;
+    a.force32 = nullptr;
+    a.force64 = nullptr;
     return a;
 }
 
@@ -347,8 +354,21 @@ StepArgs step_args_at(const nco_lattice* lat, long t) {
         a.n_modes = lat->n_modes;
         a.fk = lat->d_fk;
         a.fhat = lat->d_fhat + (size_t)(t % lat->force_steps) * lat->n_modes * 6;
+        if (lat->storage == NCO_F64)
+            a.force64 = static_cast<const double*>(lat->d_force);
+        else
+            a.force32 = static_cast<const float*>(lat->d_force);
     }
     return a;
+}
+
+// The force field of the step with arguments a (a.fhat set), on stream st.
+int force_field(nco_lattice* lat, const StepArgs& a, hipStream_t st) {
+    if (a.n_modes <= 0) return NCO_OK;
+    HIP_TRY(launch_force_field(a, lat->force_kx,
+                               lat->storage == NCO_F64 ? nullptr : static_cast<float*>(lat->d_force),
+                               lat->storage == NCO_F64 ? static_cast<double*>(lat->d_force) : nullptr, st));
+    return NCO_OK;
 }
 
 // F_hat (then u_hat) of recorded step `slot` under the velocity-dependent phase.
@@ -372,6 +392,7 @@ int launch_one(nco_lattice* lat, const void* fin, void* fout, long t, int slot =
                                        slot >= 0 ? fh + 6 * lat->n_modes : nullptr, lat->stream));
         a.fhat = fh;
     }
+    if (int rc = force_field(lat, a, lat->stream)) return rc;
     if (use_mfma(lat))
         HIP_TRY(launch_nco_mfma(lat->storage, lat->mlp_prec, fin, fout, a, mfma_lane_tab(lat), mfma_group_tab(lat),
                                 nullptr, lat->stream));
@@ -465,6 +486,7 @@ int nco_lattice_destroy(nco_lattice* lat) {
     if (lat->spec_work) hipFree(lat->spec_work);
     if (lat->d_fk) hipFree(lat->d_fk);
     if (lat->d_fhat) hipFree(lat->d_fhat);
+    if (lat->d_force) hipFree(lat->d_force);
     if (lat->d_fbasis) hipFree(lat->d_fbasis);
     if (lat->d_fdraw) hipFree(lat->d_fdraw);
     if (lat->d_fpart) hipFree(lat->d_fpart);
@@ -789,6 +811,7 @@ int nco_batch_step(nco_lattice** lats, int n, const int* nsteps) {
                 d.fin = lat->f[lat->cur];
                 d.fout = lat->f[1 - lat->cur];
                 d.a = step_args_at(lat, lat->force_t);
+                if (int rc = force_field(lat, d.a, st)) return rc;
                 d.lane_tab = lat->op == NCO_OP_NCO ? mfma_lane_tab(lat) : nullptr;
                 d.gtab = lat->op == NCO_OP_NCO ? mfma_group_tab(lat) : nullptr;
                 g.prefix[g.count + 1] = g.prefix[g.count] + (lat->n + 255) / 256;
@@ -827,12 +850,19 @@ int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double
     if (phase_rule && n_modes > 1024) return fail(NCO_E_INVALID, "at most 1024 modes with the phase rule");
     if (n_modes > 0 && lat->domain != NCO_DOMAIN_PERIODIC)
         return fail(NCO_E_UNSUPPORTED, "spectral forcing needs the periodic domain");
+    int kx_max = 0;
+    for (int m = 0; m < n_modes; ++m) kx_max = std::max(kx_max, std::abs(k[3 * m]));
+    if (kx_max > FORCE_KX_MAX)
+        return fail(NCO_E_UNSUPPORTED, "forced wavevectors need |k_x| <= %d (got %d)", FORCE_KX_MAX, kx_max);
     if (int rc = set_device(lat)) return rc;
     HIP_TRY(hipStreamSynchronize(lat->stream));
     if (lat->d_fk) HIP_TRY(hipFree(lat->d_fk));
     if (lat->d_fhat) HIP_TRY(hipFree(lat->d_fhat));
+    if (lat->d_force) HIP_TRY(hipFree(lat->d_force));
     lat->d_fk = nullptr;
     lat->d_fhat = nullptr;
+    lat->d_force = nullptr;
+    lat->force_kx = 0;
     for (double** b : {&lat->d_fbasis, &lat->d_fdraw, &lat->d_fpart, &lat->d_fhat_cur, &lat->d_phist,
                        &lat->d_fduhat}) {
         if (*b) HIP_TRY(hipFree(*b));
@@ -883,6 +913,8 @@ int nco_set_forcing_ex(nco_lattice* lat, int n_modes, const int* k, const double
             }
         }
     }
+    HIP_TRY(hipMalloc(&lat->d_force, 3 * (size_t)lat->n * (lat->storage == NCO_F64 ? sizeof(double) : sizeof(float))));
+    lat->force_kx = kx_max;
     HIP_TRY(hipMalloc(&lat->d_fk, sizeof(int) * 3 * n_modes));
     HIP_TRY(hipMalloc(&lat->d_fhat, sizeof(double) * fh.size()));
     HIP_TRY(hipMemcpyAsync(lat->d_fk, k, sizeof(int) * 3 * n_modes, hipMemcpyHostToDevice, lat->stream));
@@ -1111,6 +1143,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
             StepArgs a = step_args_at(lat, lat->rec_force_t0 + t);
             const bool phase = lat->phase_rule && lat->n_modes > 0;
             if (phase) a.fhat = phase_slot(lat, t);
+            if (int rc = force_field(lat, a, lat->stream)) return rc;
             if (mfma) {
                 const char* tab = static_cast<const char*>(lat->adj_tab);
                 const float* lt32 = reinterpret_cast<const float*>(tab);

@@ -29,6 +29,11 @@ struct StepArgs {
     int n_modes;
     const int* fk;           // [n_modes][3] integer wavevectors
     const double* fhat;      // [n_modes][6] Re/Im of Fhat_x, Fhat_y, Fhat_z for this step
+    // The same force synthesised on every node for this step ([3][n], by
+    // launch_force_field before the step): float64 for float64 storage,
+    // float32 otherwise.  The step kernels read it instead of summing modes.
+    const float* force32;
+    const double* force64;
 };
 
 // Phases of the spectral modes at a node, e^{i 2 pi (k_x x / nx + k_y y / ny
@@ -73,25 +78,20 @@ __device__ __forceinline__ Phasor mode_phase(const int* k, const NodePhasors& b)
     return phasor_mul(phasor_mul(phasor_pow(b.x, k[0]), phasor_pow(b.y, k[1])), phasor_pow(b.z, k[2]));
 }
 
-// Force density at node (x, y, z) for the current step (float64 synthesis).
-// Inlined into every stream-collide kernel, so it keeps to per-mode
-// arithmetic without loops (the axis-phasor form above, with its powering
-// loops, raised the scalar-register pressure of the vector-unit network
-// kernels into spills).
-__device__ __forceinline__ void force_at(const StepArgs& a, int x, int y, int z, double& Fx, double& Fy,
-                                         double& Fz) {
-    Fx = Fy = Fz = 0.0;
-    for (int m = 0; m < a.n_modes; ++m) {
-        const int* k = a.fk + 3 * m;
-        // Phase as a fraction of a turn, reduced exactly in integers.
-        const long px = ((long)k[0] * x) % a.nx, py = ((long)k[1] * y) % a.ny, pz = ((long)k[2] * z) % a.nz;
-        const double turn = (double)px / a.nx + (double)py / a.ny + (double)pz / a.nz;
-        double s, c;
-        sincospi(2.0 * turn, &s, &c);
-        const double* fh = a.fhat + 6 * m;
-        Fx += 2.0 * (fh[0] * c - fh[1] * s);
-        Fy += 2.0 * (fh[2] * c - fh[3] * s);
-        Fz += 2.0 * (fh[4] * c - fh[5] * s);
+// Force density at node idx for the current step, from the field
+// synthesised by launch_force_field (zero without forcing).
+template <typename R>
+__device__ __forceinline__ void read_force(const StepArgs& a, int idx, R& Fx, R& Fy, R& Fz) {
+    if (a.force64) {
+        Fx = (R)a.force64[idx];
+        Fy = (R)a.force64[(size_t)a.n + idx];
+        Fz = (R)a.force64[2 * (size_t)a.n + idx];
+    } else if (a.force32) {
+        Fx = (R)a.force32[idx];
+        Fy = (R)a.force32[(size_t)a.n + idx];
+        Fz = (R)a.force32[2 * (size_t)a.n + idx];
+    } else {
+        Fx = Fy = Fz = R(0);
     }
 }
 
@@ -123,6 +123,11 @@ hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs&
 // Velocity-dependent Alvelius phase: F_hat of this step's forced modes from
 // the state f (partial: nblocks(n) x n_modes x 6 doubles of work space), and
 // u_hat into uhat (6 doubles per mode) unless it is null.
+// Force field of one step, F(x) = sum_m 2 Re(Fhat_m e^{i k_m . x}), on every
+// node in float64 arithmetic, written to out32 or out64 ([3][n]); kx_max
+// is the largest |k_x| of the modes (at most FORCE_KX_MAX).
+constexpr int FORCE_KX_MAX = 16;
+hipError_t launch_force_field(const StepArgs& a, int kx_max, float* out32, double* out64, hipStream_t st);
 hipError_t launch_force_phase(int storage, const void* f, int n, int nx, int ny, int nz, const int* fk,
                               int n_modes, double* partial, const double* basis, const double* draw, double* fhat,
                               double* uhat, hipStream_t st);

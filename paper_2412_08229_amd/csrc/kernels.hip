@@ -2,6 +2,8 @@
 // float64 reductions.  One thread per node; populations in structure-of-
 // arrays layout [27][z][y][x] so that each of the 27 loads and stores of a
 // wavefront is a contiguous row segment of one velocity plane.
+#include <algorithm>
+
 #include "kernels.h"
 #include "stream.h"
 
@@ -70,9 +72,9 @@ __device__ __forceinline__ void stream_collide_node(const typename Codec<S>::sto
     const NodeIdx p = node_of(idx, a.nx, a.ny);
     pull<S>(fin, a, p, f);
     if (a.n_modes > 0) {
-        double Fx, Fy, Fz;
-        force_at(a, p.x, p.y, p.z, Fx, Fy, Fz);
-        collide_node<R, OP, W, ACT, true, DEPTH>(f, a, (R)Fx, (R)Fy, (R)Fz);
+        R Fx, Fy, Fz;
+        read_force(a, idx, Fx, Fy, Fz);
+        collide_node<R, OP, W, ACT, true, DEPTH>(f, a, Fx, Fy, Fz);
     } else {
         collide_node<R, OP, W, ACT, false, DEPTH>(f, a, R(0), R(0), R(0));
     }
@@ -453,6 +455,110 @@ __global__ void k_check_sums(const double* __restrict__ sums, double mass0, doub
     if (bad) *flag = 1;
 }
 
+// Force field of one step, separable in x: with R_m(y, z) = 2 Fhat_m
+// e^{i 2 pi (k_y y / ny + k_z z / nz)},
+//   F(x, y, z) = sum_kx Re(S_kx(y, z) e^{i 2 pi kx x / nx}),
+//   S_kx(y, z) = sum of R_m over the modes m with k_x = kx (in mode order),
+// so a node sums 2 kx_max + 1 terms whatever the number of modes.  A block
+// serves `rows` consecutive (y, z) rows: its threads first form S for each
+// (row, kx) in LDS (one sincospi of an exact fraction per mode and row),
+// then each node takes its x phase e^{i 2 pi x / nx} (from an LDS table the
+// block fills, one sincospi per x) and the powers up to kx_max by
+// products.  float64 throughout.
+constexpr int FF_MAX_ROWS = 8;
+constexpr int FF_CHUNK = 32;
+constexpr int FF_XTAB = 1024;                   // x-phase table in LDS up to this extent
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_force_field(StepArgs a, int kx_max, int rows, T* __restrict__ out) {
+    __shared__ double2 S[FF_MAX_ROWS][2 * FORCE_KX_MAX + 1][3];
+    __shared__ double2 R[FF_MAX_ROWS][FF_CHUNK][3];
+    __shared__ int skx[FF_CHUNK];
+    __shared__ double2 xph[FF_XTAB];            // e^{i 2 pi x / nx}
+    const int row0 = blockIdx.x * rows;
+    const int nrows = a.ny * a.nz;
+    const int nk = 2 * kx_max + 1;
+    if (a.nx <= FF_XTAB)
+        for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
+            double sn, cs;
+            sincospi(2.0 * (double)x / (double)a.nx, &sn, &cs);
+            xph[x] = make_double2(cs, sn);
+        }
+    for (int e = threadIdx.x; e < rows * nk; e += blockDim.x)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) S[e / nk][e % nk][d] = make_double2(0.0, 0.0);
+    for (int m0 = 0; m0 < a.n_modes; m0 += FF_CHUNK) {
+        const int mend = min(FF_CHUNK, a.n_modes - m0);
+        // R_m(row) for every (row, mode) of the chunk, one per thread.
+        for (int e = threadIdx.x; e < rows * FF_CHUNK; e += blockDim.x) {
+            const int rr = e / FF_CHUNK, c = e % FF_CHUNK, m = m0 + c, row = row0 + rr;
+            double2 v[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            if (c < mend && row < nrows) {
+                const int y = row % a.ny, z = row / a.ny;
+                const int* k = a.fk + 3 * m;
+                const long py = ((long)k[1] * y) % a.ny, pz = ((long)k[2] * z) % a.nz;
+                const double turn = (double)py / a.ny + (double)pz / a.nz;
+                double sn, cs;
+                sincospi(2.0 * turn, &sn, &cs);
+                const double* fh = a.fhat + 6 * m;
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    v[d] = make_double2(2.0 * (fh[2 * d] * cs - fh[2 * d + 1] * sn),
+                                        2.0 * (fh[2 * d] * sn + fh[2 * d + 1] * cs));
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) R[rr][c][d] = v[d];
+        }
+        if (threadIdx.x < FF_CHUNK) skx[threadIdx.x] = (int)threadIdx.x < mend ? a.fk[3 * (m0 + threadIdx.x)] : 0;
+        __syncthreads();
+        // S_kx += the chunk's modes with that k_x, in mode order.
+        for (int e = threadIdx.x; e < rows * nk; e += blockDim.x) {
+            const int rr = e / nk, kx = e % nk - kx_max;
+            double2 acc[3] = {S[rr][kx + kx_max][0], S[rr][kx + kx_max][1], S[rr][kx + kx_max][2]};
+            for (int c = 0; c < mend; ++c)
+                if (skx[c] == kx)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        acc[d].x += R[rr][c][d].x;
+                        acc[d].y += R[rr][c][d].y;
+                    }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) S[rr][kx + kx_max][d] = acc[d];
+        }
+        __syncthreads();
+    }
+    const int nodes = rows * a.nx;
+    for (int local = threadIdx.x; local < nodes; local += blockDim.x) {
+        const int r = local / a.nx, x = local - r * a.nx;
+        if (row0 + r >= nrows) break;
+        double sn, cs;
+        if (a.nx <= FF_XTAB) {
+            sn = xph[x].y;
+            cs = xph[x].x;
+        } else {
+            sincospi(2.0 * (double)x / (double)a.nx, &sn, &cs);
+        }
+        double F[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[d] = S[r][kx_max][d].x;
+        double pc = 1.0, ps = 0.0;                  // e^{i k theta}, k = 1 .. kx_max
+        for (int k = 1; k <= kx_max; ++k) {
+            const double t = pc * cs - ps * sn;
+            ps = pc * sn + ps * cs;
+            pc = t;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double2 sp = S[r][kx_max + k][d], sm = S[r][kx_max - k][d];
+                // Re(sp e^{i k theta}) + Re(sm e^{-i k theta})
+                F[d] += (sp.x + sm.x) * pc - (sp.y - sm.y) * ps;
+            }
+        }
+        const size_t idx = (size_t)row0 * a.nx + local;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) out[(size_t)d * a.n + idx] = (T)F[d];
+    }
+}
+
 inline int nblocks(int n) { return (n + 255) / 256; }
 
 template <int S, int OP>
@@ -618,6 +724,19 @@ hipError_t launch_global_sums(int storage, const void* f, double* partial, doubl
         hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, st, partial, nb, out);
         return hipGetLastError();
     })
+}
+
+hipError_t launch_force_field(const StepArgs& a, int kx_max, float* out32, double* out64, hipStream_t st) {
+    if (a.n_modes < 1 || !a.fk || !a.fhat || (!out32 && !out64) || kx_max < 0 || kx_max > FORCE_KX_MAX)
+        return hipErrorInvalidValue;
+    const int rows = FF_MAX_ROWS;
+    const int nrows = a.ny * a.nz;
+    const unsigned nb = (unsigned)((nrows + rows - 1) / rows);
+    if (out64)
+        hipLaunchKernelGGL(k_force_field<double>, dim3(nb), dim3(256), 0, st, a, kx_max, rows, out64);
+    else
+        hipLaunchKernelGGL(k_force_field<float>, dim3(nb), dim3(256), 0, st, a, kx_max, rows, out32);
+    return hipGetLastError();
 }
 
 hipError_t launch_force_phase(int storage, const void* f, int n, int nx, int ny, int nz, const int* fk,

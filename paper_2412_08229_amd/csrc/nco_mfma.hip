@@ -484,10 +484,9 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
         for (int n = 0; n < 4; ++n) omega[n] = sw[tid * 4 + n];
         float dm[Q], df[Q];
         if (a.n_modes > 0) {
-            const NodeIdx p = node_of(idx, a.nx, a.ny);
-            double Fx, Fy, Fz;
-            force_at(a, p.x, p.y, p.z, Fx, Fy, Fz);
-            collision_delta<float, true>(m, a.omega_nu_f, omega, (float)Fx, (float)Fy, (float)Fz, dm);
+            float Fx, Fy, Fz;
+            read_force(a, idx, Fx, Fy, Fz);
+            collision_delta<float, true>(m, a.omega_nu_f, omega, Fx, Fy, Fz, dm);
         } else {
             collision_delta<float, false>(m, a.omega_nu_f, omega, 0.f, 0.f, 0.f, dm);
         }
@@ -512,28 +511,65 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
 // node c):
 //   forward recompute   r1 = act(Z1), r2 = act(Z2)          (forward tables)
 //   dz2 = dh2 (.) act'(z2),   dh2 = W3 dtt / 48 (the same for every g)
-//   dh1 = W2 dz2,   dz1 = dh1 (.) act'(z1),   dx = W1 dz1   (three products
-//         whose B operands are the previous accumulators, as in the forward)
-//   dL/dm[src_pi(k)] += sum_s chi_s(class k) dx_s[k]        (through LDS)
-//   dW2 += h1 dz2^T, dW1 += x_g dz1^T (the bias row of x_g gives db1),
-//   db2 += dz2                                               (products over
-//         the 16 nodes of the tile: h1, dz2 and dz1 are transposed through
+//   dh1 = W2 dz2,   dz1 = dh1 (.) act'(z1)                 (products whose
+//         B operands are the previous accumulators, as in the forward)
+//   Z_cl = sum_s chi_s(cl) dz1_s over the 8 reflections s of the
+//         permutation (Walsh-Hadamard transform), for the 8 parity classes
+//   dL/dm[src_pi(k)] += (W1 Z_class(k))[k]                   (through LDS)
+//   dW2 += h1 dz2^T per element, dW1 += x_pi Z_class^T per class (the bias
+//   row of x_pi gives db1), db2 += dz2                       (products over
+//         the 16 nodes of the tile: h1, dz2 and Z are transposed through
 //         a per-wave LDS buffer so that the node index becomes K)
 // For tanh, with r = 1 / (1 + 2^(kappa z)): h = 1 - 2 r, act' = 4 r (1 - r).
 
 // Per-lane table of the adjoint (4-byte words per lane).
-constexpr int AT_W2T = 0;           // [t 2][u 2][r 4]  W2[16 t + c][16 u + 4 q + r]
-constexpr int AT_W1T = 16;          // [kt 2][t 2][r 4] W1[16 kt + c][16 t + 4 q + r] (rows >= 27: 0)
-constexpr int AT_W3 = 32;           // [u 2][r 4][n 4]  W3[16 u + 4 q + r][n] / 48
-constexpr int AT_CLS = 64;          // [kt 2][r 4]      parity class of row 16 kt + 4 q + r (int)
-constexpr int AT_CLSC = 72;         // [kt 2]           parity class of row 16 kt + c (int)
-constexpr int ADJ_WORDS = 76;
-constexpr int TB = 33;              // row stride of the per-wave transpose buffers
-
-// chi_s(cls) = (-1)^popcount(s & cls) as a float sign.
-__device__ __forceinline__ float refl_sign(int s, int cls) {
-    return (__builtin_popcount(s & cls) & 1) ? -1.0f : 1.0f;
+// The reverse step's input-row tiles hold the moment rows (and the bias row
+// 27) grouped by parity class, four classes per 16-row tile, so that the
+// products through the first layer run once per class (see k_adjoint_mfma):
+// positions 0-15 hold the classes 0 (with row 27), 1, 3, 7; positions 16-27
+// the classes 2, 4, 5, 6; positions 28-31 are empty (row 28, zero).
+__host__ __device__ constexpr int adj_tile_class(int kt, int i) {
+    constexpr int c[2][4] = {{0, 1, 3, 7}, {2, 4, 5, 6}};
+    return c[kt][i];
 }
+__host__ __device__ constexpr int moment_class(int k) {
+    return k >= 27 ? 0 : (row_tensor(k) % 3) % 2 + 2 * (((row_tensor(k) / 3) % 3) % 2) + 4 * ((row_tensor(k) / 9) % 2);
+}
+// Row of M (27 = bias row, 28 = empty) at tile position p.
+__host__ __device__ constexpr int adj_row(int p) {
+    for (int kt = 0; kt < 2; ++kt) {
+        int pos = 16 * kt;
+        for (int i = 0; i < 4; ++i)
+            for (int k = 0; k < 28; ++k)
+                if (moment_class(k) == adj_tile_class(kt, i)) {
+                    if (pos == p) return k;
+                    ++pos;
+                }
+        if (p < 16 * (kt + 1)) return 28;
+    }
+    return 28;
+}
+
+constexpr int AT_W2T = 0;           // [t 2][u 2][r 4]  W2[16 t + c][16 u + 4 q + r]
+constexpr int AT_W1T = 16;          // [kt 2][t 2][r 4] W1[adj_row(16 kt + c)][16 t + 4 q + r] (rows >= 27: 0)
+constexpr int AT_W3 = 32;           // [u 2][r 4][n 4]  W3[16 u + 4 q + r][n] / 48
+constexpr int AT_CLS = 64;          // [kt 2][r 4]      class of position 16 kt + 4 q + r (-1: empty) (int)
+constexpr int AT_CLSC = 72;         // [kt 2]           class of position 16 kt + c (-1: empty) (int)
+constexpr int AT_ROWO = 74;         // [kt 2][r 4]      adj_row(16 kt + 4 q + r) (int)
+constexpr int AT_ROWC = 82;         // [kt 2]           adj_row(16 kt + c) (int)
+constexpr int ADJ_WORDS = 84;
+constexpr int ADJ_ROWS_AT = 64 * ADJ_WORDS;   // then [32] adj_row(p) (int), shared by all lanes
+constexpr int TB = 32;              // row stride of the per-wave transpose buffers
+
+// Column swizzle of row n of a per-wave transpose buffer: element (n, h) is
+// kept at n TB + (h ^ tr_swz(n)).  The buffers are written as (node c,
+// hidden 16 t + 4 q + r) and read as (node 4 st + q, hidden 16 x + c) by
+// the lanes (q, c); with node bits 0, 1, 2, 3 sent to column bits 4, 0, 1, 3
+// both patterns reach 32 distinct banks in each half-wavefront.
+__device__ __forceinline__ int tr_swz(int n) {
+    return ((n & 1) << 4) | ((n >> 1) & 1) | (((n >> 2) & 1) << 1) | (((n >> 3) & 1) << 3);
+}
+
 
 template <int ACT>
 __device__ __forceinline__ float act_grad(float r) {
@@ -591,10 +627,10 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
         for (int k = 0; k < Q; ++k) row[k] = m[row_tensor(k)];
         row[27] = 1.0f;
         row[28] = 0.0f;
-        double Fd[3] = {0.0, 0.0, 0.0};
-        if (a.n_modes > 0 && live) force_at(a, p.x, p.y, p.z, Fd[0], Fd[1], Fd[2]);
+        float Fd[3] = {0.0f, 0.0f, 0.0f};
+        if (a.n_modes > 0 && live) read_force(a, idx, Fd[0], Fd[1], Fd[2]);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sF[tid * 3 + d] = (float)Fd[d];
+        for (int d = 0; d < 3; ++d) sF[tid * 3 + d] = Fd[d];
     }
     __syncthreads();
 
@@ -690,16 +726,21 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int r = 0; r < 4; ++r) B2[u][r] = lt[LT_B2 + u * 4 + r];
-        int cls[2][4], clsc[2];
+        int cls[2][4], clsc[2], rowo[2][4], rowc[2];
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) {
             clsc[kt] = ati[AT_CLSC + kt];
+            rowc[kt] = ati[AT_ROWC + kt];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) cls[kt][r] = ati[AT_CLS + kt * 4 + r];
+            for (int r = 0; r < 4; ++r) {
+                cls[kt][r] = ati[AT_CLS + kt * 4 + r];
+                rowo[kt][r] = ati[AT_ROWO + kt * 4 + r];
+            }
         }
         float* __restrict__ bh = sbuf[wave][0];
         float* __restrict__ bz2 = sbuf[wave][1];
         float* __restrict__ bz1 = sbuf[wave][2];
+        const int swz_w = tr_swz(c);
 
 #pragma unroll 1
         for (int j = 0; j < TPW; ++j) {
@@ -751,20 +792,17 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
                                 Y[ci | bit][t] = u0 - u1;
                             }
                 // x_pi (reflection-free input) in the A layout of the dW1
-                // product: row 16 kt + c, node 4 st + q of the tile.
+                // product: the row at position 16 kt + c, node 4 st + q of
+                // the tile.
                 float xa[2][4];
 #pragma unroll
                 for (int kt = 0; kt < 2; ++kt) {
-                    const int k = 16 * kt + c;
-                    const int src = k < 27 ? sgs[pi * 27 + k] : (k == 27 ? 27 : 28);
+                    const int k = rowc[kt];
+                    const int src = k < 27 ? sgs[pi * 27 + k] : k;
 #pragma unroll
                     for (int st = 0; st < 4; ++st) xa[kt][st] = sm[(base + 4 * st + q) * NODE_STRIDE + src];
                 }
-                float D[2][4];
-#pragma unroll
-                for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) D[kt][r] = 0.0f;
+                f32x4 Z[8][2];                  // dz1 of reflection s, then its class transform
 
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
@@ -803,67 +841,109 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
 #pragma unroll
                             for (int r = 0; r < 4; ++r) h[t] = mfma4(W2T[t][u][r], dz2[u][r], h[t]);
                     }
-                    float dz1[2][4];
 #pragma unroll
                     for (int t = 0; t < 2; ++t)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) dz1[t][r] = h[t][r] * d1[t][r];
-                    // dx = W1 dz1, summed over the reflections with their signs.
-#pragma unroll
-                    for (int kt = 0; kt < 2; ++kt) {
-                        f32x4 dx = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int t = 0; t < 2; ++t)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) dx = mfma4(W1T[kt][t][r], dz1[t][r], dx);
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) D[kt][r] = fmaf(refl_sign(s, cls[kt][r]), dx[r], D[kt][r]);
-                    }
+                        for (int r = 0; r < 4; ++r) Z[s][t][r] = h[t][r] * d1[t][r];
                     // Transposes: [node c][hidden] from the accumulator layout.
 #pragma unroll
                     for (int t = 0; t < 2; ++t)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            bh[c * TB + 16 * t + 4 * q + r] = act_value<ACT>(r1[t][r]);
-                            bz2[c * TB + 16 * t + 4 * q + r] = dz2[t][r];
-                            bz1[c * TB + 16 * t + 4 * q + r] = dz1[t][r];
+                            const int o = c * TB + ((16 * t + 4 * q + r) ^ swz_w);
+                            bh[o] = act_value<ACT>(r1[t][r]);
+                            bz2[o] = dz2[t][r];
                         }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    float ha[2][4], zb2[2][4], zb1[2][4];
+                    float ha[2][4], zb2[2][4];
 #pragma unroll
                     for (int x = 0; x < 2; ++x)
 #pragma unroll
                         for (int st = 0; st < 4; ++st) {
-                            const int o = (4 * st + q) * TB + 16 * x + c;
+                            const int o = (4 * st + q) * TB + ((16 * x + c) ^ tr_swz(4 * st + q));
                             ha[x][st] = bh[o];
                             zb2[x][st] = bz2[o];
-                            zb1[x][st] = bz1[o];
                         }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    // dW2[j][o] += sum over the tile's nodes h1[j] dz2[o];
-                    // dW1[k][j] += x_g[k] dz1[j], x_g = chi_s x_pi.
+                    // dW2[j][o] += sum over the tile's nodes h1[j] dz2[o].
 #pragma unroll
                     for (int x = 0; x < 2; ++x)
 #pragma unroll
                         for (int y = 0; y < 2; ++y)
 #pragma unroll
-                            for (int st = 0; st < 4; ++st) {
-                                gW2[x][y] = mfma4(ha[x][st], zb2[y][st], gW2[x][y]);
-                                gW1[x][y] = mfma4(refl_sign(s, clsc[x]) * xa[x][st], zb1[y][st], gW1[x][y]);
-                            }
+                            for (int st = 0; st < 4; ++st) gW2[x][y] = mfma4(ha[x][st], zb2[y][st], gW2[x][y]);
                 }
-                // dL/dm of this permutation: row k feeds from moment src_pi(k).
+                // The first layer's input x_g = chi_s x_pi differs between
+                // the reflections only by the sign chi_s(class k) of each
+                // row, so dx_g and the dW1 terms of the 8 reflections need
+                // dz1 only through Z_cl = sum_s chi_s(cl) dz1_s (the
+                // Walsh-Hadamard transform over s, the same butterfly as
+                // the forward's): dL/dm[k] = (W1 Z_class(k))[k] and
+                // dW1[k][j] += x_pi[k] Z_class(k)[j].  With the rows grouped
+                // by class, four classes per 16-row tile, each runs once
+                // per class instead of once per reflection.
 #pragma unroll
-                for (int kt = 0; kt < 2; ++kt)
+                for (int bit = 1; bit < 8; bit <<= 1)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int k = 16 * kt + 4 * q + r;
-                        if (k < 27) sdm[node * 32 + sgs[pi * 27 + k]] += D[kt][r];
+                    for (int ci = 0; ci < 8; ++ci)
+                        if (!(ci & bit))
+#pragma unroll
+                            for (int t = 0; t < 2; ++t) {
+                                const f32x4 u0 = Z[ci][t], u1 = Z[ci | bit][t];
+                                Z[ci][t] = u0 + u1;
+                                Z[ci | bit][t] = u0 - u1;
+                            }
+                // dL/dm of this permutation: the row at position
+                // 16 kt + 4 q + r feeds from moment src_pi(row).
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) {
+                    float D[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int cl = adj_tile_class(kt, i);
+                        f32x4 dx = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) dx = mfma4(W1T[kt][t][r], Z[cl][t][r], dx);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) D[r] = cls[kt][r] == cl ? dx[r] : D[r];
                     }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (rowo[kt][r] < 27) sdm[node * 32 + sgs[pi * 27 + rowo[kt][r]]] += D[r];
+                }
+                // dW1 per class: A = the tile's x_pi rows of that class.
+#pragma unroll
+                for (int cl = 0; cl < 8; ++cl) {
+                    const int x = (cl == 0 || cl == 1 || cl == 3 || cl == 7) ? 0 : 1;
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) bz1[c * TB + ((16 * t + 4 * q + r) ^ swz_w)] = Z[cl][t][r];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    float zb1[2][4];
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+#pragma unroll
+                        for (int st = 0; st < 4; ++st)
+                            zb1[y][st] = bz1[(4 * st + q) * TB + ((16 * y + c) ^ tr_swz(4 * st + q))];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const bool mine = clsc[x] == cl;
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+#pragma unroll
+                        for (int st = 0; st < 4; ++st)
+                            gW1[x][y] = mfma4(mine ? xa[x][st] : 0.0f, zb1[y][st], gW1[x][y]);
+                }
             }
         }
     }
@@ -910,7 +990,8 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
         out[OFF_W2 + e] += (double)v;
     }
     __syncthreads();
-    // dW1 and db1: lane (q, c) holds [k = 16 x + 4 q + r][j = 16 y + c]; row 27 is b1.
+    // dW1 and db1: lane (q, c) holds [position 16 x + 4 q + r][j = 16 y + c];
+    // the position's row is adj_row (27 is b1, 28 empty).
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -918,9 +999,13 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
 #pragma unroll
             for (int r = 0; r < 4; ++r) red[wave * 1024 + (16 * x + 4 * q + r) * 32 + 16 * y + c] = gW1[x][y][r];
     __syncthreads();
-    for (int e = tid; e < 28 * 32; e += 256) {
+    // Rows are tile positions (class-grouped): back to the parameter order.
+    const int* __restrict__ adj_rows = reinterpret_cast<const int*>(adj_tab + ADJ_ROWS_AT);
+    for (int e = tid; e < 32 * 32; e += 256) {
+        const int k = adj_rows[e >> 5], j = e & 31;
+        if (k > 27) continue;
         const float v = red[e] + red[1024 + e] + red[2048 + e] + red[3072 + e];
-        out[(e < 27 * 32 ? OFF_W1 + e : OFF_B1 + e - 27 * 32)] += (double)v;
+        out[(k < 27 ? OFF_W1 + k * 32 + j : OFF_B1 + j)] += (double)v;
     }
     __syncthreads();
     // db2: lane (q, c) holds rows o = 16 u + 4 q + r summed over its nodes c.
@@ -1093,7 +1178,7 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
             }
 }
 
-size_t mfma_adjoint_table_floats() { return 64 * ADJ_WORDS; }
+size_t mfma_adjoint_table_floats() { return 64 * ADJ_WORDS + 32; }
 
 // Per-lane table of the matrix-core adjoint from the flat parameters of a
 // width-32 network (unfolded weights: the adjoint works with h = tanh(z)).
@@ -1112,7 +1197,7 @@ void mfma_prepare_adjoint_table(const float* params, float* tab) {
         for (int kt = 0; kt < 2; ++kt)
             for (int t = 0; t < 2; ++t)
                 for (int r = 0; r < 4; ++r) {
-                    const int k = 16 * kt + c;
+                    const int k = adj_row(16 * kt + c);
                     at[AT_W1T + kt * 8 + t * 4 + r] = k < 27 ? W1[k * W + 16 * t + 4 * q + r] : 0.0f;
                 }
         for (int u = 0; u < 2; ++u)
@@ -1120,10 +1205,18 @@ void mfma_prepare_adjoint_table(const float* params, float* tab) {
                 for (int n = 0; n < 4; ++n)
                     at[AT_W3 + (u * 4 + r) * 4 + n] = W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
         for (int kt = 0; kt < 2; ++kt) {
-            for (int r = 0; r < 4; ++r) ai[AT_CLS + kt * 4 + r] = row_class(16 * kt + 4 * q + r);
-            ai[AT_CLSC + kt] = row_class(16 * kt + c);
+            for (int r = 0; r < 4; ++r) {
+                const int k = adj_row(16 * kt + 4 * q + r);
+                ai[AT_CLS + kt * 4 + r] = k < 28 ? moment_class(k) : -1;
+                ai[AT_ROWO + kt * 4 + r] = k;
+            }
+            const int k = adj_row(16 * kt + c);
+            ai[AT_CLSC + kt] = k < 28 ? moment_class(k) : -1;
+            ai[AT_ROWC + kt] = k;
         }
     }
+    int* rows = reinterpret_cast<int*>(tab + ADJ_ROWS_AT);
+    for (int p = 0; p < 32; ++p) rows[p] = adj_row(p);
 }
 
 // One 4-wavefront block per CU (the kernel's registers): with 256-node
