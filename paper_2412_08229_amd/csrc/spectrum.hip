@@ -111,20 +111,18 @@ __global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, size_
     if (i < count) p[i] = 0.0;
 }
 
-// One block per shell: fixed-order strided sums, then a fixed tree.
+// One block per shell: fixed-order strided sums, a wavefront shuffle
+// reduction, then the four wavefront sums in order.
 __global__ __launch_bounds__(256) void k_shell_final(const double* __restrict__ partial, int rows,
                                                      double* __restrict__ E) {
     const int b = blockIdx.x;
     double s = 0.0;
     for (int r = threadIdx.x; r < rows; r += blockDim.x) s += partial[(size_t)b * rows + r];
-    __shared__ double red[256];
-    red[threadIdx.x] = s;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) E[b] = red[0];
+    if (threadIdx.x == 0) E[b] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // dL/dE at every wavevector: A[c][e] *= dL/dE(shell of e).
