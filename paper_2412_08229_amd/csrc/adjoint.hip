@@ -27,22 +27,38 @@ namespace {
 // row of NPAR3 values.
 //
 // A block holds 64 nodes (one per lane) and SPLIT wavefronts.  Wavefront w
-// takes the group elements w G .. w G + G - 1, G = 48 / SPLIT, of every
-// node in both passes, with its own LDS rows, so the serial chain of one
-// lane is G group elements instead of 48.  The per-node parts (the group
+// takes the group elements w G .. w G + G - 1, G = 48 / SPLIT (without the
+// split over blocks below), of every node in both passes, with its own LDS
+// rows, so the serial chain of one lane is G group elements instead of 48.  The per-node parts (the group
 // sum of pass 1, the collision adjoint) are formed from the wavefronts'
 // partial sums in a fixed order; every wavefront writes its own partial
-// gradient row, blockIdx.x * SPLIT + w, and wavefront 0 scatters dL/dx.
-template <int S, int ACT, int DEPTH, int SPLIT>
+// gradient row, and wavefront 0 scatters dL/dx.
+//
+// On lattices too small to fill the device the group elements are also
+// split over gridDim.y blocks per 64 nodes (MODE != ADJ_WHOLE), in three
+// launches that exchange through xwork: ADJ_SUMS writes each block's share
+// of the group sum of pass 1 ([gridDim.y][n][W]); ADJ_MAIN adds the shares
+// in block order, runs pass 2 on its own elements and writes its share of
+// the network's dL/dm ([gridDim.y][27][n], paper row order), the blocks with
+// blockIdx.y = 0 also the collision's part of dL/dx before streaming
+// ([27][n]); k_adjoint_finish adds the shares in order and scatters.
+// Block (x, y) wavefront w takes the group elements from
+// (y SPLIT + w) Gw, Gw = 48 / (gridDim.y SPLIT), and writes gradient row
+// (y gridDim.x + x) SPLIT + w.
+constexpr int ADJ_WHOLE = 0, ADJ_SUMS = 1, ADJ_MAIN = 2;
+
+template <int S, int ACT, int DEPTH, int SPLIT, int MODE = ADJ_WHOLE>
 __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>::store_t* __restrict__ xin,
                                                 const float* __restrict__ lam_in, float* __restrict__ lam_out,
                                                 StepArgs a, const int* __restrict__ gsrc,
-                                                float* __restrict__ partial) {
+                                                float* __restrict__ partial, float* __restrict__ xwork) {
     constexpr int W = AW;
     constexpr int W3X = DEPTH == 3 ? W : 1;     // extent of the third layer's arrays
     constexpr int ROW = DEPTH == 3 ? NPAR3 : NPAR;
     static_assert(NGROUP % SPLIT == 0, "the group elements split evenly over the wavefronts");
-    constexpr int G = NGROUP / SPLIT;
+    const int GY = gridDim.y, gy = blockIdx.y;
+    const int G = NGROUP / (SPLIT * GY);        // group elements per wavefront
+    const int g0 = (gy * SPLIT + (int)(threadIdx.x >> 6)) * G;
     // Network (unstacked W1 [27][W], b1, W2 [W][W], b2, W3 [W][4], b3), read
     // by every lane with the same address (LDS broadcast).
     __shared__ float s_w1[27 * W], s_b1[W], s_w2[W * W], s_b2[W], s_w3[W * 4], s_b3[4];
@@ -109,7 +125,7 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
 #pragma unroll
     for (int o = 0; o < W; ++o) S2[o] = 0.0f;
 #pragma unroll 1
-    for (int g = wave * G; g < wave * G + G; ++g) {
+    for (int g = g0; g < (MODE == ADJ_MAIN ? g0 : g0 + G); ++g) {
         const int* __restrict__ gs = gsrc + g * 27;
         float h[W];
 #pragma unroll
@@ -147,8 +163,8 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
             for (int o = 0; o < W; ++o) S2[o] += act_f<ACT>(z3[o]);
         }
     }
-    if constexpr (SPLIT > 1) {
-        // The full group sum, in wavefront order (every wavefront the same).
+    if constexpr (SPLIT > 1 && MODE != ADJ_MAIN) {
+        // The block's group sum, in wavefront order (every wavefront the same).
 #pragma unroll
         for (int o = 0; o < W; ++o) s_h1[wave][lane][o] = S2[o];
         __syncthreads();
@@ -160,6 +176,19 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
             S2[o] = t;
         }
         __syncthreads();
+    }
+    if constexpr (MODE == ADJ_SUMS) {
+        if (wave == 0 && live)
+#pragma unroll
+            for (int o = 0; o < W; ++o) xwork[((size_t)gy * a.n + idx) * W + o] = S2[o];
+        return;
+    }
+    if constexpr (MODE == ADJ_MAIN) {
+        // The full group sum: the blocks' shares in block order.
+        if (live)
+            for (int y = 0; y < GY; ++y)
+#pragma unroll
+                for (int o = 0; o < W; ++o) S2[o] += xwork[((size_t)y * a.n + idx) * W + o];
     }
     float tt[4], omega[4], tau[4];
 #pragma unroll
@@ -219,7 +248,7 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
 
     // Pass 2: per group element, recompute, back-propagate, reduce.
 #pragma unroll 1
-    for (int g = wave * G; g < wave * G + G; ++g) {
+    for (int g = g0; g < g0 + G; ++g) {
         const int* __restrict__ gs = gsrc + g * 27;
         float h1[W];
 #pragma unroll
@@ -349,24 +378,48 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
     // dL/dy = lambda + M^T g_m, with the network's share of g_m from the
     // wavefronts' s_dm rows (in wavefront order); wavefront 0 scatters.
     __syncthreads();
-    float* __restrict__ out = partial + ((size_t)blockIdx.x * SPLIT + wave) * ROW;
+    float* __restrict__ out = partial + (((size_t)gy * gridDim.x + blockIdx.x) * SPLIT + wave) * ROW;
     if (wave == 0) {
+        if constexpr (MODE == ADJ_MAIN) {
+            // This block's share of the network's dL/dm; the collision's part
+            // of dL/dx before streaming from the first block of the node.
+            if (live) {
+                float* __restrict__ dmo = xwork + (size_t)GY * a.n * W + (size_t)gy * Q * a.n + idx;
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            float t = s_dm[0][lane][k];
+                for (int k = 0; k < Q; ++k) {
+                    float t = s_dm[0][lane][k];
 #pragma unroll
-            for (int w = 1; w < SPLIT; ++w) t += s_dm[w][lane][k];
-            gm[row_tensor(k)] += t;
+                    for (int w = 1; w < SPLIT; ++w) t += s_dm[w][lane][k];
+                    dmo[(size_t)k * a.n] = t;
+                }
+                if (gy == 0) {
+                    float gf[Q];
+                    moments_T(gm, gf);
+                    float* __restrict__ v0 = xwork + (size_t)GY * a.n * (W + Q) + idx;
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) v0[(size_t)i * a.n] = lam[i] + gf[i];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                float t = s_dm[0][lane][k];
+#pragma unroll
+                for (int w = 1; w < SPLIT; ++w) t += s_dm[w][lane][k];
+                gm[row_tensor(k)] += t;
+            }
+            float gf[Q];
+            moments_T(gm, gf);
+            // Scatter back along the streaming: the slot the pull read.
+            if (live) {
+                float v[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) v[i] = lam[i] + gf[i];
+                scatter_to_sources(lam_out, a, p, v);
+            }
         }
-        float gf[Q];
-        moments_T(gm, gf);
-        // Scatter back along the streaming: the slot the pull read.
-        if (live) {
-            float v[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) v[i] = lam[i] + gf[i];
-            scatter_to_sources(lam_out, a, p, v);
-        }
+    }
+    if (wave == 0 && gy == 0) {
 
         // Output-layer gradients: dW3 = sum (S2/48) dtt^T, db3 = sum dtt.
 #pragma unroll
@@ -387,7 +440,7 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
         out[OFF_W3 + e1] = w3b;
         if (lane < 4) out[OFF_B3 + lane] = b3a;
     } else {
-        // The output layer's gradient is wavefront 0's.
+        // The output layer's gradient is that of wavefront 0 of the first block.
         out[OFF_W3 + 2 * lane] = 0.0f;
         out[OFF_W3 + 2 * lane + 1] = 0.0f;
         if (lane < 4) out[OFF_B3 + lane] = 0.0f;
@@ -420,13 +473,49 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
 
 // grad[p] += sum over blocks of partial[b][p] (rows of npar), in block
 // order, in float64.
-__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial, int nblocks, int npar,
+// The split reverse step's last part: dL/dx before streaming is the
+// collision's part plus M^T of the network's dL/dm (the blocks' shares
+// added in order), scattered back along the streaming.
+__global__ __launch_bounds__(64) void k_adjoint_finish(float* __restrict__ lam_out, StepArgs a, int gy_count,
+                                                        const float* __restrict__ xwork) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n) return;
+    const float* __restrict__ dm = xwork + (size_t)gy_count * a.n * AW + idx;     // [gy][27][n]
+    const float* __restrict__ v0 = xwork + (size_t)gy_count * a.n * (AW + Q) + idx;  // [27][n]
+    float gm[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        float t = dm[(size_t)k * a.n];
+        for (int y = 1; y < gy_count; ++y) t += dm[((size_t)y * Q + k) * a.n];
+        gm[row_tensor(k)] = t;
+    }
+    float gf[Q], v[Q];
+    moments_T(gm, gf);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = v0[(size_t)i * a.n] + gf[i];
+    scatter_to_sources(lam_out, a, node_of(idx, a.nx, a.ny), v);
+}
+
+// grad[p] += sum over the rows of partial[row][p], in a fixed order: a block
+// takes 8 parameters, its 32 row slices (rows s, s + 32, ...) are summed by
+// 32 threads each, then the slices in order.  Many partial rows (the split
+// reverse step of small lattices writes thousands) are spread over 256
+// threads per 8 parameters instead of one thread per parameter.
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ partial, int nrows, int npar,
                                                      double* __restrict__ grad) {
-    const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pidx >= npar) return;
+    const int pl = threadIdx.x & 7, sl = threadIdx.x >> 3;
+    const int pidx = blockIdx.x * 8 + pl;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += (double)partial[(size_t)b * npar + pidx];
-    grad[pidx] += s;
+    if (pidx < npar)
+        for (int b = sl; b < nrows; b += 32) s += (double)partial[(size_t)b * npar + pidx];
+    __shared__ double red[32][8];
+    red[sl][pl] = s;
+    __syncthreads();
+    if (threadIdx.x < 8 && blockIdx.x * 8 + (int)threadIdx.x < npar) {
+        double t = 0.0;
+        for (int k = 0; k < 32; ++k) t += red[k][threadIdx.x];
+        grad[blockIdx.x * 8 + threadIdx.x] += t;
+    }
 }
 
 // stage[g][p] = sum of partial[64 g .. 64 g + 63][p] in row order.
@@ -717,22 +806,63 @@ static int adjoint_split(int n, int depth) {
     return (n + 63) / 64 <= ADJ_SPLIT_D2_MAX_BLOCKS ? ADJ_SPLIT_D2 : 1;
 }
 
-int adjoint_blocks(int n, int depth) { return (n + 63) / 64 * adjoint_split(n, depth); }
+// Blocks per 64 nodes (gridDim.y) of the depth-3 reverse step: doubled while
+// the grid stays within two blocks per compute unit (a block holds ~160 KiB
+// of LDS, so one runs per CU at a time) and the 48 group elements still
+// divide evenly, so that small lattices (the reduced Taylor-Green cubes)
+// fill the device instead of running 48 / 3 elements per lane in series.
+// Depth 2 keeps one block per 64 nodes.
+static int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus[dev] = 256;
+    return cus[dev] > 0 ? cus[dev] : 256;
+}
+static int adjoint_gsplit(int n, int depth) {
+    if (depth != 3) return 1;
+    const int nb = (n + 63) / 64, target = 2 * device_cus();
+    int gy = 1;
+    while (nb * gy * 2 <= target && NGROUP % (2 * gy * ADJ_SPLIT_D3) == 0) gy *= 2;
+    return gy;
+}
+
+int adjoint_blocks(int n, int depth) { return (n + 63) / 64 * adjoint_gsplit(n, depth) * adjoint_split(n, depth); }
+
+size_t adjoint_xwork_floats(int n, int depth) {
+    const int gy = adjoint_gsplit(n, depth);
+    return gy > 1 ? (size_t)gy * n * (AW + Q) + (size_t)n * Q : 0;
+}
 
 hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
-                          const int* gsrc, float* partial, hipStream_t st) {
+                          const int* gsrc, float* partial, float* xwork, hipStream_t st) {
     const int split = adjoint_split(a.n, a.depth);
-    const dim3 grid((a.n + 63) / 64), block(64 * split);
-#define ADJ_LAUNCH(SS, ACT, DEPTH, SPLIT)                                                                    \
-    hipLaunchKernelGGL((k_adjoint<SS, ACT, DEPTH, SPLIT>), grid, block, 0, st,                                \
-                       static_cast<const typename Codec<SS>::store_t*>(xin), lam_in, lam_out, a, gsrc, partial)
+    const int gy = adjoint_gsplit(a.n, a.depth);
+    if (gy > 1 && !xwork) return hipErrorInvalidValue;
+    const dim3 grid((a.n + 63) / 64, gy), block(64 * split);
+#define ADJ_LAUNCH_M(SS, ACT, DEPTH, SPLIT, MODE)                                                            \
+    hipLaunchKernelGGL((k_adjoint<SS, ACT, DEPTH, SPLIT, MODE>), grid, block, 0, st,                          \
+                       static_cast<const typename Codec<SS>::store_t*>(xin), lam_in, lam_out, a, gsrc, partial, \
+                       xwork)
+#define ADJ_LAUNCH(SS, ACT, DEPTH, SPLIT) ADJ_LAUNCH_M(SS, ACT, DEPTH, SPLIT, ADJ_WHOLE)
+#define ADJ_LAUNCH_D3(SS, ACT)                                                                               \
+    if (gy > 1) {                                                                                            \
+        ADJ_LAUNCH_M(SS, ACT, 3, ADJ_SPLIT_D3, ADJ_SUMS);                                                    \
+        ADJ_LAUNCH_M(SS, ACT, 3, ADJ_SPLIT_D3, ADJ_MAIN);                                                    \
+        hipLaunchKernelGGL(k_adjoint_finish, dim3((a.n + 63) / 64), dim3(64), 0, st, lam_out, a, gy,         \
+                           (const float*)xwork);                                                             \
+    } else {                                                                                                 \
+        ADJ_LAUNCH(SS, ACT, 3, ADJ_SPLIT_D3);                                                                \
+    }
 #define ADJ_CASE(SS)                                                                                         \
     case SS:                                                                                                 \
         if (a.depth == 3) {                                                                                  \
-            if (a.act == ACT_TANH)                                                                           \
-                ADJ_LAUNCH(SS, ACT_TANH, 3, ADJ_SPLIT_D3);                                                   \
-            else                                                                                             \
-                ADJ_LAUNCH(SS, ACT_RELU, 3, ADJ_SPLIT_D3);                                                   \
+            if (a.act == ACT_TANH) {                                                                         \
+                ADJ_LAUNCH_D3(SS, ACT_TANH)                                                                  \
+            } else {                                                                                         \
+                ADJ_LAUNCH_D3(SS, ACT_RELU)                                                                  \
+            }                                                                                                \
         } else if (split > 1) {                                                                              \
             if (a.act == ACT_TANH)                                                                           \
                 ADJ_LAUNCH(SS, ACT_TANH, 2, ADJ_SPLIT_D2);                                                   \
@@ -752,11 +882,13 @@ hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, flo
         default: return hipErrorInvalidValue;
     }
 #undef ADJ_CASE
+#undef ADJ_LAUNCH_D3
 #undef ADJ_LAUNCH
+#undef ADJ_LAUNCH_M
 }
 
 hipError_t launch_grad_reduce(const float* partial, int nblocks, int npar, double* grad, hipStream_t st) {
-    hipLaunchKernelGGL(k_grad_reduce, dim3((npar + 255) / 256), dim3(256), 0, st, partial, nblocks, npar, grad);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((npar + 7) / 8), dim3(256), 0, st, partial, nblocks, npar, grad);
     return hipGetLastError();
 }
 

@@ -216,6 +216,8 @@ struct nco_lattice {
     float* lam[2] = {nullptr, nullptr};
     float* adj_partial = nullptr;
     size_t adj_partial_floats = 0;
+    float* adj_xwork = nullptr;   // exchange space of the split depth-3 reverse step
+    size_t adj_xwork_floats = 0;
     double* d_grad = nullptr;
     double* d_dE = nullptr;
     int* d_gsrc = nullptr;        // [48][27] group source row | sign bit
@@ -499,6 +501,7 @@ int nco_lattice_destroy(nco_lattice* lat) {
     for (int b = 0; b < 2; ++b)
         if (lat->lam[b]) hipFree(lat->lam[b]);
     if (lat->adj_partial) hipFree(lat->adj_partial);
+    if (lat->adj_xwork) hipFree(lat->adj_xwork);
     if (lat->d_grad) hipFree(lat->d_grad);
     if (lat->d_dE) hipFree(lat->d_dE);
     if (lat->d_gsrc) hipFree(lat->d_gsrc);
@@ -1103,6 +1106,15 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
         HIP_TRY(hipMalloc(&lat->adj_partial, sizeof(float) * (size_t)nblk * npar));
         lat->adj_partial_floats = (size_t)nblk * npar;
     }
+    if (!mfma && adjoint_xwork_floats(lat->n, lat->depth) > lat->adj_xwork_floats) {
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        if (lat->adj_xwork) HIP_TRY(hipFree(lat->adj_xwork));
+        lat->adj_xwork = nullptr;
+        lat->adj_xwork_floats = 0;
+        const size_t nx = adjoint_xwork_floats(lat->n, lat->depth);
+        HIP_TRY(hipMalloc(&lat->adj_xwork, sizeof(float) * nx));
+        lat->adj_xwork_floats = nx;
+    }
     if (!lat->d_grad) HIP_TRY(hipMalloc(&lat->d_grad, sizeof(double) * adjoint_param_count_depth(3)));
     while ((int)lat->seg.size() < lat->rec_every) {
         void* p = nullptr;
@@ -1154,7 +1166,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
                                             lat->d_gsrc, lat->adj_partial64, lat->stream));
             } else {
                 HIP_TRY(launch_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_gsrc, lat->adj_partial,
-                                       lat->stream));
+                                       lat->adj_xwork, lat->stream));
                 HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, npar, lat->d_grad, lat->stream));
             }
             if (phase) {

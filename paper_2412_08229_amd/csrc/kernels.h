@@ -164,8 +164,11 @@ hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchG
 int adjoint_param_count();
 // Partial gradient rows of one launch_adjoint (several per 64-node block).
 int adjoint_blocks(int n, int depth);
+size_t adjoint_xwork_floats(int n, int depth);
+// xwork: adjoint_xwork_floats(n, depth) floats of exchange space for the
+// split reverse step of small depth-3 lattices (may be null when that is 0).
 hipError_t launch_adjoint(int storage, const void* xin, const float* lam_in, float* lam_out, const StepArgs& a,
-                          const int* gsrc, float* partial, hipStream_t st);
+                          const int* gsrc, float* partial, float* xwork, hipStream_t st);
 hipError_t launch_grad_reduce(const float* partial, int nblocks, int npar, double* grad, hipStream_t st);
 int adjoint_param_count_depth(int depth);
 // lam += coef d(sum over nodes of |u|^2 / 2) / df for the state f (float64 arithmetic).
