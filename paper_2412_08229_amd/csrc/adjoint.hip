@@ -47,27 +47,36 @@ namespace {
 // (y gridDim.x + x) SPLIT + w.
 constexpr int ADJ_WHOLE = 0, ADJ_SUMS = 1, ADJ_MAIN = 2;
 
+typedef const __attribute__((address_space(4))) float cfloat;
+
 template <int S, int ACT, int DEPTH, int SPLIT, int MODE = ADJ_WHOLE>
 __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>::store_t* __restrict__ xin,
                                                 const float* __restrict__ lam_in, float* __restrict__ lam_out,
                                                 StepArgs a, const int* __restrict__ gsrc,
                                                 float* __restrict__ partial, float* __restrict__ xwork) {
     constexpr int W = AW;
-    constexpr int W3X = DEPTH == 3 ? W : 1;     // extent of the third layer's arrays
     constexpr int ROW = DEPTH == 3 ? NPAR3 : NPAR;
     static_assert(NGROUP % SPLIT == 0, "the group elements split evenly over the wavefronts");
     const int GY = gridDim.y, gy = blockIdx.y;
     const int G = NGROUP / (SPLIT * GY);        // group elements per wavefront
     const int g0 = (gy * SPLIT + (int)(threadIdx.x >> 6)) * G;
     // Network (unstacked W1 [27][W], b1, W2 [W][W], b2, W3 [W][4], b3), read
-    // by every lane with the same address (LDS broadcast).
-    __shared__ float s_w1[27 * W], s_b1[W], s_w2[W * W], s_b2[W], s_w3[W * 4], s_b3[4];
-    __shared__ float s_w2b[W3X * W3X], s_b2b[W3X];
-    __shared__ float s_h2[SPLIT][64][W3X];
-    __shared__ float s_d3[SPLIT][64][W3X];
+    // by every lane at the same address: through the constant address space,
+    // so that the weights come by scalar loads into scalar registers and feed
+    // the FMAs directly (no LDS traffic, no vector registers).
+    const float* const net = a.net;
+    cfloat* __restrict__ c_w1 = (cfloat*)net;     // the identity element's slice
+    cfloat* __restrict__ c_b1 = (cfloat*)(net + net_off_b1(W));
+    cfloat* __restrict__ c_w2 = (cfloat*)(net + net_off_w2(W));
+    cfloat* __restrict__ c_b2 = (cfloat*)(net + net_off_b2(W));
+    cfloat* __restrict__ c_w3 = (cfloat*)(net + net_off_w3(W));
+    cfloat* __restrict__ c_b3 = (cfloat*)(net + net_off_b3(W));
+    cfloat* __restrict__ c_w2b = (cfloat*)(net + net_off_w2b(W));
+    cfloat* __restrict__ c_b2b = (cfloat*)(net + net_off_b2b(W));
     // Per-node rows: moments (paper order, [27] = 1); per wavefront dL/dm
     // and the vectors of the current group element for the parameter-
-    // gradient reduction.
+    // gradient reduction: h1, dz2 and dz1 (at depth 3 the last two rows hold
+    // h2 and dz3 first, for the third layer's reduction).
     __shared__ float s_m[64][28];
     __shared__ float s_dm[SPLIT][64][27];
     __shared__ float s_h1[SPLIT][64][W];
@@ -77,23 +86,6 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
     const int lane = tid & 63, wave = tid >> 6;
     const int idx = blockIdx.x * 64 + lane;
     const bool live = idx < a.n;
-    {
-        // Unstacked W1 is the identity element's slice (g = 0, no permutation).
-        const float* __restrict__ net = a.net;
-        for (int e = tid; e < 27 * W; e += 64 * SPLIT) s_w1[e] = net[e];
-        for (int e = tid; e < W * W; e += 64 * SPLIT) s_w2[e] = net[net_off_w2(W) + e];
-        for (int e = tid; e < W * 4; e += 64 * SPLIT) s_w3[e] = net[net_off_w3(W) + e];
-        if (tid < W) {
-            s_b1[tid] = net[net_off_b1(W) + tid];
-            s_b2[tid] = net[net_off_b2(W) + tid];
-        }
-        if (tid < 4) s_b3[tid] = net[net_off_b3(W) + tid];
-        if constexpr (DEPTH == 3) {
-            for (int e = tid; e < W * W; e += 64 * SPLIT) s_w2b[e] = net[net_off_w2b(W) + e];
-            if (tid < W) s_b2b[tid] = net[net_off_b2b(W) + tid];
-        }
-    }
-
     // Forward quantities of the node: pulled populations and moments (one
     // wavefront pulls; the others read the moments back).
     float m[Q];
@@ -129,22 +121,22 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
         const int* __restrict__ gs = gsrc + g * 27;
         float h[W];
 #pragma unroll
-        for (int j = 0; j < W; ++j) h[j] = s_b1[j];
+        for (int j = 0; j < W; ++j) h[j] = c_b1[j];
 #pragma unroll 3
         for (int k = 0; k < Q; ++k) {
             const int e = gs[k];
             const float xk = __int_as_float(__float_as_int(s_m[lane][e & 31]) ^ (e & (int)0x80000000));
 #pragma unroll
-            for (int j = 0; j < W; ++j) h[j] = fmaf(s_w1[k * W + j], xk, h[j]);
+            for (int j = 0; j < W; ++j) h[j] = fmaf(c_w1[k * W + j], xk, h[j]);
         }
         float z[W];
 #pragma unroll
-        for (int o = 0; o < W; ++o) z[o] = s_b2[o];
+        for (int o = 0; o < W; ++o) z[o] = c_b2[o];
 #pragma unroll 4
         for (int j = 0; j < W; ++j) {
             const float hj = act_f<ACT>(h[j]);
 #pragma unroll
-            for (int o = 0; o < W; ++o) z[o] = fmaf(s_w2[j * W + o], hj, z[o]);
+            for (int o = 0; o < W; ++o) z[o] = fmaf(c_w2[j * W + o], hj, z[o]);
         }
         if constexpr (DEPTH == 2) {
 #pragma unroll
@@ -152,12 +144,12 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
         } else {
             float z3[W];
 #pragma unroll
-            for (int o = 0; o < W; ++o) z3[o] = s_b2b[o];
+            for (int o = 0; o < W; ++o) z3[o] = c_b2b[o];
 #pragma unroll 4
             for (int j = 0; j < W; ++j) {
                 const float hj = act_f<ACT>(z[j]);
 #pragma unroll
-                for (int o = 0; o < W; ++o) z3[o] = fmaf(s_w2b[j * W + o], hj, z3[o]);
+                for (int o = 0; o < W; ++o) z3[o] = fmaf(c_w2b[j * W + o], hj, z3[o]);
             }
 #pragma unroll
             for (int o = 0; o < W; ++o) S2[o] += act_f<ACT>(z3[o]);
@@ -195,8 +187,8 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
     for (int n = 0; n < 4; ++n) {
         float t = 0.0f;
 #pragma unroll
-        for (int o = 0; o < W; ++o) t = fmaf(s_w3[o * 4 + n], S2[o], t);
-        tt[n] = t * (1.0f / NGROUP) + s_b3[n];
+        for (int o = 0; o < W; ++o) t = fmaf(c_w3[o * 4 + n], S2[o], t);
+        tt[n] = t * (1.0f / NGROUP) + c_b3[n];
         tau[n] = 0.5f + 0.5f / (1.0f + expf(tt[n]));
         omega[n] = 1.0f / tau[n];
     }
@@ -229,7 +221,7 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
     for (int o = 0; o < W; ++o) {
         float s = 0.0f;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) s = fmaf(s_w3[o * 4 + n], dtt[n], s);
+        for (int n = 0; n < 4; ++n) s = fmaf(c_w3[o * 4 + n], dtt[n], s);
         dh2[o] = s * (1.0f / NGROUP);
     }
 
@@ -252,13 +244,13 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
         const int* __restrict__ gs = gsrc + g * 27;
         float h1[W];
 #pragma unroll
-        for (int j = 0; j < W; ++j) h1[j] = s_b1[j];
+        for (int j = 0; j < W; ++j) h1[j] = c_b1[j];
 #pragma unroll 3
         for (int k = 0; k < Q; ++k) {
             const int e = gs[k];
             const float xk = __int_as_float(__float_as_int(s_m[lane][e & 31]) ^ (e & (int)0x80000000));
 #pragma unroll
-            for (int j = 0; j < W; ++j) h1[j] = fmaf(s_w1[k * W + j], xk, h1[j]);
+            for (int j = 0; j < W; ++j) h1[j] = fmaf(c_w1[k * W + j], xk, h1[j]);
         }
 #pragma unroll
         for (int j = 0; j < W; ++j) {
@@ -267,11 +259,11 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
         }
         float dz2[W];
 #pragma unroll
-        for (int o = 0; o < W; ++o) dz2[o] = s_b2[o];
+        for (int o = 0; o < W; ++o) dz2[o] = c_b2[o];
 #pragma unroll 4
         for (int j = 0; j < W; ++j)
 #pragma unroll
-            for (int o = 0; o < W; ++o) dz2[o] = fmaf(s_w2[j * W + o], h1[j], dz2[o]);
+            for (int o = 0; o < W; ++o) dz2[o] = fmaf(c_w2[j * W + o], h1[j], dz2[o]);
         if constexpr (DEPTH == 2) {
 #pragma unroll
             for (int o = 0; o < W; ++o) {
@@ -281,29 +273,51 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
         } else {
             // h2 = act(z2); z3 = W2b^T h2 + b2b; dz3 = dh3 act'(z3) with dh3
             // the output layer's adjoint (dh2 above); dz2 = (W2b dz3) act'(z2).
+            // h2 and dz3 go through the dz2 and dz1 rows, reduced into the
+            // third layer's gradient before dz2 and dz1 take their place.
 #pragma unroll
             for (int o = 0; o < W; ++o) {
                 dz2[o] = act_f<ACT>(dz2[o]);
-                s_h2[wave][lane][o] = dz2[o];
+                s_d2[wave][lane][o] = dz2[o];
             }
             float dz3[W];
 #pragma unroll
-            for (int o = 0; o < W; ++o) dz3[o] = s_b2b[o];
+            for (int o = 0; o < W; ++o) dz3[o] = c_b2b[o];
 #pragma unroll 4
             for (int j = 0; j < W; ++j)
 #pragma unroll
-                for (int o = 0; o < W; ++o) dz3[o] = fmaf(s_w2b[j * W + o], dz2[j], dz3[o]);
+                for (int o = 0; o < W; ++o) dz3[o] = fmaf(c_w2b[j * W + o], dz2[j], dz3[o]);
 #pragma unroll
             for (int o = 0; o < W; ++o) {
                 dz3[o] = dh2[o] * act_d<ACT>(act_f<ACT>(dz3[o]));
-                s_d3[wave][lane][o] = dz3[o];
+                s_d1[wave][lane][o] = dz3[o];
             }
+            // Only this wavefront's rows are exchanged: a wavefront barrier.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 4
+            for (int nd = 0; nd < 64; ++nd) {
+                float h2v[4], d3v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) h2v[i] = s_d2[wave][nd][r2 + i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) d3v[c] = s_d1[wave][nd][c2 + c];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc3[i][c] = fmaf(h2v[i], d3v[c], acc3[i][c]);
+                if (lane >= 64 - W) accb2b += s_d1[wave][nd][lane - (64 - W)];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll 4
             for (int j = 0; j < W; ++j) {
                 float t = 0.0f;
 #pragma unroll
-                for (int o = 0; o < W; ++o) t = fmaf(s_w2b[j * W + o], dz3[o], t);
-                dz2[j] = t * act_d<ACT>(s_h2[wave][lane][j]);
+                for (int o = 0; o < W; ++o) t = fmaf(c_w2b[j * W + o], dz3[o], t);
+                dz2[j] = t * act_d<ACT>(dz2[j]);       // dz2[j] held h2[j]
                 s_d2[wave][lane][j] = dz2[j];
             }
         }
@@ -312,7 +326,7 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
         for (int j = 0; j < W; ++j) {
             float s = 0.0f;
 #pragma unroll
-            for (int o = 0; o < W; ++o) s = fmaf(s_w2[j * W + o], dz2[o], s);
+            for (int o = 0; o < W; ++o) s = fmaf(c_w2[j * W + o], dz2[o], s);
             dz1[j] = s * act_d<ACT>(s_h1[wave][lane][j]);
             s_d1[wave][lane][j] = dz1[j];
         }
@@ -321,7 +335,7 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
         for (int k = 0; k < Q; ++k) {
             float s = 0.0f;
 #pragma unroll
-            for (int j = 0; j < W; ++j) s = fmaf(s_w1[k * W + j], dz1[j], s);
+            for (int j = 0; j < W; ++j) s = fmaf(c_w1[k * W + j], dz1[j], s);
             const int e = gs[k];
             s_dm[wave][lane][e & 31] += __int_as_float(__float_as_int(s) ^ (e & (int)0x80000000));
         }
@@ -356,18 +370,6 @@ __global__ __launch_bounds__(64 * SPLIT) void k_adjoint(const typename Codec<S>:
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc2[i][c] = fmaf(hv[i], d2v[c], acc2[i][c]);
             if (lane < W) accb2 += s_d2[wave][nd][lane];
-            if constexpr (DEPTH == 3) {
-                float h2v[4], d3v[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) h2v[i] = s_h2[wave][nd][r2 + i];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) d3v[c] = s_d3[wave][nd][c2 + c];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc3[i][c] = fmaf(h2v[i], d3v[c], acc3[i][c]);
-                if (lane >= 64 - W) accb2b += s_d3[wave][nd][lane - (64 - W)];
-            }
         }
         // Only this wavefront's rows are exchanged: a wavefront barrier.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -793,24 +795,24 @@ __global__ __launch_bounds__(256) void k_f32_to_f64(const float* __restrict__ sr
 
 int adjoint_param_count() { return NPAR; }
 int adjoint_param_count_depth(int depth) { return depth == 3 ? NPAR3 : NPAR; }
-// Wavefronts per 64-node block of the vector-unit adjoint: as many as the
-// 160 KiB of LDS holds (each keeps five [64][32] rows at depth 3, three at
-// depth 2), which shortens the serial chain of every lane.  Measured on the
-// reduced Taylor-Green cubes and periodic boxes from 16^3 to 96^3, the split
-// wins at every size at depth 3 (2.4x at 16^3, 1.1x at 96^3); at depth 2 it
-// wins up to ~2000 blocks, breaks even at 4096 and loses at 13824, where one
-// wavefront per block leaves room for more blocks per CU.
-constexpr int ADJ_SPLIT_D3 = 3, ADJ_SPLIT_D2 = 4, ADJ_SPLIT_D2_MAX_BLOCKS = 2048;
+// Wavefronts per 64-node block of the vector-unit adjoint: one per SIMD (each
+// keeps three [64][32] rows and its dL/dm rows in LDS, 130 KiB for four),
+// which shortens the serial chain of every lane.  Measured on the reduced
+// Taylor-Green cubes and periodic boxes from 16^3 to 96^3, the split wins at
+// every size at depth 3; at depth 2 it wins up to ~2000 blocks, breaks even
+// at 4096 and loses at 13824, where one wavefront per block leaves room for
+// more blocks per CU.
+constexpr int ADJ_SPLIT_D3 = 4, ADJ_SPLIT_D2 = 4, ADJ_SPLIT_D2_MAX_BLOCKS = 2048;
 static int adjoint_split(int n, int depth) {
     if (depth == 3) return ADJ_SPLIT_D3;
     return (n + 63) / 64 <= ADJ_SPLIT_D2_MAX_BLOCKS ? ADJ_SPLIT_D2 : 1;
 }
 
-// Blocks per 64 nodes (gridDim.y) of the depth-3 reverse step: doubled while
-// the grid stays within two blocks per compute unit (a block holds ~160 KiB
-// of LDS, so one runs per CU at a time) and the 48 group elements still
-// divide evenly, so that small lattices (the reduced Taylor-Green cubes)
-// fill the device instead of running 48 / 3 elements per lane in series.
+// Blocks per 64 nodes (gridDim.y) of the depth-3 reverse step: the largest
+// divisor of the 48 / SPLIT group elements per wavefront that keeps the grid
+// within two blocks per compute unit (a block holds 130 KiB of LDS, so one
+// runs per CU at a time), so that small lattices (the reduced Taylor-Green
+// cubes) fill the device instead of running 12 elements per lane in series.
 // Depth 2 keeps one block per 64 nodes.
 static int device_cus() {
     static int cus[64] = {};
@@ -822,9 +824,11 @@ static int device_cus() {
 }
 static int adjoint_gsplit(int n, int depth) {
     if (depth != 3) return 1;
-    const int nb = (n + 63) / 64, target = 2 * device_cus();
+    const int nb = (n + 63) / 64;
+    const int target = 2 * device_cus();
     int gy = 1;
-    while (nb * gy * 2 <= target && NGROUP % (2 * gy * ADJ_SPLIT_D3) == 0) gy *= 2;
+    for (int d = 2; d <= NGROUP / ADJ_SPLIT_D3; ++d)
+        if ((NGROUP / ADJ_SPLIT_D3) % d == 0 && nb * d <= target) gy = d;
     return gy;
 }
 

@@ -5,7 +5,8 @@
 // E(k) = 1/2 sum |u_hat|^2 over the integer wavevectors in [-n/2, n/2)^3 with
 // round(|k|) = k.  Lattice sizes such as 96 and 192 are not powers of two,
 // so the transform is a sum-factorised direct DFT: one O(n) dot product per
-// output element and axis (x, then y, then z), with a float64 twiddle table.
+// output element and axis (x, then y, then z), register-blocked over 64
+// frequencies and 16 lines per wavefront, with a float64 twiddle table.
 // The shell sums are deterministic: for each (k_z, k_y) row the k_x values
 // are visited in order of |k_x|, so the shell index never decreases and each
 // (shell, row) partial is written exactly once; a second kernel adds the
@@ -37,36 +38,101 @@ __global__ __launch_bounds__(256) void k_velocity(const typename Codec<S>::store
     u[2 * (size_t)n + idx] = jz / r;
 }
 
-// One axis of the forward DFT over a [3][n][n][n] field; AXIS 0 = x (stride
-// 1), 1 = y (stride n), 2 = z (stride n^2).  REAL_IN reads a real field.
-// CONJ = true applies the conjugate twiddles (the unnormalised inverse DFT).
+// One axis of the DFT over a [3][n][n][n] field, out[k] = sum_j w^(j k) in[j]
+// along AXIS (0 = x, stride 1; 1 = y, stride n; 2 = z, stride n^2) for every
+// one of the 3 n^2 lines ("columns"), w = exp(-2 pi i / n), or its conjugate
+// with CONJ (the unnormalised inverse).  REAL_IN reads a real field.
+//
+// Register-blocked: a block of 8 wavefronts takes 128 columns and 64
+// frequencies; lane l of wavefront v accumulates frequency k0 + l for the
+// columns 16 v .. 16 v + 15.  The inputs come through LDS in chunks of 32
+// along the axis (loaded once per block, read by every lane of a wavefront
+// at the same address), and a lane's twiddle w^(j k) starts each chunk from
+// the table and is advanced by w^k from one j to the next.  Every input is
+// loaded once per 64 frequencies instead of once per output, and a complex
+// multiply-add is 4 FMAs on operands in registers.
+constexpr int DB_COLS = 128, DB_CPW = 16, DB_KB = 64, DB_JC = 32, DB_THREADS = 512;
+
+template <int AXIS>
+__device__ __forceinline__ size_t dft_base(size_t col, int n) {
+    const size_t nn = (size_t)n * n;
+    if constexpr (AXIS == 0) return col * n;
+    else if constexpr (AXIS == 1) return (col / n) * nn + col % n;
+    else return (col / nn) * nn * n + col % nn;
+}
+
+template <int AXIS>
+__device__ __forceinline__ size_t dft_stride(int n) {
+    return AXIS == 0 ? 1 : AXIS == 1 ? (size_t)n : (size_t)n * n;
+}
+
 template <int AXIS, bool REAL_IN, bool CONJ = false>
-__global__ __launch_bounds__(256) void k_dft_axis(const void* __restrict__ in_, double2* __restrict__ out,
-                                                  const double2* __restrict__ tw, int n) {
-    const size_t n3 = (size_t)n * n * n;
-    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= 3 * n3) return;
-    const size_t stride = AXIS == 0 ? 1 : AXIS == 1 ? (size_t)n : (size_t)n * n;
-    const int k = (int)((gid / stride) % n);
-    const size_t base = gid - (size_t)k * stride;
-    double re = 0.0, im = 0.0;
-    int m = 0;
-    for (int j = 0; j < n; ++j) {
-        double2 w = tw[m];
-        if constexpr (CONJ) w.y = -w.y;
-        if constexpr (REAL_IN) {
-            const double v = static_cast<const double*>(in_)[base + (size_t)j * stride];
-            re = fma(v, w.x, re);
-            im = fma(v, w.y, im);
-        } else {
-            const double2 v = static_cast<const double2*>(in_)[base + (size_t)j * stride];
-            re = fma(v.x, w.x, fma(-v.y, w.y, re));
-            im = fma(v.x, w.y, fma(v.y, w.x, im));
-        }
-        m += k;
-        if (m >= n) m -= n;
+__global__ __launch_bounds__(DB_THREADS) void k_dft_axis(const void* __restrict__ in_, double2* __restrict__ out,
+                                                         const double2* __restrict__ tw, int n) {
+    // x: [column][j], so that the loads along a line write consecutive LDS
+    // words; y, z: [j][column].  Either way a wavefront reads one word.
+    __shared__ double2 tile[DB_JC * DB_COLS];
+    auto at_tile = [](int j, int c) { return AXIS == 0 ? c * DB_JC + j : j * DB_COLS + c; };
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k = blockIdx.y * DB_KB + lane;
+    const size_t ncol = 3 * (size_t)n * n;
+    const size_t col0 = (size_t)blockIdx.x * DB_COLS;
+    const size_t S = dft_stride<AXIS>(n);
+    double2 acc[DB_CPW];
+#pragma unroll
+    for (int c = 0; c < DB_CPW; ++c) acc[c] = make_double2(0.0, 0.0);
+    double2 wk = make_double2(1.0, 0.0);
+    if (k < n) {
+        wk = tw[k];
+        if constexpr (CONJ) wk.y = -wk.y;
     }
-    out[gid] = make_double2(re, im);
+    for (int j0 = 0; j0 < n; j0 += DB_JC) {
+        const int jn = min(DB_JC, n - j0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < DB_JC * DB_COLS; e += DB_THREADS) {
+            // x: a column's inputs are contiguous; y, z: a line of columns is.
+            const int j = AXIS == 0 ? e % DB_JC : e / DB_COLS;
+            const int c = AXIS == 0 ? e / DB_JC : e % DB_COLS;
+            double2 v = make_double2(0.0, 0.0);
+            if (j < jn && col0 + c < ncol) {
+                const size_t at = dft_base<AXIS>(col0 + c, n) + (size_t)(j0 + j) * S;
+                if constexpr (REAL_IN)
+                    v.x = static_cast<const double*>(in_)[at];
+                else
+                    v = static_cast<const double2*>(in_)[at];
+            }
+            tile[at_tile(j, c)] = v;
+        }
+        __syncthreads();
+        if (k < n) {
+            double2 w = tw[(int)(((long)j0 * k) % n)];
+            if constexpr (CONJ) w.y = -w.y;
+            for (int j = 0; j < jn; ++j) {
+#pragma unroll
+                for (int c = 0; c < DB_CPW; ++c) {
+                    const double2 v = tile[at_tile(j, wave * DB_CPW + c)];
+                    acc[c].x = fma(w.x, v.x, fma(-w.y, v.y, acc[c].x));
+                    acc[c].y = fma(w.x, v.y, fma(w.y, v.x, acc[c].y));
+                }
+                const double t = w.x * wk.x - w.y * wk.y;
+                w.y = w.x * wk.y + w.y * wk.x;
+                w.x = t;
+            }
+        }
+    }
+    if (k < n)
+#pragma unroll
+        for (int c = 0; c < DB_CPW; ++c) {
+            const size_t col = col0 + wave * DB_CPW + c;
+            if (col < ncol) out[dft_base<AXIS>(col, n) + (size_t)k * S] = acc[c];
+        }
+}
+
+// Launch of one axis pass over the [3][n][n][n] field.
+template <int AXIS, bool REAL_IN, bool CONJ = false>
+void dft_pass(const void* in, double2* out, const double2* tw, int n, hipStream_t st) {
+    const dim3 grid((unsigned)((3 * (size_t)n * n + DB_COLS - 1) / DB_COLS), (unsigned)((n + DB_KB - 1) / DB_KB));
+    hipLaunchKernelGGL((k_dft_axis<AXIS, REAL_IN, CONJ>), grid, dim3(DB_THREADS), 0, st, in, out, tw, n);
 }
 
 __device__ __forceinline__ int wavenumber(int idx, int n) { return idx < n - n / 2 ? idx : idx - n; }
@@ -256,15 +322,13 @@ hipError_t launch_spectrum_adjoint(int storage, const void* f, int n, void* work
         case ST_F64: hipLaunchKernelGGL(k_rho_u<ST_F64>, dim3(nb), dim3(256), 0, st, static_cast<const double*>(f), u, rho, n3); break;
         default: return hipErrorInvalidValue;
     }
-    const size_t tot = 3 * (size_t)n3;
-    const unsigned nbt = (unsigned)((tot + 255) / 256);
-    hipLaunchKernelGGL((k_dft_axis<0, true>), dim3(nbt), dim3(256), 0, st, (const void*)u, A, tw, n);
-    hipLaunchKernelGGL((k_dft_axis<1, false>), dim3(nbt), dim3(256), 0, st, (const void*)A, B, tw, n);
-    hipLaunchKernelGGL((k_dft_axis<2, false>), dim3(nbt), dim3(256), 0, st, (const void*)B, A, tw, n);
+    dft_pass<0, true>(u, A, tw, n, st);
+    dft_pass<1, false>(A, B, tw, n, st);
+    dft_pass<2, false>(B, A, tw, n, st);
     hipLaunchKernelGGL(k_scale_shells, dim3(nb), dim3(256), 0, st, A, n, dE, nbins);
-    hipLaunchKernelGGL((k_dft_axis<0, false, true>), dim3(nbt), dim3(256), 0, st, (const void*)A, B, tw, n);
-    hipLaunchKernelGGL((k_dft_axis<1, false, true>), dim3(nbt), dim3(256), 0, st, (const void*)B, A, tw, n);
-    hipLaunchKernelGGL((k_dft_axis<2, false, true>), dim3(nbt), dim3(256), 0, st, (const void*)A, B, tw, n);
+    dft_pass<0, false, true>(A, B, tw, n, st);
+    dft_pass<1, false, true>(B, A, tw, n, st);
+    dft_pass<2, false, true>(A, B, tw, n, st);
     const double scale = 1.0 / ((double)n3 * (double)n3);
     hipLaunchKernelGGL(k_lambda_from_u, dim3(nb), dim3(256), 0, st, B, u, rho, n3, scale, lam);
     return hipGetLastError();
@@ -312,11 +376,9 @@ hipError_t launch_energy_spectrum(int storage, const void* f, int n, void* work,
         case ST_F64: hipLaunchKernelGGL(k_velocity<ST_F64>, dim3(nb), dim3(256), 0, st, static_cast<const double*>(f), u, n3); break;
         default: return hipErrorInvalidValue;
     }
-    const size_t tot = 3 * (size_t)n3;
-    const unsigned nbt = (unsigned)((tot + 255) / 256);
-    hipLaunchKernelGGL((k_dft_axis<0, true>), dim3(nbt), dim3(256), 0, st, (const void*)u, A, tw, n);
-    hipLaunchKernelGGL((k_dft_axis<1, false>), dim3(nbt), dim3(256), 0, st, (const void*)A, B, tw, n);
-    hipLaunchKernelGGL((k_dft_axis<2, false>), dim3(nbt), dim3(256), 0, st, (const void*)B, A, tw, n);
+    dft_pass<0, true>(u, A, tw, n, st);
+    dft_pass<1, false>(A, B, tw, n, st);
+    dft_pass<2, false>(B, A, tw, n, st);
     const size_t pc = (size_t)nbins * n * n;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((pc + 255) / 256)), dim3(256), 0, st, part, pc);
     hipLaunchKernelGGL(k_shell_rows, dim3((n * n + 255) / 256), dim3(256), 0, st, A, n, part, nbins);

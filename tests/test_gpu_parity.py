@@ -124,7 +124,9 @@ def test_global_sums_match_oracle(storage):
     np.testing.assert_allclose(u2, uu, atol=1e-16)
 
 
-@pytest.mark.parametrize("n", [8, 9, 12, 16])
+# 40 and 70: several 32-long input chunks and 64-frequency blocks of the
+# DFT, each with a ragged tail, and a ragged last block of lines.
+@pytest.mark.parametrize("n", [8, 9, 12, 16, 40, 70])
 def test_energy_spectrum_matches_oracle(n):
     rho, u = inputs.turbulence(n, seed=8, k0=2.0, urms=0.05)
     with Lattice((n, n, n), "f64", "bgk", 0.6) as lat:
