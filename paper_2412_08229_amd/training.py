@@ -20,20 +20,24 @@ def log_spectrum_loss(E, E_target, kmin, kmax):
     return float(np.mean(r * r)), dE
 
 
-def paper_spectrum_loss(E, E_target, kmin=4, kmax=10, omega=20.0, kappa_max=None):
+def paper_spectrum_loss(E, E_target, kmin=4, kmax=10, omega=20.0, kappa_max=None, e_unit=1.0):
     """The loss of Eq. (loss) in Sec. "Learning Task": the mean squared gap
     of the spectrum to the target over kmin <= k <= kmax plus omega E(kappa_max),
     which presses down the energy piling up at the grid cutoff; kappa_max is
     the shell N/2 of an N^3 box (without it, the smallest N whose spectrum
-    has len(E) shells is taken).  Returns (L, dL/dE)."""
-    E = np.asarray(E, np.float64)
+    has len(E) shells is taken).  Spectra are measured in units of e_unit
+    (E / e_unit enters the loss): lattice-unit spectra are ~1e-5, and a
+    loss of ~1e-10 leaves Adam's update under its epsilon.  Returns
+    (L, dL/dE)."""
+    E = np.asarray(E, np.float64) / e_unit
+    Et = np.asarray(E_target, np.float64) / e_unit
     ks = np.arange(kmin, kmax + 1)
     kc = int(kappa_max) if kappa_max is not None else _cutoff_shell(len(E))
-    r = E[ks] - E_target[ks]
+    r = E[ks] - Et[ks]
     dE = np.zeros_like(E)
     dE[ks] = 2.0 * r / len(ks)
     dE[kc] += omega
-    return float(np.mean(r * r) + omega * E[kc]), dE
+    return float(np.mean(r * r) + omega * E[kc]), dE / e_unit
 
 
 def _cutoff_shell(nbins):
@@ -52,18 +56,21 @@ class Unroll:
     an optional sixth, phase_rule."""
 
     def __init__(self, shape, tau, init, nsteps, ckpt_every, target, kmin, kmax, forcing=None,
-                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, loss="log", omega=20.0):
+                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, loss="log", omega=20.0,
+                 e_unit=1.0):
         self.lat = Lattice(shape, storage, "nco", tau, stream=stream)
         self.init, self.nsteps, self.ckpt_every = init, int(nsteps), int(ckpt_every)
         self.target, self.kmin, self.kmax = np.asarray(target, np.float64), int(kmin), int(kmax)
         self.forcing, self.act, self.mlp, self.width = forcing, act, mlp, width
         # 'log': mean squared log gap over kmin..kmax; 'paper': Eq. (loss),
-        # the squared gap over kmin..kmax plus omega E(N/2).
-        self.loss_kind, self.omega = loss, float(omega)
+        # the squared gap over kmin..kmax plus omega E(N/2), spectra in units
+        # of e_unit.
+        self.loss_kind, self.omega, self.e_unit = loss, float(omega), float(e_unit)
 
     def _loss(self, E):
         if self.loss_kind == "paper":
-            return paper_spectrum_loss(E, self.target, self.kmin, self.kmax, self.omega, self.lat.nx // 2)
+            return paper_spectrum_loss(E, self.target, self.kmin, self.kmax, self.omega, self.lat.nx // 2,
+                                       self.e_unit)
         return log_spectrum_loss(E, self.target, self.kmin, self.kmax)
 
     def _reset(self, params):

@@ -175,6 +175,69 @@ def test_spectrum_loss_gradient_matches_oracle(act, mlp, forced):
     assert rel < 2e-3 and relf < 2e-3
 
 
+def test_spectrum_loss_gradient_matches_oracle_above_64():
+    """The spectrum and its reverse mode on a 66^3 lattice: the complex DFT
+    passes take two 64-frequency groups per lane above 64, with a ragged
+    frequency block (66 of 128) and a ragged last block of lines; the readout
+    transforms the half spectrum, the reverse mode the full one.  Two steps
+    (the collision keeps the velocity, so the spectrum of one step does not
+    depend on the network) of the 27-8-8-8-4 tanh network (depth 3,
+    matrix-core forward) keep the oracle's run short."""
+    n, width, tau, kmin, kmax = 66, 8, 0.56, 2, 12
+    params = inputs.mlp_params(width, 4, depth=3)
+    _, u = inputs.turbulence(n, seed=5, k0=4.0, urms=0.04)
+    f0 = collision.equilibrium(np.ones((n, n, n)), u)
+    Et = observables.spectrum(f0) * np.linspace(0.7, 1.3, observables.n_bins(n)) + 1e-12
+    with Lattice((n, n, n), "f32", "nco", tau) as lat:
+        lat.set_net_weights(params, width, "tanh", "f32_mfma", depth=3)
+        lat.init_populations(f0)
+        lat.forward_record(2, 1)
+        E = lat.energy_spectrum()
+        f2 = lat.populations()
+        Lg, dE = log_spectrum_loss(E, Et, kmin, kmax)
+        g, df0 = lat.backward(dL_dE=dE, want_df0=True)
+    np.testing.assert_allclose(E, observables.spectrum(f2.astype(np.float64)), rtol=1e-11, atol=1e-18)
+    layers = collision.unpack_params(params, width, depth=3)
+
+    def loss_grad(x):
+        Lx, d = adjoint.log_spectrum_loss(observables.spectrum(x), Et, kmin, kmax)
+        return Lx, adjoint.spectrum_vjp(x, d)
+    Lo, go, gfo = adjoint.run_and_grad(f0, tau, layers, "tanh", 2, loss_grad)
+    go = adjoint.flatten(go)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    relf = np.linalg.norm(df0 - gfo) / np.linalg.norm(gfo)
+    print("66^3 x 2: loss %.8e vs %.8e, grad rel err %.2e, dL/df0 rel err %.2e" % (Lg, Lo, rel, relf))
+    assert abs(Lg - Lo) < 1e-4 * abs(Lo)
+    assert rel < 2e-3 and relf < 2e-3
+
+
+@pytest.mark.parametrize("n", [48, 129])
+def test_spectrum_reverse_mode_through_one_step_at_size(n):
+    """A property that holds at any size: the collision keeps rho and j, and
+    a dL/dx that depends on rho and j only passes its adjoint unchanged (the
+    rates act on non-conserved moments only), so after one step the gradient
+    of a spectrum loss with respect to the start is the streaming's adjoint of
+    the spectrum's reverse mode, dL/df0 = unstream(spectrum_vjp(x_1, dL/dE)).
+    48^3 takes one 64-frequency group per lane, 129^3 four (odd: no Nyquist
+    shell, ragged blocks of lines and frequencies); the readout E(k) of x_1
+    is checked against the oracle on the way."""
+    _, u = inputs.turbulence(n, seed=11, k0=4.0, urms=0.04)
+    with Lattice((n, n, n), "f32", "nco", 0.56) as lat:
+        lat.set_net_weights(inputs.mlp_params(32, 9), 32, "tanh", "f32_mfma")
+        lat.init_equilibrium(None, u)
+        lat.forward_record(1, 1)
+        E = lat.energy_spectrum()
+        f1 = lat.populations().astype(np.float64)
+        Et = E * np.linspace(0.8, 1.2, len(E)) + 1e-12
+        _, dE = log_spectrum_loss(E, Et, 2, n // 3)
+        _, df0 = lat.backward(dL_dE=dE, want_df0=True)
+    np.testing.assert_allclose(E, observables.spectrum(f1), rtol=1e-11, atol=1e-18)
+    want = step.unstream(adjoint.spectrum_vjp(f1, dE))
+    rel = np.linalg.norm(df0 - want) / np.linalg.norm(want)
+    print("%d^3: dL/df0 through one step vs unstream(spectrum_vjp), rel err %.2e" % (n, rel))
+    assert rel < 2e-5
+
+
 @pytest.mark.parametrize("shape,mlp", [((6, 6, 6), "f32"), ((6, 6, 6), "f32_mfma"), ((7, 6, 9), "f32_mfma"),
                                        ((3, 11, 17), "f32_mfma")])
 def test_population_loss_gradient_and_determinism(shape, mlp):

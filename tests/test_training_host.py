@@ -28,6 +28,27 @@ def test_paper_loss_value_and_gradient():
         assert paper_spectrum_loss(np.ones(n_bins(m)), np.ones(n_bins(m)), omega=1.0)[0] == 1.0
 
 
+def test_paper_loss_spectrum_unit():
+    """Spectra in units of e_unit: the loss equals the unit-free loss of
+    E / e_unit, and the gradient with respect to E carries the chain factor
+    1 / e_unit (central differences at the lattice-unit scale)."""
+    rng = np.random.Generator(np.random.PCG64(4))
+    n, unit = 32, 3e-5
+    E = rng.random(n_bins(n)) * 1e-5
+    Et = rng.random(n_bins(n)) * 1e-5
+    L, dE = paper_spectrum_loss(E, Et, kappa_max=n // 2, e_unit=unit)
+    L1, dE1 = paper_spectrum_loss(E / unit, Et / unit, kappa_max=n // 2)
+    assert np.isclose(L, L1, rtol=1e-14)
+    np.testing.assert_allclose(dE, dE1 / unit, rtol=1e-14)
+    h = 1e-11
+    for k in (4, 7, 10, 16):
+        e = np.zeros_like(E)
+        e[k] = h
+        fd = (paper_spectrum_loss(E + e, Et, kappa_max=16, e_unit=unit)[0]
+              - paper_spectrum_loss(E - e, Et, kappa_max=16, e_unit=unit)[0]) / (2 * h)
+        assert abs(fd - dE[k]) < 1e-6 * abs(dE[k])
+
+
 def test_curriculum_schedule():
     assert [curriculum_steps(e) for e in (0, 9, 10, 19, 20, 89)] == [200, 200, 400, 400, 600, 1800]
 
