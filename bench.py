@@ -411,8 +411,7 @@ def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-
     proportion to the amplitude, and one coarse step must inject what r fine
     steps do.  The loss is the paper's (squared
     spectrum gap over kmin <= k <= kmax plus omega E(N/2)) against the fine
-    run's spectrum averaged over the snapshots, spectra in units of the
-    target's peak.  Adam over the samples with
+    run's spectrum averaged over the snapshots.  Adam over the samples with
     the unroll curriculum (start steps, grow more every ``every`` epochs).
     Reports the loss per sample at the final unroll length for the untrained
     and trained network, the fixed-rate operator and BGK, and the times.
@@ -458,9 +457,8 @@ def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-
         return curriculum_steps(ep, start=start, grow=grow, every=every)
     final = sched(epochs - 1)
     forcing = (ks, inputs.uniform_draws(4096, len(ks), 103), amp_c, 1.5, 1.0, True)
-    e_unit = float(np.max(target))
     runs = [Unroll((n_coarse,) * 3, tau_c, ("pop", f0), final, 20, target, kmin, kmax, forcing=forcing,
-                   loss="paper", omega=omega, e_unit=e_unit) for f0 in snaps]
+                   loss="paper", omega=omega) for f0 in snaps]
     p0 = inputs.mlp_params(32, seed=1)
 
     spec = {"untrained": [], "trained": [], "fixed_rate": [], "bgk": []}
@@ -487,8 +485,7 @@ def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-
                     "spinup_large_eddy_times": spinup, "mean_kinetic_energy": float(kin),
                     "seconds": t_data},
            "coarse": {"n": n_coarse, "ratio": r, "tau": tau_c, "forcing_amplitude": amp_c},
-           "loss": {"kmin": kmin, "kmax": kmax, "omega": omega, "target": "fine spectrum averaged over the snapshots",
-                    "e_unit": e_unit},
+           "loss": {"kmin": kmin, "kmax": kmax, "omega": omega, "target": "fine spectrum averaged over the snapshots"},
            "curriculum": {"start": start, "grow": grow, "every": every, "final": final},
            "epochs": epochs, "lr": lr, "seconds_per_epoch": t_epoch,
            "history": [h if np.isfinite(h) else None for h in hist], "samples": {}}
@@ -503,7 +500,7 @@ def spectrum_training(n_fine, n_coarse, n_snap, epochs, lr, tau_f=0.6, amp_f=1e-
                 try:
                     lat.step(final)
                     E = lat.energy_spectrum()
-                    v = paper_spectrum_loss(E, target, kmin, kmax, omega, n_coarse // 2, e_unit)[0]
+                    v = paper_spectrum_loss(E, target, kmin, kmax, omega, n_coarse // 2)[0]
                     other[kind] = v if np.isfinite(v) else "non-finite"
                     if np.isfinite(v):
                         spec["fixed_rate" if kind == "mrt" else kind].append(E)

@@ -20,24 +20,20 @@ def log_spectrum_loss(E, E_target, kmin, kmax):
     return float(np.mean(r * r)), dE
 
 
-def paper_spectrum_loss(E, E_target, kmin=4, kmax=10, omega=20.0, kappa_max=None, e_unit=1.0):
+def paper_spectrum_loss(E, E_target, kmin=4, kmax=10, omega=20.0, kappa_max=None):
     """The loss of Eq. (loss) in Sec. "Learning Task": the mean squared gap
     of the spectrum to the target over kmin <= k <= kmax plus omega E(kappa_max),
     which presses down the energy piling up at the grid cutoff; kappa_max is
     the shell N/2 of an N^3 box (without it, the smallest N whose spectrum
-    has len(E) shells is taken).  Spectra are measured in units of e_unit
-    (E / e_unit enters the loss): lattice-unit spectra are ~1e-5, and a
-    loss of ~1e-10 leaves Adam's update under its epsilon.  Returns
-    (L, dL/dE)."""
-    E = np.asarray(E, np.float64) / e_unit
-    Et = np.asarray(E_target, np.float64) / e_unit
+    has len(E) shells is taken).  Returns (L, dL/dE)."""
+    E = np.asarray(E, np.float64)
     ks = np.arange(kmin, kmax + 1)
     kc = int(kappa_max) if kappa_max is not None else _cutoff_shell(len(E))
-    r = E[ks] - Et[ks]
+    r = E[ks] - E_target[ks]
     dE = np.zeros_like(E)
     dE[ks] = 2.0 * r / len(ks)
     dE[kc] += omega
-    return float(np.mean(r * r) + omega * E[kc]), dE / e_unit
+    return float(np.mean(r * r) + omega * E[kc]), dE
 
 
 def _cutoff_shell(nbins):
@@ -56,21 +52,18 @@ class Unroll:
     an optional sixth, phase_rule."""
 
     def __init__(self, shape, tau, init, nsteps, ckpt_every, target, kmin, kmax, forcing=None,
-                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, loss="log", omega=20.0,
-                 e_unit=1.0):
+                 storage="f32", act="tanh", mlp="f32_mfma", width=32, stream=None, loss="log", omega=20.0):
         self.lat = Lattice(shape, storage, "nco", tau, stream=stream)
         self.init, self.nsteps, self.ckpt_every = init, int(nsteps), int(ckpt_every)
         self.target, self.kmin, self.kmax = np.asarray(target, np.float64), int(kmin), int(kmax)
         self.forcing, self.act, self.mlp, self.width = forcing, act, mlp, width
         # 'log': mean squared log gap over kmin..kmax; 'paper': Eq. (loss),
-        # the squared gap over kmin..kmax plus omega E(N/2), spectra in units
-        # of e_unit.
-        self.loss_kind, self.omega, self.e_unit = loss, float(omega), float(e_unit)
+        # the squared gap over kmin..kmax plus omega E(N/2).
+        self.loss_kind, self.omega = loss, float(omega)
 
     def _loss(self, E):
         if self.loss_kind == "paper":
-            return paper_spectrum_loss(E, self.target, self.kmin, self.kmax, self.omega, self.lat.nx // 2,
-                                       self.e_unit)
+            return paper_spectrum_loss(E, self.target, self.kmin, self.kmax, self.omega, self.lat.nx // 2)
         return log_spectrum_loss(E, self.target, self.kmin, self.kmax)
 
     def _reset(self, params):
@@ -235,10 +228,28 @@ def curriculum_steps(epoch, start=200, grow=200, every=10):
     return start + grow * (epoch // every)
 
 
+ADAM_EPS_REL = 1e-8
+
+
+def _scale_free_eps(opt, grad):
+    """Adam's epsilon as a fraction of the first gradient's RMS (once).  Adam's
+    step is then independent of the loss's scale: the paper's loss on
+    lattice-unit spectra (~1e-5, losses ~1e-10 on small lattices) would
+    otherwise leave every update under a fixed epsilon of 1e-8."""
+    group = opt.param_groups[0]
+    if group.get("eps_set"):
+        return
+    rms = float(np.sqrt(np.mean(np.square(np.asarray(grad, np.float64)))))
+    if rms > 0.0 and np.isfinite(rms):
+        group["eps"] = ADAM_EPS_REL * rms
+        group["eps_set"] = True
+
+
 def train(unrolls, params0, epochs, lr=1e-3, log=None, schedule=None):
-    """Adam (torch.optim) over the given samples; returns (params, losses).
-    schedule: None, or a function epoch -> unroll length (e.g.
-    ``curriculum_steps``) applied to every sample at the start of an epoch."""
+    """Adam (torch.optim, epsilon relative to the first gradient) over the
+    given samples; returns (params, losses).  schedule: None, or a function
+    epoch -> unroll length (e.g. ``curriculum_steps``) applied to every
+    sample at the start of an epoch."""
     import torch
     p = torch.nn.Parameter(torch.tensor(np.asarray(params0, np.float64)))
     opt = torch.optim.Adam([p], lr=lr)
@@ -253,6 +264,7 @@ def train(unrolls, params0, epochs, lr=1e-3, log=None, schedule=None):
             opt.zero_grad()
             loss = fn(p)
             loss.backward()
+            _scale_free_eps(opt, p.grad.detach().numpy())
             opt.step()
             with torch.no_grad():
                 p.copy_(p.float().double())          # parameters live as float32 values
@@ -264,7 +276,8 @@ def train(unrolls, params0, epochs, lr=1e-3, log=None, schedule=None):
 
 
 def train_batched(unrolls, params0, epochs, lr=1e-3, log=None, schedule=None):
-    """Adam with one step per epoch on the mean loss of all samples.  The
+    """Adam (epsilon relative to the first gradient) with one step per epoch
+    on the mean loss of all samples.  The
     samples' recorded runs and reverse sweeps go concurrently, one host
     thread per sample, each lattice on its own stream (the library's calls
     on different lattices are independent and release the interpreter
@@ -295,6 +308,7 @@ def train_batched(unrolls, params0, epochs, lr=1e-3, log=None, schedule=None):
                 break
             opt.zero_grad()
             p.grad = torch.from_numpy(np.mean([r[1] for r in ok], axis=0))
+            _scale_free_eps(opt, p.grad.numpy())
             opt.step()
             with torch.no_grad():
                 p.copy_(p.float().double())          # parameters live as float32 values
