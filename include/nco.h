@@ -119,6 +119,21 @@ int nco_set_op(nco_lattice* lat, int op, double tau);
  * lattice.  Takes effect from the next step; it drops a recorded run. */
 int nco_set_domain(nco_lattice* lat, int domain);
 
+/* Pairs of steps in place (enable = 1, the default) or always between two
+ * buffers (0).  With 1, nco_step runs two consecutive BGK or fixed-rate
+ * steps (Sec. II.A) on one population buffer when that buffer fits the
+ * device's 256 MB last-level cache and the two buffers together do not (a
+ * 128^3 float32 lattice): the first step pulls as usual and writes each
+ * post-collision population i to the opposite slot of node x + c_i, the
+ * second reads those slots at its own node and writes the standard layout.
+ * Every slot is read and written by one node, and the results equal those
+ * of two-buffer steps bit for bit; only the memory traffic changes (the
+ * lattice stays cache-resident).  Pairs are not split by a stability check,
+ * and the periodic domain without the velocity-dependent forcing phase is
+ * required (otherwise steps run between two buffers).  NCO_E_INVALID for
+ * another value. */
+int nco_set_inplace(nco_lattice* lat, int enable);
+
 /* Fixed rates omega_3..omega_6 of the four higher-order groups (NCO_OP_MRT). */
 int nco_set_rates(nco_lattice* lat, const double omega_high[4]);
 

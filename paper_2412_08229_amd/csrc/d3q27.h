@@ -130,6 +130,8 @@ template <> struct Codec<ST_F32> {
     using real = float;
     static __device__ __forceinline__ real load(const store_t* p, int) { return *p; }
     static __device__ __forceinline__ void store(store_t* p, int, real v) { __builtin_nontemporal_store(v, p); }
+    // Ordinary store, for a buffer that is read again while it stays cached.
+    static __device__ __forceinline__ void store_cached(store_t* p, int, real v) { *p = v; }
     static __device__ __forceinline__ real from_double(double v, int) { return (float)v; }
     static __device__ __forceinline__ double to_double(store_t v, int) { return (double)v; }
 };
@@ -139,6 +141,7 @@ template <> struct Codec<ST_F64> {
     using real = double;
     static __device__ __forceinline__ real load(const store_t* p, int) { return *p; }
     static __device__ __forceinline__ void store(store_t* p, int, real v) { *p = v; }
+    static __device__ __forceinline__ void store_cached(store_t* p, int i, real v) { store(p, i, v); }
     static __device__ __forceinline__ store_t from_double(double v, int) { return v; }
     static __device__ __forceinline__ double to_double(store_t v, int) { return v; }
 };
@@ -152,6 +155,7 @@ template <> struct Codec<ST_F16> {
     static __device__ __forceinline__ void store(store_t* p, int i, real v) {
         *p = __float2half_rn((v - (float)weight_of(i)) * dev_scale(i));
     }
+    static __device__ __forceinline__ void store_cached(store_t* p, int i, real v) { store(p, i, v); }
     static __device__ __forceinline__ store_t from_double(double v, int i) {
         return __float2half_rn((float)((v - weight_of(i)) * dev_scale(i)));
     }
@@ -169,6 +173,7 @@ template <> struct Codec<ST_BF16> {
     static __device__ __forceinline__ void store(store_t* p, int i, real v) {
         *p = __float2bfloat16((v - (float)weight_of(i)) * dev_scale(i));
     }
+    static __device__ __forceinline__ void store_cached(store_t* p, int i, real v) { store(p, i, v); }
     static __device__ __forceinline__ store_t from_double(double v, int i) {
         return __float2bfloat16((float)((v - weight_of(i)) * dev_scale(i)));
     }

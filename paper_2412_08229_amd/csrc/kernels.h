@@ -120,6 +120,9 @@ __device__ __forceinline__ int group_member(const LaunchGroup& g, int b) {
 }
 
 hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs& a, hipStream_t st);
+// One step of an in-place pair on a single buffer (BGK or fixed-rate,
+// periodic): phase 0 from the standard layout, phase 1 back to it.
+hipError_t launch_step_inplace(int storage, void* f, const StepArgs& a, int phase, hipStream_t st);
 // Velocity-dependent Alvelius phase: F_hat of this step's forced modes from
 // the state f (partial: nblocks(n) x n_modes x 6 doubles of work space), and
 // u_hat into uhat (6 doubles per mode) unless it is null.

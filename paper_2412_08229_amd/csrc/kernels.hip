@@ -2,6 +2,12 @@
 // float64 reductions.  One thread per node; populations in structure-of-
 // arrays layout [27][z][y][x] so that each of the 27 loads and stores of a
 // wavefront is a contiguous row segment of one velocity plane.
+//
+// Multiply-adds are fused only within one source expression (not across
+// statements, as hipcc's default allows), before any header is read: the
+// collision code inlined into different kernels (two-buffer, in-place pair,
+// grouped) then rounds identically, and those kernels agree bit for bit.
+#pragma STDC FP_CONTRACT ON
 #include <algorithm>
 
 #include "kernels.h"
@@ -79,6 +85,58 @@ __device__ __forceinline__ void stream_collide_node(const typename Codec<S>::sto
         collide_node<R, OP, W, ACT, false, DEPTH>(f, a, R(0), R(0), R(0));
     }
     store_local<S>(fout, a.n, idx, f);
+}
+
+// Two steps in place on one population buffer (periodic lattices).  With
+// opp(i) = 26 - i the population of velocity -c_i:
+//   PHASE 0 reads the standard layout by the usual pull, f_i(x) = F(i, x - c_i),
+//     and writes the post-collision f_i of node x to slot (opp(i), x + c_i);
+//   PHASE 1 reads f_i(x) = F(opp(i), x), which the first step wrote there
+//     from node x - c_i (its pull), and writes F(i, x): the standard layout.
+// In either phase the slots a node writes are exactly the slots it read
+// (PHASE 0: node x is the only reader of (opp(i), x + c_i), the slot its own
+// pull of population opp(i) reads), so threads never race and the pair of
+// steps computes what two steps between two buffers compute, bit for bit,
+// with one buffer: a 128^3 float32 lattice (226 MB) then stays in the 256 MB
+// last-level cache instead of streaming 453 MB through it.  Stores are
+// cached, since the next step reads them back at once.
+template <int S, int OP, int PHASE>
+__global__ __launch_bounds__(256) void k_stream_collide_inplace(typename Codec<S>::store_t* f, StepArgs a) {
+    using R = typename Codec<S>::real;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n) return;
+    const NodeIdx p = node_of(idx, a.nx, a.ny);
+    R v[Q];
+    if constexpr (PHASE == 0) {
+        pull<S>(f, a, p, v);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = Codec<S>::load(f + (size_t)(Q - 1 - i) * a.n + idx, i);
+    }
+    if (a.n_modes > 0) {
+        R Fx, Fy, Fz;
+        read_force(a, idx, Fx, Fy, Fz);
+        collide_node<R, OP, 8, ACT_TANH, true>(v, a, Fx, Fy, Fz);
+    } else {
+        collide_node<R, OP, 8, ACT_TANH, false>(v, a, R(0), R(0), R(0));
+    }
+    if constexpr (PHASE == 0) {
+        // Destination coordinate for c = -1, 0, +1 is x - 1, x, x + 1.
+        const int xd[3] = {p.x == 0 ? a.nx - 1 : p.x - 1, p.x, p.x == a.nx - 1 ? 0 : p.x + 1};
+        const int yd[3] = {(p.y == 0 ? a.ny - 1 : p.y - 1) * a.nx, p.y * a.nx,
+                           (p.y == a.ny - 1 ? 0 : p.y + 1) * a.nx};
+        const int nxy = a.nx * a.ny;
+        const int zd[3] = {(p.z == 0 ? a.nz - 1 : p.z - 1) * nxy, p.z * nxy,
+                           (p.z == a.nz - 1 ? 0 : p.z + 1) * nxy};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int dst = zd[cz_of(i) + 1] + yd[cy_of(i) + 1] + xd[cx_of(i) + 1];
+            Codec<S>::store_cached(f + (size_t)(Q - 1 - i) * a.n + dst, i, v[i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) Codec<S>::store_cached(f + (size_t)i * a.n + idx, i, v[i]);
+    }
 }
 
 // Streaming alone: the raw stored values are moved, so the result is an exact
@@ -636,6 +694,26 @@ hipError_t launch_step(int storage, const void* fin, void* fout, const StepArgs&
         case OP_NONE: DISPATCH_STORAGE(storage, return (launch_step_op<SS, OP_NONE>(fin, fout, a, st)))
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_step_inplace(int storage, void* f, const StepArgs& a, int phase, hipStream_t st) {
+    if (a.domain != DOMAIN_PERIODIC || (a.op != OP_BGK && a.op != OP_MRT) || (phase != 0 && phase != 1))
+        return hipErrorInvalidValue;
+    const dim3 grid(nblocks(a.n)), block(256);
+#define INPLACE(OPV)                                                                                          \
+    DISPATCH_STORAGE(storage, {                                                                               \
+        using T = typename Codec<SS>::store_t;                                                                \
+        if (phase == 0)                                                                                       \
+            hipLaunchKernelGGL((k_stream_collide_inplace<SS, OPV, 0>), grid, block, 0, st, static_cast<T*>(f), a); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_stream_collide_inplace<SS, OPV, 1>), grid, block, 0, st, static_cast<T*>(f), a); \
+        return hipGetLastError();                                                                             \
+    })
+    if (a.op == OP_BGK) {
+        INPLACE(OP_BGK)
+    }
+    INPLACE(OP_MRT)
+#undef INPLACE
 }
 
 hipError_t launch_step_grouped(int storage, int op, const LaunchGroup& g, hipStream_t st) {

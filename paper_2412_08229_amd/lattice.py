@@ -102,6 +102,11 @@ class Lattice:
         initialise it with ``inputs.tgv3d_octant``."""
         L.nco_set_domain(self._h, domain)
 
+    def set_inplace(self, enable):
+        """True (the default): pairs of BGK / fixed-rate steps run in place on
+        one buffer where it fits the last-level cache (nco_set_inplace)."""
+        L.nco_set_inplace(self._h, 1 if enable else 0)
+
     def set_check(self, every, mass_rel_tol):
         """Stability check every ``every`` steps (0: off); ``sync`` raises
         NCOError(NCO_E_UNSTABLE) once it has failed."""
