@@ -119,6 +119,20 @@ int nco_set_op(nco_lattice* lat, int op, double tau);
  * lattice.  Takes effect from the next step; it drops a recorded run. */
 int nco_set_domain(nco_lattice* lat, int domain);
 
+/* Rounding of NCO_BF16_DEV storage in the following steps: enable = 0 (the
+ * default) rounds each stored deviation to nearest even; 1 rounds it
+ * stochastically, up with probability equal to the fraction dropped, so that
+ * stored values are unbiased (a per-step change below half a bfloat16 step
+ * is kept on average instead of rounded away).  The random bits are a
+ * counter-based hash of (seed, step index, node, population), so runs are
+ * repeatable and independent of launch shapes, and two-buffer steps,
+ * in-place pairs, batched steps and the recomputation of the reverse mode
+ * store the same values.  Initialisation keeps round-to-nearest.  The
+ * rounding is a property of the storage format; the paper's method is the
+ * arithmetic around it.  NCO_E_UNSUPPORTED for other storages,
+ * NCO_E_INVALID for another enable value.  Drops a recorded run. */
+int nco_set_stochastic_rounding(nco_lattice* lat, int enable, unsigned seed);
+
 /* Pairs of steps in place (enable = 1, the default) or always between two
  * buffers (0).  With 1, nco_step runs two consecutive BGK or fixed-rate
  * steps (Sec. II.A) on one population buffer when that buffer fits the

@@ -42,6 +42,7 @@ SIGNATURES = {
     "nco_set_rates": (_I, [_P, _D]),
     "nco_set_domain": (_I, [_P, _I]),
     "nco_set_inplace": (_I, [_P, _I]),
+    "nco_set_stochastic_rounding": (_I, [_P, _I, ctypes.c_uint]),
     "nco_restrict": (_I, [_P, _P]),
     "nco_set_net_weights": (_I, [_P, _I, _I, _I, _F, _SZ]),
     "nco_set_net_weights_depth": (_I, [_P, _I, _I, _I, _I, _F, _SZ]),
@@ -194,6 +195,10 @@ DOMAINS = {"periodic": 0, "tgv_octant": 1}
 
 def nco_set_domain(h, domain):
     check(lib().nco_set_domain(h, DOMAINS[domain] if isinstance(domain, str) else int(domain)))
+
+
+def nco_set_stochastic_rounding(h, enable, seed):
+    check(lib().nco_set_stochastic_rounding(h, int(enable), int(seed) & 0xffffffff))
 
 
 def nco_set_inplace(h, enable):

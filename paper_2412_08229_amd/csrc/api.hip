@@ -235,6 +235,9 @@ struct nco_lattice {
     // Pairs of BGK / fixed-rate steps in place on one buffer when it fits
     // the last-level cache (nco_set_inplace; on by default).
     bool inplace = true;
+    // Stochastic rounding of bfloat16 deviation storage (nco_set_stochastic_rounding).
+    bool sr = false;
+    unsigned sr_seed = 0;
 };
 
 namespace {
@@ -349,12 +352,16 @@ StepArgs step_args(const nco_lattice* lat) {
     a.fhat = nullptr;
     a.force32 = nullptr;
     a.force64 = nullptr;
+    a.sr_key = 0;
     return a;
 }
 
 // Arguments of the step that uses forcing step t.
 StepArgs step_args_at(const nco_lattice* lat, long t) {
     StepArgs a = step_args(lat);
+    // Each step's stochastic-rounding key from the lattice's seed and the
+    // step index (never 0, which means round to nearest even).
+    if (lat->sr) a.sr_key = lowbias32(lat->sr_seed ^ lowbias32((unsigned)t * 2654435769u)) | 1u;
     if (lat->n_modes > 0) {
         a.n_modes = lat->n_modes;
         a.fk = lat->d_fk;
@@ -766,6 +773,17 @@ int nco_step(nco_lattice* lat, int nsteps) {
         if (int rc = maybe_check(lat, lat->stream)) return rc;
         ++s;
     }
+    return NCO_OK;
+}
+
+int nco_set_stochastic_rounding(nco_lattice* lat, int enable, unsigned seed) {
+    if (int rc = check_lat(lat)) return rc;
+    if (enable != 0 && enable != 1) return fail(NCO_E_INVALID, "enable must be 0 or 1");
+    if (enable && lat->storage != NCO_BF16_DEV)
+        return fail(NCO_E_UNSUPPORTED, "stochastic rounding is for bfloat16 deviation storage");
+    lat->sr = enable == 1;
+    lat->sr_seed = seed;
+    lat->rec_steps = -1;  // a recorded run used the other rounding
     return NCO_OK;
 }
 

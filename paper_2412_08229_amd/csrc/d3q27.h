@@ -164,6 +164,25 @@ template <> struct Codec<ST_F16> {
     }
 };
 
+// Stochastic rounding of bfloat16 deviations: the float32 value's low 16
+// bits plus 16 random bits, truncated, rounds up with probability equal to
+// the dropped fraction, so the stored value is unbiased.  The random bits
+// come from a counter-based hash of (step key, node, population): C.
+// Wellons' "lowbias32" integer hash (xor-shift / multiply rounds, constants
+// 0x7feb352d and 0x846ca68b).
+__host__ __device__ __forceinline__ unsigned lowbias32(unsigned x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__device__ __forceinline__ unsigned sr_bits(unsigned key, int node, int i) {
+    return lowbias32(key ^ lowbias32((unsigned)node * 27u + (unsigned)i));
+}
+
 template <> struct Codec<ST_BF16> {
     using store_t = __hip_bfloat16;
     using real = float;
@@ -174,6 +193,12 @@ template <> struct Codec<ST_BF16> {
         *p = __float2bfloat16((v - (float)weight_of(i)) * dev_scale(i));
     }
     static __device__ __forceinline__ void store_cached(store_t* p, int i, real v) { store(p, i, v); }
+    // Stochastic rounding with 16 random bits r (finite values; a value
+    // within one bfloat16 step of the largest may round to infinity).
+    static __device__ __forceinline__ void store_sr(store_t* p, int i, real v, unsigned r) {
+        const unsigned bits = __float_as_uint((v - (float)weight_of(i)) * dev_scale(i)) + (r & 0xffffu);
+        *reinterpret_cast<unsigned short*>(p) = (unsigned short)(bits >> 16);
+    }
     static __device__ __forceinline__ store_t from_double(double v, int i) {
         return __float2bfloat16((float)((v - weight_of(i)) * dev_scale(i)));
     }

@@ -34,6 +34,10 @@ struct StepArgs {
     // float32 otherwise.  The step kernels read it instead of summing modes.
     const float* force32;
     const double* force64;
+    // Rounding of bfloat16 deviation storage in this step: 0 rounds to
+    // nearest even, any other value rounds stochastically with random bits
+    // keyed by it (see sr_bits).
+    unsigned sr_key;
 };
 
 // Phases of the spectral modes at a node, e^{i 2 pi (k_x x / nx + k_y y / ny

@@ -84,7 +84,7 @@ __device__ __forceinline__ void stream_collide_node(const typename Codec<S>::sto
     } else {
         collide_node<R, OP, W, ACT, false, DEPTH>(f, a, R(0), R(0), R(0));
     }
-    store_local<S>(fout, a.n, idx, f);
+    store_local<S>(fout, a.n, idx, f, a.sr_key);
 }
 
 // Two steps in place on one population buffer (periodic lattices).  With
@@ -131,11 +131,11 @@ __global__ __launch_bounds__(256) void k_stream_collide_inplace(typename Codec<S
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int dst = zd[cz_of(i) + 1] + yd[cy_of(i) + 1] + xd[cx_of(i) + 1];
-            Codec<S>::store_cached(f + (size_t)(Q - 1 - i) * a.n + dst, i, v[i]);
+            store_one_cached<S>(f + (size_t)(Q - 1 - i) * a.n + dst, idx, i, v[i], a.sr_key);
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Codec<S>::store_cached(f + (size_t)i * a.n + idx, i, v[i]);
+        for (int i = 0; i < Q; ++i) store_one_cached<S>(f + (size_t)i * a.n + idx, idx, i, v[i], a.sr_key);
     }
 }
 

@@ -493,7 +493,7 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
         from_moments(dm, df);
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] -= df[i];
-        store_local<S>(fout, a.n, idx, f);
+        store_local<S>(fout, a.n, idx, f, a.sr_key);
     }
 }
 

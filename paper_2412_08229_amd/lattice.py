@@ -102,6 +102,11 @@ class Lattice:
         initialise it with ``inputs.tgv3d_octant``."""
         L.nco_set_domain(self._h, domain)
 
+    def set_stochastic_rounding(self, enable, seed=0):
+        """Stochastic rounding of bfloat16 deviation storage in the following
+        steps (nco_set_stochastic_rounding)."""
+        L.nco_set_stochastic_rounding(self._h, 1 if enable else 0, seed)
+
     def set_inplace(self, enable):
         """True (the default): pairs of BGK / fixed-rate steps run in place on
         one buffer where it fits the last-level cache (nco_set_inplace)."""

@@ -2,7 +2,7 @@
 against the two-buffer steps, through the C ABI: the populations must agree
 bit for bit.  The sizes are those where the pairs run (one buffer fits the
 256 MB last-level cache, two do not): 128^3 float32, a non-cubic float64
-lattice, a bfloat16-deviation lattice.  Seven steps with a stability check
+lattice, a bfloat16-deviation lattice (also with stochastic rounding).  Seven steps with a stability check
 every three mix pairs and single steps (a pair never straddles a check)."""
 import numpy as np
 import pytest
@@ -13,10 +13,12 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(shape, storage, op, forced, inplace, nsteps=7):
-    nz, ny, nx = shape
     rho, u = inputs.random_velocity(shape, seed=21, amp=0.05)
-    with Lattice(shape, storage, op, 0.56) as lat:
+    sr = storage == "bf16sr"                 # with stochastic rounding
+    with Lattice(shape, "bf16" if sr else storage, op, 0.56) as lat:
         lat.set_inplace(inplace)
+        if sr:
+            lat.set_stochastic_rounding(True, 3)
         if op == "mrt":
             lat.set_rates([1.3, 1.1, 1.2, 1.4])
         if forced:
@@ -34,6 +36,7 @@ def _run(shape, storage, op, forced, inplace, nsteps=7):
     ((128, 128, 128), "f32", "mrt", True),
     ((94, 92, 90), "f64", "bgk", True),
     ((170, 160, 150), "bf16", "mrt", False),
+    ((170, 160, 150), "bf16sr", "bgk", True),
 ])
 def test_inplace_pairs_equal_two_buffer_steps(shape, storage, op, forced):
     print("in-place pairs vs two buffers: %s %s %s forced=%s" % (shape, storage, op, forced), flush=True)
