@@ -106,6 +106,10 @@ class GpuEngine:
         tau, rho, u = prep if prep is not None else self.prepare(req)
         lat = Lattice((req.n, req.n, req.n), storage, "nco", tau, stream=self.stream)
         lat.set_net_weights(self.params, self.width, "tanh", mlp)
+        if storage == "bf16":
+            # BF16 deviations rounded stochastically (keyed by the request, so
+            # a request's result does not depend on what it is served with).
+            lat.set_stochastic_rounding(True, req.rid)
         lat.init_equilibrium(rho, u)
         lat.set_check(self.check_every, self.mass_tol)
         return lat
