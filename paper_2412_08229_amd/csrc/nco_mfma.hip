@@ -334,12 +334,13 @@ __device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const
             for (int i = 0; i < 8; ++i) x[i] = mrow[ge[i]];
             const u32x4 xb = {pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]), pack_bf16(x[4], x[5]),
                               pack_bf16(x[6], x[7])};
+            // The 8 reflections in Gray-code order k ^ (k >> 1): consecutive
+            // ones differ in one reflection bit (bit ctz(k)), so one mask XOR
+            // per word moves to the next instead of one per set bit.
+            u32x4 bs = xb;
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                u32x4 bs = xb;
-                if (s & 1) bs ^= SM[0];
-                if (s & 2) bs ^= SM[1];
-                if (s & 4) bs ^= SM[2];
+            for (int k = 0; k < 8; ++k) {
+                if (k > 0) bs ^= SM[__builtin_ctz(k)];
                 f32x4 c1[2];
 #pragma unroll
                 for (int t = 0; t < 2; ++t) c1[t] = mfma32(A1[t], bs, f32x4{0.f, 0.f, 0.f, 0.f});
