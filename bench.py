@@ -175,8 +175,8 @@ def precision_horizon(n, convective_times, every, f64_steps):
     params = inputs.mlp_params(32, seed=0)
 
     def run(storage, mlp, steps, samples):
-        sr = storage == "bf16sr"              # BF16 deviation storage, stochastic rounding
-        with Lattice((n, n, n), "bf16" if sr else storage, "nco", tau, stream=stream) as lat:
+        sr = storage.endswith("sr")           # 16-bit deviation storage, stochastic rounding
+        with Lattice((n, n, n), storage[:-2] if sr else storage, "nco", tau, stream=stream) as lat:
             lat.set_net_weights(params, 32, "tanh", mlp)
             if sr:
                 lat.set_stochastic_rounding(True, 0)
@@ -202,7 +202,7 @@ def precision_horizon(n, convective_times, every, f64_steps):
     ref = run("f32", "f32_mfma", nsteps, every)
     out["f32/f32_mfma"] = {"wall_s": ref[2], "kinetic_energy_final": float(ref[0][-1] / ref[0][0])}
     seg = len(ref[0]) // 10
-    for storage, mlp in [("f32", "bf16"), ("f16", "bf16"), ("bf16", "bf16"), ("bf16sr", "bf16")]:
+    for storage, mlp in [("f32", "bf16"), ("f16", "bf16"), ("bf16", "bf16"), ("f16sr", "bf16"), ("bf16sr", "bf16")]:
         ke, spec, wall = run(storage, mlp, nsteps, every)
         d = [(ke[i * seg] - ke[(i + 1) * seg]) for i in range(10)]
         d_r = [(ref[0][i * seg] - ref[0][(i + 1) * seg]) for i in range(10)]
@@ -554,8 +554,8 @@ def precision_leg(n, nsteps, tstream, torch):
     float32 run's: energy-weighted error sum |E - E_f32| / sum E_f32 and the
     largest relative error of one shell among the shells holding at least
     1e-6 of the peak shell's energy; kinetic-energy error; ms per step.
-    BF16-deviation storage runs with round-to-nearest-even (bf16_dev) and
-    with stochastic rounding (bf16_dev_sr)."""
+    The 16-bit deviation storages run with round-to-nearest-even (f16_dev,
+    bf16_dev) and with stochastic rounding (f16_dev_sr, bf16_dev_sr)."""
     from paper_2412_08229_amd import Lattice, inputs
     u0 = 0.1 / math.sqrt(3.0)
     _, tau = inputs.viscosity(n, u0, 1600.0)
@@ -563,10 +563,10 @@ def precision_leg(n, nsteps, tstream, torch):
     params = inputs.mlp_params(32, seed=0)
     runs = {}
     for name, storage, mlp in [("f32", "f32", "f32_mfma"), ("f16_dev", "f16", "bf16"), ("bf16_dev", "bf16", "bf16"),
-                               ("bf16_dev_sr", "bf16", "bf16")]:
+                               ("f16_dev_sr", "f16", "bf16"), ("bf16_dev_sr", "bf16", "bf16")]:
         with Lattice((n, n, n), storage, "nco", tau, stream=tstream.cuda_stream) as lat:
             lat.set_net_weights(params, 32, "tanh", mlp)
-            if name == "bf16_dev_sr":
+            if name.endswith("_sr"):
                 lat.set_stochastic_rounding(True, 0)
             lat.init_equilibrium(rho, u)
             ms = time_op(lat, nsteps, 0, torch, tstream)
@@ -576,7 +576,7 @@ def precision_leg(n, nsteps, tstream, torch):
     sh = sh[(sh >= 1) & (e0 >= 1e-6 * e0.max())]
     out = {"lattice": n, "steps": nsteps, "reference": "float32 storage + float32 network",
            "shells": "1 <= k with E_f32(k) >= 1e-6 max E_f32", "f32_ms_per_step": ms0}
-    for name in ("f16_dev", "bf16_dev", "bf16_dev_sr"):
+    for name in ("f16_dev", "bf16_dev", "f16_dev_sr", "bf16_dev_sr"):
         ms, e, k = runs[name]
         out[name] = {"ms_per_step": ms, "speedup": ms0 / ms,
                      "spectrum_err": float(np.abs(e - e0).sum() / e0.sum()),

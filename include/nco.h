@@ -119,11 +119,12 @@ int nco_set_op(nco_lattice* lat, int op, double tau);
  * lattice.  Takes effect from the next step; it drops a recorded run. */
 int nco_set_domain(nco_lattice* lat, int domain);
 
-/* Rounding of NCO_BF16_DEV storage in the following steps: enable = 0 (the
- * default) rounds each stored deviation to nearest even; 1 rounds it
- * stochastically, up with probability equal to the fraction dropped, so that
- * stored values are unbiased (a per-step change below half a bfloat16 step
- * is kept on average instead of rounded away).  The random bits are a
+/* Rounding of NCO_BF16_DEV and NCO_F16_DEV storage in the following steps:
+ * enable = 0 (the default) rounds each stored deviation to nearest even; 1
+ * rounds it stochastically, up (away from zero) with probability equal to
+ * its position between the two neighbouring 16-bit values, so that stored
+ * values are unbiased (a per-step change below half a 16-bit step is kept
+ * on average instead of rounded away).  The random bits are a
  * counter-based hash of (seed, step index, node, population), so runs are
  * repeatable and independent of launch shapes, and two-buffer steps,
  * in-place pairs, batched steps and the recomputation of the reverse mode
@@ -132,6 +133,16 @@ int nco_set_domain(nco_lattice* lat, int domain);
  * arithmetic around it.  NCO_E_UNSUPPORTED for other storages,
  * NCO_E_INVALID for another enable value.  Drops a recorded run. */
 int nco_set_stochastic_rounding(nco_lattice* lat, int enable, unsigned seed);
+
+/* Memory the reverse mode may use to keep network values between a
+ * recomputed forward step and its adjoint (float32 matrix-core networks,
+ * Sec. "Learning Task"): 144 bytes per node for each of the K - 1
+ * recomputed states of a segment (K = ckpt_every).  When they fit (default
+ * 4 GiB), the adjoint of those steps reads the group sums of the second layer
+ * and the pre-squash outputs instead of running the network forward again;
+ * the gradient is the same bit for bit.  0 switches it off.  Takes effect
+ * at the next nco_backward. */
+int nco_set_reverse_cache(nco_lattice* lat, size_t bytes);
 
 /* Pairs of steps in place (enable = 1, the default) or always between two
  * buffers (0).  With 1, nco_step runs two consecutive BGK or fixed-rate

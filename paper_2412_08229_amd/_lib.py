@@ -42,6 +42,7 @@ SIGNATURES = {
     "nco_set_rates": (_I, [_P, _D]),
     "nco_set_domain": (_I, [_P, _I]),
     "nco_set_inplace": (_I, [_P, _I]),
+    "nco_set_reverse_cache": (_I, [_P, ctypes.c_size_t]),
     "nco_set_stochastic_rounding": (_I, [_P, _I, ctypes.c_uint]),
     "nco_restrict": (_I, [_P, _P]),
     "nco_set_net_weights": (_I, [_P, _I, _I, _I, _F, _SZ]),
@@ -199,6 +200,10 @@ def nco_set_domain(h, domain):
 
 def nco_set_stochastic_rounding(h, enable, seed):
     check(lib().nco_set_stochastic_rounding(h, int(enable), int(seed) & 0xffffffff))
+
+
+def nco_set_reverse_cache(h, nbytes):
+    check(lib().nco_set_reverse_cache(h, int(nbytes)))
 
 
 def nco_set_inplace(h, enable):

@@ -235,9 +235,15 @@ struct nco_lattice {
     // Pairs of BGK / fixed-rate steps in place on one buffer when it fits
     // the last-level cache (nco_set_inplace; on by default).
     bool inplace = true;
-    // Stochastic rounding of bfloat16 deviation storage (nco_set_stochastic_rounding).
+    // Stochastic rounding of 16-bit deviation storage (nco_set_stochastic_rounding).
     bool sr = false;
     unsigned sr_seed = 0;
+    // Reverse mode of float32 matrix-core networks: the network values each
+    // recomputed forward step keeps for its adjoint (K - 1 states of a
+    // segment), within a budget of net_cache_bytes (nco_set_reverse_cache).
+    float* net_sums = nullptr;
+    size_t net_sums_floats = 0;
+    size_t net_cache_bytes = (size_t)4 << 30;
 };
 
 namespace {
@@ -353,6 +359,7 @@ StepArgs step_args(const nco_lattice* lat) {
     a.force32 = nullptr;
     a.force64 = nullptr;
     a.sr_key = 0;
+    a.net_sums = nullptr;
     return a;
 }
 
@@ -405,8 +412,10 @@ bool inplace_pair_ok(const nco_lattice* lat) {
            !lat->phase_rule && lat->pop_bytes <= LLC_BYTES && 2 * lat->pop_bytes > LLC_BYTES;
 }
 
-int launch_one(nco_lattice* lat, const void* fin, void* fout, long t, int slot = -1, bool replay = false) {
+int launch_one(nco_lattice* lat, const void* fin, void* fout, long t, int slot = -1, bool replay = false,
+               float* net_sums = nullptr) {
     StepArgs a = step_args_at(lat, t);
+    a.net_sums = net_sums;
     if (lat->phase_rule && lat->n_modes > 0) {
         double* fh = slot >= 0 ? phase_slot(lat, slot) : lat->d_fhat_cur;
         // This step's coefficients from the velocity of the state it starts from.
@@ -508,6 +517,7 @@ int nco_lattice_destroy(nco_lattice* lat) {
     if (lat->flag) hipFree(lat->flag);
     if (lat->adj_tab) hipFree(lat->adj_tab);
     if (lat->adj_partial64) hipFree(lat->adj_partial64);
+    if (lat->net_sums) hipFree(lat->net_sums);
     if (lat->spec_work) hipFree(lat->spec_work);
     if (lat->d_fk) hipFree(lat->d_fk);
     if (lat->d_fhat) hipFree(lat->d_fhat);
@@ -779,11 +789,17 @@ int nco_step(nco_lattice* lat, int nsteps) {
 int nco_set_stochastic_rounding(nco_lattice* lat, int enable, unsigned seed) {
     if (int rc = check_lat(lat)) return rc;
     if (enable != 0 && enable != 1) return fail(NCO_E_INVALID, "enable must be 0 or 1");
-    if (enable && lat->storage != NCO_BF16_DEV)
-        return fail(NCO_E_UNSUPPORTED, "stochastic rounding is for bfloat16 deviation storage");
+    if (enable && lat->storage != NCO_BF16_DEV && lat->storage != NCO_F16_DEV)
+        return fail(NCO_E_UNSUPPORTED, "stochastic rounding is for 16-bit deviation storage");
     lat->sr = enable == 1;
     lat->sr_seed = seed;
     lat->rec_steps = -1;  // a recorded run used the other rounding
+    return NCO_OK;
+}
+
+int nco_set_reverse_cache(nco_lattice* lat, size_t bytes) {
+    if (int rc = check_lat(lat)) return rc;
+    lat->net_cache_bytes = bytes;
     return NCO_OK;
 }
 
@@ -1173,6 +1189,23 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
         lat->adj_xwork_floats = nx;
     }
     if (!lat->d_grad) HIP_TRY(hipMalloc(&lat->d_grad, sizeof(double) * adjoint_param_count_depth(3)));
+    // Float32 matrix-core networks: each recomputed forward step keeps its
+    // network values (group sums and tilde tau), and the adjoint of that
+    // step reads them instead of running the network forward again (the
+    // same arithmetic on the same state: the gradient is unchanged, bit for
+    // bit).  The last state of a segment has no recomputed step and runs it.
+    const size_t sums_stride = (size_t)((lat->n + 255) / 256) * 256 * NET_SUMS_PER_NODE;
+    const bool keep_sums = mfma && lat->mlp_prec == NCO_MLP_F32_MFMA && lat->rec_every > 1 &&
+                           (size_t)(lat->rec_every - 1) * sums_stride * sizeof(float) <= lat->net_cache_bytes;
+    if (keep_sums && lat->net_sums_floats < (size_t)(lat->rec_every - 1) * sums_stride) {
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        if (lat->net_sums) HIP_TRY(hipFree(lat->net_sums));
+        lat->net_sums = nullptr;
+        lat->net_sums_floats = 0;
+        HIP_TRY(hipMalloc(&lat->net_sums, sizeof(float) * (size_t)(lat->rec_every - 1) * sums_stride));
+        lat->net_sums_floats = (size_t)(lat->rec_every - 1) * sums_stride;
+    }
+    auto sums_of = [&](int i) { return keep_sums ? lat->net_sums + (size_t)i * sums_stride : nullptr; };
     while ((int)lat->seg.size() < lat->rec_every) {
         void* p = nullptr;
         HIP_TRY(hipMalloc(&p, lat->pop_bytes));
@@ -1206,7 +1239,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
         HIP_TRY(hipMemcpyAsync(lat->seg[0], lat->ckpt[sgi], lat->pop_bytes, hipMemcpyDeviceToDevice, lat->stream));
         for (int i = 1; i < len; ++i)
             if (int rc = launch_one(lat, lat->seg[i - 1], lat->seg[i], lat->rec_force_t0 + t0 + i - 1, t0 + i - 1,
-                                    true))
+                                    true, sums_of(i - 1)))
                 return rc;
         for (int t = t0 + len - 1; t >= t0; --t) {
             StepArgs a = step_args_at(lat, lat->rec_force_t0 + t);
@@ -1214,6 +1247,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
             if (phase) a.fhat = phase_slot(lat, t);
             if (int rc = force_field(lat, a, lat->stream)) return rc;
             if (mfma) {
+                a.net_sums = t - t0 < len - 1 ? sums_of(t - t0) : nullptr;
                 const char* tab = static_cast<const char*>(lat->adj_tab);
                 const float* lt32 = reinterpret_cast<const float*>(tab);
                 const int* gt32 = reinterpret_cast<const int*>(tab + sizeof(float) * mfma_lane_table_floats());

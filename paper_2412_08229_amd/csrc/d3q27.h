@@ -156,6 +156,20 @@ template <> struct Codec<ST_F16> {
         *p = __float2half_rn((v - (float)weight_of(i)) * dev_scale(i));
     }
     static __device__ __forceinline__ void store_cached(store_t* p, int i, real v) { store(p, i, v); }
+    // Stochastic rounding with 16 random bits r: |x| rounded toward zero to
+    // the half value lo, then up to the next half value (gap above lo, a
+    // power of two) when r / 2^16 < (|x| - lo) / gap.  The largest finite
+    // half has gap infinity and never rounds up.
+    static __device__ __forceinline__ void store_sr(store_t* p, int i, real v, unsigned r) {
+        const float x = (v - (float)weight_of(i)) * dev_scale(i);
+        const float ax = fabsf(x);
+        const unsigned short bz = __half_as_ushort(__float2half_rz(ax));
+        const float lo = __half2float(__ushort_as_half(bz));
+        const float gap = __half2float(__ushort_as_half((unsigned short)(bz + 1))) - lo;
+        const bool up = (float)(r & 0xffffu) * (1.0f / 65536.0f) * gap < ax - lo;
+        const unsigned short b = (unsigned short)((bz + (up ? 1 : 0)) | (x < 0.0f ? 0x8000u : 0u));
+        *reinterpret_cast<unsigned short*>(p) = b;
+    }
     static __device__ __forceinline__ store_t from_double(double v, int i) {
         return __float2half_rn((float)((v - weight_of(i)) * dev_scale(i)));
     }
@@ -164,12 +178,13 @@ template <> struct Codec<ST_F16> {
     }
 };
 
-// Stochastic rounding of bfloat16 deviations: the float32 value's low 16
-// bits plus 16 random bits, truncated, rounds up with probability equal to
-// the dropped fraction, so the stored value is unbiased.  The random bits
-// come from a counter-based hash of (step key, node, population): C.
+// Random bits of the stochastic rounding of 16-bit deviations (Codec
+// store_sr): a counter-based hash of (step key, node, population), C.
 // Wellons' "lowbias32" integer hash (xor-shift / multiply rounds, constants
-// 0x7feb352d and 0x846ca68b).
+// 0x7feb352d and 0x846ca68b).  For bfloat16 the float32 value's low 16 bits
+// plus 16 random bits, truncated, rounds up with probability equal to the
+// dropped fraction, so the stored value is unbiased; float16 compares the
+// random fraction with the position of |x| between its two half neighbours.
 __host__ __device__ __forceinline__ unsigned lowbias32(unsigned x) {
     x ^= x >> 16;
     x *= 0x7feb352du;

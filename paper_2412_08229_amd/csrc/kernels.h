@@ -34,11 +34,18 @@ struct StepArgs {
     // float32 otherwise.  The step kernels read it instead of summing modes.
     const float* force32;
     const double* force64;
-    // Rounding of bfloat16 deviation storage in this step: 0 rounds to
+    // Rounding of 16-bit deviation storage in this step: 0 rounds to
     // nearest even, any other value rounds stochastically with random bits
     // keyed by it (see sr_bits).
     unsigned sr_key;
+    // Network values of this step, [node][NET_SUMS_PER_NODE] over the nodes
+    // rounded up to a multiple of 256: the 32 group sums of the second layer
+    // and the 4 pre-squash outputs tilde tau.  A float32 matrix-core step
+    // writes them when set; the matrix-core adjoint of the same step reads
+    // them instead of running the network forward again.  nullptr: neither.
+    float* net_sums;
 };
+constexpr int NET_SUMS_PER_NODE = 36;
 
 // Phases of the spectral modes at a node, e^{i 2 pi (k_x x / nx + k_y y / ny
 // + k_z z / nz)}, as the product over the axes of integer powers of the

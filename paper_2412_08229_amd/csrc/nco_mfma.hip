@@ -119,7 +119,8 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
 // RAW the pre-squash outputs tilde tau_n (for the adjoint).
 template <bool RAW = false>
 __device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float* __restrict__ w3,
-                                             const float* __restrict__ b3, int q, float* __restrict__ sw_node) {
+                                             const float* __restrict__ b3, int q, float* __restrict__ sw_node,
+                                             float* __restrict__ tt_node = nullptr) {
     float pn[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
@@ -137,13 +138,16 @@ __device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float*
         for (int n = 0; n < 4; ++n) {
             const float t = pn[n] + b3[n];
             sw_node[n] = RAW ? t : 1.0f / (0.5f + 0.5f / (1.0f + expf(t)));
+            if (tt_node) tt_node[n] = t;
         }
     }
 }
 
 // s2 != nullptr (adjoint): sw receives tilde tau instead of the rates and
 // s2[node][32] the group sum of the folded second-layer activations (row
-// 16 u + 4 q + r in lane (q, c)).
+// 16 u + 4 q + r in lane (q, c)).  sums != nullptr (a step whose adjoint
+// follows): sw receives the rates, and sums[node][NET_SUMS_PER_NODE] (global
+// memory, the block's nodes) the same group sums and tilde tau.
 //
 // DEPTH = 3: a third hidden layer (W2b, b2b) between the second layer and
 // the group sum, one more product per group element whose B operand is the
@@ -153,7 +157,8 @@ __device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float*
 template <int ACT, int DEPTH = 2, int TPW = 4>
 __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const int* __restrict__ sg,
                                             float* __restrict__ sw, const float* __restrict__ lt, int wave,
-                                            int q, int c, float* __restrict__ s2 = nullptr) {
+                                            int q, int c, float* __restrict__ s2 = nullptr,
+                                            float* __restrict__ sums = nullptr) {
     float A1[2][KSTEPS], A2[2][2][4], B2[2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -294,6 +299,13 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) s2[node * 32 + 16 * u + 4 * q + r] = acc[u][r];
             output_layer<true>(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
+        } else if (sums) {
+            float* __restrict__ row = sums + (size_t)node * NET_SUMS_PER_NODE;
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) row[16 * u + 4 * q + r] = acc[u][r];
+            output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4, row + 32);
         } else {
             output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
         }
@@ -379,7 +391,7 @@ struct BlockLds {
     float* sw;      // [NODES][4] rates
 };
 
-template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH = 2, int TPW = 4>
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH = 2, int TPW = 4, bool SUMS = false>
 __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t* __restrict__ fin,
                                                typename Codec<S>::store_t* __restrict__ fout, const StepArgs& a,
                                                const float* __restrict__ lane_tab, const int* __restrict__ gtab,
@@ -393,12 +405,12 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
 
 constexpr int mfma_block_threads(int nodes, int tpw) { return nodes / (16 * tpw) * 64; }
 
-template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW>
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW, bool SUMS = false>
 __global__ __launch_bounds__(mfma_block_threads(NODES, TPW)) void k_nco_mfma(
     const typename Codec<S>::store_t* __restrict__ fin, typename Codec<S>::store_t* __restrict__ fout,
     StepArgs a, const float* __restrict__ lane_tab, const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
-    nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x,
+    nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW, SUMS>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x,
                                                            lds);
 }
 
@@ -418,7 +430,7 @@ __global__ __launch_bounds__(256) void k_nco_mfma_grouped(LaunchGroup g) {
     grouped_block<S, ACT, PREC>(g.d[i], blockIdx.x - g.prefix[i], lds);
 }
 
-template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW>
+template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW, bool SUMS>
 __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t* __restrict__ fin,
                                                typename Codec<S>::store_t* __restrict__ fout, const StepArgs& a,
                                                const float* __restrict__ lane_tab, const int* __restrict__ gtab,
@@ -459,10 +471,16 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
     {
         const int lane = tid & 63;
         const float* __restrict__ lt = lane_tab + lane * LANE_WORDS;
-        if constexpr (PREC == MLP_PREC_BF16)
+        if constexpr (PREC == MLP_PREC_BF16) {
             network_bf16<ACT, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
-        else
+        } else if constexpr (SUMS) {
+            // A separate instantiation: the stores of the sums would cost the
+            // plain step kernel registers (and half its occupancy).
+            float* sums = a.net_sums + (size_t)blk * NODES * NET_SUMS_PER_NODE;
+            network_f32<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15, nullptr, sums);
+        } else {
             network_f32<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
+        }
     }
     __syncthreads();
 
@@ -636,8 +654,20 @@ __global__ __launch_bounds__(256) void k_adjoint_mfma(const typename Codec<S>::s
     __syncthreads();
 
     const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
-    // Phase B1: the network forward for tilde tau and the group sums.
-    network_f32<ACT, 2, TPW>(sm, sg, sw, lane_tab + lane * LANE_WORDS, wave, q, c, sdm);
+    // Phase B1: the network forward for tilde tau and the group sums, or the
+    // values the forward step of this state kept (the same arithmetic on the
+    // same moments, so the same values).
+    if (a.net_sums) {
+        if (tid < NB) {
+            const float* __restrict__ src = a.net_sums + ((size_t)blockIdx.x * NB + tid) * NET_SUMS_PER_NODE;
+#pragma unroll
+            for (int k = 0; k < 32; ++k) sdm[tid * 32 + k] = src[k];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) sw[tid * 4 + n] = src[32 + n];
+        }
+    } else {
+        network_f32<ACT, 2, TPW>(sm, sg, sw, lane_tab + lane * LANE_WORDS, wave, q, c, sdm);
+    }
     __syncthreads();
 
     // Phase B2: per node, dL/d tilde tau from the node-local collision adjoint.
@@ -1303,6 +1333,24 @@ hipError_t launch_mfma_kind(int kind, const void* fin, void* fout, const StepArg
     using T = typename Codec<S>::store_t;
     const int nodes = kind == MFMA_BLOCK_256 ? 256 : 64;
     const dim3 grid((a.n + nodes - 1) / nodes);
+    if constexpr (!RR && PP == MLP_PREC_F32 && DD == 2) {
+        if (a.net_sums) {
+            // The step also keeps its network values for the adjoint.
+            if (kind == MFMA_BLOCK_64_TILE)
+                hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 1, true>), dim3(grid), dim3(mfma_block_threads(64, 1)),
+                                   0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+            else if (kind == MFMA_BLOCK_64)
+                hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 4, true>), dim3(grid), dim3(mfma_block_threads(64, 4)),
+                                   0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+            else
+                hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 256, DD, 4, true>), dim3(grid),
+                                   dim3(mfma_block_threads(256, 4)), 0, st, static_cast<const T*>(fin),
+                                   static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+            return hipGetLastError();
+        }
+    } else {
+        if (a.net_sums) return hipErrorInvalidValue;
+    }
     if (kind == MFMA_BLOCK_64_TILE)
         hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 1>), dim3(grid), dim3(mfma_block_threads(64, 1)), 0,
                            st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);

@@ -135,12 +135,12 @@ __device__ __forceinline__ void load_local(const typename Codec<S>::store_t* __r
     for (int i = 0; i < Q; ++i) f[i] = Codec<S>::load(fin + (size_t)i * n + idx, i);
 }
 
-// Store the 27 post-collision populations of node idx; with bfloat16
+// Store the 27 post-collision populations of node idx; with 16-bit
 // deviation storage and sr_key != 0 by stochastic rounding.
 template <int S>
 __device__ __forceinline__ void store_local(typename Codec<S>::store_t* __restrict__ fout, int n,
                                             int idx, const typename Codec<S>::real (&f)[Q], unsigned sr_key = 0) {
-    if constexpr (S == ST_BF16) {
+    if constexpr (S == ST_BF16 || S == ST_F16) {
         if (sr_key) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) Codec<S>::store_sr(fout + (size_t)i * n + idx, i, f[i], sr_bits(sr_key, idx, i));
@@ -156,7 +156,7 @@ __device__ __forceinline__ void store_local(typename Codec<S>::store_t* __restri
 template <int S>
 __device__ __forceinline__ void store_one_cached(typename Codec<S>::store_t* p, int idx, int i,
                                                  typename Codec<S>::real v, unsigned sr_key) {
-    if constexpr (S == ST_BF16) {
+    if constexpr (S == ST_BF16 || S == ST_F16) {
         if (sr_key) {
             Codec<S>::store_sr(p, i, v, sr_bits(sr_key, idx, i));
             return;

@@ -103,9 +103,14 @@ class Lattice:
         L.nco_set_domain(self._h, domain)
 
     def set_stochastic_rounding(self, enable, seed=0):
-        """Stochastic rounding of bfloat16 deviation storage in the following
+        """Stochastic rounding of 16-bit deviation storage in the following
         steps (nco_set_stochastic_rounding)."""
         L.nco_set_stochastic_rounding(self._h, 1 if enable else 0, seed)
+
+    def set_reverse_cache(self, nbytes):
+        """Memory for network values kept between a recomputed step and its
+        adjoint (nco_set_reverse_cache; 0: off)."""
+        L.nco_set_reverse_cache(self._h, nbytes)
 
     def set_inplace(self, enable):
         """True (the default): pairs of BGK / fixed-rate steps run in place on

@@ -503,3 +503,30 @@ def test_vector_adjoint_matches_matrix_core_adjoint_at_size(n):
     relf = np.linalg.norm(out["f32"][1] - out["f32_mfma"][1]) / np.linalg.norm(out["f32_mfma"][1])
     print("%d^3: vector vs matrix-core adjoint, grad rel diff %.2e, dL/df0 rel diff %.2e" % (n, rel, relf))
     assert rel < 1e-3 and relf < 1e-5
+
+
+@pytest.mark.parametrize("n,forced", [(24, False), (48, True)])
+def test_reverse_cache_leaves_the_gradient_unchanged(n, forced):
+    """The recomputed forward steps of a segment keep their network values
+    (group sums, tilde tau) and the matrix-core adjoint reads them instead of
+    running the network again: the same arithmetic on the same states, so
+    the gradient must not change at all.  24^3 runs the 64-node kernels, 48^3
+    the 256-node ones; 12 steps with checkpoints every 5 give segments of 5,
+    5 and 2 states (each with a last state that runs the network itself)."""
+    width, tau, T, K = 32, 0.56, 12, 5
+    params = inputs.mlp_params(width, 81)
+    _, u = inputs.turbulence(n, seed=82, k0=4.0, urms=0.05)
+    w = np.random.Generator(np.random.PCG64(83)).standard_normal((27, n, n, n))
+    out = []
+    for cache in (0, 1 << 30):
+        with Lattice((n, n, n), "f32", "nco", tau) as lat:
+            lat.set_net_weights(params, width, "tanh", "f32_mfma")
+            lat.set_reverse_cache(cache)
+            if forced:
+                ks, draws = _forcing(T, seed=84)
+                lat.set_forcing(ks, draws, AMP, KF, CW)
+            lat.init_equilibrium(None, u)
+            lat.forward_record(T, K)
+            out.append(lat.backward(dL_df=w, want_df0=True))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])

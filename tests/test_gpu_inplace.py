@@ -2,7 +2,7 @@
 against the two-buffer steps, through the C ABI: the populations must agree
 bit for bit.  The sizes are those where the pairs run (one buffer fits the
 256 MB last-level cache, two do not): 128^3 float32, a non-cubic float64
-lattice, a bfloat16-deviation lattice (also with stochastic rounding).  Seven steps with a stability check
+lattice, 16-bit deviation lattices (also with stochastic rounding).  Seven steps with a stability check
 every three mix pairs and single steps (a pair never straddles a check)."""
 import numpy as np
 import pytest
@@ -14,8 +14,8 @@ pytestmark = pytest.mark.gpu
 
 def _run(shape, storage, op, forced, inplace, nsteps=7):
     rho, u = inputs.random_velocity(shape, seed=21, amp=0.05)
-    sr = storage == "bf16sr"                 # with stochastic rounding
-    with Lattice(shape, "bf16" if sr else storage, op, 0.56) as lat:
+    sr = storage.endswith("sr")              # with stochastic rounding
+    with Lattice(shape, storage[:-2] if sr else storage, op, 0.56) as lat:
         lat.set_inplace(inplace)
         if sr:
             lat.set_stochastic_rounding(True, 3)
@@ -37,6 +37,7 @@ def _run(shape, storage, op, forced, inplace, nsteps=7):
     ((94, 92, 90), "f64", "bgk", True),
     ((170, 160, 150), "bf16", "mrt", False),
     ((170, 160, 150), "bf16sr", "bgk", True),
+    ((170, 160, 150), "f16sr", "mrt", False),
 ])
 def test_inplace_pairs_equal_two_buffer_steps(shape, storage, op, forced):
     print("in-place pairs vs two buffers: %s %s %s forced=%s" % (shape, storage, op, forced), flush=True)

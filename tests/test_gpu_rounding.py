@@ -1,4 +1,4 @@
-"""Stochastic rounding of BF16-deviation storage (nco_set_stochastic_rounding),
+"""Stochastic rounding of 16-bit deviation storage (nco_set_stochastic_rounding),
 through the C ABI.
 
 * The storage rounds each deviation up with probability equal to the dropped
@@ -8,7 +8,7 @@ through the C ABI.
 * The random bits are a counter-based hash of (seed, step, node, population):
   runs repeat bit for bit, another seed changes them, and batched steps store
   what single steps store.
-* Only BF16-deviation storage accepts it."""
+* Only the 16-bit deviation storages accept it."""
 import numpy as np
 import pytest
 
@@ -21,11 +21,11 @@ pytestmark = pytest.mark.gpu
 SHAPE = (20, 18, 22)
 
 
-def _start():
+def _start(storage):
     rho, u = inputs.random_velocity(SHAPE, seed=31, amp=0.05)
-    with Lattice(SHAPE, "bf16", "bgk", 0.56) as lat:
+    with Lattice(SHAPE, storage, "bgk", 0.56) as lat:
         lat.init_equilibrium(rho, u)
-        return lat.populations()            # exactly representable in BF16-deviation storage
+        return lat.populations()            # exactly representable in that storage
 
 
 def _one_step(f0, storage, sr=None):
@@ -37,21 +37,22 @@ def _one_step(f0, storage, sr=None):
         return lat.populations()
 
 
-def test_stochastic_rounding_is_unbiased():
-    f0 = _start()
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_stochastic_rounding_is_unbiased(storage):
+    f0 = _start(storage)
     x = _one_step(f0, "f32")                   # the values before rounding (float32 arithmetic)
-    y_rne = _one_step(f0, "bf16")
+    y_rne = _one_step(f0, storage)
     K = 64
     acc = np.zeros_like(x)
     for seed in range(K):
-        acc += _one_step(f0, "bf16", sr=seed)
+        acc += _one_step(f0, storage, sr=seed)
     y_sr = acc / K
     e_rne = np.sqrt(np.mean((y_rne - x) ** 2))
-    e_one = np.sqrt(np.mean((_one_step(f0, "bf16", sr=1000) - x) ** 2))
+    e_one = np.sqrt(np.mean((_one_step(f0, storage, sr=1000) - x) ** 2))
     e_avg = np.sqrt(np.mean((y_sr - x) ** 2))
     bias = abs(np.mean(y_sr - x))
-    print("rms error: nearest-even %.3e, one stochastic step %.3e, mean of %d seeds %.3e, bias %.2e"
-          % (e_rne, e_one, K, e_avg, bias))
+    print("%s rms error: nearest-even %.3e, one stochastic step %.3e, mean of %d seeds %.3e, bias %.2e"
+          % (storage, e_rne, e_one, K, e_avg, bias))
     # One stochastic rounding has rms error sqrt(2/3)/sqrt(2) ~ 1.4x that of
     # nearest-even (uniform fractions); the mean of K independent ones falls
     # as 1/sqrt(K): 8x below a single one for K = 64.
@@ -105,8 +106,8 @@ def test_stochastic_rounding_in_a_batch_equals_single_steps():
         assert np.array_equal(g, w)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
-def test_stochastic_rounding_needs_bf16_storage(storage):
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_stochastic_rounding_needs_16_bit_storage(storage):
     with Lattice((4, 4, 4), storage, "bgk", 0.6) as lat:
         with pytest.raises(L.NCOError):
             lat.set_stochastic_rounding(True, 1)
