@@ -37,6 +37,8 @@ TRAFFIC_BYTES = {"nco": 243.6e6 + 226.5e6}
 # activation).  "nco" is the headline (float32 storage and network).
 VARIANTS = {
     "nco": ("nco", "f32", "f32_mfma", "tanh"),
+    # Float32-class network products split over the f16 matrix cores.
+    "nco_f32split": ("nco", "f32", "f32_split", "tanh"),
     "nco_bf16net": ("nco", "f32", "bf16", "tanh"),
     "nco_f16store_bf16net": ("nco", "f16", "bf16", "tanh"),
     "nco_bf16store_bf16net": ("nco", "bf16", "bf16", "tanh"),

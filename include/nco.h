@@ -63,9 +63,15 @@ typedef enum { NCO_F32 = 0, NCO_F16_DEV = 1, NCO_BF16_DEV = 2, NCO_F64 = 3 } nco
 
 typedef enum { NCO_OP_BGK = 0, NCO_OP_MRT = 1, NCO_OP_NCO = 2, NCO_OP_STREAM = 3 } nco_op;
 
-/* Arithmetic of the network: float32 (VALU), float32 matrix cores, or bf16
- * matrix-core products with float32 accumulation. */
-typedef enum { NCO_MLP_F32 = 0, NCO_MLP_F32_MFMA = 1, NCO_MLP_BF16 = 2 } nco_mlp_prec;
+/* Arithmetic of the network: float32 (VALU), float32 matrix cores, bf16
+ * matrix-core products with float32 accumulation, or float32 split over the
+ * f16 matrix cores (NCO_MLP_F32_SPLIT: the first layer on the float32
+ * matrix cores; the second layer's weights and activations each split into
+ * an f16 head and an f16 remainder, three f16 products hi*hi + hi*lo + lo*hi
+ * accumulated in float32, which keeps the product to about 2^-21 of the
+ * terms' magnitude, the order of float32 rounding; tanh and depth 2 only,
+ * the activations being bounded). */
+typedef enum { NCO_MLP_F32 = 0, NCO_MLP_F32_MFMA = 1, NCO_MLP_BF16 = 2, NCO_MLP_F32_SPLIT = 3 } nco_mlp_prec;
 
 typedef enum { NCO_ACT_TANH = 0, NCO_ACT_RELU = 1 } nco_act;
 
@@ -169,8 +175,9 @@ int nco_set_rates(nco_lattice* lat, const double omega_high[4]);
  * m^(g) = M Pi_g f in the row order of M; the output is tilde tau_n for the
  * orders 3..6.  width must be 8, 16, 20 or 32 (the paper's network is
  * width 20 with ReLU).  The matrix-core arithmetics (NCO_MLP_F32_MFMA,
- * NCO_MLP_BF16) need float32 or 16-bit storage and run narrower networks
- * zero-padded to width 32, at the cost of width 32. */
+ * NCO_MLP_BF16, NCO_MLP_F32_SPLIT) need float32 or 16-bit storage and run
+ * narrower networks zero-padded to width 32, at the cost of width 32;
+ * NCO_MLP_F32_SPLIT needs tanh (NCO_E_UNSUPPORTED otherwise). */
 int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec,
                         const float* params, size_t n_params);
 

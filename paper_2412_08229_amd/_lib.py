@@ -17,13 +17,13 @@ NCO_OK, NCO_E_INVALID, NCO_E_OOM, NCO_E_HIP, NCO_E_UNSTABLE, NCO_E_STATE, NCO_E_
     0, -1, -2, -3, -4, -5, -6
 F32, F16_DEV, BF16_DEV, F64 = 0, 1, 2, 3
 OP_BGK, OP_MRT, OP_NCO, OP_STREAM = 0, 1, 2, 3
-MLP_F32, MLP_F32_MFMA, MLP_BF16 = 0, 1, 2
+MLP_F32, MLP_F32_MFMA, MLP_BF16, MLP_F32_SPLIT = 0, 1, 2, 3
 ACT_TANH, ACT_RELU = 0, 1
 
 STORAGE = {"f32": F32, "f16": F16_DEV, "bf16": BF16_DEV, "f64": F64}
 OPS = {"bgk": OP_BGK, "mrt": OP_MRT, "nco": OP_NCO, "stream": OP_STREAM}
 ACTS = {"tanh": ACT_TANH, "relu": ACT_RELU}
-MLP_PREC = {"f32": MLP_F32, "f32_mfma": MLP_F32_MFMA, "bf16": MLP_BF16}
+MLP_PREC = {"f32": MLP_F32, "f32_mfma": MLP_F32_MFMA, "bf16": MLP_BF16, "f32_split": MLP_F32_SPLIT}
 
 # Every exported symbol with (restype, argtypes); the CPU tests check that
 # the library exports exactly these names.

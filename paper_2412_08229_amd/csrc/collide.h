@@ -24,7 +24,7 @@ namespace nco {
 enum Op { OP_BGK = 0, OP_MRT = 1, OP_NCO = 2, OP_NONE = 3 };
 enum Act { ACT_TANH = 0, ACT_RELU = 1 };
 // Matrix-core network arithmetic (values of nco_mlp_prec).
-enum MlpPrec { MLP_PREC_F32 = 1, MLP_PREC_BF16 = 2 };
+enum MlpPrec { MLP_PREC_F32 = 1, MLP_PREC_BF16 = 2, MLP_PREC_F32S = 3 };
 
 constexpr int NGROUP = 48;
 

@@ -39,6 +39,8 @@
 // time, and writes the four rates per node to LDS.  Phase C: each thread pulls
 // its populations again (the kernel is compute bound; the second read is
 // cheap), relaxes with the rates and stores.
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "adjoint.h"
@@ -60,6 +62,8 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 // K-step -> parity class ci = cx + 2 cy + 4 cz of the W1 rows it holds.
 __host__ __device__ constexpr int step_class(int st) {
@@ -76,6 +80,10 @@ constexpr int LT_W3 = 44;           // [u 2][r 4][n 4] W3 / 48
 constexpr int LT_B3 = 76;           // [n 4]
 constexpr int LT_A2B = 80;          // [v 2][t 2][r 4] W2b as A operand (depth 3)
 constexpr int LT_B2B = 96;          // [v 2][r 4]      b2b as accumulator init (depth 3)
+// Split arithmetic (depth 2): LT_A2 holds [u 2][hi 4 words, lo 4 words] of
+// sigma W2 as f16 pairs (the K slots of the f16 product, as LB_A2), LT_B2
+// sigma 2^11 b2, and this word 1 / (sigma 2^11).
+constexpr int LT_SPLIT_BACK = LT_A2B;
 // bf16 path (A operands as packed bf16 pairs, two per word):
 constexpr int LB_A1 = 0;            // [t 2][4 words]  W1 rows 8q..8q+7 / b1
 constexpr int LB_A2 = 8;            // [u 2][4 words]  W2
@@ -114,6 +122,36 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
     return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
 }
 
+__device__ __forceinline__ f32x4 mfma32h(u32x4 a, u32x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                  0, 0);
+}
+
+// Two floats to a packed f16 pair (round to nearest even), low half first.
+__device__ __forceinline__ unsigned pack_f16(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, f16x2));
+}
+
+// The f16 pair (round to nearest even) of the remainders x0 - h0, x1 - h1,
+// h0 and h1 being the two halves of hw: one mixed-precision fused
+// multiply-add per value (the f16 half read in place, the difference exact
+// in float32, one rounding to f16).
+__device__ __forceinline__ unsigned residual_f16(unsigned hw, float x0, float x1) {
+    unsigned d;
+    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(d) : "v"(hw), "v"(x0));
+    asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(d) : "v"(hw), "v"(x1));
+    return d;
+}
+
+// tanh activation of the split arithmetic: 2^11 r with r as in act_scaled,
+// from (1 + 2^x) 2^-11 in one fused multiply-add (exact scaling by a power
+// of two), so that the head and the remainder of 2^11 r in (0, 2048] are
+// both normal f16 numbers down to r ~ 3e-8.
+__device__ __forceinline__ float act_split(float x) {
+    constexpr float S = 0x1p-11f;
+    return __builtin_amdgcn_rcpf(fmaf(__builtin_amdgcn_exp2f(x), S, S));
+}
+
 // Output layer on the group sum of one node tile and the rate squashing;
 // lanes of group q = 0 write the four rates of node (tile, c) to LDS, or with
 // RAW the pre-squash outputs tilde tau_n (for the adjoint).
@@ -141,6 +179,40 @@ __device__ __forceinline__ void output_layer(const f32x4 (&acc)[2], const float*
             if (tt_node) tt_node[n] = t;
         }
     }
+}
+
+// Layer 1 of one axis permutation on the float32 matrix cores for lane group
+// q of a node tile (mrow: the node's moment row, ge: the permutation's gather
+// slots of the group): the eight parity-class partial products over 10
+// K-steps, then their Walsh-Hadamard transform over the class index, after
+// which Y[s][t] is the pre-activation of reflection pattern s (hidden rows
+// 16 t + 4 q + r).
+__device__ __forceinline__ void layer1_reflections(const float (&A1)[2][KSTEPS], const float* __restrict__ mrow,
+                                                   const int* __restrict__ ge, f32x4 (&Y)[8][2]) {
+    // Moment operand of this permutation, one K-step per register.
+    float b[KSTEPS];
+#pragma unroll
+    for (int st = 0; st < KSTEPS; ++st) b[st] = mrow[ge[st]];
+#pragma unroll
+    for (int ci = 0; ci < 8; ++ci) {
+        Y[ci][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+        Y[ci][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int st = 0; st < KSTEPS; ++st)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) Y[step_class(st)][t] = mfma4(A1[t][st], b[st], Y[step_class(st)][t]);
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int ci = 0; ci < 8; ++ci)
+            if (!(ci & bit))
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const f32x4 u0 = Y[ci][t], u1 = Y[ci | bit][t];
+                    Y[ci][t] = u0 + u1;
+                    Y[ci | bit][t] = u0 - u1;
+                }
 }
 
 // s2 != nullptr (adjoint): sw receives tilde tau instead of the rates and
@@ -182,35 +254,8 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
         f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll 1
         for (int p = 0; p < 6; ++p) {
-            // Moment operand of this permutation, one K-step per register.
-            const int* __restrict__ ge = sg + (p * 4 + q) * GT_STRIDE;
-            float b[KSTEPS];
-#pragma unroll
-            for (int st = 0; st < KSTEPS; ++st) b[st] = mrow[ge[st]];
-            // Eight parity-class partial products.
             f32x4 Y[8][2];
-#pragma unroll
-            for (int ci = 0; ci < 8; ++ci) {
-                Y[ci][0] = f32x4{0.f, 0.f, 0.f, 0.f};
-                Y[ci][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-            for (int st = 0; st < KSTEPS; ++st)
-#pragma unroll
-                for (int t = 0; t < 2; ++t) Y[step_class(st)][t] = mfma4(A1[t][st], b[st], Y[step_class(st)][t]);
-            // Walsh-Hadamard transform over the class index: Y[s] becomes the
-            // layer-1 pre-activation of reflection pattern s.
-#pragma unroll
-            for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-                for (int ci = 0; ci < 8; ++ci)
-                    if (!(ci & bit))
-#pragma unroll
-                        for (int t = 0; t < 2; ++t) {
-                            const f32x4 u0 = Y[ci][t], u1 = Y[ci | bit][t];
-                            Y[ci][t] = u0 + u1;
-                            Y[ci | bit][t] = u0 - u1;
-                        }
+            layer1_reflections(A1, mrow, sg + (p * 4 + q) * GT_STRIDE, Y);
             if constexpr (DEPTH == 3) {
                 // Unrolled: Y[s] must stay in registers.
 #pragma unroll
@@ -309,6 +354,73 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
         } else {
             output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
         }
+    }
+}
+
+// Float32-accurate network on the f16 matrix cores (tanh, depth 2).  Layer 1
+// as in network_f32.  Layer 2: with A = sigma W2 (sigma a power of two that
+// puts max |A| in [128, 256)) and B = 2^11 r (act_split), each is split into
+// an f16 head and the f16 remainder, A = Ah + Al, B = Bh + Bl, and
+// A B = Ah Bh + Ah Bl + Al Bh + Al Bl is taken without the last term (below
+// 2^-22 |A B|) as three f16 products accumulated in float32 from
+// sigma 2^11 b2; the pre-activation is that sum times 1 / (sigma 2^11).
+// Per element and tile: 6 products of 16x16x32 instead of 16 of 16x16x4,
+// and 20 vector instructions for the splits and the scaling.
+template <int TPW = 4>
+__device__ __forceinline__ void network_split(const float* __restrict__ sm, const int* __restrict__ sg,
+                                              float* __restrict__ sw, const float* __restrict__ lt, int wave, int q,
+                                              int c) {
+    const unsigned* __restrict__ lw = reinterpret_cast<const unsigned*>(lt);
+    float A1[2][KSTEPS], B2[2][4];
+    u32x4 AH[2], AL[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const unsigned* w = lw + LT_A2 + 8 * u;
+        AH[u] = u32x4{w[0], w[1], w[2], w[3]};
+        AL[u] = u32x4{w[4], w[5], w[6], w[7]};
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) B2[u][r] = lt[LT_B2 + u * 4 + r];
+    const float back = lt[LT_SPLIT_BACK];
+
+#pragma unroll 1
+    for (int j = 0; j < TPW; ++j) {
+        const int node = wave * 16 * TPW + j * 16 + c;
+        const float* __restrict__ mrow = sm + node * NODE_STRIDE;
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll 1
+        for (int p = 0; p < 6; ++p) {
+            f32x4 Y[8][2];
+            layer1_reflections(A1, mrow, sg + (p * 4 + q) * GT_STRIDE, Y);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                // K slot 2 w + e of the product holds hidden unit
+                // 16 (w / 2) + 4 q + 2 (w % 2) + e: Y[s][w / 2][2 (w % 2) + e].
+                u32x4 bh, bl;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const float x0 = act_split(Y[s][w >> 1][2 * (w & 1)]);
+                    const float x1 = act_split(Y[s][w >> 1][2 * (w & 1) + 1]);
+                    bh[w] = pack_f16(x0, x1);
+                    bl[w] = residual_f16(bh[w], x0, x1);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    f32x4 c2 = mfma32h(AH[u], bh, f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]});
+                    c2 = mfma32h(AH[u], bl, c2);
+                    c2 = mfma32h(AL[u], bh, c2);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT_TANH>(c2[r] * back);
+                }
+            }
+        }
+        output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
     }
 }
 
@@ -473,6 +585,9 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
         const float* __restrict__ lt = lane_tab + lane * LANE_WORDS;
         if constexpr (PREC == MLP_PREC_BF16) {
             network_bf16<ACT, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
+        } else if constexpr (PREC == MLP_PREC_F32S) {
+            static_assert(ACT == ACT_TANH && DEPTH == 2 && !SUMS, "split arithmetic: tanh, depth 2");
+            network_split<TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
         } else if constexpr (SUMS) {
             // A separate instantiation: the stores of the sums would cost the
             // plain step kernel registers (and half its occupancy).
@@ -1082,6 +1197,13 @@ unsigned bf16_bits(float v) {                 // round to nearest even
     return u >> 16;
 }
 
+unsigned f16_bits(float v) {                  // round to nearest even (the compiler's conversion)
+    const _Float16 h = (_Float16)v;
+    unsigned short u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+
 }  // namespace
 
 size_t mfma_lane_table_floats() { return 64 * LANE_WORDS; }
@@ -1123,6 +1245,15 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
         b3f[n] = (float)s;
     }
     auto w1row = [&](int k, int h) { return k < 27 ? W1[k * W + h] : k == 27 ? b1[h] : 0.0f; };
+    // Split arithmetic: the power of two sigma that puts max |kappa fold W2|
+    // into [128, 256), well inside the f16 range, with the remainders of all
+    // but the smallest weights normal.
+    float split_sigma = 1.0f;
+    if (prec == MLP_PREC_F32S) {
+        float amax = 0.0f;
+        for (int i = 0; i < W * W; ++i) amax = std::max(amax, std::fabs(kappa * fold * W2[i]));
+        if (amax > 0.0f) split_sigma = std::ldexp(1.0f, 7 - std::ilogb(amax));
+    }
     int slot_row[KSTEPS][4];
     class_slots(slot_row);
     for (int lane = 0; lane < 64; ++lane) {
@@ -1130,18 +1261,41 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
         float* lt = lane_tab + lane * LANE_WORDS;
         unsigned* lw = reinterpret_cast<unsigned*>(lt);
         for (int i = 0; i < LANE_WORDS; ++i) lt[i] = 0.0f;
-        if (prec == MLP_PREC_F32) {
+        if (prec != MLP_PREC_BF16) {
             for (int t = 0; t < 2; ++t)
                 for (int st = 0; st < KSTEPS; ++st) {
                     const int k = slot_row[st][q];
                     lt[LT_A1 + t * KSTEPS + st] = k < 0 ? 0.0f : kappa * w1row(k, 16 * t + c);
                 }
-            for (int u = 0; u < 2; ++u)
-                for (int t = 0; t < 2; ++t)
+            if (prec == MLP_PREC_F32S) {
+                // Head and remainder of sigma W2 in the K slots of the f16
+                // product (slot j: hidden unit 16 (j / 4) + 4 q + j % 4).
+                auto hid = [&](int j) { return 16 * (j / 4) + 4 * q + j % 4; };
+                for (int u = 0; u < 2; ++u)
+                    for (int w = 0; w < 4; ++w) {
+                        unsigned hw = 0, lwd = 0;
+                        for (int e = 0; e < 2; ++e) {
+                            const float a = split_sigma * (kappa * fold * W2[hid(2 * w + e) * W + 16 * u + c]);
+                            const unsigned h = f16_bits(a);
+                            const _Float16 hh = (_Float16)a;
+                            hw |= h << (16 * e);
+                            lwd |= f16_bits(a - (float)hh) << (16 * e);
+                        }
+                        lw[LT_A2 + 8 * u + w] = hw;
+                        lw[LT_A2 + 8 * u + 4 + w] = lwd;
+                    }
+                for (int u = 0; u < 2; ++u)
                     for (int r = 0; r < 4; ++r)
-                        lt[LT_A2 + u * 8 + t * 4 + r] = kappa * fold * W2[(16 * t + 4 * q + r) * W + 16 * u + c];
-            for (int u = 0; u < 2; ++u)
-                for (int r = 0; r < 4; ++r) lt[LT_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
+                        lt[LT_B2 + u * 4 + r] = split_sigma * 2048.0f * (kappa * b2f[16 * u + 4 * q + r]);
+                lt[LT_SPLIT_BACK] = 1.0f / (split_sigma * 2048.0f);
+            } else {
+                for (int u = 0; u < 2; ++u)
+                    for (int t = 0; t < 2; ++t)
+                        for (int r = 0; r < 4; ++r)
+                            lt[LT_A2 + u * 8 + t * 4 + r] = kappa * fold * W2[(16 * t + 4 * q + r) * W + 16 * u + c];
+                for (int u = 0; u < 2; ++u)
+                    for (int r = 0; r < 4; ++r) lt[LT_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
+            }
             for (int u = 0; u < 2; ++u)
                 for (int r = 0; r < 4; ++r)
                     for (int n = 0; n < 4; ++n)
@@ -1197,7 +1351,7 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
             for (int i = 0; i < GT_STRIDE; ++i) {
                 // Row k placed in this slot; 27 is the constant-1 row, 28 zero.
                 int k = -1;
-                if (prec == MLP_PREC_F32) {
+                if (prec != MLP_PREC_BF16) {
                     if (i < KSTEPS) k = slot_row[i][q];
                 } else if (i < 8) {
                     k = 8 * q + i;
@@ -1300,6 +1454,9 @@ hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchG
         if (prec == MLP_PREC_BF16) {                                      \
             if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_BF16); \
             else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_BF16);                 \
+        } else if (prec == MLP_PREC_F32S) {                               \
+            if (act != ACT_TANH) return hipErrorInvalidValue;             \
+            GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_F32S);                      \
         } else {                                                          \
             if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_F32);  \
             else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_F32);                  \
@@ -1369,6 +1526,14 @@ hipError_t launch_mfma_prec(int prec, const void* fin, void* fout, const StepArg
     const int kind = mfma_block_kind(a.n);
     if (prec == MLP_PREC_BF16)
         return launch_mfma_kind<S, ACT, RR, MLP_PREC_BF16, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
+    if (prec == MLP_PREC_F32S) {
+        if constexpr (ACT == ACT_TANH) {
+            if (a.depth == 2)
+                return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32S, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out,
+                                                                      st);
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.depth == 3)
         return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 3>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
     return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);

@@ -38,6 +38,8 @@ MIX = [
     ((6, 6, 6), "f16", "mrt", None, None, 5),
     ((1, 1, 1), "bf16", "bgk", None, None, 2),
     ((4, 9, 2), "f32", "mrt", None, None, 7),
+    ((6, 10, 7), "f32", "nco", "f32_split", "tanh", 5),
+    ((12, 12, 12), "bf16", "nco", "f32_split", "tanh", 3),
 ]
 
 

@@ -60,7 +60,8 @@ def _tgv16():
     return n, rho, u
 
 
-@pytest.mark.parametrize("kind,mlp", [("bgk", "f32"), ("mrt", "f32"), ("nco", "f32"), ("nco", "f32_mfma")])
+@pytest.mark.parametrize("kind,mlp", [("bgk", "f32"), ("mrt", "f32"), ("nco", "f32"), ("nco", "f32_mfma"),
+                                      ("nco", "f32_split")])
 def test_f32_tgv16_100_steps_within_1e5(kind, mlp):
     n, rho, u = _tgv16()
     tau = inputs.viscosity(n, 0.05, 100.0)[1] if kind == "nco" else 0.6
@@ -139,7 +140,7 @@ def test_energy_spectrum_matches_oracle(n):
 
 
 @pytest.mark.parametrize("storage,mlp,tol", [("f64", "f32", 1e-12), ("f32", "f32", 1e-7),
-                                             ("f32", "f32_mfma", 1e-7)])
+                                             ("f32", "f32_mfma", 1e-7), ("f32", "f32_split", 1e-7)])
 def test_conservation_on_gpu(storage, mlp, tol):
     n = 16
     rho, u = inputs.random_velocity((n, n, n), seed=9, amp=0.05)
@@ -174,7 +175,8 @@ def _apply_symmetry(f, name):
 
 @pytest.mark.parametrize("sym", sorted(_SYMMETRIES))
 @pytest.mark.parametrize("storage, mlp, tol", [("f64", "f32", 1e-13), ("f32", "f32", 1e-6),
-                                               ("f32", "f32_mfma", 1e-6), ("f32", "bf16", 1e-5)])
+                                               ("f32", "f32_mfma", 1e-6), ("f32", "f32_split", 1e-6),
+                                               ("f32", "bf16", 1e-5)])
 def test_lattice_symmetry_equivariance_on_gpu(sym, storage, mlp, tol):
     """A lattice symmetry applied to the whole field commutes with two NCO
     steps (Sec. II.B: the group-averaged rates are invariant, the collision
@@ -207,7 +209,7 @@ def test_symmetry_maps_are_lattice_symmetries():
         assert np.array_equal(_apply_symmetry(res[0], name), res[1]), name
 
 
-@pytest.mark.parametrize("mlp", ["f32", "f32_mfma"])
+@pytest.mark.parametrize("mlp", ["f32", "f32_mfma", "f32_split"])
 def test_bench_size_sampled_against_oracle(mlp):
     """128^3 float32 NCO in the benchmark's launch configuration: one step
     checked node by node on a sample of 256 nodes."""
@@ -232,7 +234,7 @@ def test_bench_size_sampled_against_oracle(mlp):
     assert np.abs(got - want).max() < 1e-6
 
 
-@pytest.mark.parametrize("mlp", ["f32", "f32_mfma"])
+@pytest.mark.parametrize("mlp", ["f32", "f32_mfma", "f32_split"])
 def test_repeatable_bitwise(mlp):
     n = 12
     rho, u = inputs.random_velocity((n, n, n), seed=12)
@@ -303,11 +305,33 @@ def test_mfma_network_rates_match_oracle(storage, act):
     assert err < 2e-6
 
 
-@pytest.mark.parametrize("shape", [(5, 7, 9), (1, 1, 1), (16, 16, 16)])
-def test_mfma_step_matches_oracle_ragged(shape):
+@pytest.mark.parametrize("mlp", ["f32_mfma", "f32_split"])
+@pytest.mark.parametrize("shape", [(5, 7, 9), (1, 1, 1), (16, 16, 16), (67, 65, 66)])
+def test_mfma_step_matches_oracle_ragged(shape, mlp):
+    """Two steps against the oracle, from a ragged partial block to a lattice
+    of 256-node blocks (67 x 65 x 66 = 287,430 nodes) with a partial last
+    block."""
     f0 = inputs.random_populations(shape, seed=16, lo=0.9, hi=1.1)
     tau = 0.56
-    with _lattice(shape, "f32", "nco", tau, mlp="f32_mfma") as lat:
+    if shape[0] > 16:
+        # The oracle on a sample of nodes (their pulled neighbourhoods).
+        with _lattice(shape, "f32", "nco", tau, mlp=mlp) as lat:
+            lat.init_populations(f0)
+            lat.step(1)
+            before = lat.populations()
+            lat.step(1)
+            after = lat.populations()
+        rng = np.random.Generator(np.random.PCG64(21))
+        pts = np.concatenate([rng.integers(0, shape, size=(200, 3)), [[s - 1 for s in shape], [0, 0, 0]]])
+        C = np.array([(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)])
+        pulled = np.empty((27, len(pts)))
+        for i, (cx, cy, cz) in enumerate(C):
+            pulled[i] = before[i, (pts[:, 0] - cz) % shape[0], (pts[:, 1] - cy) % shape[1],
+                               (pts[:, 2] - cx) % shape[2]]
+        want = _oracle_op("nco", tau).collide(pulled)
+        assert np.abs(after[:, pts[:, 0], pts[:, 1], pts[:, 2]] - want).max() < 1e-6
+        return
+    with _lattice(shape, "f32", "nco", tau, mlp=mlp) as lat:
         lat.init_populations(f0)
         f_stored = lat.populations()
         lat.step(2)
@@ -324,7 +348,7 @@ def test_mfma_requires_float_storage():
 
 
 @pytest.mark.parametrize("width, act", [(20, "relu"), (20, "tanh"), (8, "tanh"), (16, "relu")])
-@pytest.mark.parametrize("mlp, tol", [("f32_mfma", 2e-6), ("bf16", 5e-3)])
+@pytest.mark.parametrize("mlp, tol", [("f32_mfma", 2e-6), ("bf16", 5e-3), ("f32_split", 2e-6)])
 def test_mfma_narrow_networks_match_oracle(width, act, mlp, tol):
     """Widths below 32 on the matrix cores (zero-padded to 32), among them
     the paper's 27-20-20-4 ReLU network: rates on a ragged lattice against
@@ -333,6 +357,8 @@ def test_mfma_narrow_networks_match_oracle(width, act, mlp, tol):
     rho, u = inputs.random_velocity(shape, seed=17, amp=0.1)
     f0 = collision.equilibrium(rho, u) + 0.01 * (inputs.random_populations(shape, seed=18) - 1.0 / 27)
     layers = collision.unpack_params(_params(width, 19), width)
+    if mlp == "f32_split" and act != "tanh":
+        pytest.skip("the split arithmetic runs tanh networks only (refusal tested separately)")
     with _lattice(shape, "f32", "nco", 0.58, width=width, seed=19, act=act, mlp=mlp) as lat:
         lat.init_populations(f0)
         f_stored = lat.populations()
@@ -342,7 +368,49 @@ def test_mfma_narrow_networks_match_oracle(width, act, mlp, tol):
     want = collision.nco_rates(f_stored, layers, act)
     assert np.abs(got - want).max() < tol
     op = step.Operator("nco", 0.58, layers=layers, act=act)
-    assert np.abs(after - step.run(f_stored, op, 2)).max() < (2e-6 if mlp == "f32_mfma" else 1e-4)
+    assert np.abs(after - step.run(f_stored, op, 2)).max() < (1e-4 if mlp == "bf16" else 2e-6)
+
+
+# ------------------------------------------- float32 split over f16 products --
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("w2_scale", [1.0, 1e-3, 40.0])
+def test_split_network_rates_match_oracle(storage, w2_scale):
+    """Split arithmetic (second layer as three f16 products of heads and
+    remainders): rates on a ragged lattice against the float64 oracle at the
+    float32 matrix cores' bound, with the second layer's weights scaled
+    over five decades (the power-of-two scale that keeps the f16 heads in
+    range), and its error within a few times that of the float32 matrix
+    cores on the same state."""
+    shape = (5, 7, 9)
+    rho, u = inputs.random_velocity(shape, seed=13, amp=0.1)
+    f0 = collision.equilibrium(rho, u) + 0.01 * (inputs.random_populations(shape, seed=14) - 1.0 / 27)
+    params = _params(32, 15).copy()
+    n1 = 27 * 32 + 32
+    params[n1:n1 + 32 * 32] *= w2_scale
+    params = params.astype(np.float32).astype(np.float64)      # the weights the lattice holds
+    layers = collision.unpack_params(params, 32)
+    errs = {}
+    for mlp in ("f32_mfma", "f32_split"):
+        with Lattice(shape, storage, "nco", 0.6) as lat:
+            lat.set_net_weights(params, 32, "tanh", mlp)
+            lat.init_populations(f0)
+            got = lat.rates()
+            f_stored = lat.populations()
+        want = collision.nco_rates(f_stored, layers, "tanh")
+        errs[mlp] = np.abs(got - want).max()
+    print("rates %s, W2 x %g: float32 matrix cores %.3e, split %.3e" % (storage, w2_scale, errs["f32_mfma"],
+                                                                        errs["f32_split"]))
+    assert errs["f32_split"] < 2e-6
+    assert errs["f32_split"] < 4 * errs["f32_mfma"] + 1e-7
+
+
+@pytest.mark.parametrize("act, depth", [("relu", 2), ("tanh", 3)])
+def test_split_network_refuses_relu_and_depth_3(act, depth):
+    with Lattice((4, 4, 4), "f32", "nco", 0.6) as lat:
+        with pytest.raises(L.NCOError) as e:
+            lat.set_net_weights(inputs.mlp_params(32, 3, depth=depth), 32, act, "f32_split", depth=depth)
+        assert e.value.status == L.NCO_E_UNSUPPORTED
 
 
 # ------------------------------------------------------ precision forms -------
@@ -369,7 +437,7 @@ def test_bf16_network_rates_close_to_oracle(storage, act):
 # Measured errors against the float64 oracle after 100 steps of the 16^3
 # Taylor-Green case (NCO, 27-32-32-4 tanh); bounds carry a margin of ~3x.
 PRECISION_BOUNDS = {
-    ("f32", "f32"): 1e-5, ("f32", "f32_mfma"): 1e-5, ("f32", "bf16"): 3e-5,
+    ("f32", "f32"): 1e-5, ("f32", "f32_mfma"): 1e-5, ("f32", "f32_split"): 1e-5, ("f32", "bf16"): 3e-5,
     ("f16", "f32_mfma"): 3e-5, ("f16", "bf16"): 5e-5,
     ("bf16", "f32_mfma"): 3e-4, ("bf16", "bf16"): 3e-4,
 }
