@@ -65,12 +65,12 @@ typedef enum { NCO_OP_BGK = 0, NCO_OP_MRT = 1, NCO_OP_NCO = 2, NCO_OP_STREAM = 3
 
 /* Arithmetic of the network: float32 (VALU), float32 matrix cores, bf16
  * matrix-core products with float32 accumulation, or float32 split over the
- * f16 matrix cores (NCO_MLP_F32_SPLIT: the first layer on the float32
- * matrix cores; the second layer's weights and activations each split into
- * an f16 head and an f16 remainder, three f16 products hi*hi + hi*lo + lo*hi
- * accumulated in float32, which keeps the product to about 2^-21 of the
- * terms' magnitude, the order of float32 rounding; tanh and depth 2 only,
- * the activations being bounded). */
+ * 16-bit matrix cores (NCO_MLP_F32_SPLIT: the first layer on the float32
+ * matrix cores; each hidden-to-hidden layer's weights and activations split
+ * into parts whose products, accumulated in float32, give the float32
+ * product to a few units of its rounding: an f16 head and remainder of
+ * power-of-two-scaled operands and three products for tanh, three bf16
+ * parts and six products for ReLU, whose activations are unbounded). */
 typedef enum { NCO_MLP_F32 = 0, NCO_MLP_F32_MFMA = 1, NCO_MLP_BF16 = 2, NCO_MLP_F32_SPLIT = 3 } nco_mlp_prec;
 
 typedef enum { NCO_ACT_TANH = 0, NCO_ACT_RELU = 1 } nco_act;
@@ -176,8 +176,7 @@ int nco_set_rates(nco_lattice* lat, const double omega_high[4]);
  * orders 3..6.  width must be 8, 16, 20 or 32 (the paper's network is
  * width 20 with ReLU).  The matrix-core arithmetics (NCO_MLP_F32_MFMA,
  * NCO_MLP_BF16, NCO_MLP_F32_SPLIT) need float32 or 16-bit storage and run
- * narrower networks zero-padded to width 32, at the cost of width 32;
- * NCO_MLP_F32_SPLIT needs tanh (NCO_E_UNSUPPORTED otherwise). */
+ * narrower networks zero-padded to width 32, at the cost of width 32. */
 int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec,
                         const float* params, size_t n_params);
 
@@ -186,8 +185,9 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec,
  * 27 -> width -> width -> width -> 4, params in the order W1[27][width],
  * b1, W2[width][width], b2, W2b[width][width], b2b, W3[width][4], b3
  * (n_params = width*(27 + 2 width + 4) + 3 width + 4).  Depth 3 runs on the
- * vector units (NCO_MLP_F32) or the float32 matrix cores (NCO_MLP_F32_MFMA),
- * not the bf16 ones (NCO_E_UNSUPPORTED), with narrower networks zero-padded
+ * vector units (NCO_MLP_F32), the float32 matrix cores (NCO_MLP_F32_MFMA)
+ * or split over the 16-bit ones (NCO_MLP_F32_SPLIT), not on the bf16
+ * network (NCO_E_UNSUPPORTED), with narrower networks zero-padded
  * to width 32, and has the reverse mode (vector-unit adjoint): nco_backward
  * returns the gradient in this parameter order.  nco_batch_step refuses
  * depth-3 lattices.  Setting the weights drops a recorded run. */

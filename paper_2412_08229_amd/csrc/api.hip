@@ -594,10 +594,8 @@ int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, i
         return fail(NCO_E_INVALID, "unknown network precision %d", mlp_prec);
     if (mlp_prec != NCO_MLP_F32 && lat->storage == NCO_F64)
         return fail(NCO_E_UNSUPPORTED, "the matrix-core network needs float32 or 16-bit storage");
-    if (depth == 3 && (mlp_prec == NCO_MLP_BF16 || mlp_prec == NCO_MLP_F32_SPLIT))
-        return fail(NCO_E_UNSUPPORTED, "a third hidden layer runs on the vector units or the float32 matrix cores");
-    if (mlp_prec == NCO_MLP_F32_SPLIT && act != NCO_ACT_TANH)
-        return fail(NCO_E_UNSUPPORTED, "the split float32 arithmetic needs the bounded activation (tanh)");
+    if (depth == 3 && mlp_prec == NCO_MLP_BF16)
+        return fail(NCO_E_UNSUPPORTED, "a third hidden layer runs on the vector units or float32-class matrix cores");
     if (!params) return fail(NCO_E_INVALID, "null parameters");
     if (n_params != n_params_depth(width, depth))
         return fail(NCO_E_INVALID, "expected %zu parameters for width %d and depth %d, got %zu",

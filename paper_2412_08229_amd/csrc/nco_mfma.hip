@@ -80,10 +80,18 @@ constexpr int LT_W3 = 44;           // [u 2][r 4][n 4] W3 / 48
 constexpr int LT_B3 = 76;           // [n 4]
 constexpr int LT_A2B = 80;          // [v 2][t 2][r 4] W2b as A operand (depth 3)
 constexpr int LT_B2B = 96;          // [v 2][r 4]      b2b as accumulator init (depth 3)
-// Split arithmetic (depth 2): LT_A2 holds [u 2][hi 4 words, lo 4 words] of
-// sigma W2 as f16 pairs (the K slots of the f16 product, as LB_A2), LT_B2
-// sigma 2^11 b2, and this word 1 / (sigma 2^11).
-constexpr int LT_SPLIT_BACK = LT_A2B;
+// Split arithmetic (network_split; layer 1 at LT_A1, W3 / b3 at LT_W3 /
+// LT_B3 as above): per split layer (the second, and the third at depth 3)
+// the parts of its A operand as packed pairs in the K slots of the 16x16x32
+// product ([u 2][part 3][4 words]: f16 head and remainder for tanh, bf16
+// head, middle and tail for ReLU), the accumulator init [u 2][r 4] and the
+// scale that returns the product to the pre-activation.
+constexpr int LS_A2 = 20;
+constexpr int LS_B2 = 80;
+constexpr int LS_A3 = 88;
+constexpr int LS_B3 = 112;
+constexpr int LS_BACK = 120;        // [layer 2]
+constexpr int LS_NEG1 = 122;        // -1.0 (see residual_f16)
 // bf16 path (A operands as packed bf16 pairs, two per word):
 constexpr int LB_A1 = 0;            // [t 2][4 words]  W1 rows 8q..8q+7 / b1
 constexpr int LB_A2 = 8;            // [u 2][4 words]  W2
@@ -91,7 +99,7 @@ constexpr int LB_B2 = 16;           // [u 2][r 4]
 constexpr int LB_W3 = 24;           // [u 2][r 4][n 4]
 constexpr int LB_B3 = 56;           // [n 4]
 constexpr int LB_SM = 60;           // [bit 3][4 words] sign masks of classes with that bit
-constexpr int LANE_WORDS = 104;
+constexpr int LANE_WORDS = 128;
 
 // Activation as evaluated on this path.  For tanh the pre-activation arrives
 // scaled by kappa = 2 log2(e) and the function returns r = 1 / (1 + 2^(kappa z)),
@@ -133,14 +141,29 @@ __device__ __forceinline__ unsigned pack_f16(float lo, float hi) {
 }
 
 // The f16 pair (round to nearest even) of the remainders x0 - h0, x1 - h1,
-// h0 and h1 being the two halves of hw: one mixed-precision fused
-// multiply-add per value (the f16 half read in place, the difference exact
-// in float32, one rounding to f16).
-__device__ __forceinline__ unsigned residual_f16(unsigned hw, float x0, float x1) {
-    unsigned d;
-    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(d) : "v"(hw), "v"(x0));
-    asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(d) : "v"(hw), "v"(x1));
-    return d;
+// h0 and h1 being the two halves of hw (the differences are exact in
+// float32).  neg1 = -1 arrives as data: with it the compiler emits one
+// mixed-precision multiply-add per value that reads the f16 half in place
+// (a literal -1 turns into a subtraction after a separate conversion), and,
+// unlike hand-written assembly, it sees the write and keeps the wait
+// states a matrix-core read of the result needs.
+__device__ __forceinline__ unsigned residual_f16(unsigned hw, float x0, float x1, float neg1) {
+    const f16x2 h = __builtin_bit_cast(f16x2, hw);
+    return pack_f16(fmaf((float)h[0], neg1, x0), fmaf((float)h[1], neg1, x1));
+}
+
+// Three-part bf16 split of a float32 pair into head, middle and tail words
+// (low half: x0's part), each part the nearest bf16 of what the previous
+// parts leave (those differences are exact in float32): |x - head| <=
+// 2^-8 |x|, |x - head - middle| <= 2^-16 |x|, |x - head - middle - tail| <=
+// 2^-24 |x|.  bf16 has float32's exponent range, so no part overflows or
+// leaves the normal range before float32 itself would.
+__device__ __forceinline__ void split3_bf16(float x0, float x1, unsigned& h, unsigned& m, unsigned& t) {
+    h = pack_bf16(x0, x1);
+    const float r0 = x0 - __uint_as_float(h << 16), r1 = x1 - __uint_as_float(h & 0xffff0000u);
+    m = pack_bf16(r0, r1);
+    const float s0 = r0 - __uint_as_float(m << 16), s1 = r1 - __uint_as_float(m & 0xffff0000u);
+    t = pack_bf16(s0, s1);
 }
 
 // tanh activation of the split arithmetic: 2^11 r with r as in act_scaled,
@@ -357,37 +380,105 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
     }
 }
 
-// Float32-accurate network on the f16 matrix cores (tanh, depth 2).  Layer 1
-// as in network_f32.  Layer 2: with A = sigma W2 (sigma a power of two that
-// puts max |A| in [128, 256)) and B = 2^11 r (act_split), each is split into
-// an f16 head and the f16 remainder, A = Ah + Al, B = Bh + Bl, and
-// A B = Ah Bh + Ah Bl + Al Bh + Al Bl is taken without the last term (below
-// 2^-22 |A B|) as three f16 products accumulated in float32 from
-// sigma 2^11 b2; the pre-activation is that sum times 1 / (sigma 2^11).
-// Per element and tile: 6 products of 16x16x32 instead of 16 of 16x16x4,
-// and 20 vector instructions for the splits and the scaling.
-template <int TPW = 4>
+// One split layer: the pre-activations c[u] (rows 16 u + 4 q + r, f32x4 over
+// r) of A h + b for the activations h[t][r] (hidden unit 16 t + 4 q + r) of
+// the previous layer, K slot 2 w + e of the products holding
+// h[w / 2][2 (w % 2) + e].
+//   tanh: h = 2^11 r (act_split), A = sigma W (sigma a power of two putting
+//     max |A| in [128, 256)); each split into an f16 head and the f16
+//     remainder, A h = Ah hh + Ah hl + Al hh (the dropped Al hl is below
+//     2^-22 |A h|), three f16 products accumulated in float32 from
+//     sigma 2^11 b, times back = 1 / (sigma 2^11).
+//   ReLU: h unbounded, so three bf16 parts of each (split3_bf16), unscaled,
+//     and the six products whose parts' orders sum to at most 2 (the dropped
+//     ones are below 2^-23 |A h|), accumulated from b.
+// A[u][part]: the operand parts of the layer (A[u][2] unused for tanh).
+template <int ACT>
+__device__ __forceinline__ void split_layer(const u32x4 (&A)[2][3], const float (&b)[2][4], float back, float neg1,
+                                            const float (&h)[2][4], f32x4 (&c)[2]) {
+    if constexpr (ACT == ACT_TANH) {
+        u32x4 bh, bl;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const float x0 = h[w >> 1][2 * (w & 1)], x1 = h[w >> 1][2 * (w & 1) + 1];
+            bh[w] = pack_f16(x0, x1);
+            bl[w] = residual_f16(bh[w], x0, x1, neg1);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            f32x4 t = mfma32h(A[u][0], bh, f32x4{b[u][0], b[u][1], b[u][2], b[u][3]});
+            t = mfma32h(A[u][0], bl, t);
+            t = mfma32h(A[u][1], bh, t);
+            c[u] = t * back;
+        }
+    } else {
+        u32x4 bp[3];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            unsigned x, y, z;
+            split3_bf16(h[w >> 1][2 * (w & 1)], h[w >> 1][2 * (w & 1) + 1], x, y, z);
+            bp[0][w] = x;
+            bp[1][w] = y;
+            bp[2][w] = z;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            f32x4 t = mfma32(A[u][0], bp[0], f32x4{b[u][0], b[u][1], b[u][2], b[u][3]});
+            t = mfma32(A[u][0], bp[1], t);
+            t = mfma32(A[u][1], bp[0], t);
+            t = mfma32(A[u][0], bp[2], t);
+            t = mfma32(A[u][2], bp[0], t);
+            c[u] = mfma32(A[u][1], bp[1], t);
+        }
+    }
+}
+
+// Activation feeding a split layer: 2^11 r for tanh (act_split), max(x, 0)
+// for ReLU.
+template <int ACT>
+__device__ __forceinline__ float act_into_split(float x) {
+    if constexpr (ACT == ACT_TANH)
+        return act_split(x);
+    else
+        return fmaxf(x, 0.0f);
+}
+
+// Float32-class network with its hidden-to-hidden layers on the f16 / bf16
+// matrix cores (split_layer; the products equal float32's to a few units of
+// its rounding).  Layer 1 as in network_f32 (float32 matrix cores with the
+// Walsh-Hadamard fold).  Per group element and tile, a split layer runs 6
+// (tanh) or 12 (ReLU) products of 16x16x32 instead of 16 of 16x16x4.
+template <int ACT, int DEPTH = 2, int TPW = 4>
 __device__ __forceinline__ void network_split(const float* __restrict__ sm, const int* __restrict__ sg,
                                               float* __restrict__ sw, const float* __restrict__ lt, int wave, int q,
                                               int c) {
     const unsigned* __restrict__ lw = reinterpret_cast<const unsigned*>(lt);
-    float A1[2][KSTEPS], B2[2][4];
-    u32x4 AH[2], AL[2];
+    constexpr int NP = ACT == ACT_TANH ? 2 : 3;
+    float A1[2][KSTEPS], B2[2][4], B3[2][4];
+    u32x4 AS2[2][3], AS3[2][3];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const unsigned* w = lw + LT_A2 + 8 * u;
-        AH[u] = u32x4{w[0], w[1], w[2], w[3]};
-        AL[u] = u32x4{w[4], w[5], w[6], w[7]};
-    }
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const unsigned* w2 = lw + LS_A2 + 12 * u + 4 * k;
+            AS2[u][k] = k < NP ? u32x4{w2[0], w2[1], w2[2], w2[3]} : u32x4{0u, 0u, 0u, 0u};
+            if constexpr (DEPTH == 3) {
+                const unsigned* w3 = lw + LS_A3 + 12 * u + 4 * k;
+                AS3[u][k] = k < NP ? u32x4{w3[0], w3[1], w3[2], w3[3]} : u32x4{0u, 0u, 0u, 0u};
+            }
+        }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) B2[u][r] = lt[LT_B2 + u * 4 + r];
-    const float back = lt[LT_SPLIT_BACK];
+        for (int r = 0; r < 4; ++r) {
+            B2[u][r] = lt[LS_B2 + u * 4 + r];
+            B3[u][r] = DEPTH == 3 ? lt[LS_B3 + u * 4 + r] : 0.0f;
+        }
+    const float back2 = lt[LS_BACK], back3 = lt[LS_BACK + 1], neg1 = lt[LS_NEG1];
 
 #pragma unroll 1
     for (int j = 0; j < TPW; ++j) {
@@ -400,24 +491,25 @@ __device__ __forceinline__ void network_split(const float* __restrict__ sm, cons
             layer1_reflections(A1, mrow, sg + (p * 4 + q) * GT_STRIDE, Y);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                // K slot 2 w + e of the product holds hidden unit
-                // 16 (w / 2) + 4 q + 2 (w % 2) + e: Y[s][w / 2][2 (w % 2) + e].
-                u32x4 bh, bl;
+                float h1[2][4];
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const float x0 = act_split(Y[s][w >> 1][2 * (w & 1)]);
-                    const float x1 = act_split(Y[s][w >> 1][2 * (w & 1) + 1]);
-                    bh[w] = pack_f16(x0, x1);
-                    bl[w] = residual_f16(bh[w], x0, x1);
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) h1[t][r] = act_into_split<ACT>(Y[s][t][r]);
+                f32x4 cz[2];
+                split_layer<ACT>(AS2, B2, back2, neg1, h1, cz);
+                if constexpr (DEPTH == 3) {
+                    float h2[2][4];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h2[u][r] = act_into_split<ACT>(cz[u][r]);
+                    split_layer<ACT>(AS3, B3, back3, neg1, h2, cz);
                 }
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    f32x4 c2 = mfma32h(AH[u], bh, f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]});
-                    c2 = mfma32h(AH[u], bl, c2);
-                    c2 = mfma32h(AL[u], bh, c2);
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT_TANH>(c2[r] * back);
-                }
+                    for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(cz[u][r]);
             }
         }
         output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
@@ -517,8 +609,17 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
 
 constexpr int mfma_block_threads(int nodes, int tpw) { return nodes / (16 * tpw) * 64; }
 
+// Waves per SIMD the register allocation must leave room for: 3 for the
+// split tanh network at depth 2 (it fits 168 registers without spilling and
+// is bound by its vector instructions, which a third wave keeps issuing), no
+// constraint otherwise.
+constexpr int mfma_min_waves(int prec, int act, int depth) {
+    return prec == MLP_PREC_F32S && act == ACT_TANH && depth == 2 ? 3 : 1;
+}
+
 template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW, bool SUMS = false>
-__global__ __launch_bounds__(mfma_block_threads(NODES, TPW)) void k_nco_mfma(
+__global__ __launch_bounds__(mfma_block_threads(NODES, TPW))
+__attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC, ACT, DEPTH)))) void k_nco_mfma(
     const typename Codec<S>::store_t* __restrict__ fin, typename Codec<S>::store_t* __restrict__ fout,
     StepArgs a, const float* __restrict__ lane_tab, const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
@@ -586,8 +687,8 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
         if constexpr (PREC == MLP_PREC_BF16) {
             network_bf16<ACT, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
         } else if constexpr (PREC == MLP_PREC_F32S) {
-            static_assert(ACT == ACT_TANH && DEPTH == 2 && !SUMS, "split arithmetic: tanh, depth 2");
-            network_split<TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
+            static_assert(!SUMS, "the split arithmetic keeps no network values");
+            network_split<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
         } else if constexpr (SUMS) {
             // A separate instantiation: the stores of the sums would cost the
             // plain step kernel registers (and half its occupancy).
@@ -1197,6 +1298,13 @@ unsigned bf16_bits(float v) {                 // round to nearest even
     return u >> 16;
 }
 
+float bf16_value(unsigned bits) {
+    const unsigned u = bits << 16;
+    float v;
+    std::memcpy(&v, &u, 4);
+    return v;
+}
+
 unsigned f16_bits(float v) {                  // round to nearest even (the compiler's conversion)
     const _Float16 h = (_Float16)v;
     unsigned short u;
@@ -1245,15 +1353,27 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
         b3f[n] = (float)s;
     }
     auto w1row = [&](int k, int h) { return k < 27 ? W1[k * W + h] : k == 27 ? b1[h] : 0.0f; };
-    // Split arithmetic: the power of two sigma that puts max |kappa fold W2|
-    // into [128, 256), well inside the f16 range, with the remainders of all
-    // but the smallest weights normal.
-    float split_sigma = 1.0f;
-    if (prec == MLP_PREC_F32S) {
-        float amax = 0.0f;
-        for (int i = 0; i < W * W; ++i) amax = std::max(amax, std::fabs(kappa * fold * W2[i]));
-        if (amax > 0.0f) split_sigma = std::ldexp(1.0f, 7 - std::ilogb(amax));
+    // Split arithmetic, tanh: per split layer the power of two sigma that
+    // puts max |kappa fold W| into [128, 256), well inside the f16 range,
+    // with the remainders of all but negligible weights normal; b2bf the
+    // third layer's bias with the tanh fold.
+    float split_sigma[2] = {1.0f, 1.0f};
+    float b2bf[MW] = {};
+    if (prec == MLP_PREC_F32S && th) {
+        for (int l = 0; l < (depth == 3 ? 2 : 1); ++l) {
+            const float* Wl = l == 0 ? W2 : W2b;
+            float amax = 0.0f;
+            for (int i = 0; i < W * W; ++i) amax = std::max(amax, std::fabs(kappa * fold * Wl[i]));
+            if (amax > 0.0f) split_sigma[l] = std::ldexp(1.0f, 7 - std::ilogb(amax));
+        }
     }
+    if (depth == 3)
+        for (int o = 0; o < W; ++o) {
+            double sb = b2b[o];
+            if (th)
+                for (int h = 0; h < W; ++h) sb += W2b[h * W + o];
+            b2bf[o] = (float)sb;
+        }
     int slot_row[KSTEPS][4];
     class_slots(slot_row);
     for (int lane = 0; lane < 64; ++lane) {
@@ -1268,26 +1388,35 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
                     lt[LT_A1 + t * KSTEPS + st] = k < 0 ? 0.0f : kappa * w1row(k, 16 * t + c);
                 }
             if (prec == MLP_PREC_F32S) {
-                // Head and remainder of sigma W2 in the K slots of the f16
-                // product (slot j: hidden unit 16 (j / 4) + 4 q + j % 4).
+                // Parts of each split layer's A operand in the K slots of
+                // its product (slot j: hidden unit 16 (j / 4) + 4 q + j % 4).
                 auto hid = [&](int j) { return 16 * (j / 4) + 4 * q + j % 4; };
-                for (int u = 0; u < 2; ++u)
-                    for (int w = 0; w < 4; ++w) {
-                        unsigned hw = 0, lwd = 0;
-                        for (int e = 0; e < 2; ++e) {
-                            const float a = split_sigma * (kappa * fold * W2[hid(2 * w + e) * W + 16 * u + c]);
-                            const unsigned h = f16_bits(a);
-                            const _Float16 hh = (_Float16)a;
-                            hw |= h << (16 * e);
-                            lwd |= f16_bits(a - (float)hh) << (16 * e);
-                        }
-                        lw[LT_A2 + 8 * u + w] = hw;
-                        lw[LT_A2 + 8 * u + 4 + w] = lwd;
-                    }
-                for (int u = 0; u < 2; ++u)
-                    for (int r = 0; r < 4; ++r)
-                        lt[LT_B2 + u * 4 + r] = split_sigma * 2048.0f * (kappa * b2f[16 * u + 4 * q + r]);
-                lt[LT_SPLIT_BACK] = 1.0f / (split_sigma * 2048.0f);
+                auto fill = [&](const float* Wl, const float* bfold, float sigma, int offA, int offB, int slot) {
+                    for (int u = 0; u < 2; ++u)
+                        for (int w = 0; w < 4; ++w)
+                            for (int e = 0; e < 2; ++e) {
+                                const float a = sigma * (kappa * fold * Wl[hid(2 * w + e) * W + 16 * u + c]);
+                                unsigned part[3];
+                                if (th) {
+                                    part[0] = f16_bits(a);
+                                    part[1] = f16_bits(a - (float)(_Float16)a);
+                                    part[2] = 0;
+                                } else {
+                                    part[0] = bf16_bits(a);
+                                    const float r = a - bf16_value(part[0]);
+                                    part[1] = bf16_bits(r);
+                                    part[2] = bf16_bits(r - bf16_value(part[1]));
+                                }
+                                for (int k = 0; k < 3; ++k) lw[offA + 12 * u + 4 * k + w] |= part[k] << (16 * e);
+                            }
+                    const float up = th ? sigma * 2048.0f : 1.0f;
+                    for (int u = 0; u < 2; ++u)
+                        for (int r = 0; r < 4; ++r) lt[offB + u * 4 + r] = up * (kappa * bfold[16 * u + 4 * q + r]);
+                    lt[LS_BACK + slot] = 1.0f / up;
+                };
+                lt[LS_NEG1] = -1.0f;
+                fill(W2, b2f, split_sigma[0], LS_A2, LS_B2, 0);
+                if (depth == 3) fill(W2b, b2bf, split_sigma[1], LS_A3, LS_B3, 1);
             } else {
                 for (int u = 0; u < 2; ++u)
                     for (int t = 0; t < 2; ++t)
@@ -1301,7 +1430,7 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
                     for (int n = 0; n < 4; ++n)
                         lt[LT_W3 + (u * 4 + r) * 4 + n] = fold * W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
             for (int n = 0; n < 4; ++n) lt[LT_B3 + n] = b3f[n];
-            if (depth == 3) {
+            if (depth == 3 && prec == MLP_PREC_F32) {
                 // Third layer: tanh of the second folded in as for W2 above.
                 for (int v = 0; v < 2; ++v)
                     for (int t = 0; t < 2; ++t)
@@ -1455,8 +1584,8 @@ hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchG
             if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_BF16); \
             else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_BF16);                 \
         } else if (prec == MLP_PREC_F32S) {                               \
-            if (act != ACT_TANH) return hipErrorInvalidValue;             \
-            GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_F32S);                      \
+            if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_F32S); \
+            else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_F32S);                 \
         } else {                                                          \
             if (act == ACT_TANH) GRP_LAUNCH(SS, ACT_TANH, MLP_PREC_F32);  \
             else GRP_LAUNCH(SS, ACT_RELU, MLP_PREC_F32);                  \
@@ -1527,12 +1656,9 @@ hipError_t launch_mfma_prec(int prec, const void* fin, void* fout, const StepArg
     if (prec == MLP_PREC_BF16)
         return launch_mfma_kind<S, ACT, RR, MLP_PREC_BF16, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
     if (prec == MLP_PREC_F32S) {
-        if constexpr (ACT == ACT_TANH) {
-            if (a.depth == 2)
-                return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32S, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out,
-                                                                      st);
-        }
-        return hipErrorInvalidValue;
+        if (a.depth == 3)
+            return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32S, 3>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
+        return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32S, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
     }
     if (a.depth == 3)
         return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32, 3>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);

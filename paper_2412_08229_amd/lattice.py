@@ -77,7 +77,7 @@ class Lattice:
         3 adds the third hidden layer (vector units or float32 matrix cores).
         mlp_prec: "f32" (vector units), "f32_mfma" (float32 matrix cores),
         "bf16" (bf16 products) or "f32_split" (float32-class products split
-        over the f16 matrix cores; tanh, depth 2)."""
+        over the 16-bit matrix cores)."""
         L.nco_set_net_weights(self._h, width, L.ACTS[act], L.MLP_PREC[mlp_prec], params, depth)
         self.n_params = int(np.asarray(params).size)
 

@@ -40,6 +40,7 @@ MIX = [
     ((4, 9, 2), "f32", "mrt", None, None, 7),
     ((6, 10, 7), "f32", "nco", "f32_split", "tanh", 5),
     ((12, 12, 12), "bf16", "nco", "f32_split", "tanh", 3),
+    ((7, 9, 8), "f16", "nco", "f32_split", "relu", 4),
 ]
 
 

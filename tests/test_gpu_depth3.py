@@ -37,16 +37,18 @@ def test_depth3_steps_match_oracle(storage, tol, width, act):
     assert err < tol
 
 
+@pytest.mark.parametrize("mlp", ["f32_mfma", "f32_split"])
 @pytest.mark.parametrize("width,act", [(20, "relu"), (32, "tanh")])
-def test_depth3_matrix_cores_match_oracle(width, act):
-    """The third layer on the float32 matrix cores (one more product per
-    group element, chained on the second layer's accumulator): 10 steps and
-    the rates readout against the oracle, in float32 storage; on a 9^3
-    lattice (ragged against the 64-node blocks)."""
+def test_depth3_matrix_cores_match_oracle(width, act, mlp):
+    """The third layer on the matrix cores (float32, or split over the
+    16-bit ones; one more product per group element, chained on the second
+    layer's accumulator): 10 steps and the rates readout against the
+    oracle, in float32 storage; on a 9^3 lattice (ragged against the 64-node
+    blocks)."""
     params, layers, rho, u = _setup(width, act, 48, n=9)
     tau, n = 0.56, 9
     with Lattice((n, n, n), "f32", "nco", tau) as lat:
-        lat.set_net_weights(params, width, act, "f32_mfma", depth=3)
+        lat.set_net_weights(params, width, act, mlp, depth=3)
         lat.init_equilibrium(rho, u)
         f0 = lat.populations()
         om = lat.rates()
@@ -55,7 +57,7 @@ def test_depth3_matrix_cores_match_oracle(width, act):
     want = step.run(f0, step.Operator("nco", tau, layers=layers, act=act), 10)
     err = np.abs(got - want).max()
     rerr = np.abs(om - collision.nco_rates(f0, layers, act)).max()
-    print("depth 3 on matrix cores, width %d %s: max err %.3e, rates %.3e" % (width, act, err, rerr))
+    print("depth 3 on matrix cores (%s), width %d %s: max err %.3e, rates %.3e" % (mlp, width, act, err, rerr))
     assert err < 1e-5 and rerr < 1e-5
 
 

@@ -357,8 +357,6 @@ def test_mfma_narrow_networks_match_oracle(width, act, mlp, tol):
     rho, u = inputs.random_velocity(shape, seed=17, amp=0.1)
     f0 = collision.equilibrium(rho, u) + 0.01 * (inputs.random_populations(shape, seed=18) - 1.0 / 27)
     layers = collision.unpack_params(_params(width, 19), width)
-    if mlp == "f32_split" and act != "tanh":
-        pytest.skip("the split arithmetic runs tanh networks only (refusal tested separately)")
     with _lattice(shape, "f32", "nco", 0.58, width=width, seed=19, act=act, mlp=mlp) as lat:
         lat.init_populations(f0)
         f_stored = lat.populations()
@@ -374,14 +372,16 @@ def test_mfma_narrow_networks_match_oracle(width, act, mlp, tol):
 # ------------------------------------------- float32 split over f16 products --
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("act", ["tanh", "relu"])
 @pytest.mark.parametrize("w2_scale", [1.0, 1e-3, 40.0])
-def test_split_network_rates_match_oracle(storage, w2_scale):
-    """Split arithmetic (second layer as three f16 products of heads and
-    remainders): rates on a ragged lattice against the float64 oracle at the
-    float32 matrix cores' bound, with the second layer's weights scaled
-    over five decades (the power-of-two scale that keeps the f16 heads in
-    range), and its error within a few times that of the float32 matrix
-    cores on the same state."""
+def test_split_network_rates_match_oracle(storage, act, w2_scale):
+    """Split arithmetic (second layer as f16 products of heads and
+    remainders for tanh, bf16 products of three parts for ReLU): rates on a
+    ragged lattice against the float64 oracle at the float32 matrix cores'
+    bound, with the second layer's weights scaled over five decades (for
+    tanh, the power-of-two scale that keeps the f16 parts in range), and its
+    error within a few times that of the float32 matrix cores on the same
+    state."""
     shape = (5, 7, 9)
     rho, u = inputs.random_velocity(shape, seed=13, amp=0.1)
     f0 = collision.equilibrium(rho, u) + 0.01 * (inputs.random_populations(shape, seed=14) - 1.0 / 27)
@@ -393,24 +393,17 @@ def test_split_network_rates_match_oracle(storage, w2_scale):
     errs = {}
     for mlp in ("f32_mfma", "f32_split"):
         with Lattice(shape, storage, "nco", 0.6) as lat:
-            lat.set_net_weights(params, 32, "tanh", mlp)
+            lat.set_net_weights(params, 32, act, mlp)
             lat.init_populations(f0)
             got = lat.rates()
             f_stored = lat.populations()
-        want = collision.nco_rates(f_stored, layers, "tanh")
+        want = collision.nco_rates(f_stored, layers, act)
         errs[mlp] = np.abs(got - want).max()
-    print("rates %s, W2 x %g: float32 matrix cores %.3e, split %.3e" % (storage, w2_scale, errs["f32_mfma"],
-                                                                        errs["f32_split"]))
+    print("rates %s %s, W2 x %g: float32 matrix cores %.3e, split %.3e" % (storage, act, w2_scale, errs["f32_mfma"],
+                                                                           errs["f32_split"]))
     assert errs["f32_split"] < 2e-6
     assert errs["f32_split"] < 4 * errs["f32_mfma"] + 1e-7
 
-
-@pytest.mark.parametrize("act, depth", [("relu", 2), ("tanh", 3)])
-def test_split_network_refuses_relu_and_depth_3(act, depth):
-    with Lattice((4, 4, 4), "f32", "nco", 0.6) as lat:
-        with pytest.raises(L.NCOError) as e:
-            lat.set_net_weights(inputs.mlp_params(32, 3, depth=depth), 32, act, "f32_split", depth=depth)
-        assert e.value.status == L.NCO_E_UNSUPPORTED
 
 
 # ------------------------------------------------------ precision forms -------
