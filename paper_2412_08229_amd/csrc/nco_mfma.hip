@@ -80,18 +80,24 @@ constexpr int LT_W3 = 44;           // [u 2][r 4][n 4] W3 / 48
 constexpr int LT_B3 = 76;           // [n 4]
 constexpr int LT_A2B = 80;          // [v 2][t 2][r 4] W2b as A operand (depth 3)
 constexpr int LT_B2B = 96;          // [v 2][r 4]      b2b as accumulator init (depth 3)
-// Split arithmetic (network_split; layer 1 at LT_A1, W3 / b3 at LT_W3 /
-// LT_B3 as above): per split layer (the second, and the third at depth 3)
-// the parts of its A operand as packed pairs in the K slots of the 16x16x32
-// product ([u 2][part 3][4 words]: f16 head and remainder for tanh, bf16
-// head, middle and tail for ReLU), the accumulator init [u 2][r 4] and the
-// scale that returns the product to the pre-activation.
-constexpr int LS_A2 = 20;
-constexpr int LS_B2 = 80;
-constexpr int LS_A3 = 88;
-constexpr int LS_B3 = 112;
-constexpr int LS_BACK = 120;        // [layer 2]
-constexpr int LS_NEG1 = 122;        // -1.0 (see residual_f16)
+// Split arithmetic (network_split): per layer the parts of its A operand as
+// packed pairs in the K slots of the 16x16x32 product ([t or u 2][part 3][4
+// words]: f16 head and remainder for tanh, bf16 head, middle and tail for
+// ReLU; layer 1 of tanh in the slots of the bf16 path, K slot j of lane
+// group q holding input row 8 q + j, layer 1 of ReLU as LT_A1 on the
+// float32 matrix cores), the accumulator inits of the hidden-to-hidden
+// layers, the scales that return each product to the pre-activation, the
+// sign masks of the reflections and the output layer.
+constexpr int LS_A1 = 0;
+constexpr int LS_A2 = 24;
+constexpr int LS_A3 = 48;
+constexpr int LS_B2 = 72;           // [u 2][r 4]
+constexpr int LS_B3 = 80;           // [u 2][r 4]
+constexpr int LS_BACK = 88;         // [layer 1, 2, 3]
+constexpr int LS_NEG1 = 91;         // -1.0 (see residual_f16)
+constexpr int LS_SM = 92;           // [bit 3][4 words] as LB_SM
+constexpr int LS_W3 = 104;          // [u 2][r 4][n 4] W3 / 48
+constexpr int LS_B3O = 136;         // [n 4]
 // bf16 path (A operands as packed bf16 pairs, two per word):
 constexpr int LB_A1 = 0;            // [t 2][4 words]  W1 rows 8q..8q+7 / b1
 constexpr int LB_A2 = 8;            // [u 2][4 words]  W2
@@ -99,7 +105,7 @@ constexpr int LB_B2 = 16;           // [u 2][r 4]
 constexpr int LB_W3 = 24;           // [u 2][r 4][n 4]
 constexpr int LB_B3 = 56;           // [n 4]
 constexpr int LB_SM = 60;           // [bit 3][4 words] sign masks of classes with that bit
-constexpr int LANE_WORDS = 128;
+constexpr int LANE_WORDS = 144;
 
 // Activation as evaluated on this path.  For tanh the pre-activation arrives
 // scaled by kappa = 2 log2(e) and the function returns r = 1 / (1 + 2^(kappa z)),
@@ -380,6 +386,56 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
     }
 }
 
+// Activation feeding a split layer: 2^11 r for tanh (act_split), max(x, 0)
+// for ReLU.
+template <int ACT>
+__device__ __forceinline__ float act_into_split(float x) {
+    if constexpr (ACT == ACT_TANH)
+        return act_split(x);
+    else
+        return fmaxf(x, 0.0f);
+}
+
+// The parts of the moment operand of one axis permutation (K slot 2 w + e
+// holding x[2 w + e]): f16 head and remainder for tanh, three bf16 parts
+// for ReLU.
+template <int ACT>
+__device__ __forceinline__ void split_input(const float (&x)[8], float neg1, u32x4 (&bp)[3]) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        if constexpr (ACT == ACT_TANH) {
+            bp[0][w] = pack_f16(x[2 * w], x[2 * w + 1]);
+            bp[1][w] = residual_f16(bp[0][w], x[2 * w], x[2 * w + 1], neg1);
+            bp[2][w] = 0u;
+        } else {
+            unsigned h, m, t;
+            split3_bf16(x[2 * w], x[2 * w + 1], h, m, t);
+            bp[0][w] = h;
+            bp[1][w] = m;
+            bp[2][w] = t;
+        }
+    }
+}
+
+// The split products of one 16-row tile of A with the parts bp of B,
+// accumulated from c: Ah Bh + Ah Bl + Al Bh (f16, tanh) or the six bf16
+// products whose parts' orders sum to at most 2 (ReLU).
+template <int ACT>
+__device__ __forceinline__ f32x4 split_product(const u32x4 (&A)[3], const u32x4 (&bp)[3], f32x4 c) {
+    if constexpr (ACT == ACT_TANH) {
+        c = mfma32h(A[0], bp[0], c);
+        c = mfma32h(A[0], bp[1], c);
+        return mfma32h(A[1], bp[0], c);
+    } else {
+        c = mfma32(A[0], bp[0], c);
+        c = mfma32(A[0], bp[1], c);
+        c = mfma32(A[1], bp[0], c);
+        c = mfma32(A[0], bp[2], c);
+        c = mfma32(A[2], bp[0], c);
+        return mfma32(A[1], bp[1], c);
+    }
+}
+
 // One split layer: the pre-activations c[u] (rows 16 u + 4 q + r, f32x4 over
 // r) of A h + b for the activations h[t][r] (hidden unit 16 t + 4 q + r) of
 // the previous layer, K slot 2 w + e of the products holding
@@ -396,81 +452,60 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
 template <int ACT>
 __device__ __forceinline__ void split_layer(const u32x4 (&A)[2][3], const float (&b)[2][4], float back, float neg1,
                                             const float (&h)[2][4], f32x4 (&c)[2]) {
-    if constexpr (ACT == ACT_TANH) {
-        u32x4 bh, bl;
+    float x[8];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const float x0 = h[w >> 1][2 * (w & 1)], x1 = h[w >> 1][2 * (w & 1) + 1];
-            bh[w] = pack_f16(x0, x1);
-            bl[w] = residual_f16(bh[w], x0, x1, neg1);
-        }
+    for (int i = 0; i < 8; ++i) x[i] = h[i >> 2][i & 3];
+    u32x4 bp[3];
+    split_input<ACT>(x, neg1, bp);
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            f32x4 t = mfma32h(A[u][0], bh, f32x4{b[u][0], b[u][1], b[u][2], b[u][3]});
-            t = mfma32h(A[u][0], bl, t);
-            t = mfma32h(A[u][1], bh, t);
-            c[u] = t * back;
-        }
-    } else {
-        u32x4 bp[3];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            unsigned x, y, z;
-            split3_bf16(h[w >> 1][2 * (w & 1)], h[w >> 1][2 * (w & 1) + 1], x, y, z);
-            bp[0][w] = x;
-            bp[1][w] = y;
-            bp[2][w] = z;
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            f32x4 t = mfma32(A[u][0], bp[0], f32x4{b[u][0], b[u][1], b[u][2], b[u][3]});
-            t = mfma32(A[u][0], bp[1], t);
-            t = mfma32(A[u][1], bp[0], t);
-            t = mfma32(A[u][0], bp[2], t);
-            t = mfma32(A[u][2], bp[0], t);
-            c[u] = mfma32(A[u][1], bp[1], t);
-        }
+    for (int u = 0; u < 2; ++u) {
+        c[u] = split_product<ACT>(A[u], bp, f32x4{b[u][0], b[u][1], b[u][2], b[u][3]});
+        if constexpr (ACT == ACT_TANH) c[u] *= back;
     }
 }
 
-// Activation feeding a split layer: 2^11 r for tanh (act_split), max(x, 0)
-// for ReLU.
-template <int ACT>
-__device__ __forceinline__ float act_into_split(float x) {
-    if constexpr (ACT == ACT_TANH)
-        return act_split(x);
-    else
-        return fmaxf(x, 0.0f);
-}
-
-// Float32-class network with its hidden-to-hidden layers on the f16 / bf16
-// matrix cores (split_layer; the products equal float32's to a few units of
-// its rounding).  Layer 1 as in network_f32 (float32 matrix cores with the
-// Walsh-Hadamard fold).  Per group element and tile, a split layer runs 6
-// (tanh) or 12 (ReLU) products of 16x16x32 instead of 16 of 16x16x4.
+// Float32-class network on the f16 / bf16 matrix cores, the products equal
+// to float32's to a few units of its rounding.  tanh: every layer but the
+// output one as split f16 products, layer 1 per group element like the
+// bf16 network (the reflections as sign flips of the moment operand's
+// parts, in Gray-code order) and scaled back by 1 / sigma_1; 12 products of
+// 16x16x32 per group element and 16-node tile at depth 2.  ReLU: layer 1 on
+// the float32 matrix cores with the Walsh-Hadamard fold (layer1_reflections;
+// split into three bf16 parts it would take 12 more products, and these
+// kernels are bound by the matrix cores), the hidden-to-hidden layers as 12
+// split bf16 products each.
 template <int ACT, int DEPTH = 2, int TPW = 4>
 __device__ __forceinline__ void network_split(const float* __restrict__ sm, const int* __restrict__ sg,
                                               float* __restrict__ sw, const float* __restrict__ lt, int wave, int q,
                                               int c) {
     const unsigned* __restrict__ lw = reinterpret_cast<const unsigned*>(lt);
     constexpr int NP = ACT == ACT_TANH ? 2 : 3;
-    float A1[2][KSTEPS], B2[2][4], B3[2][4];
-    u32x4 AS2[2][3], AS3[2][3];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
+    float B2[2][4], B3[2][4], A1[2][KSTEPS];
+    u32x4 AS1[2][3], AS2[2][3], AS3[2][3], SM[3];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
+            const unsigned* w1 = lw + LS_A1 + 12 * u + 4 * k;
             const unsigned* w2 = lw + LS_A2 + 12 * u + 4 * k;
+            if constexpr (ACT == ACT_TANH)
+                AS1[u][k] = k < NP ? u32x4{w1[0], w1[1], w1[2], w1[3]} : u32x4{0u, 0u, 0u, 0u};
             AS2[u][k] = k < NP ? u32x4{w2[0], w2[1], w2[2], w2[3]} : u32x4{0u, 0u, 0u, 0u};
             if constexpr (DEPTH == 3) {
                 const unsigned* w3 = lw + LS_A3 + 12 * u + 4 * k;
                 AS3[u][k] = k < NP ? u32x4{w3[0], w3[1], w3[2], w3[3]} : u32x4{0u, 0u, 0u, 0u};
             }
         }
+    if constexpr (ACT == ACT_TANH) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            SM[b] = u32x4{lw[LS_SM + 4 * b], lw[LS_SM + 4 * b + 1], lw[LS_SM + 4 * b + 2], lw[LS_SM + 4 * b + 3]};
+    } else {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
+    }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -478,7 +513,7 @@ __device__ __forceinline__ void network_split(const float* __restrict__ sm, cons
             B2[u][r] = lt[LS_B2 + u * 4 + r];
             B3[u][r] = DEPTH == 3 ? lt[LS_B3 + u * 4 + r] : 0.0f;
         }
-    const float back2 = lt[LS_BACK], back3 = lt[LS_BACK + 1], neg1 = lt[LS_NEG1];
+    const float back1 = lt[LS_BACK], back2 = lt[LS_BACK + 1], back3 = lt[LS_BACK + 2], neg1 = lt[LS_NEG1];
 
 #pragma unroll 1
     for (int j = 0; j < TPW; ++j) {
@@ -487,15 +522,38 @@ __device__ __forceinline__ void network_split(const float* __restrict__ sm, cons
         f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll 1
         for (int p = 0; p < 6; ++p) {
+            const int* __restrict__ ge = sg + (p * 4 + q) * GT_STRIDE;
+            u32x4 bp[3];
             f32x4 Y[8][2];
-            layer1_reflections(A1, mrow, sg + (p * 4 + q) * GT_STRIDE, Y);
+            if constexpr (ACT == ACT_TANH) {
+                float x[8];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
+                for (int i = 0; i < 8; ++i) x[i] = mrow[ge[i]];
+                split_input<ACT>(x, neg1, bp);
+            } else {
+                layer1_reflections(A1, mrow, ge, Y);
+            }
+            // tanh: the 8 reflections in Gray-code order, consecutive ones
+            // differing in one reflection bit: one mask XOR per word and part.
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
                 float h1[2][4];
+                if constexpr (ACT == ACT_TANH) {
+                    if (k > 0)
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                        for (int e = 0; e < NP; ++e) bp[e] ^= SM[__builtin_ctz(k)];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) h1[t][r] = act_into_split<ACT>(Y[s][t][r]);
+                    for (int t = 0; t < 2; ++t) {
+                        const f32x4 c1 = split_product<ACT>(AS1[t], bp, f32x4{0.f, 0.f, 0.f, 0.f}) * back1;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h1[t][r] = act_into_split<ACT>(c1[r]);
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h1[t][r] = act_into_split<ACT>(Y[k][t][r]);
+                }
                 f32x4 cz[2];
                 split_layer<ACT>(AS2, B2, back2, neg1, h1, cz);
                 if constexpr (DEPTH == 3) {
@@ -512,7 +570,7 @@ __device__ __forceinline__ void network_split(const float* __restrict__ sm, cons
                     for (int r = 0; r < 4; ++r) acc[u][r] += act_scaled<ACT>(cz[u][r]);
             }
         }
-        output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
+        output_layer(acc, lt + LS_W3, lt + LS_B3O, q, sw + node * 4);
     }
 }
 
@@ -1353,19 +1411,23 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
         b3f[n] = (float)s;
     }
     auto w1row = [&](int k, int h) { return k < 27 ? W1[k * W + h] : k == 27 ? b1[h] : 0.0f; };
-    // Split arithmetic, tanh: per split layer the power of two sigma that
-    // puts max |kappa fold W| into [128, 256), well inside the f16 range,
+    // Split arithmetic, tanh: per layer (first, second, third) the power of
+    // two sigma that puts the largest |A| (kappa W1 with the bias row, kappa
+    // fold W2, kappa fold W2b) into [128, 256), well inside the f16 range,
     // with the remainders of all but negligible weights normal; b2bf the
     // third layer's bias with the tanh fold.
-    float split_sigma[2] = {1.0f, 1.0f};
+    float split_sigma[3] = {1.0f, 1.0f, 1.0f};
     float b2bf[MW] = {};
     if (prec == MLP_PREC_F32S && th) {
-        for (int l = 0; l < (depth == 3 ? 2 : 1); ++l) {
-            const float* Wl = l == 0 ? W2 : W2b;
-            float amax = 0.0f;
-            for (int i = 0; i < W * W; ++i) amax = std::max(amax, std::fabs(kappa * fold * Wl[i]));
-            if (amax > 0.0f) split_sigma[l] = std::ldexp(1.0f, 7 - std::ilogb(amax));
+        float amax[3] = {0.0f, 0.0f, 0.0f};
+        for (int k = 0; k < 28; ++k)
+            for (int h = 0; h < W; ++h) amax[0] = std::max(amax[0], std::fabs(kappa * w1row(k, h)));
+        for (int i = 0; i < W * W; ++i) {
+            amax[1] = std::max(amax[1], std::fabs(kappa * fold * W2[i]));
+            if (depth == 3) amax[2] = std::max(amax[2], std::fabs(kappa * fold * W2b[i]));
         }
+        for (int l = 0; l < 3; ++l)
+            if (amax[l] > 0.0f) split_sigma[l] = std::ldexp(1.0f, 7 - std::ilogb(amax[l]));
     }
     if (depth == 3)
         for (int o = 0; o < W; ++o) {
@@ -1381,56 +1443,81 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
         float* lt = lane_tab + lane * LANE_WORDS;
         unsigned* lw = reinterpret_cast<unsigned*>(lt);
         for (int i = 0; i < LANE_WORDS; ++i) lt[i] = 0.0f;
-        if (prec != MLP_PREC_BF16) {
+        if (prec == MLP_PREC_F32S) {
+            // Parts of each layer's A operand in the K slots of its product:
+            // layer 1 slot j of lane group q holds input row 8 q + j, a
+            // hidden-to-hidden layer's slot j hidden unit 16 (j / 4) + 4 q +
+            // j % 4.
+            auto hid = [&](int j) { return 16 * (j / 4) + 4 * q + j % 4; };
+            auto put = [&](int off, int t, int w, int e, float a) {
+                unsigned part[3];
+                if (th) {
+                    part[0] = f16_bits(a);
+                    part[1] = f16_bits(a - (float)(_Float16)a);
+                    part[2] = 0;
+                } else {
+                    part[0] = bf16_bits(a);
+                    const float r = a - bf16_value(part[0]);
+                    part[1] = bf16_bits(r);
+                    part[2] = bf16_bits(r - bf16_value(part[1]));
+                }
+                for (int k = 0; k < 3; ++k) lw[off + 12 * t + 4 * k + w] |= part[k] << (16 * e);
+            };
+            if (th) {
+                for (int t = 0; t < 2; ++t)
+                    for (int w = 0; w < 4; ++w)
+                        for (int e = 0; e < 2; ++e)
+                            put(LS_A1, t, w, e, split_sigma[0] * (kappa * w1row(8 * q + 2 * w + e, 16 * t + c)));
+                lt[LS_BACK] = 1.0f / split_sigma[0];
+            } else {
+                for (int t = 0; t < 2; ++t)
+                    for (int st = 0; st < KSTEPS; ++st) {
+                        const int k = slot_row[st][q];
+                        lt[LT_A1 + t * KSTEPS + st] = k < 0 ? 0.0f : w1row(k, 16 * t + c);
+                    }
+            }
+            auto fill = [&](const float* Wl, const float* bfold, float sigma, int offA, int offB, int slot) {
+                for (int u = 0; u < 2; ++u)
+                    for (int w = 0; w < 4; ++w)
+                        for (int e = 0; e < 2; ++e)
+                            put(offA, u, w, e, sigma * (kappa * fold * Wl[hid(2 * w + e) * W + 16 * u + c]));
+                const float up = th ? sigma * 2048.0f : 1.0f;
+                for (int u = 0; u < 2; ++u)
+                    for (int r = 0; r < 4; ++r) lt[offB + u * 4 + r] = up * (kappa * bfold[16 * u + 4 * q + r]);
+                lt[LS_BACK + slot] = 1.0f / up;
+            };
+            fill(W2, b2f, split_sigma[1], LS_A2, LS_B2, 1);
+            if (depth == 3) fill(W2b, b2bf, split_sigma[2], LS_A3, LS_B3, 2);
+            lt[LS_NEG1] = -1.0f;
+            for (int b = 0; b < 3; ++b)
+                for (int w = 0; w < 4; ++w) {
+                    const int k0 = 8 * q + 2 * w, k1 = k0 + 1;
+                    lw[LS_SM + 4 * b + w] = ((row_class(k0) >> b) & 1 ? 0x8000u : 0u) |
+                                            ((row_class(k1) >> b) & 1 ? 0x80000000u : 0u);
+                }
+            for (int u = 0; u < 2; ++u)
+                for (int r = 0; r < 4; ++r)
+                    for (int n = 0; n < 4; ++n)
+                        lt[LS_W3 + (u * 4 + r) * 4 + n] = fold * W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
+            for (int n = 0; n < 4; ++n) lt[LS_B3O + n] = b3f[n];
+        } else if (prec == MLP_PREC_F32) {
             for (int t = 0; t < 2; ++t)
                 for (int st = 0; st < KSTEPS; ++st) {
                     const int k = slot_row[st][q];
                     lt[LT_A1 + t * KSTEPS + st] = k < 0 ? 0.0f : kappa * w1row(k, 16 * t + c);
                 }
-            if (prec == MLP_PREC_F32S) {
-                // Parts of each split layer's A operand in the K slots of
-                // its product (slot j: hidden unit 16 (j / 4) + 4 q + j % 4).
-                auto hid = [&](int j) { return 16 * (j / 4) + 4 * q + j % 4; };
-                auto fill = [&](const float* Wl, const float* bfold, float sigma, int offA, int offB, int slot) {
-                    for (int u = 0; u < 2; ++u)
-                        for (int w = 0; w < 4; ++w)
-                            for (int e = 0; e < 2; ++e) {
-                                const float a = sigma * (kappa * fold * Wl[hid(2 * w + e) * W + 16 * u + c]);
-                                unsigned part[3];
-                                if (th) {
-                                    part[0] = f16_bits(a);
-                                    part[1] = f16_bits(a - (float)(_Float16)a);
-                                    part[2] = 0;
-                                } else {
-                                    part[0] = bf16_bits(a);
-                                    const float r = a - bf16_value(part[0]);
-                                    part[1] = bf16_bits(r);
-                                    part[2] = bf16_bits(r - bf16_value(part[1]));
-                                }
-                                for (int k = 0; k < 3; ++k) lw[offA + 12 * u + 4 * k + w] |= part[k] << (16 * e);
-                            }
-                    const float up = th ? sigma * 2048.0f : 1.0f;
-                    for (int u = 0; u < 2; ++u)
-                        for (int r = 0; r < 4; ++r) lt[offB + u * 4 + r] = up * (kappa * bfold[16 * u + 4 * q + r]);
-                    lt[LS_BACK + slot] = 1.0f / up;
-                };
-                lt[LS_NEG1] = -1.0f;
-                fill(W2, b2f, split_sigma[0], LS_A2, LS_B2, 0);
-                if (depth == 3) fill(W2b, b2bf, split_sigma[1], LS_A3, LS_B3, 1);
-            } else {
-                for (int u = 0; u < 2; ++u)
-                    for (int t = 0; t < 2; ++t)
-                        for (int r = 0; r < 4; ++r)
-                            lt[LT_A2 + u * 8 + t * 4 + r] = kappa * fold * W2[(16 * t + 4 * q + r) * W + 16 * u + c];
-                for (int u = 0; u < 2; ++u)
-                    for (int r = 0; r < 4; ++r) lt[LT_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
-            }
+            for (int u = 0; u < 2; ++u)
+                for (int t = 0; t < 2; ++t)
+                    for (int r = 0; r < 4; ++r)
+                        lt[LT_A2 + u * 8 + t * 4 + r] = kappa * fold * W2[(16 * t + 4 * q + r) * W + 16 * u + c];
+            for (int u = 0; u < 2; ++u)
+                for (int r = 0; r < 4; ++r) lt[LT_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
             for (int u = 0; u < 2; ++u)
                 for (int r = 0; r < 4; ++r)
                     for (int n = 0; n < 4; ++n)
                         lt[LT_W3 + (u * 4 + r) * 4 + n] = fold * W3[(16 * u + 4 * q + r) * 4 + n] / (float)NGROUP;
             for (int n = 0; n < 4; ++n) lt[LT_B3 + n] = b3f[n];
-            if (depth == 3 && prec == MLP_PREC_F32) {
+            if (depth == 3) {
                 // Third layer: tanh of the second folded in as for W2 above.
                 for (int v = 0; v < 2; ++v)
                     for (int t = 0; t < 2; ++t)
@@ -1480,7 +1567,7 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
             for (int i = 0; i < GT_STRIDE; ++i) {
                 // Row k placed in this slot; 27 is the constant-1 row, 28 zero.
                 int k = -1;
-                if (prec != MLP_PREC_BF16) {
+                if (prec == MLP_PREC_F32 || (prec == MLP_PREC_F32S && !th)) {
                     if (i < KSTEPS) k = slot_row[i][q];
                 } else if (i < 8) {
                     k = 8 * q + i;

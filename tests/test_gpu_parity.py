@@ -373,21 +373,23 @@ def test_mfma_narrow_networks_match_oracle(width, act, mlp, tol):
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("act", ["tanh", "relu"])
-@pytest.mark.parametrize("w2_scale", [1.0, 1e-3, 40.0])
-def test_split_network_rates_match_oracle(storage, act, w2_scale):
-    """Split arithmetic (second layer as f16 products of heads and
-    remainders for tanh, bf16 products of three parts for ReLU): rates on a
-    ragged lattice against the float64 oracle at the float32 matrix cores'
-    bound, with the second layer's weights scaled over five decades (for
-    tanh, the power-of-two scale that keeps the f16 parts in range), and its
-    error within a few times that of the float32 matrix cores on the same
-    state."""
+@pytest.mark.parametrize("layer, scale", [(2, 1.0), (2, 1e-3), (2, 40.0), (1, 1e-3), (1, 40.0)])
+def test_split_network_rates_match_oracle(storage, act, layer, scale):
+    """Split arithmetic (f16 products of heads and remainders for tanh, bf16
+    products of three parts for ReLU): rates on a ragged lattice against the
+    float64 oracle at the float32 matrix cores' bound, with the first or the
+    second layer's weights scaled over five decades (for tanh, the
+    power-of-two scales that keep the f16 parts in range), and its error
+    within a few times that of the float32 matrix cores on the same state."""
     shape = (5, 7, 9)
     rho, u = inputs.random_velocity(shape, seed=13, amp=0.1)
     f0 = collision.equilibrium(rho, u) + 0.01 * (inputs.random_populations(shape, seed=14) - 1.0 / 27)
     params = _params(32, 15).copy()
     n1 = 27 * 32 + 32
-    params[n1:n1 + 32 * 32] *= w2_scale
+    if layer == 2:
+        params[n1:n1 + 32 * 32] *= scale
+    else:
+        params[:27 * 32] *= scale
     params = params.astype(np.float32).astype(np.float64)      # the weights the lattice holds
     layers = collision.unpack_params(params, 32)
     errs = {}
@@ -399,8 +401,8 @@ def test_split_network_rates_match_oracle(storage, act, w2_scale):
             f_stored = lat.populations()
         want = collision.nco_rates(f_stored, layers, act)
         errs[mlp] = np.abs(got - want).max()
-    print("rates %s %s, W2 x %g: float32 matrix cores %.3e, split %.3e" % (storage, act, w2_scale, errs["f32_mfma"],
-                                                                           errs["f32_split"]))
+    print("rates %s %s, W%d x %g: float32 matrix cores %.3e, split %.3e" % (storage, act, layer, scale,
+                                                                            errs["f32_mfma"], errs["f32_split"]))
     assert errs["f32_split"] < 2e-6
     assert errs["f32_split"] < 4 * errs["f32_mfma"] + 1e-7
 
