@@ -688,8 +688,11 @@ __attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC, ACT, DEPTH)))) void k_nc
 template <int S, int ACT, int PREC>
 __device__ __forceinline__ void grouped_block(const GroupDesc& d, int blk, BlockLds lds) {
     using T = typename Codec<S>::store_t;
-    nco_mfma_block<S, ACT, false, PREC, 256>(static_cast<const T*>(d.fin), static_cast<T*>(d.fout), d.a,
-                                             d.lane_tab, d.gtab, nullptr, blk, lds);
+    // The float32 network through the instantiation with the (here unused)
+    // network-value branch, for its register allocation (see
+    // launch_mfma_kind).
+    nco_mfma_block<S, ACT, false, PREC, 256, 2, 4, PREC == MLP_PREC_F32>(
+        static_cast<const T*>(d.fin), static_cast<T*>(d.fout), d.a, d.lane_tab, d.gtab, nullptr, blk, lds);
 }
 
 // One step of several lattices with the same storage, activation and
@@ -748,9 +751,9 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
             static_assert(!SUMS, "the split arithmetic keeps no network values");
             network_split<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
         } else if constexpr (SUMS) {
-            // A separate instantiation: the stores of the sums would cost the
-            // plain step kernel registers (and half its occupancy).
-            float* sums = a.net_sums + (size_t)blk * NODES * NET_SUMS_PER_NODE;
+            // Keeps the network values when a.net_sums is set, else a plain
+            // step (a uniform branch after each tile).
+            float* sums = a.net_sums ? a.net_sums + (size_t)blk * NODES * NET_SUMS_PER_NODE : nullptr;
             network_f32<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15, nullptr, sums);
         } else {
             network_f32<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
@@ -1707,23 +1710,23 @@ hipError_t launch_mfma_kind(int kind, const void* fin, void* fout, const StepArg
     const int nodes = kind == MFMA_BLOCK_256 ? 256 : 64;
     const dim3 grid((a.n + nodes - 1) / nodes);
     if constexpr (!RR && PP == MLP_PREC_F32 && DD == 2) {
-        if (a.net_sums) {
-            // The step also keeps its network values for the adjoint.
-            if (kind == MFMA_BLOCK_64_TILE)
-                hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 1, true>), dim3(grid), dim3(mfma_block_threads(64, 1)),
-                                   0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
-            else if (kind == MFMA_BLOCK_64)
-                hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 4, true>), dim3(grid), dim3(mfma_block_threads(64, 4)),
-                                   0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
-            else
-                hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 256, DD, 4, true>), dim3(grid),
-                                   dim3(mfma_block_threads(256, 4)), 0, st, static_cast<const T*>(fin),
-                                   static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
-            return hipGetLastError();
-        }
-    } else {
-        if (a.net_sums) return hipErrorInvalidValue;
+        // The instantiation that can keep the network values for the adjoint
+        // (when a.net_sums is set) runs the plain steps too: with that branch
+        // the compiler allocates 154-161 VGPRs, 3 waves per SIMD, where the
+        // instantiation without it takes 230 and 2 waves and runs 3 % slower.
+        if (kind == MFMA_BLOCK_64_TILE)
+            hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 1, true>), dim3(grid), dim3(mfma_block_threads(64, 1)),
+                               0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+        else if (kind == MFMA_BLOCK_64)
+            hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 4, true>), dim3(grid), dim3(mfma_block_threads(64, 4)),
+                               0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+        else
+            hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 256, DD, 4, true>), dim3(grid),
+                               dim3(mfma_block_threads(256, 4)), 0, st, static_cast<const T*>(fin),
+                               static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+        return hipGetLastError();
     }
+    if (a.net_sums) return hipErrorInvalidValue;
     if (kind == MFMA_BLOCK_64_TILE)
         hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 1>), dim3(grid), dim3(mfma_block_threads(64, 1)), 0,
                            st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
