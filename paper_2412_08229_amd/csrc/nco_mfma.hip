@@ -668,16 +668,15 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
 constexpr int mfma_block_threads(int nodes, int tpw) { return nodes / (16 * tpw) * 64; }
 
 // Waves per SIMD the register allocation must leave room for: 3 for the
-// split tanh network at depth 2 (it fits 168 registers without spilling and
-// is bound by its vector instructions, which a third wave keeps issuing), no
-// constraint otherwise.
-constexpr int mfma_min_waves(int prec, int act, int depth) {
-    return prec == MLP_PREC_F32S && act == ACT_TANH && depth == 2 ? 3 : 1;
-}
+// split networks (156 VGPRs for tanh at depth 2; the others spill 12-57
+// registers into scratch and still run 1-7 % faster than at 2 waves, the
+// third wave keeping their vector instructions issuing), no constraint
+// otherwise.
+constexpr int mfma_min_waves(int prec) { return prec == MLP_PREC_F32S ? 3 : 1; }
 
 template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW, bool SUMS = false>
 __global__ __launch_bounds__(mfma_block_threads(NODES, TPW))
-__attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC, ACT, DEPTH)))) void k_nco_mfma(
+__attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC)))) void k_nco_mfma(
     const typename Codec<S>::store_t* __restrict__ fin, typename Codec<S>::store_t* __restrict__ fout,
     StepArgs a, const float* __restrict__ lane_tab, const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
