@@ -670,13 +670,17 @@ constexpr int mfma_block_threads(int nodes, int tpw) { return nodes / (16 * tpw)
 // Waves per SIMD the register allocation must leave room for: 3 for the
 // split networks (156 VGPRs for tanh at depth 2; the others spill 12-57
 // registers into scratch and still run 1-7 % faster than at 2 waves, the
-// third wave keeping their vector instructions issuing), no constraint
-// otherwise.
-constexpr int mfma_min_waves(int prec) { return prec == MLP_PREC_F32S ? 3 : 1; }
+// third wave keeping their vector instructions issuing) and for the float32
+// depth-3 steps (the instantiation with the network-value branch, 177
+// VGPRs unconstrained; at 168, 0-17 spilled, 4 % faster at 128^3 and 8 % on
+// a 16^3 lattice), no constraint otherwise.
+constexpr int mfma_min_waves(int prec, int depth, bool sums) {
+    return prec == MLP_PREC_F32S || (prec == MLP_PREC_F32 && depth == 3 && sums) ? 3 : 1;
+}
 
 template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW, bool SUMS = false>
 __global__ __launch_bounds__(mfma_block_threads(NODES, TPW))
-__attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC)))) void k_nco_mfma(
+__attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC, DEPTH, SUMS)))) void k_nco_mfma(
     const typename Codec<S>::store_t* __restrict__ fin, typename Codec<S>::store_t* __restrict__ fout,
     StepArgs a, const float* __restrict__ lane_tab, const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
@@ -1708,11 +1712,13 @@ hipError_t launch_mfma_kind(int kind, const void* fin, void* fout, const StepArg
     using T = typename Codec<S>::store_t;
     const int nodes = kind == MFMA_BLOCK_256 ? 256 : 64;
     const dim3 grid((a.n + nodes - 1) / nodes);
-    if constexpr (!RR && PP == MLP_PREC_F32 && DD == 2) {
+    if constexpr (!RR && PP == MLP_PREC_F32) {
         // The instantiation that can keep the network values for the adjoint
-        // (when a.net_sums is set) runs the plain steps too: with that branch
-        // the compiler allocates 154-161 VGPRs, 3 waves per SIMD, where the
-        // instantiation without it takes 230 and 2 waves and runs 3 % slower.
+        // (when a.net_sums is set; depth 2) runs the plain steps too: with
+        // that branch the compiler allocates 154-161 VGPRs at depth 2, 3
+        // waves per SIMD, where the instantiation without it takes 230 and 2
+        // waves and runs 3 % slower; at depth 3, 177 against 254 (with
+        // mfma_min_waves, 3 waves).
         if (kind == MFMA_BLOCK_64_TILE)
             hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 1, true>), dim3(grid), dim3(mfma_block_threads(64, 1)),
                                0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
