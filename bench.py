@@ -110,14 +110,18 @@ def time_op(lat, steps, warmup, torch, stream):
     return start.elapsed_time(end) / steps
 
 
-def train_step(n, tau, rho, u, params, width, stream, T=40, K=10):
+def train_step(n, tau, rho, u, params, width, stream, T=40, K=10, cache_bytes=None):
     """One training step of the float32 matrix-core NCO on the benchmark
     lattice: a T-step recorded forward (checkpoints every K) and the reverse
-    pass (segment recompute + matrix-core adjoint) for a population loss."""
+    pass (segment recompute + matrix-core adjoint) for a population loss.
+    cache_bytes: the reverse-mode budget for kept network values (library
+    default if None)."""
     from paper_2412_08229_amd import Lattice
     w = np.random.Generator(np.random.PCG64(1)).standard_normal((27, n, n, n)) * 1e-3
     with Lattice((n, n, n), "f32", "nco", tau, stream=stream) as lat:
         lat.set_net_weights(params, width, "tanh", "f32_mfma")
+        if cache_bytes is not None:
+            lat.set_reverse_cache(cache_bytes)
         for rep in range(2):                    # the first pass allocates the checkpoints
             lat.init_equilibrium(rho, u)
             t0 = time.perf_counter()
@@ -130,9 +134,12 @@ def train_step(n, tau, rho, u, params, width, stream, T=40, K=10):
             raise RuntimeError("non-finite gradient")
     fwd = (t1 - t0) / T * 1e3
     rev = (t2 - t1) / T * 1e3
-    return {"forward_ms_per_step": fwd, "reverse_ms_per_step": rev,
-            "train_glups": n ** 3 / ((t2 - t0) / T) / 1e9, "steps": T, "checkpoint_every": K,
-            "lattice": n, "network": "f32_mfma", "activation": "tanh"}
+    out = {"forward_ms_per_step": fwd, "reverse_ms_per_step": rev,
+           "train_glups": n ** 3 / ((t2 - t0) / T) / 1e9, "steps": T, "checkpoint_every": K,
+           "lattice": n, "network": "f32_mfma", "activation": "tanh"}
+    if cache_bytes is not None:
+        out["reverse_cache_bytes"] = cache_bytes
+    return out
 
 
 def cpu_baseline(n_sample=64, nsteps=6):
@@ -624,7 +631,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--ops", default=",".join(list(VARIANTS) + ["nco_train"]))
+    ap.add_argument("--ops", default=",".join(list(VARIANTS) + ["nco_train", "nco_train_stored"]))
     ap.add_argument("--serving-requests", type=int, default=16,
                     help="requests of the serving leg (0: no serving leg)")
     ap.add_argument("--serving-load", type=float, default=0.8)
@@ -685,10 +692,15 @@ def main():
     spectra = {}
     fields = {n: (tau, rho, u)}
     for op in args.ops.split(","):
-        if op == "nco_train":
-            results[op] = train_step(n, tau, rho, u, params, width, stream)
-            print("# nco_train: forward %.4f ms/step, reverse %.4f ms/step" % (
-                results[op]["forward_ms_per_step"], results[op]["reverse_ms_per_step"]), file=sys.stderr, flush=True)
+        if op in ("nco_train", "nco_train_stored"):
+            # nco_train_stored: every state a checkpoint (no recompute) and
+            # every step's network values kept (40 x 0.3 GB at 128^3 beside
+            # the 40 x 0.23 GB of states), the memory-rich form.
+            kw = {} if op == "nco_train" else {"K": 1, "cache_bytes": 16 << 30}
+            results[op] = train_step(n, tau, rho, u, params, width, stream, **kw)
+            print("# %s: forward %.4f ms/step, reverse %.4f ms/step" % (
+                op, results[op]["forward_ms_per_step"], results[op]["reverse_ms_per_step"]), file=sys.stderr,
+                flush=True)
             continue
         kind, storage, mlp, act = VARIANTS[op]
         domain = DOMAIN.get(op, "periodic")
@@ -775,9 +787,14 @@ def main():
     copy_gbs = 2 * nbytes / (t0.elapsed_time(t1) / 20 * 1e-3) / 1e9
     del src, dst
 
-    main_op = "nco" if "nco" in results else list(results)[0]
-    r = results[main_op]
-    if main_op == "nco":
+    # The headline variant, else the first timed one (an --ops list of
+    # training legs only has no roofline and no value).
+    timed = [k for k in results if "ms_per_step" in results[k]]
+    main_op = "nco" if "nco" in results else (timed[0] if timed else None)
+    r = results[main_op] if main_op else {"glups": None, "ms_per_step": None}
+    if main_op is None:
+        roof = None
+    elif main_op == "nco":
         flops = nco_flops_per_node(width) * nodes
         achieved = flops / (r["ms_per_step"] * 1e-3) / 1e12
         executed = nco_executed_flops_per_node() * nodes / (r["ms_per_step"] * 1e-3) / 1e12
@@ -809,7 +826,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "Taylor-Green vortex %d^3 D3Q27, Re 1600, Ma 0.1, %s collision, "
-                               "27-32-32-4 tanh network, float32 storage, forward only" % (n, main_op.upper()),
+                               "27-32-32-4 tanh network, float32 storage, forward only" % (n, (main_op or "nco").upper()),
                    "lattice": [n, n, n], "operator": main_op, "storage": "f32", "width": width},
         "roofline": roof,
         "operators": results,

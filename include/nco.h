@@ -140,14 +140,19 @@ int nco_set_domain(nco_lattice* lat, int domain);
  * NCO_E_INVALID for another enable value.  Drops a recorded run. */
 int nco_set_stochastic_rounding(nco_lattice* lat, int enable, unsigned seed);
 
-/* Memory the reverse mode may use to keep network values between a
- * recomputed forward step and its adjoint (float32 matrix-core networks,
- * Sec. "Learning Task"): 144 bytes per node for each of the K - 1
- * recomputed states of a segment (K = ckpt_every).  When they fit (default
- * 4 GiB), the adjoint of those steps reads the group sums of the second layer
- * and the pre-squash outputs instead of running the network forward again;
- * the gradient is the same bit for bit.  0 switches it off.  Takes effect
- * at the next nco_backward. */
+/* Memory the reverse mode may use to keep network values between a forward
+ * step and the adjoint of its state (float32 matrix-core networks of depth
+ * 2, Sec. "Learning Task"): 144 bytes per node for each of the K - 1
+ * recomputed states of a segment (K = ckpt_every), and as many for the last
+ * state of each of the ceil(T / K) segments, which nco_forward_record keeps
+ * when both fit.  Where they are kept (default budget 4 GiB), the adjoint
+ * reads the group sums of the second layer and the pre-squash outputs
+ * instead of running the network forward again; the gradient is the same
+ * bit for bit.  With K = 1 every state is a checkpoint, nothing is
+ * recomputed, and every adjoint reads kept values (T x 144 bytes per node
+ * beside the T checkpoints).  0 switches it off.  The recompute's share
+ * takes effect at the next nco_backward, the segment ends' at the next
+ * nco_forward_record. */
 int nco_set_reverse_cache(nco_lattice* lat, size_t bytes);
 
 /* Pairs of steps in place (enable = 1, the default) or always between two

@@ -240,9 +240,14 @@ struct nco_lattice {
     unsigned sr_seed = 0;
     // Reverse mode of float32 matrix-core networks: the network values each
     // recomputed forward step keeps for its adjoint (K - 1 states of a
-    // segment), within a budget of net_cache_bytes (nco_set_reverse_cache).
+    // segment), and those the recorded run kept for the last state of each
+    // segment (net_ends, when rec_ends), within a budget of net_cache_bytes
+    // (nco_set_reverse_cache).
     float* net_sums = nullptr;
     size_t net_sums_floats = 0;
+    float* net_ends = nullptr;
+    size_t net_ends_floats = 0;
+    bool rec_ends = false;
     size_t net_cache_bytes = (size_t)4 << 30;
 };
 
@@ -412,6 +417,16 @@ bool inplace_pair_ok(const nco_lattice* lat) {
            !lat->phase_rule && lat->pop_bytes <= LLC_BYTES && 2 * lat->pop_bytes > LLC_BYTES;
 }
 
+// Floats of the network values of one state (NET_SUMS_PER_NODE per node,
+// the node count rounded up to whole 256-node blocks).
+size_t net_values_stride(const nco_lattice* lat) { return (size_t)((lat->n + 255) / 256) * 256 * NET_SUMS_PER_NODE; }
+
+// The reverse mode runs on the matrix cores and can read kept network values
+// (float32 matrix-core network of depth 2).
+bool net_values_apply(const nco_lattice* lat) {
+    return lat->mlp_prec == NCO_MLP_F32_MFMA && lat->adj_tab && lat->depth == 2;
+}
+
 int launch_one(nco_lattice* lat, const void* fin, void* fout, long t, int slot = -1, bool replay = false,
                float* net_sums = nullptr) {
     StepArgs a = step_args_at(lat, t);
@@ -518,6 +533,7 @@ int nco_lattice_destroy(nco_lattice* lat) {
     if (lat->adj_tab) hipFree(lat->adj_tab);
     if (lat->adj_partial64) hipFree(lat->adj_partial64);
     if (lat->net_sums) hipFree(lat->net_sums);
+    if (lat->net_ends) hipFree(lat->net_ends);
     if (lat->spec_work) hipFree(lat->spec_work);
     if (lat->d_fk) hipFree(lat->d_fk);
     if (lat->d_fhat) hipFree(lat->d_fhat);
@@ -1077,6 +1093,21 @@ int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, doub
         HIP_TRY(hipMalloc(&p, lat->pop_bytes));
         lat->ckpt.push_back(p);
     }
+    // The last step of each segment keeps its network values for the adjoint
+    // of its state (no recomputed step precedes that adjoint) when they fit
+    // the budget beside the recompute's K - 1 states.
+    const size_t stride = net_values_stride(lat);
+    const size_t ends_floats = (size_t)ncp * stride;
+    lat->rec_ends = net_values_apply(lat) &&
+                    ((size_t)(ckpt_every - 1) * stride + ends_floats) * sizeof(float) <= lat->net_cache_bytes;
+    if (lat->rec_ends && lat->net_ends_floats < ends_floats) {
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        if (lat->net_ends) HIP_TRY(hipFree(lat->net_ends));
+        lat->net_ends = nullptr;
+        lat->net_ends_floats = 0;
+        HIP_TRY(hipMalloc(&lat->net_ends, sizeof(float) * ends_floats));
+        lat->net_ends_floats = ends_floats;
+    }
     const int nk = every > 0 ? nsteps / every + 1 : 0;
     if (nk > lat->d_k_cap) {
         // Kept between calls: a free would wait for the whole device.
@@ -1103,7 +1134,10 @@ int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, doub
                 break;
             }
         }
-        if ((rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t, s))) break;
+        float* ends = lat->rec_ends && (s % ckpt_every == ckpt_every - 1 || s == nsteps - 1)
+                          ? lat->net_ends + (size_t)(s / ckpt_every) * stride
+                          : nullptr;
+        if ((rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t, s, false, ends))) break;
         lat->cur = 1 - lat->cur;
         ++lat->force_t;
         if (nk > 0 && (s + 1) % every == 0) rc = sample((s + 1) / every);
@@ -1195,8 +1229,10 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
     // step reads them instead of running the network forward again (the
     // same arithmetic on the same state: the gradient is unchanged, bit for
     // bit).  The last state of a segment has no recomputed step and runs it.
-    const size_t sums_stride = (size_t)((lat->n + 255) / 256) * 256 * NET_SUMS_PER_NODE;
-    const bool keep_sums = mfma && lat->mlp_prec == NCO_MLP_F32_MFMA && lat->rec_every > 1 &&
+    // The last state of a segment reads what the recorded run kept for it
+    // (rec_ends), if it did.
+    const size_t sums_stride = net_values_stride(lat);
+    const bool keep_sums = mfma && net_values_apply(lat) && lat->rec_every > 1 &&
                            (size_t)(lat->rec_every - 1) * sums_stride * sizeof(float) <= lat->net_cache_bytes;
     if (keep_sums && lat->net_sums_floats < (size_t)(lat->rec_every - 1) * sums_stride) {
         HIP_TRY(hipStreamSynchronize(lat->stream));
@@ -1207,6 +1243,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
         lat->net_sums_floats = (size_t)(lat->rec_every - 1) * sums_stride;
     }
     auto sums_of = [&](int i) { return keep_sums ? lat->net_sums + (size_t)i * sums_stride : nullptr; };
+    auto end_of = [&](int sgi) { return lat->rec_ends ? lat->net_ends + (size_t)sgi * sums_stride : nullptr; };
     while ((int)lat->seg.size() < lat->rec_every) {
         void* p = nullptr;
         HIP_TRY(hipMalloc(&p, lat->pop_bytes));
@@ -1248,7 +1285,7 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
             if (phase) a.fhat = phase_slot(lat, t);
             if (int rc = force_field(lat, a, lat->stream)) return rc;
             if (mfma) {
-                a.net_sums = t - t0 < len - 1 ? sums_of(t - t0) : nullptr;
+                a.net_sums = t - t0 < len - 1 ? sums_of(t - t0) : end_of(sgi);
                 const char* tab = static_cast<const char*>(lat->adj_tab);
                 const float* lt32 = reinterpret_cast<const float*>(tab);
                 const int* gt32 = reinterpret_cast<const int*>(tab + sizeof(float) * mfma_lane_table_floats());

@@ -505,20 +505,23 @@ def test_vector_adjoint_matches_matrix_core_adjoint_at_size(n):
     assert rel < 1e-3 and relf < 1e-5
 
 
-@pytest.mark.parametrize("n,forced", [(24, False), (48, True)])
-def test_reverse_cache_leaves_the_gradient_unchanged(n, forced):
+@pytest.mark.parametrize("n,forced,K", [(24, False, 5), (48, True, 5), (24, True, 1)])
+def test_reverse_cache_leaves_the_gradient_unchanged(n, forced, K):
     """The recomputed forward steps of a segment keep their network values
-    (group sums, tilde tau) and the matrix-core adjoint reads them instead of
+    (group sums, tilde tau), the recorded run keeps those of the last state
+    of each segment, and the matrix-core adjoint reads them instead of
     running the network again: the same arithmetic on the same states, so
-    the gradient must not change at all.  24^3 runs the 64-node kernels, 48^3
-    the 256-node ones; 12 steps with checkpoints every 5 give segments of 5,
-    5 and 2 states (each with a last state that runs the network itself)."""
-    width, tau, T, K = 32, 0.56, 12, 5
+    the gradient must not change at all, whether nothing, only the
+    recompute's share or everything fits the budget.  24^3 runs the 64-node
+    kernels, 48^3 the 256-node ones; 12 steps with checkpoints every 5 give
+    segments of 5, 5 and 2 states, with checkpoints every step 12 of 1."""
+    width, tau, T = 32, 0.56, 12
     params = inputs.mlp_params(width, 81)
     _, u = inputs.turbulence(n, seed=82, k0=4.0, urms=0.05)
     w = np.random.Generator(np.random.PCG64(83)).standard_normal((27, n, n, n))
+    state_bytes = -(-n ** 3 // 256) * 256 * 36 * 4
     out = []
-    for cache in (0, 1 << 30):
+    for cache in (0, (K - 1) * state_bytes + 1, 1 << 30):
         with Lattice((n, n, n), "f32", "nco", tau) as lat:
             lat.set_net_weights(params, width, "tanh", "f32_mfma")
             lat.set_reverse_cache(cache)
@@ -528,5 +531,6 @@ def test_reverse_cache_leaves_the_gradient_unchanged(n, forced):
             lat.init_equilibrium(None, u)
             lat.forward_record(T, K)
             out.append(lat.backward(dL_df=w, want_df0=True))
-    assert np.array_equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0])
+        assert np.array_equal(out[0][1], o[1])
