@@ -632,6 +632,9 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ops", default=",".join(list(VARIANTS) + ["nco_train", "nco_train_stored"]))
+    ap.add_argument("--reverse-cache", type=int, default=None,
+                    help="bytes of kept network values for nco_train's reverse mode (library default if unset; "
+                         "0: every adjoint runs the network forward)")
     ap.add_argument("--serving-requests", type=int, default=16,
                     help="requests of the serving leg (0: no serving leg)")
     ap.add_argument("--serving-load", type=float, default=0.8)
@@ -696,7 +699,7 @@ def main():
             # nco_train_stored: every state a checkpoint (no recompute) and
             # every step's network values kept (40 x 0.3 GB at 128^3 beside
             # the 40 x 0.23 GB of states), the memory-rich form.
-            kw = {} if op == "nco_train" else {"K": 1, "cache_bytes": 16 << 30}
+            kw = {"cache_bytes": args.reverse_cache} if op == "nco_train" else {"K": 1, "cache_bytes": 16 << 30}
             results[op] = train_step(n, tau, rho, u, params, width, stream, **kw)
             print("# %s: forward %.4f ms/step, reverse %.4f ms/step" % (
                 op, results[op]["forward_ms_per_step"], results[op]["reverse_ms_per_step"]), file=sys.stderr,
