@@ -362,7 +362,11 @@ int nco_set_forcing_power(nco_lattice* lat, int n_modes, const int* k, const dou
 
 /* Run nsteps steps (NCO operator, width 32, float storage) keeping a
  * checkpoint of the state every ckpt_every steps in device memory, for a
- * following nco_backward (the gradient of Adam in Sec. "Learning Task"). */
+ * following nco_backward (the gradient of Adam in Sec. "Learning Task").
+ * With a float32 matrix-core network of depth 2 it also keeps the network
+ * values of the last step of each checkpoint segment when the reverse-mode
+ * budget allows (nco_set_reverse_cache); ckpt_every = 1 keeps every state
+ * and nco_backward then recomputes nothing. */
 int nco_forward_record(nco_lattice* lat, int nsteps, int ckpt_every);
 
 /* nco_forward_record, and the mean kinetic energy k(t) = <|u|^2> / 2
