@@ -1244,9 +1244,10 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
     }
     auto sums_of = [&](int i) { return keep_sums ? lat->net_sums + (size_t)i * sums_stride : nullptr; };
     auto end_of = [&](int sgi) { return lat->rec_ends ? lat->net_ends + (size_t)sgi * sums_stride : nullptr; };
+    // States 1..K-1 of a segment (its state 0 is the checkpoint).
     while ((int)lat->seg.size() < lat->rec_every) {
         void* p = nullptr;
-        HIP_TRY(hipMalloc(&p, lat->pop_bytes));
+        if (!lat->seg.empty()) HIP_TRY(hipMalloc(&p, lat->pop_bytes));
         lat->seg.push_back(p);
     }
     // Adjoint of the final state.
@@ -1273,10 +1274,11 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
     const int ncp = (T + K - 1) / K;
     for (int sgi = ncp - 1; sgi >= 0; --sgi) {
         const int t0 = sgi * K, len = std::min(K, T - t0);
-        // Recompute the states of this segment from its checkpoint.
-        HIP_TRY(hipMemcpyAsync(lat->seg[0], lat->ckpt[sgi], lat->pop_bytes, hipMemcpyDeviceToDevice, lat->stream));
+        // Recompute the states of this segment from its checkpoint, which
+        // serves as the segment's first state itself (only read from here).
+        auto state = [&](int i) -> void* { return i == 0 ? lat->ckpt[sgi] : lat->seg[i]; };
         for (int i = 1; i < len; ++i)
-            if (int rc = launch_one(lat, lat->seg[i - 1], lat->seg[i], lat->rec_force_t0 + t0 + i - 1, t0 + i - 1,
+            if (int rc = launch_one(lat, state(i - 1), lat->seg[i], lat->rec_force_t0 + t0 + i - 1, t0 + i - 1,
                                     true, sums_of(i - 1)))
                 return rc;
         for (int t = t0 + len - 1; t >= t0; --t) {
@@ -1291,22 +1293,22 @@ int backward(nco_lattice* lat, const double* dL_dk, int every, const double* dL_
                 const int* gt32 = reinterpret_cast<const int*>(tab + sizeof(float) * mfma_lane_table_floats());
                 const float* adj = reinterpret_cast<const float*>(tab + sizeof(float) * mfma_lane_table_floats() +
                                                                   sizeof(int) * mfma_group_table_ints());
-                HIP_TRY(launch_adjoint_mfma(lat->storage, lat->act, lat->seg[t - t0], lin, lout, a, lt32, gt32, adj,
+                HIP_TRY(launch_adjoint_mfma(lat->storage, lat->act, state(t - t0), lin, lout, a, lt32, gt32, adj,
                                             lat->d_gsrc, lat->adj_partial64, lat->stream));
             } else {
-                HIP_TRY(launch_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_gsrc, lat->adj_partial,
+                HIP_TRY(launch_adjoint(lat->storage, state(t - t0), lin, lout, a, lat->d_gsrc, lat->adj_partial,
                                        lat->adj_xwork, lat->stream));
                 HIP_TRY(launch_grad_reduce(lat->adj_partial, nblk, npar, lat->d_grad, lat->stream));
             }
             if (phase) {
                 // The force of step t also depends on x_t through its velocity modes.
                 const long ft = (lat->rec_force_t0 + t) % lat->force_steps;
-                HIP_TRY(launch_force_phase_adjoint(lat->storage, lat->seg[t - t0], lin, lout, a, lat->d_fpart,
+                HIP_TRY(launch_force_phase_adjoint(lat->storage, state(t - t0), lin, lout, a, lat->d_fpart,
                                                    lat->d_fbasis, lat->d_fdraw + (size_t)ft * lat->n_modes * 2,
                                                    phase_slot(lat, t) + 6 * lat->n_modes, lat->d_fduhat,
                                                    lat->stream));
             }
-            if (int rc = inject(t, lat->seg[t - t0], lout)) return rc;
+            if (int rc = inject(t, state(t - t0), lout)) return rc;
             std::swap(lin, lout);
         }
     }
