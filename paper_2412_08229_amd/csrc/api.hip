@@ -1128,16 +1128,18 @@ int forward_record(nco_lattice* lat, int nsteps, int ckpt_every, int every, doub
     if (nk > 0) rc = sample(0);
     for (int s = 0; s < nsteps && rc == NCO_OK; ++s) {
         if (s % ckpt_every == 0) {
-            if (hipMemcpyAsync(lat->ckpt[s / ckpt_every], lat->f[lat->cur], lat->pop_bytes, hipMemcpyDeviceToDevice,
-                               lat->stream) != hipSuccess) {
-                rc = fail(NCO_E_HIP, "checkpoint copy failed");
-                break;
-            }
+            // The checkpoint takes over the buffer that holds the state (no
+            // copy; every buffer has the lattice's size), the step reads it
+            // there, and the checkpoint's previous buffer joins the two step
+            // buffers (nco_device_populations' pointer is valid until the
+            // next step).
+            std::swap(lat->ckpt[s / ckpt_every], lat->f[lat->cur]);
         }
+        const void* fin = s % ckpt_every == 0 ? lat->ckpt[s / ckpt_every] : lat->f[lat->cur];
         float* ends = lat->rec_ends && (s % ckpt_every == ckpt_every - 1 || s == nsteps - 1)
                           ? lat->net_ends + (size_t)(s / ckpt_every) * stride
                           : nullptr;
-        if ((rc = launch_one(lat, lat->f[lat->cur], lat->f[1 - lat->cur], lat->force_t, s, false, ends))) break;
+        if ((rc = launch_one(lat, fin, lat->f[1 - lat->cur], lat->force_t, s, false, ends))) break;
         lat->cur = 1 - lat->cur;
         ++lat->force_t;
         if (nk > 0 && (s + 1) % every == 0) rc = sample((s + 1) / every);
