@@ -667,6 +667,19 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
 
 constexpr int mfma_block_threads(int nodes, int tpw) { return nodes / (16 * tpw) * 64; }
 
+// XCD-aware block order: workgroups are dispatched to the 8 XCDs in turn
+// (workgroup b to XCD b mod 8), each XCD with its own L2.  Block b takes
+// the logical block that makes the blocks of one XCD a contiguous run of
+// the lattice (XCD x: its i-th block is the i-th of the x-th run), so the
+// halo rows that neighbouring blocks share, and the second pull after the
+// network, meet in that XCD's L2.  A bijection of [0, n): the results do
+// not depend on it.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    constexpr int XCDS = 8;
+    const int x = b % XCDS, i = b / XCDS, q = n / XCDS, r = n % XCDS;
+    return x * q + min(x, r) + i;
+}
+
 // Waves per SIMD the register allocation must leave room for: 3 for the
 // split networks (156 VGPRs for tanh at depth 2; the others spill 12-57
 // registers into scratch and still run 1-7 % faster than at 2 waves, the
@@ -684,8 +697,8 @@ __attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC, DEPTH, SUMS)))) void k_n
     const typename Codec<S>::store_t* __restrict__ fin, typename Codec<S>::store_t* __restrict__ fout,
     StepArgs a, const float* __restrict__ lane_tab, const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
-    nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW, SUMS>(fin, fout, a, lane_tab, gtab, omega_out, blockIdx.x,
-                                                           lds);
+    nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW, SUMS>(fin, fout, a, lane_tab, gtab, omega_out,
+                                                           xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 template <int S, int ACT, int PREC>
