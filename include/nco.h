@@ -382,7 +382,12 @@ int nco_forward_record_energy(nco_lattice* lat, int nsteps, int ckpt_every, int 
  * or NULL).  Writes grad (n_params = 2084 values, the parameter order of
  * nco_set_net_weights) in float64 and, if dL_df0 is not NULL, dL/d(initial
  * populations) (27N values).  Segments are recomputed from their checkpoints;
- * the result is deterministic (fixed-order reductions). */
+ * the result is deterministic (fixed-order reductions).  The recorded and
+ * recomputed steps run the lattice's own network arithmetic; the adjoint
+ * differentiates the network in float32: on the matrix cores for the
+ * depth-2 matrix-core networks (NCO_MLP_F32_MFMA, and NCO_MLP_F32_SPLIT and
+ * NCO_MLP_BF16, whose product rounding it does not differentiate), on the
+ * vector units for NCO_MLP_F32 and depth 3. */
 int nco_backward(nco_lattice* lat, const double* dL_dE, int nbins, const double* dL_df, double* grad,
                  size_t n_params, double* dL_df0);
 

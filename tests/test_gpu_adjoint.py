@@ -143,7 +143,10 @@ def _setup(n, width, seed, act):
 
 @pytest.mark.parametrize("act,mlp,forced", [("tanh", "f32", False), ("tanh", "f32_mfma", True),
                                             ("relu", "f32", False), ("tanh", "f32_mfma", False),
-                                            ("relu", "f32_mfma", True)])
+                                            ("relu", "f32_mfma", True),
+                                            # split products in the recorded and recomputed steps,
+                                            # the float32 matrix-core adjoint behind them
+                                            ("tanh", "f32_split", True), ("relu", "f32_split", False)])
 def test_spectrum_loss_gradient_matches_oracle(act, mlp, forced):
     n, width, tau, T, K = 8, 32, 0.56, 6, 4
     params, rho, u, f0, Et = _setup(n, width, 4, act)
