@@ -62,12 +62,14 @@ VARIANTS["nco_w20_relu_bf16net"] = ("nco", "f32", "bf16", "relu")
 VARIANTS["nco_w20_relu_f32split"] = ("nco", "f32", "f32_split", "relu")
 NET_WIDTH = {"nco_w20_relu": 20, "nco_w20_relu_bf16net": 20, "nco_w20_relu_f32split": 20}
 # The paper's network for the dissipation training, 27-20-20-20-4 ReLU (third
-# hidden layer; float32 matrix cores or vector units, zero-padded to width 32).
+# hidden layer; on the matrix cores zero-padded to width 32).
 VARIANTS["nco_d3_w20_relu"] = ("nco", "f32", "f32_mfma", "relu")
 VARIANTS["nco_d3_w20_relu_valu"] = ("nco", "f32", "f32", "relu")
 VARIANTS["nco_d3_w20_relu_f32split"] = ("nco", "f32", "f32_split", "relu")
-NET_WIDTH["nco_d3_w20_relu"] = NET_WIDTH["nco_d3_w20_relu_valu"] = NET_WIDTH["nco_d3_w20_relu_f32split"] = 20
-NET_DEPTH = {"nco_d3_w20_relu": 3, "nco_d3_w20_relu_valu": 3, "nco_d3_w20_relu_f32split": 3}
+VARIANTS["nco_d3_w20_relu_bf16net"] = ("nco", "f32", "bf16", "relu")
+NET_DEPTH = {}
+for _v in ("nco_d3_w20_relu", "nco_d3_w20_relu_valu", "nco_d3_w20_relu_f32split", "nco_d3_w20_relu_bf16net"):
+    NET_WIDTH[_v], NET_DEPTH[_v] = 20, 3
 # The same Taylor-Green vortex on the reduced cube of Appendix A: an n/4
 # cube standing for the n box (the node grid is offset by half a spacing).
 VARIANTS["nco_octant"] = ("nco", "f32", "f32_mfma", "tanh")

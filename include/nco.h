@@ -189,11 +189,9 @@ int nco_set_net_weights(nco_lattice* lat, int width, int act, int mlp_prec,
  * Sec. "Training based on dissipation rates", which adds a hidden layer:
  * 27 -> width -> width -> width -> 4, params in the order W1[27][width],
  * b1, W2[width][width], b2, W2b[width][width], b2b, W3[width][4], b3
- * (n_params = width*(27 + 2 width + 4) + 3 width + 4).  Depth 3 runs on the
- * vector units (NCO_MLP_F32), the float32 matrix cores (NCO_MLP_F32_MFMA)
- * or split over the 16-bit ones (NCO_MLP_F32_SPLIT), not on the bf16
- * network (NCO_E_UNSUPPORTED), with narrower networks zero-padded
- * to width 32, and has the reverse mode (vector-unit adjoint): nco_backward
+ * (n_params = width*(27 + 2 width + 4) + 3 width + 4).  Depth 3 runs in
+ * every network arithmetic (the matrix-core ones with narrower networks
+ * zero-padded to width 32) and has the reverse mode (vector-unit adjoint): nco_backward
  * returns the gradient in this parameter order.  nco_batch_step refuses
  * depth-3 lattices.  Setting the weights drops a recorded run. */
 int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, int mlp_prec,

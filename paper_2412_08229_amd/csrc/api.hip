@@ -610,8 +610,6 @@ int nco_set_net_weights_depth(nco_lattice* lat, int depth, int width, int act, i
         return fail(NCO_E_INVALID, "unknown network precision %d", mlp_prec);
     if (mlp_prec != NCO_MLP_F32 && lat->storage == NCO_F64)
         return fail(NCO_E_UNSUPPORTED, "the matrix-core network needs float32 or 16-bit storage");
-    if (depth == 3 && mlp_prec == NCO_MLP_BF16)
-        return fail(NCO_E_UNSUPPORTED, "a third hidden layer runs on the vector units or float32-class matrix cores");
     if (!params) return fail(NCO_E_INVALID, "null parameters");
     if (n_params != n_params_depth(width, depth))
         return fail(NCO_E_INVALID, "expected %zu parameters for width %d and depth %d, got %zu",

@@ -105,6 +105,8 @@ constexpr int LB_B2 = 16;           // [u 2][r 4]
 constexpr int LB_W3 = 24;           // [u 2][r 4][n 4]
 constexpr int LB_B3 = 56;           // [n 4]
 constexpr int LB_SM = 60;           // [bit 3][4 words] sign masks of classes with that bit
+constexpr int LB_A2B = 72;          // [v 2][4 words]  W2b (depth 3)
+constexpr int LB_B2B = 80;          // [v 2][r 4]      b2b (depth 3)
 constexpr int LANE_WORDS = 144;
 
 // Activation as evaluated on this path.  For tanh the pre-activation arrives
@@ -574,13 +576,15 @@ __device__ __forceinline__ void network_split(const float* __restrict__ sm, cons
     }
 }
 
-template <int ACT, int TPW = 4>
+// DEPTH 3: the third hidden layer as one more bf16 product per group
+// element, fed by the second layer's activations packed like the first's.
+template <int ACT, int DEPTH = 2, int TPW = 4>
 __device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const int* __restrict__ sg,
                                              float* __restrict__ sw, const float* __restrict__ lt, int wave,
                                              int q, int c) {
     const unsigned* __restrict__ lw = reinterpret_cast<const unsigned*>(lt);
-    u32x4 A1[2], A2[2], SM[3];
-    float B2[2][4];
+    u32x4 A1[2], A2[2], SM[3], A3[2];
+    float B2[2][4], B3[2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
         A1[t] = u32x4{lw[LB_A1 + 4 * t], lw[LB_A1 + 4 * t + 1], lw[LB_A1 + 4 * t + 2], lw[LB_A1 + 4 * t + 3]};
@@ -594,6 +598,14 @@ __device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) B2[u][r] = lt[LB_B2 + u * 4 + r];
+    if constexpr (DEPTH == 3) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            A3[v] = u32x4{lw[LB_A2B + 4 * v], lw[LB_A2B + 4 * v + 1], lw[LB_A2B + 4 * v + 2], lw[LB_A2B + 4 * v + 3]};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) B3[v][r] = lt[LB_B2B + v * 4 + r];
+        }
+    }
 
 #pragma unroll 1
     for (int j = 0; j < TPW; ++j) {
@@ -628,6 +640,17 @@ __device__ __forceinline__ void network_bf16(const float* __restrict__ sm, const
                 f32x4 c2[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) c2[u] = mfma32(A2[u], hb, f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]});
+                if constexpr (DEPTH == 3) {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) h[u][r] = act_scaled<ACT>(c2[u][r]);
+                    const u32x4 h2b = {pack_bf16(h[0][0], h[0][1]), pack_bf16(h[0][2], h[0][3]),
+                                       pack_bf16(h[1][0], h[1][1]), pack_bf16(h[1][2], h[1][3])};
+#pragma unroll
+                    for (int v = 0; v < 2; ++v)
+                        c2[v] = mfma32(A3[v], h2b, f32x4{B3[v][0], B3[v][1], B3[v][2], B3[v][3]});
+                }
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -686,9 +709,13 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 // third wave keeping their vector instructions issuing) and for the float32
 // depth-3 steps (the instantiation with the network-value branch, 177
 // VGPRs unconstrained; at 168, 0-17 spilled, 4 % faster at 128^3 and 8 % on
-// a 16^3 lattice), no constraint otherwise.
+// a 16^3 lattice), 4 for the bf16 depth-3 steps (ReLU 132 VGPRs
+// unconstrained, 128 without spills at 4 waves, 2 % faster), no constraint
+// otherwise.
 constexpr int mfma_min_waves(int prec, int depth, bool sums) {
-    return prec == MLP_PREC_F32S || (prec == MLP_PREC_F32 && depth == 3 && sums) ? 3 : 1;
+    return prec == MLP_PREC_BF16 && depth == 3 ? 4
+           : prec == MLP_PREC_F32S || (prec == MLP_PREC_F32 && depth == 3 && sums) ? 3
+                                                                                     : 1;
 }
 
 template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH, int TPW, bool SUMS = false>
@@ -762,7 +789,7 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
         const int lane = tid & 63;
         const float* __restrict__ lt = lane_tab + lane * LANE_WORDS;
         if constexpr (PREC == MLP_PREC_BF16) {
-            network_bf16<ACT, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
+            network_bf16<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
         } else if constexpr (PREC == MLP_PREC_F32S) {
             static_assert(!SUMS, "the split arithmetic keeps no network values");
             network_split<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
@@ -1568,6 +1595,17 @@ void mfma_prepare_tables(const float* params, int act, int prec, const int (*gsr
                         (bf16_bits(kappa * fold * W2[hid(2 * w + 1) * W + 16 * u + c]) << 16);
             for (int u = 0; u < 2; ++u)
                 for (int r = 0; r < 4; ++r) lt[LB_B2 + u * 4 + r] = kappa * b2f[16 * u + 4 * q + r];
+            if (depth == 3) {
+                // Third layer, in the second's layout, tanh of the second
+                // folded in as for W2.
+                for (int v = 0; v < 2; ++v)
+                    for (int w = 0; w < 4; ++w)
+                        lw[LB_A2B + 4 * v + w] =
+                            bf16_bits(kappa * fold * W2b[hid(2 * w) * W + 16 * v + c]) |
+                            (bf16_bits(kappa * fold * W2b[hid(2 * w + 1) * W + 16 * v + c]) << 16);
+                for (int v = 0; v < 2; ++v)
+                    for (int r = 0; r < 4; ++r) lt[LB_B2B + v * 4 + r] = kappa * b2bf[16 * v + 4 * q + r];
+            }
             for (int u = 0; u < 2; ++u)
                 for (int r = 0; r < 4; ++r)
                     for (int n = 0; n < 4; ++n)
@@ -1761,8 +1799,11 @@ template <int S, int ACT, bool RR>
 hipError_t launch_mfma_prec(int prec, const void* fin, void* fout, const StepArgs& a, const float* lane_tab,
                             const int* gtab, double* omega_out, hipStream_t st) {
     const int kind = mfma_block_kind(a.n);
-    if (prec == MLP_PREC_BF16)
+    if (prec == MLP_PREC_BF16) {
+        if (a.depth == 3)
+            return launch_mfma_kind<S, ACT, RR, MLP_PREC_BF16, 3>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
         return launch_mfma_kind<S, ACT, RR, MLP_PREC_BF16, 2>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);
+    }
     if (prec == MLP_PREC_F32S) {
         if (a.depth == 3)
             return launch_mfma_kind<S, ACT, RR, MLP_PREC_F32S, 3>(kind, fin, fout, a, lane_tab, gtab, omega_out, st);

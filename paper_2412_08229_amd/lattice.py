@@ -74,7 +74,7 @@ class Lattice:
 
     def set_net_weights(self, params, width, act="tanh", mlp_prec="f32", depth=2):
         """Network weights (order W1, b1, W2, b2, [W2b, b2b,] W3, b3); depth
-        3 adds the third hidden layer (vector units or float32 matrix cores).
+        3 adds the third hidden layer (any arithmetic).
         mlp_prec: "f32" (vector units), "f32_mfma" (float32 matrix cores),
         "bf16" (bf16 products) or "f32_split" (float32-class products split
         over the 16-bit matrix cores)."""
