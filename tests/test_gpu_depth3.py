@@ -88,6 +88,38 @@ def test_depth3_bf16_network_close_to_oracle(width, act, storage):
     assert err < {"f32": 3e-5, "bf16": 3e-4}[storage]
 
 
+@pytest.mark.parametrize("mlp,tol", [("f32_mfma", 1e-6), ("f32_split", 1e-6), ("bf16", 1e-5)])
+@pytest.mark.parametrize("n", [41, 128])
+def test_depth3_sampled_against_oracle_at_size(n, mlp, tol):
+    """The 27-20-20-20-4 ReLU network in the block shapes of larger
+    lattices: 64-node blocks of four tiles per wavefront (41^3, a ragged
+    last block) and 256-node blocks (128^3, the benchmark's launch), one step
+    of the Taylor-Green vortex checked on 256 sampled nodes.  Bounds: those
+    of the depth-2 sampled checks of the same arithmetics."""
+    u0 = 0.1 / np.sqrt(3.0)
+    _, tau = inputs.viscosity(n, u0, 1600.0)
+    rho, u = inputs.tgv3d(n, u0)
+    params = inputs.mlp_params(20, 50, depth=3)
+    layers = collision.unpack_params(params, 20, depth=3)
+    with Lattice((n, n, n), "f32", "nco", tau) as lat:
+        lat.set_net_weights(params, 20, "relu", mlp, depth=3)
+        lat.init_equilibrium(rho, u)
+        lat.step(3)
+        before = lat.populations()
+        lat.step(1)
+        after = lat.populations()
+    pts = np.random.Generator(np.random.PCG64(51)).integers(0, n, size=(256, 3))
+    C = [(cx, cy, cz) for cz in (-1, 0, 1) for cy in (-1, 0, 1) for cx in (-1, 0, 1)]
+    pulled = np.empty((27, len(pts)))
+    for i, (cx, cy, cz) in enumerate(C):
+        pulled[i] = before[i, (pts[:, 0] - cz) % n, (pts[:, 1] - cy) % n, (pts[:, 2] - cx) % n]
+    want = step.Operator("nco", tau, layers=layers, act="relu").collide(pulled)
+    got = after[:, pts[:, 0], pts[:, 1], pts[:, 2]]
+    err = np.abs(got - want).max()
+    print("depth 3 %s at %d^3, sampled: max err %.3e" % (mlp, n, err))
+    assert err < tol
+
+
 def test_depth3_rates_match_oracle():
     params, layers, _, _ = _setup(20, "relu", 41)
     f = inputs.random_populations((6, 5, 7), seed=42, lo=0.8, hi=1.2)
