@@ -306,11 +306,12 @@ def test_mfma_network_rates_match_oracle(storage, act):
 
 
 @pytest.mark.parametrize("mlp", ["f32_mfma", "f32_split"])
-@pytest.mark.parametrize("shape", [(5, 7, 9), (1, 1, 1), (16, 16, 16), (67, 65, 66)])
+@pytest.mark.parametrize("shape", [(5, 7, 9), (1, 1, 1), (16, 16, 16), (41, 43, 45), (67, 65, 66)])
 def test_mfma_step_matches_oracle_ragged(shape, mlp):
-    """Two steps against the oracle, from a ragged partial block to a lattice
-    of 256-node blocks (67 x 65 x 66 = 287,430 nodes) with a partial last
-    block."""
+    """Two steps against the oracle, from a ragged partial block to
+    lattices of 64-node blocks of four tiles per wavefront (41 x 43 x 45 =
+    79,335 nodes) and of 256-node blocks (67 x 65 x 66 = 287,430 nodes),
+    each with a partial last block."""
     f0 = inputs.random_populations(shape, seed=16, lo=0.9, hi=1.1)
     tau = 0.56
     if shape[0] > 16:
@@ -494,11 +495,12 @@ def test_bench_256_datapath_sampled_against_oracle(kind):
     assert err < 1e-6
 
 
-def test_bench_size_bf16_network_sampled_against_oracle():
+@pytest.mark.parametrize("n", [43, 128])
+def test_bench_size_bf16_network_sampled_against_oracle(n):
     """128^3 NCO with the bf16 matrix-core network (the benchmark's
-    nco_bf16net variant): one step on 256 sampled nodes, within the bf16
-    network's rounding (its rates carry ~1e-3 relative error)."""
-    n = 128
+    nco_bf16net variant), and 43^3 (64-node blocks of four tiles, a ragged
+    last block): one step on 256 sampled nodes, within the bf16 network's
+    rounding (its rates carry ~1e-3 relative error)."""
     _, tau = inputs.viscosity(n, 0.1 / np.sqrt(3.0), 1600.0)
     rho, u = inputs.tgv3d(n, 0.1 / np.sqrt(3.0))
     with _lattice((n, n, n), "f32", "nco", tau, mlp="bf16") as lat:
@@ -511,5 +513,5 @@ def test_bench_size_bf16_network_sampled_against_oracle():
     want = _oracle_op("nco", tau).collide(_pulled(before, pts, n))
     got = after[:, pts[:, 0], pts[:, 1], pts[:, 2]]
     err = np.abs(got - want).max()
-    print("128^3 bf16 network, sampled: max err %.3e" % err)
+    print("%d^3 bf16 network, sampled: max err %.3e" % (n, err))
     assert err < 1e-5
