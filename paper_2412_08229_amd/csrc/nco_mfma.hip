@@ -246,6 +246,140 @@ __device__ __forceinline__ void layer1_reflections(const float (&A1)[2][KSTEPS],
                 }
 }
 
+// One axis permutation p of a node tile on the float32 matrix cores (ge:
+// the permutation's gather slots of lane group q), the arithmetic of one
+// pass of network_f32's permutation loop: layer 1 of the 8 reflections, the
+// hidden layers (DEPTH 2 or 3), and each activation of the last hidden layer
+// handed to sink(s, u, r, value) (reflection s, hidden row 16 u + 4 q + r)
+// in the order network_f32 adds it to the group sum.
+template <int ACT, int DEPTH, typename Sink>
+__device__ __forceinline__ void permutation_f32(const float (&A1)[2][KSTEPS], const float (&A2)[2][2][4],
+                                                const float (&B2)[2][4], const float* __restrict__ lt,
+                                                const float* __restrict__ mrow, const int* __restrict__ ge,
+                                                Sink&& sink) {
+    f32x4 Y[8][2];
+    layer1_reflections(A1, mrow, ge, Y);
+    if constexpr (DEPTH == 3) {
+        // Unrolled: Y[s] must stay in registers.
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            float h1v[2][4];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h1v[t][r] = act_scaled<ACT>(Y[s][t][r]);
+            f32x4 c2[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) c2[u] = mfma4(A2[u][t][r], h1v[t][r], c2[u]);
+            float h2v[2][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h2v[u][r] = act_scaled<ACT>(c2[u][r]);
+            f32x4 c3[2];
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+                c3[v] = f32x4{lt[LT_B2B + v * 4], lt[LT_B2B + v * 4 + 1], lt[LT_B2B + v * 4 + 2],
+                              lt[LT_B2B + v * 4 + 3]};
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) c3[v] = mfma4(lt[LT_A2B + v * 8 + t * 4 + r], h2v[t][r], c3[v]);
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sink(s, v, r, act_scaled<ACT>(c3[v][r]));
+        }
+        return;
+    }
+    // Layer 2 and the two activations, software-pipelined over the
+    // reflections: while the 16 products of reflection s run on the matrix
+    // cores, the vector units activate layer 1 of reflection s + 1 and layer
+    // 2 of reflection s - 1 (independent of them).
+    f32x4 h1[2], c2p[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h1[t][r] = act_scaled<ACT>(Y[0][t][r]);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        f32x4 c2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) c2[u] = f32x4{B2[u][0], B2[u][1], B2[u][2], B2[u][3]};
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) c2[u] = mfma4(A2[u][t][r], h1[t][r], c2[u]);
+        if (s > 0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sink(s - 1, u, r, act_scaled<ACT>(c2p[u][r]));
+        }
+        if (s < 7) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h1[t][r] = act_scaled<ACT>(Y[s + 1][t][r]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) c2p[u] = c2[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sink(7, u, r, act_scaled<ACT>(c2p[u][r]));
+}
+
+// The float32 network's weights in registers, from the lane table.
+struct NetF32Regs {
+    float A1[2][KSTEPS], A2[2][2][4], B2[2][4];
+    __device__ __forceinline__ explicit NetF32Regs(const float* __restrict__ lt) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int st = 0; st < KSTEPS; ++st) A1[t][st] = lt[LT_A1 + t * KSTEPS + st];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) A2[u][t][r] = lt[LT_A2 + u * 8 + t * 4 + r];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) B2[u][r] = lt[LT_B2 + u * 4 + r];
+    }
+};
+
+// The group sum of a node tile and what follows it: with sums (a step
+// whose adjoint follows) the sum and tilde tau into sums[node]
+// [NET_SUMS_PER_NODE] and the rates into sw, else the rates into sw; as at
+// the end of network_f32's tile loop.
+__device__ __forceinline__ void finish_tile(const f32x4 (&acc)[2], const float* __restrict__ lt, int q, int node,
+                                            float* __restrict__ sw, float* __restrict__ sums) {
+    if (sums) {
+        float* __restrict__ row = sums + (size_t)node * NET_SUMS_PER_NODE;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) row[16 * u + 4 * q + r] = acc[u][r];
+        output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4, row + 32);
+    } else {
+        output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
+    }
+}
+
 // s2 != nullptr (adjoint): sw receives tilde tau instead of the rates and
 // s2[node][32] the group sum of the folded second-layer activations (row
 // 16 u + 4 q + r in lane (q, c)).  sums != nullptr (a step whose adjoint
@@ -385,6 +519,43 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
         } else {
             output_layer(acc, lt + LT_W3, lt + LT_B3, q, sw + node * 4);
         }
+    }
+}
+
+// Small lattices: one 16-node tile per block and its six axis permutations
+// on six wavefronts (wavefront p takes permutation p), where blocks of one
+// tile per wavefront leave most SIMDs idle and run the 48 group elements of
+// a tile in series.  Each wavefront writes the last-layer activations of its
+// permutation to vals[p][s][node][hidden] in LDS; wavefront 0 adds them in
+// the order (permutation, reflection) of network_f32, so the group sums, the
+// rates and the step equal those of the other block shapes bit for bit.
+constexpr int PSPLIT_ROW = 36;      // floats per (p, s, node) row of vals: 32 hidden, 16-byte aligned rows
+constexpr int PSPLIT_VALS = 6 * 8 * 16 * PSPLIT_ROW;
+
+template <int ACT, int DEPTH>
+__device__ __forceinline__ void network_f32_psplit(const float* __restrict__ sm, const int* __restrict__ sg,
+                                                   float* __restrict__ sw, const float* __restrict__ lt, int wave,
+                                                   int q, int c, float* __restrict__ vals,
+                                                   float* __restrict__ sums) {
+    const NetF32Regs w(lt);
+    permutation_f32<ACT, DEPTH>(w.A1, w.A2, w.B2, lt, sm + c * NODE_STRIDE, sg + (wave * 4 + q) * GT_STRIDE,
+                                [&](int s, int u, int r, float v) {
+                                    vals[((wave * 8 + s) * 16 + c) * PSPLIT_ROW + 16 * u + 4 * q + r] = v;
+                                });
+    __syncthreads();
+    if (wave == 0) {
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll 4
+        for (int ps = 0; ps < 48; ++ps) {
+            const float* __restrict__ row = vals + (ps * 16 + c) * PSPLIT_ROW + 4 * q;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const f32x4 v = *reinterpret_cast<const f32x4*>(row + 16 * u);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[u][r] += v[r];
+            }
+        }
+        finish_tile(acc, lt, q, c, sw, sums);
     }
 }
 
@@ -674,6 +845,7 @@ struct BlockLds {
     float* sm;      // [NODES][NODE_STRIDE] moments, then hidden activations
     int* sg;        // [GT_ENTRIES] gather table
     float* sw;      // [NODES][4] rates
+    float* vals = nullptr;  // [PSPLIT_VALS] last-layer activations (six-wavefront tiles)
 };
 
 template <int S, int ACT, bool RATES, int PREC, int NODES, int DEPTH = 2, int TPW = 4, bool SUMS = false>
@@ -688,7 +860,8 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
     __shared__ float lds_sw[(NODES) * 4];            \
     const BlockLds lds{lds_sm, lds_sg, lds_sw};
 
-constexpr int mfma_block_threads(int nodes, int tpw) { return nodes / (16 * tpw) * 64; }
+// TPW = 0: the six-wavefront tile of network_f32_psplit (16 nodes).
+constexpr int mfma_block_threads(int nodes, int tpw) { return tpw == 0 ? 6 * 64 : nodes / (16 * tpw) * 64; }
 
 // XCD-aware block order: workgroups are dispatched to the 8 XCDs in turn
 // (workgroup b to XCD b mod 8), each XCD with its own L2.  Block b takes
@@ -724,8 +897,16 @@ __attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC, DEPTH, SUMS)))) void k_n
     const typename Codec<S>::store_t* __restrict__ fin, typename Codec<S>::store_t* __restrict__ fout,
     StepArgs a, const float* __restrict__ lane_tab, const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
-    nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW, SUMS>(fin, fout, a, lane_tab, gtab, omega_out,
-                                                           xcd_block(blockIdx.x, gridDim.x), lds);
+    if constexpr (TPW == 0) {
+        __shared__ __align__(16) float lds_vals[PSPLIT_VALS];
+        BlockLds lv = lds;
+        lv.vals = lds_vals;
+        nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW, SUMS>(fin, fout, a, lane_tab, gtab, omega_out,
+                                                               xcd_block(blockIdx.x, gridDim.x), lv);
+    } else {
+        nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW, SUMS>(fin, fout, a, lane_tab, gtab, omega_out,
+                                                               xcd_block(blockIdx.x, gridDim.x), lds);
+    }
 }
 
 template <int S, int ACT, int PREC>
@@ -788,7 +969,11 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
     {
         const int lane = tid & 63;
         const float* __restrict__ lt = lane_tab + lane * LANE_WORDS;
-        if constexpr (PREC == MLP_PREC_BF16) {
+        if constexpr (TPW == 0) {
+            static_assert(PREC == MLP_PREC_F32 && NODES == 16, "six-wavefront tiles: the float32 network");
+            float* sums = SUMS && a.net_sums ? a.net_sums + (size_t)blk * NODES * NET_SUMS_PER_NODE : nullptr;
+            network_f32_psplit<ACT, DEPTH>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15, lds.vals, sums);
+        } else if constexpr (PREC == MLP_PREC_BF16) {
             network_bf16<ACT, DEPTH, TPW>(sm, sg, sw, lt, tid >> 6, lane >> 4, lane & 15);
         } else if constexpr (PREC == MLP_PREC_F32S) {
             static_assert(!SUMS, "the split arithmetic keeps no network values");
@@ -1753,6 +1938,12 @@ hipError_t launch_nco_mfma_grouped(int storage, int prec, int act, const LaunchG
 // 32^3 before the one-tile blocks existed, equal from 64^3 up).  Above, the
 // 256-node blocks.
 enum MfmaBlock { MFMA_BLOCK_256 = 0, MFMA_BLOCK_64 = 1, MFMA_BLOCK_64_TILE = 2 };
+// Float32-network steps of lattices up to this many nodes run six-wavefront
+// tiles (network_f32_psplit): 256 blocks, one round over the 256 CUs.  A
+// block holds 111 KB of LDS, one per CU, so beyond that the blocks run in
+// rounds and the one-tile-per-wavefront blocks are faster (16^3: 15 against
+// 30 us per step; 24^3: 53 against 31).
+constexpr int PSPLIT_MAX_NODES = 4096;
 int mfma_block_kind(int n) {
     return n < 65536 ? MFMA_BLOCK_64_TILE : n < 2 * 256 * 256 ? MFMA_BLOCK_64 : MFMA_BLOCK_256;
 }
@@ -1769,8 +1960,13 @@ hipError_t launch_mfma_kind(int kind, const void* fin, void* fout, const StepArg
         // that branch the compiler allocates 154-161 VGPRs at depth 2, 3
         // waves per SIMD, where the instantiation without it takes 230 and 2
         // waves and runs 3 % slower; at depth 3, 177 against 254 (with
-        // mfma_min_waves, 3 waves).
-        if (kind == MFMA_BLOCK_64_TILE)
+        // mfma_min_waves, 3 waves).  Steps of lattices up to
+        // PSPLIT_MAX_NODES run six-wavefront tiles.
+        if (a.n <= PSPLIT_MAX_NODES)
+            hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 16, DD, 0, true>), dim3((a.n + 15) / 16),
+                               dim3(mfma_block_threads(16, 0)), 0, st, static_cast<const T*>(fin),
+                               static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
+        else if (kind == MFMA_BLOCK_64_TILE)
             hipLaunchKernelGGL((k_nco_mfma<S, ACT, RR, PP, 64, DD, 1, true>), dim3(grid), dim3(mfma_block_threads(64, 1)),
                                0, st, static_cast<const T*>(fin), static_cast<T*>(fout), a, lane_tab, gtab, omega_out);
         else if (kind == MFMA_BLOCK_64)
