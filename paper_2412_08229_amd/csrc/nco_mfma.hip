@@ -531,6 +531,8 @@ __device__ __forceinline__ void network_f32(const float* __restrict__ sm, const 
 // rates and the step equal those of the other block shapes bit for bit.
 constexpr int PSPLIT_ROW = 36;      // floats per (p, s, node) row of vals: 32 hidden, 16-byte aligned rows
 constexpr int PSPLIT_VALS = 6 * 8 * 16 * PSPLIT_ROW;
+constexpr int PSPLIT_FROW = 28;     // floats per node of the pulled populations, after vals in LDS
+constexpr int PSPLIT_LDS = PSPLIT_VALS + 16 * PSPLIT_FROW;
 
 template <int ACT, int DEPTH>
 __device__ __forceinline__ void network_f32_psplit(const float* __restrict__ sm, const int* __restrict__ sg,
@@ -898,7 +900,7 @@ __attribute__((amdgpu_waves_per_eu(mfma_min_waves(PREC, DEPTH, SUMS)))) void k_n
     StepArgs a, const float* __restrict__ lane_tab, const int* __restrict__ gtab, double* __restrict__ omega_out) {
     NCO_BLOCK_LDS(NODES)
     if constexpr (TPW == 0) {
-        __shared__ __align__(16) float lds_vals[PSPLIT_VALS];
+        __shared__ __align__(16) float lds_vals[PSPLIT_LDS];
         BlockLds lv = lds;
         lv.vals = lds_vals;
         nco_mfma_block<S, ACT, RATES, PREC, NODES, DEPTH, TPW, SUMS>(fin, fout, a, lane_tab, gtab, omega_out,
@@ -944,7 +946,31 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
     for (int e = tid; e < GT_ENTRIES; e += THREADS) sg[e] = gtab[e];
 
     // Phase A: pull and transform to moments.
-    if (THREADS == NODES || tid < NODES) {
+    if constexpr (TPW == 0) {
+        // Six-wavefront tiles: the tile's 16 x 27 pulls spread over the
+        // block's threads (each a load or a folded one at the faces of the
+        // reduced cube), kept in LDS for the relaxation as well.
+        static_assert(!RATES, "six-wavefront tiles run steps");
+        float* __restrict__ fl = lds.vals + PSPLIT_VALS;
+        for (int e = tid; e < NODES * Q; e += THREADS) {
+            const int nd = e % NODES, i = e / NODES, id = blk * NODES + nd;
+            fl[nd * PSPLIT_FROW + i] =
+                id < a.n ? pull_one<S>(fin, a, node_of(id, a.nx, a.ny), i) : (float)weight_of(i);
+        }
+        __syncthreads();
+        if (tid < NODES) {
+            float f[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[i] = fl[tid * PSPLIT_FROW + i];
+            float m[Q];
+            to_moments(f, m);
+            float* row = sm + tid * NODE_STRIDE;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) row[k] = m[row_tensor(k)];
+            row[27] = 1.0f;
+            row[28] = 0.0f;
+        }
+    } else if (THREADS == NODES || tid < NODES) {
         float f[Q];
         if (live) {
             if constexpr (RATES)
@@ -999,7 +1025,12 @@ __device__ __forceinline__ void nco_mfma_block(const typename Codec<S>::store_t*
     // Phase C: relax with the rates and store.
     if (live) {
         float f[Q], m[Q];
-        pull<S>(fin, a, node_of(idx, a.nx, a.ny), f);
+        if constexpr (TPW == 0) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[i] = lds.vals[PSPLIT_VALS + tid * PSPLIT_FROW + i];
+        } else {
+            pull<S>(fin, a, node_of(idx, a.nx, a.ny), f);
+        }
         const float* row = sm + tid * NODE_STRIDE;
 #pragma unroll
         for (int k = 0; k < Q; ++k) m[row_tensor(k)] = row[k];

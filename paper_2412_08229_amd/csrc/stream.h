@@ -104,6 +104,21 @@ __device__ __forceinline__ void pull(const typename Codec<S>::store_t* __restric
     }
 }
 
+// Population i of node (x, y, z) as pull reads it: one of its 27 loads.
+template <int S>
+__device__ __forceinline__ typename Codec<S>::real pull_one(const typename Codec<S>::store_t* __restrict__ fin,
+                                                            const StepArgs& a, NodeIdx p, int i) {
+    const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+    if (on_octant_face(a, p)) {
+        const Slot s = fold_octant(a.nx, p.x - cx, p.y - cy, p.z - cz, cx, cy, cz);
+        return Codec<S>::load(fin + (size_t)s.plane * a.n + s.node, i);
+    }
+    const int x = cx < 0 ? (p.x == a.nx - 1 ? 0 : p.x + 1) : cx > 0 ? (p.x == 0 ? a.nx - 1 : p.x - 1) : p.x;
+    const int y = cy < 0 ? (p.y == a.ny - 1 ? 0 : p.y + 1) : cy > 0 ? (p.y == 0 ? a.ny - 1 : p.y - 1) : p.y;
+    const int z = cz < 0 ? (p.z == a.nz - 1 ? 0 : p.z + 1) : cz > 0 ? (p.z == 0 ? a.nz - 1 : p.z - 1) : p.z;
+    return Codec<S>::load(fin + (size_t)i * a.n + ((size_t)z * a.ny + y) * a.nx + x, i);
+}
+
 // Adjoint of pull: v_i(x) goes to the slot the pull of population i at x
 // read, dL/df_i(x - c_i) = v_i(x) (periodic) or its folded slot.
 __device__ __forceinline__ void scatter_to_sources(float* __restrict__ out, const StepArgs& a, NodeIdx p,
